@@ -1,0 +1,37 @@
+"""FP64 CPU oracle for the lensed-image simulation -- TEST INFRASTRUCTURE ONLY.
+
+Only the test-suite, the package smoke check and the benchmark's CPU-baseline
+leg may import this package.  The HIP library never calls it and shares no
+code with it (no kernels, helpers, tables or constants).
+
+What it computes is the paper's three-step image simulation ("Improvements over
+lenstronomy in image simulation"): a coordinate grid in the observer's angles is
+ray-traced through the deflectors to the source plane, the source surface
+brightness is evaluated on the traced grid, and the lensed image is convolved
+with the PSF.  The paper gives no formulas; every profile below is the standard
+closed form from the lensing literature, named in its module, and evaluated in
+FP64 with branch forms that are well conditioned.  The direct sum over
+deflectors is an exact definition, so the oracle *is* that definition.
+
+Parity pins (closed forms, invariants, quadrature, library routines) live in
+tests/test_oracle_*.py.  The input generators are only used as data sources;
+the unpinned pieces are listed in `PARITY_UNPINNED`.
+"""
+from .grid import subpixel_coords, supersample_reduce
+from .lens import (sie_deflection, sie_kappa, shear_deflection, nfw_g, nfw_deflection,
+                   nfw_kappa, point_mass_deflection, total_deflection, ray_shoot)
+from .light import sersic_bn, sersic, surface_brightness
+from .conv import convolve_same
+from .simulate import simulate_image, simulate_unconvolved
+from .likelihood import log_likelihood, noise_variance
+
+# Functions whose result no independent pin fixes (see the test modules).
+PARITY_UNPINNED = ()
+
+__all__ = [
+    "subpixel_coords", "supersample_reduce", "sie_deflection", "sie_kappa",
+    "shear_deflection", "nfw_g", "nfw_deflection", "nfw_kappa", "point_mass_deflection",
+    "total_deflection", "ray_shoot", "sersic_bn", "sersic", "surface_brightness",
+    "convolve_same", "simulate_image", "simulate_unconvolved", "log_likelihood",
+    "noise_variance", "PARITY_UNPINNED",
+]
