@@ -1,0 +1,203 @@
+/*
+ * jt.h -- C ABI of libjt, an MI355X (gfx950) lensed-image simulator.
+ *
+ * The library computes the paper's three-step image simulation (JAXtronomy,
+ * section "Improvements over lenstronomy in image simulation"):
+ *   1. a coordinate grid in the observer's angles is ray-traced through the
+ *      deflectors to the source plane (deflection angles at each deflector);
+ *   2. the source surface brightness is evaluated on the traced grid;
+ *   3. the lensed image is convolved with the PSF.
+ * The deflectors are those of the paper's deflector table that the path uses:
+ * SIE (NIE with zero core; SIS as q = 1), external SHEAR and NFW (the subhalo
+ * profile), plus a point mass used only by tests.  The light profile is the
+ * elliptical Sersic of the flux table (SERSIC_ELLIPSE_Q_PHI parameterisation).
+ *
+ * Conventions shared by every call
+ *  - Angles are arcsec, position angles radians (counter-clockwise from +x to
+ *    the major axis).  Images are row-major float32 [ny][nx]; row i runs along
+ *    +y, column j along +x, and the grid is centred on (x0, y0).
+ *  - Sub-pixel (a, b) of pixel (i, j), a, b in [0, s):
+ *      x = x0 + (j - (nx-1)/2) d + ((b + 1/2)/s - 1/2) d,  y likewise with (i, a).
+ *    A pixel value is d^2 times the mean sub-pixel surface brightness.
+ *  - All device pointers are caller-owned; the library never frees them and
+ *    never keeps them after the call returns (except through explicit handles).
+ *    Host pointers are read during the call only.
+ *  - Calls are asynchronous on the given HIP stream (0 = the null stream).
+ *    Argument errors return synchronously and launch nothing.  A device
+ *    fault surfaces as JT_EDEVICE from jt_sync or a later call.
+ *  - Arithmetic on the device is FP32; host parameter preparation is FP64.
+ *  - Every call returning jt_status sets a thread-local message readable with
+ *    jt_last_error() when it returns anything but JT_OK.
+ */
+#ifndef JT_H
+#define JT_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  JT_OK = 0,
+  JT_EINVAL = 1,         /* bad argument (null pointer, size, parameter range) */
+  JT_ENOMEM = 2,         /* device allocation failed, or a request can never fit */
+  JT_EDEVICE = 3,        /* HIP runtime or kernel error */
+  JT_EUNSUPPORTED = 4,   /* valid but not implemented (e.g. too many components) */
+  JT_EBUSY = 5,          /* resource still in use */
+  JT_ECANCELLED = 6      /* serving ticket cancelled */
+} jt_status;
+
+/* Limits (compile-time; exceeded -> JT_EUNSUPPORTED). */
+#define JT_MAX_SERSIC 8        /* per light list (source or lens light)       */
+#define JT_MAX_POINT_MASS 16   /* point masses per lens                       */
+#define JT_MAX_PSF 255         /* largest odd PSF side for the direct path    */
+
+typedef struct jt_ctx jt_ctx;  /* one per device: workspace, resident tables, profiling */
+
+/* Create a context on HIP device `device` (it becomes current on the calling
+ * thread).  *out receives the context.  JT_EINVAL for a bad device index. */
+jt_status jt_create(int device, jt_ctx** out);
+/* Destroy a context: waits for its work, frees its workspace and handles. */
+void jt_destroy(jt_ctx* ctx);
+/* Thread-local description of the last non-OK status on this thread. */
+const char* jt_last_error(void);
+/* Library version string. */
+const char* jt_version(void);
+/* Wait for all work on `stream`; JT_EDEVICE if the device reported an error. */
+jt_status jt_sync(jt_ctx* ctx, hipStream_t stream);
+
+/* ----------------------------------------------------------------------
+ * Parameters (plain host structs, read during the call)
+ * -------------------------------------------------------------------- */
+typedef struct {
+  int nx, ny;            /* pixels, >= 1 */
+  int supersample;       /* s >= 1 sub-pixels per axis */
+  double pixel_scale;    /* d > 0, arcsec per pixel */
+  double x0, y0;         /* grid centre */
+} jt_grid;
+
+/* SIE (Kormann et al. 1994; Keeton 2001): kappa = theta_E / (2 sqrt(q x'^2 + y'^2/q)).
+ * theta_E > 0, q in (0, 1], centre (cx, cy). */
+typedef struct { double theta_E, q, phi, cx, cy; } jt_sie;
+
+/* External shear about the origin: alpha = (g1 x + g2 y, g2 x - g1 y). */
+typedef struct { double gamma1, gamma2; } jt_shear;
+
+/* NFW subhalos as device float32 structure-of-arrays of length n (arcsec):
+ * centre (x, y), scale radius Rs > 0 and alpha_Rs = |alpha| at r = Rs.
+ * alpha_k = alpha_Rs/(1 - ln 2) * g(r/Rs)/(r/Rs) * (dx, dy)/r with
+ * g(x) = ln(x/2) + F(x) (Bartelmann 1996; Golse & Kneib 2002). */
+typedef struct { int n; const float *x, *y, *Rs, *alpha_Rs; } jt_nfw;
+
+/* Point masses (test profile), host float64 arrays of length n <= 16:
+ * alpha = theta_E^2 (dx, dy) / r^2. */
+typedef struct { int n; const double *x, *y, *theta_E; } jt_point_masses;
+
+typedef struct {
+  int has_sie, has_shear;
+  jt_sie sie;
+  jt_shear shear;
+  jt_nfw nfw;                /* n = 0: no subhalos */
+  uint64_t subhalo_handle;   /* nonzero: a table from jt_upload_subhalos, `nfw` ignored */
+  jt_point_masses pm;        /* n = 0: none */
+} jt_lens;
+
+/* Elliptical Sersic: I = amp exp(-b_n [(R/R_sersic)^(1/n) - 1]),
+ * R = sqrt(q x'^2 + y'^2/q); amp = I(R_sersic); R_sersic > 0, n in [0.2, 10],
+ * q in (0, 1]. */
+typedef struct { double amp, R_sersic, n_sersic, q, phi, cx, cy; } jt_sersic;
+
+/* A list of Sersic components (host array c[n], n <= JT_MAX_SERSIC).
+ * bn_exact = 0: b_n = 1.9992 n - 0.3271 (Capaccioli 1989);
+ * bn_exact = 1: b_n solves P(2n, b_n) = 1/2 (R_sersic is the half-light radius). */
+typedef struct { int n; const jt_sersic* c; int bn_exact; } jt_light;
+
+/* b_n of the Sersic profile as the library uses it (host FP64): the
+ * Capaccioli fit 1.9992 n - 0.3271, or (exact != 0) the root of
+ * P(2n, b) = 1/2 by Newton iteration on the regularised incomplete gamma.
+ * Returns NaN for n outside [0.2, 10]. */
+double jt_sersic_bn(double n, int exact);
+
+/* ----------------------------------------------------------------------
+ * Step 1: ray shooting (deflection angles at each deflector)
+ * -------------------------------------------------------------------- */
+/* beta = theta - sum of the deflections of `lens` at the n points
+ * (x[i], y[i]) (device float32).  Outputs bx, by: device float32[n],
+ * may not alias the inputs.  n = 0 is a no-op. */
+jt_status jt_ray_shoot(jt_ctx* ctx, int n, const float* x, const float* y,
+                       const jt_lens* lens, float* bx, float* by, hipStream_t stream);
+
+/* The total deflection alpha(theta) itself (same kernel as jt_ray_shoot). */
+jt_status jt_deflection(jt_ctx* ctx, int n, const float* x, const float* y,
+                        const jt_lens* lens, float* ax, float* ay, hipStream_t stream);
+
+/* ----------------------------------------------------------------------
+ * Step 2: surface brightness on the traced grid
+ * -------------------------------------------------------------------- */
+/* sb[i] = sum_src I(bx[i], by[i]) + sum_lens_light I(x[i], y[i]).
+ * Device float32 arrays of length n.  `src` or `lens_light` may be NULL
+ * (no component); x, y may be NULL when lens_light is empty. */
+jt_status jt_source_sb(jt_ctx* ctx, int n, const float* x, const float* y,
+                       const float* bx, const float* by, const jt_light* src,
+                       const jt_light* lens_light, float* sb, hipStream_t stream);
+
+/* ----------------------------------------------------------------------
+ * Step 3: PSF convolution
+ * -------------------------------------------------------------------- */
+/* out[i][j] = sum_{a,b} psf[a][b] img[i - a + c][j - b + c], c = (k-1)/2,
+ * zero outside the image, same size (a true convolution).  img, out: device
+ * float32 [ny][nx] (must not alias); psf: device float32 [k][k], k odd.
+ * method: 0 = auto (direct below the measured crossover), 1 = direct
+ * (LDS-tiled, k <= JT_MAX_PSF), 2 = FFT (FP64 transform). */
+jt_status jt_convolve(jt_ctx* ctx, const float* img, int nx, int ny, const float* psf,
+                      int k, int method, float* out, hipStream_t stream);
+
+/* ----------------------------------------------------------------------
+ * Fused simulation: steps 1-2 and the supersample average in one kernel,
+ * then step 3.
+ * -------------------------------------------------------------------- */
+/* out: device float32 [ny][nx].  psf: device float32 [k][k] (odd k), or
+ * NULL with k = 0 to return the unconvolved image.  Uses ctx workspace for
+ * the unconvolved image when a PSF is given. */
+jt_status jt_simulate_image(jt_ctx* ctx, const jt_grid* grid, const jt_lens* lens,
+                            const jt_light* src, const jt_light* lens_light,
+                            const float* psf, int k, float* out, hipStream_t stream);
+
+/* ----------------------------------------------------------------------
+ * Resident tables
+ * -------------------------------------------------------------------- */
+/* Copy n subhalos (host float32 SoA) into a device-resident, pre-derived
+ * table owned by ctx (n = 0 allowed).  *handle != 0 on success. */
+jt_status jt_upload_subhalos(jt_ctx* ctx, int n, const float* x, const float* y,
+                             const float* Rs, const float* alpha_Rs, uint64_t* handle);
+/* Copy a host float32 [k][k] PSF (odd k) into device memory owned by ctx. */
+jt_status jt_upload_psf(jt_ctx* ctx, const float* psf, int k, uint64_t* handle);
+/* Device pointer of a resident PSF (valid until released). */
+jt_status jt_psf_pointer(jt_ctx* ctx, uint64_t handle, const float** dev_psf, int* k);
+/* Release a handle (waits for the device). JT_EINVAL if unknown. */
+jt_status jt_release(jt_ctx* ctx, uint64_t handle);
+
+/* ----------------------------------------------------------------------
+ * Kernel timing (HIP events recorded on the launch stream)
+ * -------------------------------------------------------------------- */
+typedef enum {
+  JT_K_PREP = 0,        /* subhalo table derivation */
+  JT_K_RAY = 1,         /* ray shooting (jt_ray_shoot / jt_deflection) */
+  JT_K_SB = 2,          /* surface brightness */
+  JT_K_SIM = 3,         /* fused simulate kernel */
+  JT_K_CONV = 4,        /* convolution */
+  JT_K_COUNT = 5
+} jt_kernel_id;
+/* Enable (1) or disable (0) event timing of every launch; resets the totals. */
+jt_status jt_profile_enable(jt_ctx* ctx, int on);
+/* Total milliseconds and launch count of kernel `id` since enabling (waits for
+ * the recorded events). */
+jt_status jt_profile_read(jt_ctx* ctx, int id, double* total_ms, int* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JT_H */

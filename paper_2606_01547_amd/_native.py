@@ -1,0 +1,330 @@
+"""ctypes binding of libjt (include/jt.h): argument marshalling only.
+
+Every step of the simulation runs in libjt's HIP kernels; this module turns
+Python parameter objects and torch CUDA tensors into the C structs and device
+pointers of the ABI, passes torch's current HIP stream, and raises `JtError`
+for any non-OK status.  There is no fallback: if libjt.so has not been built the
+first call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_uint64, c_void_p
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libjt.so")
+
+JT_OK, JT_EINVAL, JT_ENOMEM, JT_EDEVICE, JT_EUNSUPPORTED, JT_EBUSY, JT_ECANCELLED = range(7)
+STATUS_NAMES = {0: "JT_OK", 1: "JT_EINVAL", 2: "JT_ENOMEM", 3: "JT_EDEVICE", 4: "JT_EUNSUPPORTED",
+                5: "JT_EBUSY", 6: "JT_ECANCELLED"}
+JT_K_PREP, JT_K_RAY, JT_K_SB, JT_K_SIM, JT_K_CONV = range(5)
+KERNEL_IDS = {"prep": JT_K_PREP, "ray": JT_K_RAY, "sb": JT_K_SB, "sim": JT_K_SIM, "conv": JT_K_CONV}
+
+
+class JtError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+# ---------------------------------------------------------------- C structs
+class JtGrid(ctypes.Structure):
+    _fields_ = [("nx", c_int), ("ny", c_int), ("supersample", c_int),
+                ("pixel_scale", c_double), ("x0", c_double), ("y0", c_double)]
+
+
+class JtSie(ctypes.Structure):
+    _fields_ = [("theta_E", c_double), ("q", c_double), ("phi", c_double), ("cx", c_double), ("cy", c_double)]
+
+
+class JtShear(ctypes.Structure):
+    _fields_ = [("gamma1", c_double), ("gamma2", c_double)]
+
+
+class JtNfw(ctypes.Structure):
+    _fields_ = [("n", c_int), ("x", c_void_p), ("y", c_void_p), ("Rs", c_void_p), ("alpha_Rs", c_void_p)]
+
+
+class JtPointMasses(ctypes.Structure):
+    _fields_ = [("n", c_int), ("x", POINTER(c_double)), ("y", POINTER(c_double)), ("theta_E", POINTER(c_double))]
+
+
+class JtLens(ctypes.Structure):
+    _fields_ = [("has_sie", c_int), ("has_shear", c_int), ("sie", JtSie), ("shear", JtShear),
+                ("nfw", JtNfw), ("subhalo_handle", c_uint64), ("pm", JtPointMasses)]
+
+
+class JtSersic(ctypes.Structure):
+    _fields_ = [("amp", c_double), ("R_sersic", c_double), ("n_sersic", c_double), ("q", c_double),
+                ("phi", c_double), ("cx", c_double), ("cy", c_double)]
+
+
+class JtLight(ctypes.Structure):
+    _fields_ = [("n", c_int), ("c", POINTER(JtSersic)), ("bn_exact", c_int)]
+
+
+# ---------------------------------------------------------------- library
+_LIB = None
+
+_SIGS = {
+    "jt_create": (c_int, [c_int, POINTER(c_void_p)]),
+    "jt_destroy": (None, [c_void_p]),
+    "jt_last_error": (c_char_p, []),
+    "jt_version": (c_char_p, []),
+    "jt_sync": (c_int, [c_void_p, c_void_p]),
+    "jt_ray_shoot": (c_int, [c_void_p, c_int, c_void_p, c_void_p, POINTER(JtLens), c_void_p, c_void_p, c_void_p]),
+    "jt_deflection": (c_int, [c_void_p, c_int, c_void_p, c_void_p, POINTER(JtLens), c_void_p, c_void_p, c_void_p]),
+    "jt_source_sb": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(JtLight),
+                             POINTER(JtLight), c_void_p, c_void_p]),
+    "jt_convolve": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_int, c_void_p, c_void_p]),
+    "jt_simulate_image": (c_int, [c_void_p, POINTER(JtGrid), POINTER(JtLens), POINTER(JtLight), POINTER(JtLight),
+                                  c_void_p, c_int, c_void_p, c_void_p]),
+    "jt_upload_subhalos": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_uint64)]),
+    "jt_upload_psf": (c_int, [c_void_p, c_void_p, c_int, POINTER(c_uint64)]),
+    "jt_psf_pointer": (c_int, [c_void_p, c_uint64, POINTER(c_void_p), POINTER(c_int)]),
+    "jt_release": (c_int, [c_void_p, c_uint64]),
+    "jt_profile_enable": (c_int, [c_void_p, c_int]),
+    "jt_profile_read": (c_int, [c_void_p, c_int, POINTER(c_double), POINTER(c_int)]),
+    "jt_sersic_bn": (c_double, [c_double, c_int]),
+}
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libjt.so (once).  Raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"libjt.so not found at {path}; build it with __graft_entry__.build()")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def _check(status):
+    if status != JT_OK:
+        msg = load_library().jt_last_error()
+        raise JtError(status, msg.decode() if msg else "")
+
+
+def sersic_bn(n: float, exact: bool = False) -> float:
+    """b_n as the library computes it on the host (FP64)."""
+    return float(load_library().jt_sersic_bn(float(n), int(bool(exact))))
+
+
+# ---------------------------------------------------------------- helpers
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return c_void_p(s.cuda_stream)
+
+
+def _dev_f32(a, device, keep):
+    """Device float32 contiguous tensor view/copy of `a` (tensor or array)."""
+    torch = _torch()
+    if isinstance(a, torch.Tensor):
+        t = a
+        if t.device.type != "cuda" or t.dtype != torch.float32 or not t.is_contiguous():
+            t = t.to(device=device, dtype=torch.float32).contiguous()
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.float32))).to(device)
+    keep.append(t)
+    return t
+
+
+def _require_out(t, shape, device):
+    torch = _torch()
+    if t is None:
+        return torch.empty(shape, dtype=torch.float32, device=device)
+    if t.dtype != torch.float32 or not t.is_contiguous() or t.device.type != "cuda" or tuple(t.shape) != tuple(shape):
+        raise ValueError("output tensor must be a contiguous float32 CUDA tensor of shape %s" % (shape,))
+    return t
+
+
+class Context:
+    """One libjt context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        torch = _torch()
+        self._lib = load_library()
+        self.device = torch.device("cuda", device)
+        self._ptr = c_void_p()
+        _check(self._lib.jt_create(int(device), byref(self._ptr)))
+
+    # lifetime
+    def close(self):
+        if self._ptr:
+            self._lib.jt_destroy(self._ptr)
+            self._ptr = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync(self, stream=None):
+        _check(self._lib.jt_sync(self._ptr, _stream_handle(stream)))
+
+    # ---- parameter marshalling
+    def _lens(self, lens, keep):
+        L = JtLens()
+        sie = getattr(lens, "sie", None)
+        if sie is not None:
+            L.has_sie = 1
+            L.sie = JtSie(sie.theta_E, sie.q, sie.phi, sie.cx, sie.cy)
+        sh = getattr(lens, "shear", None)
+        if sh is not None:
+            L.has_shear = 1
+            L.shear = JtShear(sh.gamma1, sh.gamma2)
+        handle = getattr(lens, "subhalo_handle", 0) or 0
+        nfw = getattr(lens, "nfw", None)
+        if handle:
+            L.subhalo_handle = int(handle)
+        elif nfw is not None and len(nfw.x) > 0:
+            arrs = [_dev_f32(a, self.device, keep) for a in (nfw.x, nfw.y, nfw.Rs, nfw.alpha_Rs)]
+            L.nfw = JtNfw(int(arrs[0].numel()), *[c_void_p(a.data_ptr()) for a in arrs])
+        pm = getattr(lens, "point_masses", None)
+        if pm is not None and np.size(pm.x) > 0:
+            cols = [np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(-1)) for v in (pm.x, pm.y, pm.theta_E)]
+            keep.extend(cols)
+            ptrs = [c.ctypes.data_as(POINTER(c_double)) for c in cols]
+            L.pm = JtPointMasses(int(cols[0].size), *ptrs)
+        return L
+
+    @staticmethod
+    def _light(comps, bn_exact, keep):
+        comps = list(comps or [])
+        arr = (JtSersic * max(1, len(comps)))()
+        for i, c in enumerate(comps):
+            arr[i] = JtSersic(c.amp, c.R_sersic, c.n_sersic, c.q, c.phi, c.cx, c.cy)
+        keep.append(arr)
+        return JtLight(len(comps), ctypes.cast(arr, POINTER(JtSersic)), int(bool(bn_exact)))
+
+    # ---- step 1
+    def _ray(self, fn, x, y, lens, out, stream):
+        keep = []
+        xt = _dev_f32(x, self.device, keep)
+        yt = _dev_f32(y, self.device, keep)
+        n = xt.numel()
+        ox = _require_out(out[0] if out else None, xt.shape, self.device)
+        oy = _require_out(out[1] if out else None, yt.shape, self.device)
+        L = self._lens(lens, keep)
+        _check(fn(self._ptr, n, c_void_p(xt.data_ptr()), c_void_p(yt.data_ptr()), byref(L),
+                  c_void_p(ox.data_ptr()), c_void_p(oy.data_ptr()), _stream_handle(stream)))
+        self._retain(keep, stream)
+        return ox, oy
+
+    def ray_shoot(self, x, y, lens, out=None, stream=None):
+        """beta = theta - alpha(theta) at the points (x, y)."""
+        return self._ray(self._lib.jt_ray_shoot, x, y, lens, out, stream)
+
+    def deflection(self, x, y, lens, out=None, stream=None):
+        """alpha(theta) at the points (x, y)."""
+        return self._ray(self._lib.jt_deflection, x, y, lens, out, stream)
+
+    # ---- step 2
+    def source_sb(self, x, y, bx, by, source, lens_light=(), bn_exact=False, out=None, stream=None):
+        keep = []
+        bxt = _dev_f32(bx, self.device, keep)
+        byt = _dev_f32(by, self.device, keep)
+        xt = _dev_f32(x, self.device, keep) if x is not None else bxt
+        yt = _dev_f32(y, self.device, keep) if y is not None else byt
+        sb = _require_out(out, bxt.shape, self.device)
+        S = self._light(source, bn_exact, keep)
+        LL = self._light(lens_light, bn_exact, keep)
+        _check(self._lib.jt_source_sb(self._ptr, bxt.numel(), c_void_p(xt.data_ptr()), c_void_p(yt.data_ptr()),
+                                      c_void_p(bxt.data_ptr()), c_void_p(byt.data_ptr()), byref(S), byref(LL),
+                                      c_void_p(sb.data_ptr()), _stream_handle(stream)))
+        self._retain(keep, stream)
+        return sb
+
+    # ---- step 3
+    def convolve(self, img, psf, method=0, out=None, stream=None):
+        keep = []
+        it = _dev_f32(img, self.device, keep)
+        pt = _dev_f32(psf, self.device, keep)
+        if it.dim() != 2 or pt.dim() != 2 or pt.shape[0] != pt.shape[1]:
+            raise ValueError("convolve: image must be 2-D and the PSF square")
+        ny, nx = it.shape
+        o = _require_out(out, (ny, nx), self.device)
+        _check(self._lib.jt_convolve(self._ptr, c_void_p(it.data_ptr()), int(nx), int(ny), c_void_p(pt.data_ptr()),
+                                     int(pt.shape[0]), int(method), c_void_p(o.data_ptr()), _stream_handle(stream)))
+        self._retain(keep, stream)
+        return o
+
+    # ---- fused
+    def simulate_image(self, grid, lens, source, lens_light=(), psf=None, bn_exact=False, out=None, stream=None):
+        keep = []
+        G = JtGrid(int(grid.nx), int(grid.ny), int(grid.supersample), float(grid.pixel_scale),
+                   float(grid.x0), float(grid.y0))
+        L = self._lens(lens, keep)
+        S = self._light(source, bn_exact, keep)
+        LL = self._light(lens_light, bn_exact, keep)
+        o = _require_out(out, (int(grid.ny), int(grid.nx)), self.device)
+        if psf is None:
+            pp, k = c_void_p(), 0
+        else:
+            pt = _dev_f32(psf, self.device, keep)
+            pp, k = c_void_p(pt.data_ptr()), int(pt.shape[0])
+        _check(self._lib.jt_simulate_image(self._ptr, byref(G), byref(L), byref(S), byref(LL), pp, k,
+                                           c_void_p(o.data_ptr()), _stream_handle(stream)))
+        self._retain(keep, stream)
+        return o
+
+    def simulate_scene(self, scene, psf=True, **kw):
+        """simulate_image for a workloads.Scene-like object."""
+        return self.simulate_image(scene.grid, scene.lens, scene.source, scene.lens_light,
+                                   scene.psf if psf else None, getattr(scene, "bn_exact", False), **kw)
+
+    # ---- resident tables
+    def upload_subhalos(self, nfw) -> int:
+        cols = [np.ascontiguousarray(np.asarray(v, dtype=np.float32)) for v in (nfw.x, nfw.y, nfw.Rs, nfw.alpha_Rs)]
+        h = c_uint64()
+        _check(self._lib.jt_upload_subhalos(self._ptr, int(cols[0].size), *[c_void_p(c.ctypes.data) for c in cols],
+                                            byref(h)))
+        return int(h.value)
+
+    def upload_psf(self, psf) -> int:
+        p = np.ascontiguousarray(np.asarray(psf, dtype=np.float32))
+        h = c_uint64()
+        _check(self._lib.jt_upload_psf(self._ptr, c_void_p(p.ctypes.data), int(p.shape[0]), byref(h)))
+        return int(h.value)
+
+    def psf_pointer(self, handle: int):
+        p, k = c_void_p(), c_int()
+        _check(self._lib.jt_psf_pointer(self._ptr, c_uint64(handle), byref(p), byref(k)))
+        return p.value, k.value
+
+    def release(self, handle: int):
+        _check(self._lib.jt_release(self._ptr, c_uint64(handle)))
+
+    # ---- timing
+    def profile_enable(self, on=True):
+        _check(self._lib.jt_profile_enable(self._ptr, int(bool(on))))
+
+    def profile_read(self, kernel: str):
+        ms, n = c_double(), c_int()
+        _check(self._lib.jt_profile_read(self._ptr, KERNEL_IDS[kernel], byref(ms), byref(n)))
+        return ms.value, n.value
+
+    # ---- internals
+    def _retain(self, keep, stream):
+        """Device copies made for a call must outlive the kernels that read
+        them: mark them as used on the launch stream."""
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream()
+        for t in keep:
+            if isinstance(t, torch.Tensor) and t.device.type == "cuda":
+                t.record_stream(s)

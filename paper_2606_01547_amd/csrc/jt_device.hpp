@@ -1,0 +1,215 @@
+// Device-side building blocks of the lensed-image simulation (gfx950, FP32).
+//
+// Everything here is evaluated per image-plane (sub-)pixel: the macro-lens
+// deflection (SIE + external shear + test point masses), the NFW subhalo pair
+// term, and the elliptical Sersic surface brightness.  Kernel-constant structs
+// are filled on the host in FP64 and rounded once to FP32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace jt {
+
+constexpr int kMaxSersic = 8;
+constexpr int kMaxPointMass = 16;
+constexpr float kLn2 = 0.69314718055994530942f;
+
+#include "nfw_poly.inc"
+
+// ---------------------------------------------------------------------------
+// kernel constants
+// ---------------------------------------------------------------------------
+struct MacroC {
+  int has_sie, sie_series, has_shear, npm;
+  // SIE: rotate into the major-axis frame about (cx, cy); psi = sqrt(q^2 x'^2 + y'^2)
+  float cx, cy, cphi, sphi, q2, pref_f, f, pref;  // pref = theta_E sqrt(q); pref_f = pref / f
+  float g1, g2;                                   // shear
+  float pm_x[kMaxPointMass], pm_y[kMaxPointMass], pm_te2[kMaxPointMass];
+};
+
+struct SersicC {
+  float cx, cy, cphi, sphi;
+  float q, inv_q;        // R^2 = q x'^2 + y'^2 / q
+  float inv_r2;          // 1 / R_sersic^2
+  float e;               // 1 / (2 n): (R/R_s)^(1/n) = exp2(e * log2(R^2 / R_s^2))
+  float kb;              // b_n * log2(e): I = amp * exp2(kb * (1 - t))
+  float amp;
+};
+
+struct LightC {
+  int n;
+  SersicC c[kMaxSersic];
+};
+
+// Implicit sub-pixel grid: theta = origin + step * (m + 1/2) along each axis,
+// m = pixel * s + sub-pixel; origin and step in FP64 so that theta is the
+// correctly rounded FP32 value of the exact grid.
+struct GridC {
+  int nx, ny, s, s2;
+  int ppb;               // whole pixels per 256-thread block: floor(256 / s^2)
+  double ox, oy, step;   // ox = x0 - d nx / 2, step = d / s
+  float area_over_s2;    // d^2 / s^2
+};
+
+// Packed subhalo record: centre and the two derived constants of the pair term
+// alpha = c2 * g(x) / x^2 * (dx, dy), x^2 = r^2 c1, c1 = 1/Rs^2,
+// c2 = alpha_Rs / ((1 - ln 2) Rs).
+struct __align__(16) SubRec {
+  float x, y, c1, c2;
+};
+
+// ---------------------------------------------------------------------------
+// macro lens
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void macro_deflection(const MacroC& m, float tx, float ty,
+                                                 float& ax, float& ay) {
+  ax = 0.f;
+  ay = 0.f;
+  if (m.has_sie) {
+    const float dx = tx - m.cx, dy = ty - m.cy;
+    const float xp = fmaf(m.cphi, dx, m.sphi * dy);
+    const float yp = fmaf(m.cphi, dy, -m.sphi * dx);
+    const float psi = sqrtf(fmaf(m.q2, xp * xp, yp * yp));
+    float axp = 0.f, ayp = 0.f;
+    if (psi > 0.f) {
+      const float ipsi = 1.0f / psi;
+      if (m.sie_series) {
+        // atan(z)/z and atanh(z)/z by their Taylor series for f < 1e-2 (|z| < f)
+        const float zx = m.f * xp * ipsi, zy = m.f * yp * ipsi;
+        const float zx2 = zx * zx, zy2 = zy * zy;
+        axp = m.pref * xp * ipsi * fmaf(zx2, fmaf(zx2, 0.2f, -1.0f / 3.0f), 1.0f);
+        ayp = m.pref * yp * ipsi * fmaf(zy2, fmaf(zy2, 0.2f, 1.0f / 3.0f), 1.0f);
+      } else {
+        axp = m.pref_f * atanf(m.f * xp * ipsi);
+        ayp = m.pref_f * atanhf(m.f * yp * ipsi);
+      }
+    }
+    ax = fmaf(m.cphi, axp, -m.sphi * ayp);
+    ay = fmaf(m.sphi, axp, m.cphi * ayp);
+  }
+  if (m.has_shear) {
+    ax = fmaf(m.g1, tx, fmaf(m.g2, ty, ax));
+    ay = fmaf(m.g2, tx, fmaf(-m.g1, ty, ay));
+  }
+  for (int k = 0; k < m.npm; ++k) {
+    const float dx = tx - m.pm_x[k], dy = ty - m.pm_y[k];
+    const float r2 = fmaf(dx, dx, dy * dy);
+    const float fac = r2 > 0.f ? m.pm_te2[k] / r2 : 0.f;
+    ax = fmaf(fac, dx, ax);
+    ay = fmaf(fac, dy, ay);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// NFW pair term
+// ---------------------------------------------------------------------------
+// g(x)/x^2 for x^2 = X2 < 1 (rare near-field pairs), FP32 with the branch forms
+// that avoid cancellation:
+//   X2 >= 0.81:  F = sum_k (-u)^k/(2k+1), u = X2 - 1 in [-0.19, 0)
+//   X2 >= 0.25:  F = atanh(w)/w, w = sqrt(1 - X2)
+//   X2 <  0.25:  g = [-L X2/(1+w) + log1p(-X2/(2(1+w)))]/w, L = ln(x/2)
+// and 0 at X2 = 0.
+__device__ __noinline__ float nfw_near_g_over_x2(float X2) {
+  if (!(X2 > 0.f)) return 0.f;
+  const float half_ln = 0.5f * logf(X2);   // ln x
+  float g;
+  if (X2 >= 0.81f) {
+    const float u = X2 - 1.0f;
+    float F = 1.0f / 21.0f;
+    F = fmaf(F, -u, 1.0f / 19.0f);
+    F = fmaf(F, -u, 1.0f / 17.0f);
+    F = fmaf(F, -u, 1.0f / 15.0f);
+    F = fmaf(F, -u, 1.0f / 13.0f);
+    F = fmaf(F, -u, 1.0f / 11.0f);
+    F = fmaf(F, -u, 1.0f / 9.0f);
+    F = fmaf(F, -u, 1.0f / 7.0f);
+    F = fmaf(F, -u, 1.0f / 5.0f);
+    F = fmaf(F, -u, 1.0f / 3.0f);
+    F = fmaf(F, -u, 1.0f);
+    g = (half_ln - kLn2) + F;
+  } else {
+    const float w = sqrtf(1.0f - X2);
+    if (X2 >= 0.25f) {
+      g = (half_ln - kLn2) + atanhf(w) / w;
+    } else {
+      const float L = half_ln - kLn2;
+      const float opw = 1.0f + w;
+      g = (-L * X2 / opw + log1pf(-X2 / (2.0f * opw))) / w;
+    }
+  }
+  return g / X2;
+}
+
+// Far-field g(x)/x^2 for x^2 = X2 >= 1: with y = rsq(X2),
+// g = (ln2/2) log2(X2) + psi(y), psi the fitted polynomial, and g/x^2 = g y^2.
+__device__ __forceinline__ float nfw_far_g_over_x2(float X2) {
+  const float y = __builtin_amdgcn_rsqf(X2);
+  const float l2 = __builtin_amdgcn_logf(X2);
+  float p = kNfwPsi[0];
+#pragma unroll
+  for (int i = 1; i <= JT_NFW_POLY_DEGREE; ++i) p = fmaf(p, y, kNfwPsi[i]);
+  return fmaf(l2, 0.5f * kLn2, p) * (y * y);
+}
+
+// Four (sub-pixel, subhalo) pairs: adds alpha_k, k = 0..3, to (sx, sy).  All
+// four far-field terms are formed first; a single wave-level branch then
+// recomputes the rare near-field (X2 < 1) terms.
+__device__ __forceinline__ void nfw_pairs4(float tx, float ty, const SubRec& s0, const SubRec& s1,
+                                           const SubRec& s2, const SubRec& s3, float& sx,
+                                           float& sy) {
+  const float dx0 = tx - s0.x, dy0 = ty - s0.y;
+  const float dx1 = tx - s1.x, dy1 = ty - s1.y;
+  const float dx2 = tx - s2.x, dy2 = ty - s2.y;
+  const float dx3 = tx - s3.x, dy3 = ty - s3.y;
+  const float X0 = fmaf(dy0, dy0, dx0 * dx0) * s0.c1;
+  const float X1 = fmaf(dy1, dy1, dx1 * dx1) * s1.c1;
+  const float X2 = fmaf(dy2, dy2, dx2 * dx2) * s2.c1;
+  const float X3 = fmaf(dy3, dy3, dx3 * dx3) * s3.c1;
+  float h0 = nfw_far_g_over_x2(X0);
+  float h1 = nfw_far_g_over_x2(X1);
+  float h2 = nfw_far_g_over_x2(X2);
+  float h3 = nfw_far_g_over_x2(X3);
+  if (__builtin_expect(fminf(fminf(X0, X1), fminf(X2, X3)) < 1.0f, 0)) {
+    if (X0 < 1.0f) h0 = nfw_near_g_over_x2(X0);
+    if (X1 < 1.0f) h1 = nfw_near_g_over_x2(X1);
+    if (X2 < 1.0f) h2 = nfw_near_g_over_x2(X2);
+    if (X3 < 1.0f) h3 = nfw_near_g_over_x2(X3);
+  }
+  sx = fmaf(h0 * s0.c2, dx0, sx);
+  sy = fmaf(h0 * s0.c2, dy0, sy);
+  sx = fmaf(h1 * s1.c2, dx1, sx);
+  sy = fmaf(h1 * s1.c2, dy1, sy);
+  sx = fmaf(h2 * s2.c2, dx2, sx);
+  sy = fmaf(h2 * s2.c2, dy2, sy);
+  sx = fmaf(h3 * s3.c2, dx3, sx);
+  sy = fmaf(h3 * s3.c2, dy3, sy);
+}
+
+// Knuth's TwoSum: s + e == a + b exactly.
+__device__ __forceinline__ void two_sum_acc(float& hi, float& lo, float v) {
+  const float s = hi + v;
+  const float bp = s - hi;
+  const float e = (hi - (s - bp)) + (v - bp);
+  hi = s;
+  lo += e;
+}
+
+// ---------------------------------------------------------------------------
+// Sersic light
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float sersic_sum(const LightC& L, float x, float y) {
+  float acc = 0.f;
+  for (int k = 0; k < L.n; ++k) {
+    const SersicC& c = L.c[k];
+    const float dx = x - c.cx, dy = y - c.cy;
+    const float xp = fmaf(c.cphi, dx, c.sphi * dy);
+    const float yp = fmaf(c.cphi, dy, -c.sphi * dx);
+    const float R2 = fmaf(c.q, xp * xp, c.inv_q * (yp * yp));
+    const float t = __builtin_amdgcn_exp2f(c.e * __builtin_amdgcn_logf(R2 * c.inv_r2));
+    acc = fmaf(c.amp, __builtin_amdgcn_exp2f(fmaf(-c.kb, t, c.kb)), acc);
+  }
+  return acc;
+}
+
+}  // namespace jt

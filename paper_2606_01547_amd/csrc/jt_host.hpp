@@ -1,0 +1,105 @@
+// Internal host-side declarations of libjt: the context, error helpers,
+// parameter preparation (FP64 -> FP32 kernel constants) and timed launches.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "../../include/jt.h"
+#include "jt_device.hpp"
+
+#define JT_TRY(expr)            \
+  do {                          \
+    jt_status _s = (expr);      \
+    if (_s != JT_OK) return _s; \
+  } while (0)
+
+struct Buffer {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Resident {
+  int kind = 0;  // 1 = subhalo table, 2 = PSF
+  void* dev = nullptr;
+  int n = 0;     // subhalos (kind 1) or PSF side k (kind 2)
+};
+
+struct EventRec {
+  hipEvent_t a, b;
+  int id;
+};
+
+struct jt_ctx {
+  int device = 0;
+  std::mutex mu;
+  std::map<hipStream_t, Buffer> ws;  // per-stream workspace
+  std::map<uint64_t, Resident> handles;
+  uint64_t next_handle = 1;
+  jt::SubRec* empty_table = nullptr;  // padding records for lenses without subhalos
+  bool prof = false;
+  std::vector<EventRec> pending;
+  std::vector<hipEvent_t> free_events;
+  double prof_ms[JT_K_COUNT] = {0};
+  int prof_n[JT_K_COUNT] = {0};
+};
+
+namespace jt {
+
+jt_status fail(jt_status st, const char* fmt, ...);
+jt_status check_hip(hipError_t e, const char* what);
+jt_status ctx_enter(jt_ctx* ctx);
+jt_status ctx_workspace(jt_ctx* ctx, hipStream_t stream, size_t bytes, void** out);
+jt_status ctx_subhalo_handle(jt_ctx* ctx, uint64_t h, const SubRec** table, int* n);
+const SubRec* ctx_empty_table(jt_ctx* ctx);
+hipEvent_t take_event(jt_ctx* ctx);
+void drain_events(jt_ctx* ctx);
+
+// Timed launch: records HIP events around `launch` on `st` when profiling is on.
+template <class F>
+jt_status timed_launch(jt_ctx* ctx, int id, hipStream_t st, F&& launch, const char* what) {
+  hipEvent_t a = nullptr, b = nullptr;
+  bool prof;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    prof = ctx->prof;
+    if (prof) {
+      if (ctx->pending.size() > 4096) drain_events(ctx);
+      a = take_event(ctx);
+      b = take_event(ctx);
+      if (!a || !b) prof = false;
+    }
+  }
+  if (prof) (void)hipEventRecord(a, st);
+  hipError_t e = launch();
+  if (prof) {
+    (void)hipEventRecord(b, st);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->pending.push_back({a, b, id});
+  }
+  return check_hip(e, what);
+}
+
+// ---- parameter preparation (jt_params.cpp) ----
+jt_status make_macro(const jt_lens* lens, MacroC& out);
+jt_status make_light(const jt_light* light, LightC& out, const char* which);
+jt_status make_grid(const jt_grid* grid, GridC& out);
+// Median-defining b_n: the root b of P(2n, b) = 1/2 (regularised lower
+// incomplete gamma), by safeguarded Newton iteration.
+double sersic_bn_exact(double n);
+// Regularised lower incomplete gamma P(a, x).
+double gamma_p(double a, double x);
+// Packed subhalo table (with padding records) from host FP32 SoA; validates.
+jt_status pack_subhalos_host(int n, const float* x, const float* y, const float* rs, const float* ars,
+                             std::vector<SubRec>& out);
+
+// Resolves the subhalo table of a lens: resident handle, or device SoA packed
+// into `scratch` (room for subhalo_table_records(n) records) by the prep
+// kernel, or the context's empty table.  *nloop = loop count (multiple of 4).
+jt_status resolve_subhalos(jt_ctx* ctx, const jt_lens* lens, SubRec* scratch, hipStream_t st,
+                           const SubRec** table, int* nloop);
+
+}  // namespace jt

@@ -1,0 +1,29 @@
+// Host-callable launchers of the HIP kernels (internal to libjt).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "jt_device.hpp"
+
+namespace jt {
+
+// Records of a packed subhalo table for n subhalos: n rounded up to a multiple
+// of 4, plus 4 records that the prefetch of the last group reads.  Records past
+// n are padding {1e18, 1e18, 1, 0}: far field with c2 = 0, an exact zero term.
+inline int subhalo_loop_count(int n) { return (n + 3) & ~3; }
+inline int subhalo_table_records(int n) { return subhalo_loop_count(n) + 4; }
+
+// Writes all subhalo_table_records(n) records (padding included).
+hipError_t launch_prep_subhalos(int n, const float* x, const float* y, const float* rs,
+                                const float* ars, SubRec* out, hipStream_t st);
+hipError_t launch_ray_shoot(bool alpha, int n, const float* x, const float* y, const MacroC& mc,
+                            const SubRec* sub, int nsub, float* ox, float* oy, hipStream_t st);
+hipError_t launch_source_sb(int n, const float* x, const float* y, const float* bx, const float* by,
+                            const LightC& src, const LightC& ll, float* sb, hipStream_t st);
+hipError_t launch_simulate(const GridC& g, const MacroC& mc, const SubRec* sub, int nsub,
+                           const LightC& src, const LightC& ll, float* img, hipStream_t st);
+size_t conv_direct_lds_bytes(int k);
+hipError_t launch_conv_direct(const float* img, int nx, int ny, const float* psf, int k, float* out,
+                              hipStream_t st);
+
+}  // namespace jt

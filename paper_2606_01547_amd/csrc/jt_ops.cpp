@@ -1,0 +1,123 @@
+// The compute entry points of the C ABI: ray shooting, surface brightness,
+// convolution and the fused simulation.  Each validates its arguments (no
+// launch on error) and enqueues kernels on the caller's stream.
+#include <cmath>
+
+#include "jt_host.hpp"
+#include "jt_kernels.hpp"
+
+using namespace jt;
+
+namespace {
+
+jt_status ray_common(bool alpha, jt_ctx* ctx, int n, const float* x, const float* y, const jt_lens* lens,
+                     float* ox, float* oy, hipStream_t st) {
+  JT_TRY(ctx_enter(ctx));
+  if (n < 0) return fail(JT_EINVAL, "ray_shoot: n = %d", n);
+  MacroC mc;
+  JT_TRY(make_macro(lens, mc));
+  if (n == 0) return JT_OK;
+  if (!x || !y || !ox || !oy) return fail(JT_EINVAL, "ray_shoot: null array");
+  if (ox == x || ox == y || oy == x || oy == y || ox == oy) return fail(JT_EINVAL, "ray_shoot: outputs alias inputs");
+  SubRec* scratch = nullptr;
+  if (!lens->subhalo_handle && lens->nfw.n > 0) {
+    void* ws = nullptr;
+    JT_TRY(ctx_workspace(ctx, st, sizeof(SubRec) * (size_t)subhalo_table_records(lens->nfw.n), &ws));
+    scratch = (SubRec*)ws;
+  }
+  const SubRec* tab = nullptr;
+  int nloop = 0;
+  JT_TRY(resolve_subhalos(ctx, lens, scratch, st, &tab, &nloop));
+  return timed_launch(ctx, JT_K_RAY, st,
+                      [&] { return launch_ray_shoot(alpha, n, x, y, mc, tab, nloop, ox, oy, st); }, "ray_shoot");
+}
+
+jt_status check_conv_args(const float* img, int nx, int ny, const float* psf, int k, const float* out) {
+  if (!img || !out || !psf) return fail(JT_EINVAL, "convolve: null pointer");
+  if (nx < 1 || ny < 1) return fail(JT_EINVAL, "convolve: %d x %d image", nx, ny);
+  if (k < 1 || k % 2 == 0) return fail(JT_EINVAL, "convolve: PSF side %d must be odd", k);
+  if (img == out) return fail(JT_EINVAL, "convolve: output aliases input");
+  if ((double)nx * ny > 2147483647.0) return fail(JT_EUNSUPPORTED, "convolve: image too large");
+  return JT_OK;
+}
+
+jt_status convolve_on(jt_ctx* ctx, const float* img, int nx, int ny, const float* psf, int k, int method,
+                      float* out, hipStream_t st) {
+  if (method == 2) return fail(JT_EUNSUPPORTED, "convolve: FFT method not available in this build");
+  if (method != 0 && method != 1) return fail(JT_EINVAL, "convolve: method %d", method);
+  if (k > JT_MAX_PSF) return fail(JT_EUNSUPPORTED, "convolve: direct path supports k <= %d", JT_MAX_PSF);
+  return timed_launch(ctx, JT_K_CONV, st,
+                      [&] { return launch_conv_direct(img, nx, ny, psf, k, out, st); }, "conv_direct");
+}
+
+}  // namespace
+
+extern "C" jt_status jt_ray_shoot(jt_ctx* ctx, int n, const float* x, const float* y, const jt_lens* lens,
+                                  float* bx, float* by, hipStream_t stream) {
+  return ray_common(false, ctx, n, x, y, lens, bx, by, stream);
+}
+
+extern "C" jt_status jt_deflection(jt_ctx* ctx, int n, const float* x, const float* y, const jt_lens* lens,
+                                   float* ax, float* ay, hipStream_t stream) {
+  return ray_common(true, ctx, n, x, y, lens, ax, ay, stream);
+}
+
+extern "C" jt_status jt_source_sb(jt_ctx* ctx, int n, const float* x, const float* y, const float* bx,
+                                  const float* by, const jt_light* src, const jt_light* lens_light, float* sb,
+                                  hipStream_t stream) {
+  JT_TRY(ctx_enter(ctx));
+  if (n < 0) return fail(JT_EINVAL, "source_sb: n = %d", n);
+  LightC s, l;
+  JT_TRY(make_light(src, s, "source"));
+  JT_TRY(make_light(lens_light, l, "lens light"));
+  if (n == 0) return JT_OK;
+  if (!sb) return fail(JT_EINVAL, "source_sb: null output");
+  if (s.n > 0 && (!bx || !by)) return fail(JT_EINVAL, "source_sb: null traced coordinates");
+  if (l.n > 0 && (!x || !y)) return fail(JT_EINVAL, "source_sb: null image-plane coordinates");
+  const float* zx = bx ? bx : x;  // unused when the matching list is empty
+  const float* zy = by ? by : y;
+  return timed_launch(ctx, JT_K_SB, stream,
+                      [&] { return launch_source_sb(n, x ? x : zx, y ? y : zy, zx, zy, s, l, sb, stream); },
+                      "source_sb");
+}
+
+extern "C" jt_status jt_convolve(jt_ctx* ctx, const float* img, int nx, int ny, const float* psf, int k,
+                                 int method, float* out, hipStream_t stream) {
+  JT_TRY(ctx_enter(ctx));
+  JT_TRY(check_conv_args(img, nx, ny, psf, k, out));
+  return convolve_on(ctx, img, nx, ny, psf, k, method, out, stream);
+}
+
+extern "C" jt_status jt_simulate_image(jt_ctx* ctx, const jt_grid* grid, const jt_lens* lens,
+                                       const jt_light* src, const jt_light* lens_light, const float* psf,
+                                       int k, float* out, hipStream_t stream) {
+  JT_TRY(ctx_enter(ctx));
+  GridC g;
+  MacroC mc;
+  LightC s, l;
+  JT_TRY(make_grid(grid, g));
+  JT_TRY(make_macro(lens, mc));
+  JT_TRY(make_light(src, s, "source"));
+  JT_TRY(make_light(lens_light, l, "lens light"));
+  if (!out) return fail(JT_EINVAL, "simulate: null output");
+  if ((psf == nullptr) != (k == 0)) return fail(JT_EINVAL, "simulate: psf and k must be given together");
+  if (psf && (k < 1 || k % 2 == 0)) return fail(JT_EINVAL, "simulate: PSF side %d must be odd", k);
+  // workspace: [subhalo table][unconvolved image]
+  const bool pack = !lens->subhalo_handle && lens->nfw.n > 0;
+  const size_t tab_bytes = pack ? ((sizeof(SubRec) * (size_t)subhalo_table_records(lens->nfw.n) + 255) & ~size_t(255)) : 0;
+  const size_t img_bytes = psf ? sizeof(float) * (size_t)g.nx * g.ny : 0;
+  char* ws = nullptr;
+  if (tab_bytes + img_bytes > 0) {
+    void* p = nullptr;
+    JT_TRY(ctx_workspace(ctx, stream, tab_bytes + img_bytes, &p));
+    ws = (char*)p;
+  }
+  const SubRec* tab = nullptr;
+  int nloop = 0;
+  JT_TRY(resolve_subhalos(ctx, lens, pack ? (SubRec*)ws : nullptr, stream, &tab, &nloop));
+  float* img = psf ? (float*)(ws + tab_bytes) : out;
+  JT_TRY(timed_launch(ctx, JT_K_SIM, stream,
+                      [&] { return launch_simulate(g, mc, tab, nloop, s, l, img, stream); }, "simulate"));
+  if (!psf) return JT_OK;
+  return convolve_on(ctx, img, g.nx, g.ny, psf, k, 0, out, stream);
+}

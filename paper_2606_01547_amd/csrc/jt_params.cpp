@@ -1,0 +1,216 @@
+// Host parameter preparation: validates the ABI structs and turns FP64
+// parameters into the FP32 constants the kernels consume.
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+#include "jt_host.hpp"
+#include "jt_kernels.hpp"
+
+namespace jt {
+
+namespace {
+constexpr double kLn2d = 0.69314718055994530942;
+
+bool finite(double v) { return std::isfinite(v); }
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// regularised incomplete gamma and the exact Sersic b_n
+// ---------------------------------------------------------------------------
+// P(a, x) by its power series for x < a + 1 (Abramowitz & Stegun 6.5.29) and
+// otherwise through Q = 1 - P from Legendre's continued fraction
+// (A&S 6.5.31), evaluated with the modified Lentz method.
+double gamma_p(double a, double x) {
+  if (!(x > 0.0)) return 0.0;
+  const double lpref = a * std::log(x) - x - std::lgamma(a);
+  if (x < a + 1.0) {
+    double term = 1.0 / a, sum = term;
+    for (int n = 1; n < 100000; ++n) {
+      term *= x / (a + n);
+      sum += term;
+      if (std::fabs(term) < std::fabs(sum) * 1e-17) break;
+    }
+    return sum * std::exp(lpref);
+  }
+  const double tiny = 1e-300;
+  double b = x + 1.0 - a, c = 1.0 / tiny, d = 1.0 / b, h = d;
+  for (int i = 1; i < 100000; ++i) {
+    const double an = -i * (i - a);
+    b += 2.0;
+    d = an * d + b;
+    if (std::fabs(d) < tiny) d = tiny;
+    c = b + an / c;
+    if (std::fabs(c) < tiny) c = tiny;
+    d = 1.0 / d;
+    const double del = d * c;
+    h *= del;
+    if (std::fabs(del - 1.0) < 1e-16) break;
+  }
+  return 1.0 - std::exp(lpref) * h;
+}
+
+double sersic_bn_exact(double n) {
+  const double a = 2.0 * n;
+  double lo = 0.0, hi = std::numeric_limits<double>::infinity();
+  double b = std::fmax(a - 1.0 / 3.0 + 8.0 / (405.0 * a), 1e-3);
+  for (int it = 0; it < 200; ++it) {
+    const double f = gamma_p(a, b) - 0.5;
+    if (f > 0.0) hi = b; else lo = b;
+    const double dens = std::exp((a - 1.0) * std::log(b) - b - std::lgamma(a));
+    double nb = b - f / dens;
+    if (!(nb > lo && nb < hi)) nb = std::isinf(hi) ? 2.0 * b + 1.0 : 0.5 * (lo + hi);
+    if (std::fabs(nb - b) <= 1e-15 * b) return nb;
+    b = nb;
+  }
+  return b;
+}
+
+// ---------------------------------------------------------------------------
+// lens
+// ---------------------------------------------------------------------------
+jt_status make_macro(const jt_lens* lens, MacroC& m) {
+  std::memset(&m, 0, sizeof(m));
+  if (!lens) return fail(JT_EINVAL, "null lens");
+  if (lens->has_sie) {
+    const jt_sie& s = lens->sie;
+    if (!finite(s.theta_E) || !finite(s.q) || !finite(s.phi) || !finite(s.cx) || !finite(s.cy))
+      return fail(JT_EINVAL, "SIE: non-finite parameter");
+    if (s.theta_E < 0.0) return fail(JT_EINVAL, "SIE: theta_E = %g < 0", s.theta_E);
+    if (!(s.q > 0.0 && s.q <= 1.0)) return fail(JT_EINVAL, "SIE: q = %g not in (0, 1]", s.q);
+    const double f = std::sqrt((1.0 - s.q) * (1.0 + s.q));
+    const double pref = s.theta_E * std::sqrt(s.q);
+    m.has_sie = 1;
+    m.sie_series = f < 1e-2;
+    m.cx = (float)s.cx;
+    m.cy = (float)s.cy;
+    m.cphi = (float)std::cos(s.phi);
+    m.sphi = (float)std::sin(s.phi);
+    m.q2 = (float)(s.q * s.q);
+    m.f = (float)f;
+    m.pref = (float)pref;
+    m.pref_f = f > 0.0 ? (float)(pref / f) : 0.f;
+  }
+  if (lens->has_shear) {
+    if (!finite(lens->shear.gamma1) || !finite(lens->shear.gamma2))
+      return fail(JT_EINVAL, "shear: non-finite parameter");
+    m.has_shear = 1;
+    m.g1 = (float)lens->shear.gamma1;
+    m.g2 = (float)lens->shear.gamma2;
+  }
+  const jt_point_masses& pm = lens->pm;
+  if (pm.n < 0 || pm.n > JT_MAX_POINT_MASS)
+    return fail(pm.n < 0 ? JT_EINVAL : JT_EUNSUPPORTED, "point masses: n = %d (max %d)", pm.n, JT_MAX_POINT_MASS);
+  if (pm.n > 0 && (!pm.x || !pm.y || !pm.theta_E)) return fail(JT_EINVAL, "point masses: null array");
+  for (int k = 0; k < pm.n; ++k) {
+    if (!finite(pm.x[k]) || !finite(pm.y[k]) || !finite(pm.theta_E[k]))
+      return fail(JT_EINVAL, "point mass %d: non-finite parameter", k);
+    m.pm_x[k] = (float)pm.x[k];
+    m.pm_y[k] = (float)pm.y[k];
+    m.pm_te2[k] = (float)(pm.theta_E[k] * pm.theta_E[k]);
+  }
+  m.npm = pm.n;
+  if (lens->nfw.n < 0) return fail(JT_EINVAL, "NFW: n = %d", lens->nfw.n);
+  if (!lens->subhalo_handle && lens->nfw.n > 0 &&
+      (!lens->nfw.x || !lens->nfw.y || !lens->nfw.Rs || !lens->nfw.alpha_Rs))
+    return fail(JT_EINVAL, "NFW: null device array");
+  return JT_OK;
+}
+
+jt_status pack_subhalos_host(int n, const float* x, const float* y, const float* rs, const float* ars,
+                             std::vector<SubRec>& out) {
+  out.assign(subhalo_table_records(n), SubRec{1e18f, 1e18f, 1.0f, 0.0f});
+  for (int i = 0; i < n; ++i) {
+    if (!std::isfinite(x[i]) || !std::isfinite(y[i]) || !std::isfinite(ars[i]))
+      return fail(JT_EINVAL, "subhalo %d: non-finite parameter", i);
+    if (!(rs[i] > 0.0f) || !std::isfinite(rs[i])) return fail(JT_EINVAL, "subhalo %d: Rs = %g", i, (double)rs[i]);
+    const double r = rs[i];
+    out[i] = SubRec{x[i], y[i], (float)(1.0 / (r * r)), (float)((double)ars[i] / ((1.0 - kLn2d) * r))};
+  }
+  return JT_OK;
+}
+
+jt_status resolve_subhalos(jt_ctx* ctx, const jt_lens* lens, SubRec* scratch, hipStream_t st,
+                           const SubRec** table, int* nloop) {
+  if (lens->subhalo_handle) {
+    int n = 0;
+    JT_TRY(ctx_subhalo_handle(ctx, lens->subhalo_handle, table, &n));
+    *nloop = subhalo_loop_count(n);
+    return JT_OK;
+  }
+  const jt_nfw& s = lens->nfw;
+  if (s.n > 0) {
+    if (!scratch) return fail(JT_EINVAL, "internal: no scratch for the subhalo table");
+    JT_TRY(timed_launch(ctx, JT_K_PREP, st,
+                        [&] { return launch_prep_subhalos(s.n, s.x, s.y, s.Rs, s.alpha_Rs, scratch, st); },
+                        "prep_subhalos"));
+    *table = scratch;
+    *nloop = subhalo_loop_count(s.n);
+    return JT_OK;
+  }
+  *table = ctx_empty_table(ctx);
+  *nloop = 0;
+  return JT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// light
+// ---------------------------------------------------------------------------
+jt_status make_light(const jt_light* light, LightC& out, const char* which) {
+  std::memset(&out, 0, sizeof(out));
+  if (!light || light->n == 0) return JT_OK;
+  if (light->n < 0) return fail(JT_EINVAL, "%s: n = %d", which, light->n);
+  if (light->n > JT_MAX_SERSIC) return fail(JT_EUNSUPPORTED, "%s: %d components (max %d)", which, light->n, JT_MAX_SERSIC);
+  if (!light->c) return fail(JT_EINVAL, "%s: null component array", which);
+  for (int k = 0; k < light->n; ++k) {
+    const jt_sersic& c = light->c[k];
+    if (!finite(c.amp) || !finite(c.R_sersic) || !finite(c.n_sersic) || !finite(c.q) || !finite(c.phi) ||
+        !finite(c.cx) || !finite(c.cy))
+      return fail(JT_EINVAL, "%s[%d]: non-finite parameter", which, k);
+    if (!(c.R_sersic > 0.0)) return fail(JT_EINVAL, "%s[%d]: R_sersic = %g", which, k, c.R_sersic);
+    if (!(c.n_sersic >= 0.2 && c.n_sersic <= 10.0)) return fail(JT_EINVAL, "%s[%d]: n_sersic = %g not in [0.2, 10]", which, k, c.n_sersic);
+    if (!(c.q > 0.0 && c.q <= 1.0)) return fail(JT_EINVAL, "%s[%d]: q = %g not in (0, 1]", which, k, c.q);
+    const double b = light->bn_exact ? sersic_bn_exact(c.n_sersic) : 1.9992 * c.n_sersic - 0.3271;
+    SersicC& o = out.c[k];
+    o.cx = (float)c.cx;
+    o.cy = (float)c.cy;
+    o.cphi = (float)std::cos(c.phi);
+    o.sphi = (float)std::sin(c.phi);
+    o.q = (float)c.q;
+    o.inv_q = (float)(1.0 / c.q);
+    o.inv_r2 = (float)(1.0 / (c.R_sersic * c.R_sersic));
+    o.e = (float)(0.5 / c.n_sersic);
+    o.kb = (float)(b / kLn2d);
+    o.amp = (float)c.amp;
+  }
+  out.n = light->n;
+  return JT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// grid
+// ---------------------------------------------------------------------------
+jt_status make_grid(const jt_grid* g, GridC& out) {
+  std::memset(&out, 0, sizeof(out));
+  if (!g) return fail(JT_EINVAL, "null grid");
+  if (g->nx < 1 || g->ny < 1) return fail(JT_EINVAL, "grid: %d x %d pixels", g->nx, g->ny);
+  if (g->supersample < 1 || g->supersample > 16) return fail(JT_EINVAL, "grid: supersample %d not in [1, 16]", g->supersample);
+  if (!(g->pixel_scale > 0.0) || !finite(g->pixel_scale) || !finite(g->x0) || !finite(g->y0))
+    return fail(JT_EINVAL, "grid: bad pixel scale or centre");
+  const double npix = (double)g->nx * g->ny;
+  if (npix * g->supersample * g->supersample > 2147483647.0)
+    return fail(JT_EUNSUPPORTED, "grid: %g sub-pixels exceed the 32-bit index range", npix * g->supersample * g->supersample);
+  out.nx = g->nx;
+  out.ny = g->ny;
+  out.s = g->supersample;
+  out.s2 = g->supersample * g->supersample;
+  out.ppb = 256 / out.s2;
+  out.step = g->pixel_scale / g->supersample;
+  out.ox = g->x0 - 0.5 * g->pixel_scale * g->nx;
+  out.oy = g->y0 - 0.5 * g->pixel_scale * g->ny;
+  out.area_over_s2 = (float)(g->pixel_scale * g->pixel_scale / out.s2);
+  return JT_OK;
+}
+
+}  // namespace jt

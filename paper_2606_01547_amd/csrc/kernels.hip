@@ -1,0 +1,226 @@
+// HIP kernels of the lensed-image simulation for gfx950.
+//
+//  k_prep_subhalos  device SoA (x, y, Rs, alpha_Rs) -> packed SubRec table
+//  k_ray_shoot      step 1 at explicit points: beta = theta - alpha (or alpha)
+//  k_source_sb      step 2 at explicit points
+//  k_simulate       steps 1-2 plus the supersample average, fused
+//  k_conv_direct    step 3, LDS-tiled direct convolution
+//
+// Subhalo records are read with wave-uniform indices from a read-only table, so
+// they arrive through scalar loads into SGPRs and feed the VALU as scalar
+// operands; every lane runs the same subhalo at its own sub-pixel.  The
+// per-sub-pixel subhalo sum is formed tile by tile: a tile of kSubTile pairs is
+// summed in plain FP32 and the tile partial enters a TwoSum-compensated
+// accumulator.  The summation order is fixed, so results are bitwise
+// reproducible and independent of launch batching.
+#include "jt_device.hpp"
+#include "jt_kernels.hpp"
+
+namespace jt {
+
+constexpr int kSubTile = 64;
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_prep_subhalos(int n, int padded, const float* __restrict__ x,
+                                                      const float* __restrict__ y,
+                                                      const float* __restrict__ rs,
+                                                      const float* __restrict__ ars,
+                                                      SubRec* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) {
+    if (i < padded) out[i] = SubRec{1e18f, 1e18f, 1.0f, 0.0f};
+    return;
+  }
+  const double r = rs[i];
+  SubRec s;
+  s.x = x[i];
+  s.y = y[i];
+  s.c1 = (float)(1.0 / (r * r));
+  s.c2 = (float)((double)ars[i] / ((1.0 - 0.69314718055994530942) * r));
+  out[i] = s;
+}
+
+// Total deflection at one point: macro lens + compensated subhalo sum.
+// `nsub` is a multiple of 4 and the table holds 4 further readable records
+// (padding records contribute exactly zero), so the next group can always be
+// prefetched.
+__device__ __forceinline__ void deflect_point(const MacroC& mc, const SubRec* __restrict__ sub,
+                                              int nsub, float tx, float ty, float& ax, float& ay) {
+  float mx, my;
+  macro_deflection(mc, tx, ty, mx, my);
+  float hx = 0.f, lx = 0.f, hy = 0.f, ly = 0.f;
+  SubRec n0 = sub[0], n1 = sub[1], n2 = sub[2], n3 = sub[3];
+  for (int k0 = 0; k0 < nsub; k0 += kSubTile) {
+    const int kend = min(k0 + kSubTile, nsub);
+    float px = 0.f, py = 0.f;
+    for (int k = k0; k < kend; k += 4) {
+      const SubRec s0 = n0, s1 = n1, s2 = n2, s3 = n3;
+      n0 = sub[k + 4];
+      n1 = sub[k + 5];
+      n2 = sub[k + 6];
+      n3 = sub[k + 7];
+      nfw_pairs4(tx, ty, s0, s1, s2, s3, px, py);
+    }
+    two_sum_acc(hx, lx, px);
+    two_sum_acc(hy, ly, py);
+  }
+  // macro + (hi + lo), rounded once more
+  two_sum_acc(mx, lx, hx);
+  two_sum_acc(my, ly, hy);
+  ax = mx + lx;
+  ay = my + ly;
+}
+
+template <bool kAlpha>
+__global__ __launch_bounds__(256) void k_ray_shoot(int n, const float* __restrict__ x,
+                                                  const float* __restrict__ y, MacroC mc,
+                                                  const SubRec* __restrict__ sub, int nsub,
+                                                  float* __restrict__ ox, float* __restrict__ oy) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < n;
+  const float tx = valid ? x[i] : 0.f;
+  const float ty = valid ? y[i] : 0.f;
+  float ax, ay;
+  deflect_point(mc, sub, nsub, tx, ty, ax, ay);
+  if (valid) {
+    ox[i] = kAlpha ? ax : tx - ax;
+    oy[i] = kAlpha ? ay : ty - ay;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_source_sb(int n, const float* __restrict__ x,
+                                                  const float* __restrict__ y,
+                                                  const float* __restrict__ bx,
+                                                  const float* __restrict__ by, LightC src,
+                                                  LightC ll, float* __restrict__ sb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float v = sersic_sum(src, bx[i], by[i]);
+  if (ll.n > 0) v += sersic_sum(ll, x[i], y[i]);
+  sb[i] = v;
+}
+
+// One block covers g.ppb whole pixels; thread t handles sub-pixel (t mod s^2)
+// of local pixel (t / s^2).  Pixel values are reduced through LDS in a fixed
+// order.
+__global__ __launch_bounds__(256) void k_simulate(GridC g, MacroC mc,
+                                                 const SubRec* __restrict__ sub, int nsub,
+                                                 LightC src, LightC ll, float* __restrict__ img) {
+  __shared__ float red[256];
+  const int t = threadIdx.x;
+  const int lp = t / g.s2;
+  const int si = t - lp * g.s2;
+  const int npix = g.nx * g.ny;
+  const int p = blockIdx.x * g.ppb + lp;
+  const bool valid = (lp < g.ppb) && (p < npix);
+  const int pp = valid ? p : 0;
+  const int row = pp / g.nx;
+  const int col = pp - row * g.nx;
+  const int a = si / g.s;
+  const int b = si - a * g.s;
+  const float tx = (float)(g.ox + g.step * ((double)(col * g.s + b) + 0.5));
+  const float ty = (float)(g.oy + g.step * ((double)(row * g.s + a) + 0.5));
+  float ax, ay;
+  deflect_point(mc, sub, nsub, tx, ty, ax, ay);
+  float v = sersic_sum(src, tx - ax, ty - ay);
+  if (ll.n > 0) v += sersic_sum(ll, tx, ty);
+  red[t] = v;
+  __syncthreads();
+  if (t < g.ppb) {
+    const int q = blockIdx.x * g.ppb + t;
+    if (q < npix) {
+      float acc = 0.f;
+      const float* r = red + t * g.s2;
+      for (int k = 0; k < g.s2; ++k) acc += r[k];
+      img[q] = acc * g.area_over_s2;
+    }
+  }
+}
+
+// Direct convolution: 32 x 8 outputs per block; the input window of a chunk of
+// up to kConvRows kernel rows is staged in LDS (dynamic size), kernel weights
+// are read with uniform indices (scalar loads).
+constexpr int kConvTX = 32, kConvTY = 8, kConvRows = 32;
+
+__global__ __launch_bounds__(256) void k_conv_direct(const float* __restrict__ img, int nx, int ny,
+                                                    const float* __restrict__ psf, int k,
+                                                    float* __restrict__ out) {
+  extern __shared__ float tile[];
+  const int c = (k - 1) / 2;
+  const int tx = threadIdx.x % kConvTX, ty = threadIdx.x / kConvTX;
+  const int j0 = blockIdx.x * kConvTX, i0 = blockIdx.y * kConvTY;
+  const int cols = kConvTX + k - 1;
+  const int colmin = j0 + c - (k - 1);
+  float acc = 0.f;
+  for (int a0 = 0; a0 < k; a0 += kConvRows) {
+    const int ka = min(kConvRows, k - a0);
+    const int rows = kConvTY + ka - 1;
+    const int rowmin = i0 + c - (a0 + ka - 1);
+    __syncthreads();
+    for (int e = threadIdx.x; e < rows * cols; e += blockDim.x) {
+      const int lr = e / cols, lc = e - lr * cols;
+      const int gi = rowmin + lr, gj = colmin + lc;
+      tile[e] = (gi >= 0 && gi < ny && gj >= 0 && gj < nx) ? img[gi * nx + gj] : 0.f;
+    }
+    __syncthreads();
+    for (int da = 0; da < ka; ++da) {
+      const float* __restrict__ w = psf + (a0 + da) * k;
+      // input row i - a + c  ->  local row ty + (ka - 1 - da)
+      const float* trow = tile + (ty + ka - 1 - da) * cols + tx + k - 1;
+      for (int bb = 0; bb < k; ++bb) acc = fmaf(w[bb], trow[-bb], acc);
+    }
+  }
+  const int i = i0 + ty, j = j0 + tx;
+  if (i < ny && j < nx) out[i * nx + j] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_prep_subhalos(int n, const float* x, const float* y, const float* rs,
+                                const float* ars, SubRec* out, hipStream_t st) {
+  const int padded = subhalo_table_records(n);
+  hipLaunchKernelGGL(k_prep_subhalos, dim3((padded + 255) / 256), dim3(256), 0, st, n, padded, x, y, rs,
+                     ars, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ray_shoot(bool alpha, int n, const float* x, const float* y, const MacroC& mc,
+                            const SubRec* sub, int nsub, float* ox, float* oy, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid((n + 255) / 256);
+  if (alpha)
+    hipLaunchKernelGGL(k_ray_shoot<true>, grid, dim3(256), 0, st, n, x, y, mc, sub, nsub, ox, oy);
+  else
+    hipLaunchKernelGGL(k_ray_shoot<false>, grid, dim3(256), 0, st, n, x, y, mc, sub, nsub, ox, oy);
+  return hipGetLastError();
+}
+
+hipError_t launch_source_sb(int n, const float* x, const float* y, const float* bx, const float* by,
+                            const LightC& src, const LightC& ll, float* sb, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_source_sb, dim3((n + 255) / 256), dim3(256), 0, st, n, x, y, bx, by, src, ll, sb);
+  return hipGetLastError();
+}
+
+hipError_t launch_simulate(const GridC& g, const MacroC& mc, const SubRec* sub, int nsub,
+                           const LightC& src, const LightC& ll, float* img, hipStream_t st) {
+  const long npix = (long)g.nx * g.ny;
+  const long blocks = (npix + g.ppb - 1) / g.ppb;
+  hipLaunchKernelGGL(k_simulate, dim3((unsigned)blocks), dim3(256), 0, st, g, mc, sub, nsub, src, ll, img);
+  return hipGetLastError();
+}
+
+size_t conv_direct_lds_bytes(int k) {
+  const int ka = k < kConvRows ? k : kConvRows;
+  return sizeof(float) * (size_t)(kConvTY + ka - 1) * (size_t)(kConvTX + k - 1);
+}
+
+hipError_t launch_conv_direct(const float* img, int nx, int ny, const float* psf, int k, float* out,
+                              hipStream_t st) {
+  const dim3 grid((nx + kConvTX - 1) / kConvTX, (ny + kConvTY - 1) / kConvTY);
+  hipLaunchKernelGGL(k_conv_direct, grid, dim3(256), conv_direct_lds_bytes(k), st, img, nx, ny, psf, k, out);
+  return hipGetLastError();
+}
+
+}  // namespace jt

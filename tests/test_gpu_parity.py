@@ -1,0 +1,306 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, element
+by element on the same seeded FP32 inputs.
+
+Bars: deflections e_alpha <= 1e-5, images e_I <= 1e-4 (tests/parity.py).
+Sizes span several tiles and ragged tails; the full headline image (200x200
+px, s = 3, 10,000 NFW, 41x41 PSF) is checked in the launch configuration the
+benchmark times, on sampled pixels the oracle computes one by one plus a
+stage-isolated check of the convolution of the whole GPU image.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from parity import DEFLECTION_TOL, IMAGE_TOL, deflection_error, image_error
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2606_01547_amd import Context
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.float64)
+
+
+def _f32(a):
+    return np.asarray(a, dtype=np.float32)
+
+
+# ---------------------------------------------------------------- deflection
+@pytest.mark.parametrize("draw", range(6))
+def test_deflection_macro_lens(ctx, draw):
+    sc = W.config1_scene(draw=draw)
+    x, y = W.random_points(4099, 2.5, seed=draw)
+    ax, ay = ctx.deflection(x, y, sc.lens)
+    ex, ey = O.total_deflection(x, y, sc.lens)
+    assert deflection_error(_np(ax), _np(ay), ex, ey) <= DEFLECTION_TOL
+
+
+@pytest.mark.parametrize("q", [1.0, 1.0 - 1e-6, 0.9999, 0.995, 0.6, 0.2])
+def test_deflection_sie_axis_ratios(ctx, q):
+    lens = W.Lens(sie=W.SIE(1.1, q, 0.7, 0.03, -0.02))
+    x, y = W.random_points(3000, 2.0, seed=11)
+    ax, ay = ctx.deflection(x, y, lens)
+    ex, ey = O.total_deflection(x, y, lens)
+    assert deflection_error(_np(ax), _np(ay), ex, ey) <= DEFLECTION_TOL
+
+
+def test_deflection_point_masses_and_shear(ctx):
+    pm = W.PointMasses(x=np.array([0.3, -0.5, 1.1]), y=np.array([0.1, 0.4, -0.9]),
+                       theta_E=np.array([0.4, 0.2, 0.1]))
+    lens = W.Lens(shear=W.Shear(0.02, -0.03), point_masses=pm)
+    x, y = W.random_points(2000, 2.0, seed=3)
+    ax, ay = ctx.deflection(x, y, lens)
+    ex, ey = O.total_deflection(x, y, lens)
+    assert deflection_error(_np(ax), _np(ay), ex, ey) <= DEFLECTION_TOL
+
+
+def _near_points(nfw, rng, count):
+    """Points at r = X Rs around random subhalos, X spanning every branch of the
+    NFW term (centre, small x, x -> 1 from both sides, far)."""
+    idx = rng.integers(0, nfw.n, count)
+    X = rng.choice([0.0, 1e-3, 0.05, 0.3, 0.5, 0.7, 0.9, 0.95, 0.999, 1.0, 1.001, 1.05, 1.5, 3.0], count)
+    ang = rng.uniform(0, 2 * np.pi, count)
+    x = nfw.x[idx].astype(np.float64) + X * nfw.Rs[idx] * np.cos(ang)
+    y = nfw.y[idx].astype(np.float64) + X * nfw.Rs[idx] * np.sin(ang)
+    return _f32(x), _f32(y)
+
+
+def test_deflection_headline_subhalos(ctx):
+    sc = W.config2_scene()
+    rng = np.random.default_rng(5)
+    x1, y1 = W.random_points(1500, 5.0, seed=21)
+    x2, y2 = _near_points(sc.lens.nfw, rng, 700)
+    x, y = np.concatenate([x1, x2]), np.concatenate([y1, y2])
+    ax, ay = ctx.deflection(x, y, sc.lens)
+    ex, ey = O.total_deflection(x, y, sc.lens)
+    assert deflection_error(_np(ax), _np(ay), ex, ey) <= DEFLECTION_TOL
+
+
+@pytest.mark.parametrize("nsub", [0, 1, 2, 3, 5, 63, 64, 65, 129])
+@pytest.mark.parametrize("npts", [1, 255, 257])
+def test_deflection_ragged_counts(ctx, nsub, npts):
+    sc = W.config4_scene(n_sub=max(nsub, 1))
+    nfw = sc.lens.nfw
+    if nsub == 0:
+        nfw = W.NFWTable(nfw.x[:0], nfw.y[:0], nfw.Rs[:0], nfw.alpha_Rs[:0])
+    lens = W.Lens(sie=sc.lens.sie, shear=sc.lens.shear, nfw=nfw)
+    x, y = W.random_points(npts, 3.0, seed=nsub * 1000 + npts)
+    ax, ay = ctx.deflection(x, y, lens)
+    ex, ey = O.total_deflection(x, y, lens)
+    assert deflection_error(_np(ax), _np(ay), ex, ey) <= DEFLECTION_TOL
+
+
+def test_subhalos_alone(ctx):
+    """NFW sum without the macro lens: the subhalo term itself meets the bar."""
+    sc = W.config2_scene(n_sub=2000)
+    lens = W.Lens(nfw=sc.lens.nfw)
+    rng = np.random.default_rng(8)
+    x1, y1 = W.random_points(1000, 3.5, seed=4)
+    x2, y2 = _near_points(sc.lens.nfw, rng, 500)
+    x, y = np.concatenate([x1, x2]), np.concatenate([y1, y2])
+    ax, ay = ctx.deflection(x, y, lens)
+    ex, ey = O.total_deflection(x, y, lens)
+    assert deflection_error(_np(ax), _np(ay), ex, ey) <= DEFLECTION_TOL
+
+
+def test_resident_table_matches_device_soa_bitwise(ctx):
+    sc = W.config2_scene(n_sub=777)
+    x, y = W.random_points(5000, 4.0, seed=1)
+    a1 = ctx.deflection(x, y, sc.lens)
+    h = ctx.upload_subhalos(sc.lens.nfw)
+    lens_h = W.Lens(sie=sc.lens.sie, shear=sc.lens.shear)
+    lens_h.subhalo_handle = h
+    a2 = ctx.deflection(x, y, lens_h)
+    np.testing.assert_array_equal(_np(a1[0]), _np(a2[0]))
+    np.testing.assert_array_equal(_np(a1[1]), _np(a2[1]))
+    ctx.release(h)
+
+
+def test_ray_shoot_is_theta_minus_alpha(ctx):
+    sc = W.config2_scene(n_sub=500)
+    x, y = W.random_points(3333, 4.0, seed=2)
+    bx, by = ctx.ray_shoot(x, y, sc.lens)
+    ax, ay = ctx.deflection(x, y, sc.lens)
+    np.testing.assert_array_equal(_np(bx).astype(np.float32), x - _np(ax).astype(np.float32))
+    np.testing.assert_array_equal(_np(by).astype(np.float32), y - _np(ay).astype(np.float32))
+    ex, ey = O.ray_shoot(x, y, sc.lens)
+    gx, gy = _np(bx), _np(by)
+    # beta parity expressed on alpha = theta - beta (FP32 rounding of beta included)
+    assert deflection_error(x - gx, y - gy, x - ex, y - ey) <= 2 * DEFLECTION_TOL
+
+
+def test_empty_point_set(ctx):
+    sc = W.config1_scene()
+    e = np.zeros(0, np.float32)
+    ax, ay = ctx.deflection(e, e, sc.lens)
+    assert ax.numel() == 0
+
+
+# ---------------------------------------------------------------- surface brightness
+@pytest.mark.parametrize("bn_exact", [False, True])
+def test_source_sb_stage_isolated(ctx, bn_exact):
+    sc = W.config2_scene(n_sub=10)
+    x, y = W.random_points(10001, 3.0, seed=7)
+    bx, by = W.random_points(10001, 1.0, seed=8)
+    sb = ctx.source_sb(x, y, bx, by, sc.source, sc.lens_light, bn_exact=bn_exact)
+    ref = O.surface_brightness(x, y, bx, by, sc.source, sc.lens_light, bn_exact)
+    assert image_error(_np(sb), ref) <= 2e-5
+
+
+def test_source_sb_at_gpu_traced_points(ctx):
+    sc = W.config2_scene(n_sub=3000)
+    x, y = W.random_points(4000, 3.0, seed=9)
+    bx, by = ctx.ray_shoot(x, y, sc.lens)
+    sb = ctx.source_sb(x, y, bx, by, sc.source, sc.lens_light)
+    ref = O.surface_brightness(x, y, _np(bx), _np(by), sc.source, sc.lens_light)
+    assert image_error(_np(sb), ref) <= 2e-5
+
+
+# ---------------------------------------------------------------- convolution
+@pytest.mark.parametrize("shape,k", [((53, 77), 1), ((53, 77), 3), ((53, 77), 11), ((200, 200), 41),
+                                     ((64, 64), 101), ((300, 33), 129), ((9, 300), 255), ((1, 1), 5)])
+def test_convolve_direct(ctx, shape, k):
+    rng = np.random.default_rng(k)
+    img = rng.uniform(0, 1, shape).astype(np.float32)
+    psf = rng.uniform(0, 1, (k, k))
+    psf[0, :] *= 3.0          # asymmetric: a correlation would fail
+    psf = (psf / psf.sum()).astype(np.float32)
+    out = ctx.convolve(img, psf, method=1)
+    ref = O.convolve_same(img, psf)
+    assert image_error(_np(out), ref) <= (2e-5 if k <= 41 else IMAGE_TOL)
+
+
+def test_convolve_delta_is_identity(ctx):
+    img = np.random.default_rng(0).standard_normal((70, 90)).astype(np.float32)
+    psf = np.zeros((9, 9), np.float32)
+    psf[4, 4] = 1.0
+    out = ctx.convolve(img, psf)
+    np.testing.assert_array_equal(_np(out).astype(np.float32), img)
+
+
+# ---------------------------------------------------------------- fused simulation
+@pytest.mark.parametrize("draw", range(4))
+def test_simulate_plain_case(ctx, draw):
+    sc = W.config1_scene(draw=draw)
+    got = _np(ctx.simulate_scene(sc))
+    assert image_error(got, O.simulate_image(sc)) <= IMAGE_TOL
+
+
+def test_simulate_differentiation_case_forward(ctx):
+    sc = W.config4_scene()
+    got = _np(ctx.simulate_scene(sc))
+    assert image_error(got, O.simulate_image(sc)) <= IMAGE_TOL
+
+
+def test_simulate_headline_physics_reduced_grid(ctx):
+    sc = W.config2_scene(npix=44, n_sub=4000)
+    sc.grid = W.Grid(nx=44, ny=37, pixel_scale=0.05, x0=0.11, y0=-0.07, supersample=3)
+    got = _np(ctx.simulate_scene(sc))
+    assert image_error(got, O.simulate_image(sc)) <= IMAGE_TOL
+    un = _np(ctx.simulate_scene(sc, psf=False))
+    assert image_error(un, O.simulate_unconvolved(sc)) <= IMAGE_TOL
+
+
+def _oracle_pixels(sc, rows, cols):
+    g = sc.grid
+    tx, ty = O.subpixel_coords(g.nx, g.ny, g.pixel_scale, g.x0, g.y0, g.supersample)
+    tx, ty = tx[rows, cols], ty[rows, cols]
+    bx, by = O.ray_shoot(tx, ty, sc.lens)
+    sb = O.surface_brightness(tx, ty, bx, by, sc.source, sc.lens_light, sc.bn_exact)
+    return g.pixel_scale ** 2 * sb.mean(axis=(-2, -1))
+
+
+def test_simulate_headline_full_size_sampled(ctx):
+    """200x200 px, s = 3, 10,000 NFW, 41x41 PSF: the bench's launch."""
+    sc = W.config2_scene()
+    un = _np(ctx.simulate_scene(sc, psf=False))
+    rng = np.random.default_rng(0)
+    rows = rng.integers(0, 200, 260)
+    cols = rng.integers(0, 200, 260)
+    # plus the brightest pixels, where the lensed arcs sit
+    flat = np.argsort(un.reshape(-1))[-40:]
+    rows = np.concatenate([rows, flat // 200])
+    cols = np.concatenate([cols, flat % 200])
+    ref = _oracle_pixels(sc, rows, cols)
+    floor = 1e-3 * np.abs(un).max()
+    err = np.max(np.abs(un[rows, cols] - ref) / np.maximum(np.abs(ref), floor))
+    assert err <= IMAGE_TOL
+    full = _np(ctx.simulate_scene(sc))
+    # the PSF step of the fused call equals jt_convolve of the unconvolved image
+    np.testing.assert_array_equal(full, _np(ctx.convolve(un.astype(np.float32), sc.psf)))
+    assert image_error(full, O.convolve_same(un, sc.psf)) <= 2e-5
+
+
+def test_simulate_is_deterministic(ctx):
+    sc = W.config2_scene(npix=64, n_sub=3000)
+    a = _np(ctx.simulate_scene(sc))
+    b = _np(ctx.simulate_scene(sc))
+    np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("nx,ny,s", [(1, 1, 1), (1, 37, 3), (23, 5, 5), (7, 6, 16), (16, 16, 2)])
+def test_simulate_grid_edge_cases(ctx, nx, ny, s):
+    sc = W.config2_scene(n_sub=200)
+    sc.grid = W.Grid(nx=nx, ny=ny, pixel_scale=0.07, x0=0.2, y0=0.1, supersample=s)
+    got = _np(ctx.simulate_scene(sc, psf=False))
+    assert image_error(got, O.simulate_unconvolved(sc)) <= IMAGE_TOL
+
+
+def test_simulate_without_light_or_lens(ctx):
+    sc = W.config1_scene()
+    empty = W.Scene(grid=sc.grid, lens=W.Lens(), source=[], lens_light=[], psf=None)
+    assert np.all(_np(ctx.simulate_scene(empty)) == 0.0)
+    ll = W.Sersic(amp=2.0, R_sersic=0.6, n_sersic=3.0, q=0.8, phi=0.3, cx=0.0, cy=0.0)
+    only = W.Scene(grid=sc.grid, lens=W.Lens(), source=[], lens_light=[ll], psf=sc.psf)
+    assert image_error(_np(ctx.simulate_scene(only)), O.simulate_image(only)) <= IMAGE_TOL
+
+
+# ---------------------------------------------------------------- argument errors
+def test_invalid_arguments_raise_without_launch(ctx):
+    from paper_2606_01547_amd import JtError
+    from paper_2606_01547_amd._native import JT_EINVAL, JT_EUNSUPPORTED
+    sc = W.config1_scene()
+    x, y = W.random_points(10, 1.0, seed=0)
+    with pytest.raises(JtError) as e:
+        ctx.convolve(np.ones((8, 8), np.float32), np.ones((4, 4), np.float32))
+    assert e.value.status == JT_EINVAL
+    bad = W.Lens(sie=W.SIE(1.0, 0.0, 0.0, 0.0, 0.0))
+    with pytest.raises(JtError) as e:
+        ctx.deflection(x, y, bad)
+    assert e.value.status == JT_EINVAL
+    with pytest.raises(JtError):
+        ctx.deflection(x, y, W.Lens(sie=W.SIE(1.0, 1.5, 0.0, 0.0, 0.0)))
+    with pytest.raises(JtError):
+        ctx.simulate_image(W.Grid(nx=0, ny=4, pixel_scale=0.05), sc.lens, sc.source)
+    with pytest.raises(JtError):
+        ctx.simulate_image(W.Grid(nx=4, ny=4, pixel_scale=0.05, supersample=17), sc.lens, sc.source)
+    src = W.Sersic(amp=1.0, R_sersic=0.1, n_sersic=0.1, q=1.0, phi=0.0, cx=0.0, cy=0.0)
+    with pytest.raises(JtError):
+        ctx.source_sb(x, y, x, y, [src])
+    with pytest.raises(JtError) as e:
+        ctx.source_sb(x, y, x, y, [sc.source[0]] * 9)
+    assert e.value.status == JT_EUNSUPPORTED
+    with pytest.raises(JtError):
+        ctx.upload_subhalos(W.NFWTable(np.zeros(3, np.float32), np.zeros(3, np.float32),
+                                       np.array([0.1, 0.0, 0.1], np.float32), np.ones(3, np.float32)))
+    with pytest.raises(JtError):
+        ctx.release(987654321)
+    # the context still works afterwards
+    ax, ay = ctx.deflection(x, y, sc.lens)
+    ex, ey = O.total_deflection(x, y, sc.lens)
+    assert deflection_error(_np(ax), _np(ay), ex, ey) <= DEFLECTION_TOL
