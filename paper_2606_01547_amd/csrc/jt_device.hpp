@@ -104,15 +104,16 @@ __device__ __forceinline__ void macro_deflection(const MacroC& m, float tx, floa
 // ---------------------------------------------------------------------------
 // NFW pair term
 // ---------------------------------------------------------------------------
-// g(x)/x^2 for x^2 = X2 < 1 (rare near-field pairs), FP32 with the branch forms
-// that avoid cancellation:
-//   X2 >= 0.81:  F = sum_k (-u)^k/(2k+1), u = X2 - 1 in [-0.19, 0)
-//   X2 >= 0.25:  F = atanh(w)/w, w = sqrt(1 - X2)
-//   X2 <  0.25:  g = [-L X2/(1+w) + log1p(-X2/(2(1+w)))]/w, L = ln(x/2)
-// and 0 at X2 = 0.
-__device__ __noinline__ float nfw_near_g_over_x2(float X2) {
-  if (!(X2 > 0.f)) return 0.f;
-  const float half_ln = 0.5f * logf(X2);   // ln x
+// g(x)/x^2 for x^2 = X2 < 1 (rare near-field pairs), from l2 = log2(X2), with
+// hardware transcendentals and forms that avoid cancellation:
+//   X2 >= 0.81: F = sum_k (-u)^k/(2k+1), u = X2 - 1 in [-0.19, 0), and
+//               g = ln(x/2) + F;
+//   X2 <  0.81: g = [-L X2/(1+w) + log1p(-X2/(2(1+w)))]/w, L = ln(x/2),
+//               w = sqrt(1 - X2), with log1p(t) = t ln(1+t)/((1+t) - 1)
+//               (exact t when 1 + t rounds to 1);
+// 0 at X2 = 0.
+__device__ __forceinline__ float nfw_near_g_over_x2(float X2, float l2) {
+  const float L = fmaf(0.5f * kLn2, l2, -kLn2);   // ln(x/2)
   float g;
   if (X2 >= 0.81f) {
     const float u = X2 - 1.0f;
@@ -127,25 +128,22 @@ __device__ __noinline__ float nfw_near_g_over_x2(float X2) {
     F = fmaf(F, -u, 1.0f / 5.0f);
     F = fmaf(F, -u, 1.0f / 3.0f);
     F = fmaf(F, -u, 1.0f);
-    g = (half_ln - kLn2) + F;
+    g = L + F;
   } else {
-    const float w = sqrtf(1.0f - X2);
-    if (X2 >= 0.25f) {
-      g = (half_ln - kLn2) + atanhf(w) / w;
-    } else {
-      const float L = half_ln - kLn2;
-      const float opw = 1.0f + w;
-      g = (-L * X2 / opw + log1pf(-X2 / (2.0f * opw))) / w;
-    }
+    const float w = __builtin_amdgcn_sqrtf(1.0f - X2);
+    const float ropw = __builtin_amdgcn_rcpf(1.0f + w);
+    const float t = -0.5f * X2 * ropw;
+    const float u = 1.0f + t;
+    const float lp = (u == 1.0f) ? t : kLn2 * __builtin_amdgcn_logf(u) * t * __builtin_amdgcn_rcpf(u - 1.0f);
+    g = fmaf(-L * X2, ropw, lp) * __builtin_amdgcn_rcpf(w);
   }
-  return g / X2;
+  return X2 > 0.f ? g * __builtin_amdgcn_rcpf(X2) : 0.f;
 }
 
-// Far-field g(x)/x^2 for x^2 = X2 >= 1: with y = rsq(X2),
+// Far-field g(x)/x^2 for x^2 = X2 >= 1 and l2 = log2(X2): with y = rsq(X2),
 // g = (ln2/2) log2(X2) + psi(y), psi the fitted polynomial, and g/x^2 = g y^2.
-__device__ __forceinline__ float nfw_far_g_over_x2(float X2) {
+__device__ __forceinline__ float nfw_far_g_over_x2(float X2, float l2) {
   const float y = __builtin_amdgcn_rsqf(X2);
-  const float l2 = __builtin_amdgcn_logf(X2);
   float p = kNfwPsi[0];
 #pragma unroll
   for (int i = 1; i <= JT_NFW_POLY_DEGREE; ++i) p = fmaf(p, y, kNfwPsi[i]);
@@ -166,15 +164,19 @@ __device__ __forceinline__ void nfw_pairs4(float tx, float ty, const SubRec& s0,
   const float X1 = fmaf(dy1, dy1, dx1 * dx1) * s1.c1;
   const float X2 = fmaf(dy2, dy2, dx2 * dx2) * s2.c1;
   const float X3 = fmaf(dy3, dy3, dx3 * dx3) * s3.c1;
-  float h0 = nfw_far_g_over_x2(X0);
-  float h1 = nfw_far_g_over_x2(X1);
-  float h2 = nfw_far_g_over_x2(X2);
-  float h3 = nfw_far_g_over_x2(X3);
+  const float l0 = __builtin_amdgcn_logf(X0);
+  const float l1 = __builtin_amdgcn_logf(X1);
+  const float l2 = __builtin_amdgcn_logf(X2);
+  const float l3 = __builtin_amdgcn_logf(X3);
+  float h0 = nfw_far_g_over_x2(X0, l0);
+  float h1 = nfw_far_g_over_x2(X1, l1);
+  float h2 = nfw_far_g_over_x2(X2, l2);
+  float h3 = nfw_far_g_over_x2(X3, l3);
   if (__builtin_expect(fminf(fminf(X0, X1), fminf(X2, X3)) < 1.0f, 0)) {
-    if (X0 < 1.0f) h0 = nfw_near_g_over_x2(X0);
-    if (X1 < 1.0f) h1 = nfw_near_g_over_x2(X1);
-    if (X2 < 1.0f) h2 = nfw_near_g_over_x2(X2);
-    if (X3 < 1.0f) h3 = nfw_near_g_over_x2(X3);
+    if (X0 < 1.0f) h0 = nfw_near_g_over_x2(X0, l0);
+    if (X1 < 1.0f) h1 = nfw_near_g_over_x2(X1, l1);
+    if (X2 < 1.0f) h2 = nfw_near_g_over_x2(X2, l2);
+    if (X3 < 1.0f) h3 = nfw_near_g_over_x2(X3, l3);
   }
   sx = fmaf(h0 * s0.c2, dx0, sx);
   sy = fmaf(h0 * s0.c2, dy0, sy);

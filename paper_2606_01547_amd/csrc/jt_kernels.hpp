@@ -17,11 +17,14 @@ inline int subhalo_table_records(int n) { return subhalo_loop_count(n) + 4; }
 hipError_t launch_prep_subhalos(int n, const float* x, const float* y, const float* rs,
                                 const float* ars, SubRec* out, hipStream_t st);
 hipError_t launch_ray_shoot(bool alpha, int n, const float* x, const float* y, const MacroC& mc,
-                            const SubRec* sub, int nsub, float* ox, float* oy, hipStream_t st);
+                            const SubRec* sub, int nloop, float* ox, float* oy, hipStream_t st);
 hipError_t launch_source_sb(int n, const float* x, const float* y, const float* bx, const float* by,
                             const LightC& src, const LightC& ll, float* sb, hipStream_t st);
-hipError_t launch_simulate(const GridC& g, const MacroC& mc, const SubRec* sub, int nsub,
-                           const LightC& src, const LightC& ll, float* img, hipStream_t st);
+// g.ppb is set by the launcher from the chosen split.
+hipError_t launch_simulate(GridC g, const MacroC& mc, const SubRec* sub, int nloop, const LightC& src,
+                           const LightC& ll, float* img, hipStream_t st);
+// Wave-groups per block for `points` sub-pixels in whole units of `unit`.
+int pick_split(long points, int unit, int nloop);
 size_t conv_direct_lds_bytes(int k);
 hipError_t launch_conv_direct(const float* img, int nx, int ny, const float* psf, int k, float* out,
                               hipStream_t st);

@@ -40,18 +40,31 @@ __global__ __launch_bounds__(256) void k_prep_subhalos(int n, int padded, const 
   out[i] = s;
 }
 
-// Total deflection at one point: macro lens + compensated subhalo sum.
-// `nsub` is a multiple of 4 and the table holds 4 further readable records
-// (padding records contribute exactly zero), so the next group can always be
-// prefetched.
-__device__ __forceinline__ void deflect_point(const MacroC& mc, const SubRec* __restrict__ sub,
-                                              int nsub, float tx, float ty, float& ax, float& ay) {
-  float mx, my;
-  macro_deflection(mc, tx, ty, mx, my);
+// ---------------------------------------------------------------------------
+// Canonical subhalo summation order.  The nloop records (a multiple of 4) are
+// cut into kQuarters contiguous ranges with boundaries that are multiples of
+// 4; each range is summed in tiles of kSubTile pairs (plain FP32 inside a
+// tile, TwoSum across tiles), and the ranges are combined in index order.  A
+// launch may hand the ranges of one sub-pixel to 1, 2 or 4 waves (kSplit);
+// the arithmetic and its order do not change, so every launch shape gives
+// bitwise the same deflection.
+// ---------------------------------------------------------------------------
+constexpr int kQuarters = 4;
+
+__device__ __forceinline__ int quarter_bound(int nloop, int q) {
+  const int step = ((nloop + 15) / 16) * 4;  // ceil(nloop / 4) rounded up to a multiple of 4
+  return min(q * step, nloop);
+}
+
+// Sum of the pair terms over records [kb, ke) as (hi, lo) per component.  The
+// table holds 4 readable records past every range end (the next range, or
+// the padding at the end), so the next group is always prefetched.
+__device__ __forceinline__ float4 subhalo_range_sum(float tx, float ty, const SubRec* __restrict__ sub,
+                                                    int kb, int ke) {
   float hx = 0.f, lx = 0.f, hy = 0.f, ly = 0.f;
-  SubRec n0 = sub[0], n1 = sub[1], n2 = sub[2], n3 = sub[3];
-  for (int k0 = 0; k0 < nsub; k0 += kSubTile) {
-    const int kend = min(k0 + kSubTile, nsub);
+  SubRec n0 = sub[kb], n1 = sub[kb + 1], n2 = sub[kb + 2], n3 = sub[kb + 3];
+  for (int k0 = kb; k0 < ke; k0 += kSubTile) {
+    const int kend = min(k0 + kSubTile, ke);
     float px = 0.f, py = 0.f;
     for (int k = k0; k < kend; k += 4) {
       const SubRec s0 = n0, s1 = n1, s2 = n2, s3 = n3;
@@ -64,25 +77,70 @@ __device__ __forceinline__ void deflect_point(const MacroC& mc, const SubRec* __
     two_sum_acc(hx, lx, px);
     two_sum_acc(hy, ly, py);
   }
-  // macro + (hi + lo), rounded once more
+  return make_float4(hx, lx, hy, ly);
+}
+
+// macro + sum of the quarter partials, in quarter order.
+__device__ __forceinline__ void combine_deflection(float mx, float my, const float4* q, int stride,
+                                                   float& ax, float& ay) {
+  float hx = 0.f, lx = 0.f, hy = 0.f, ly = 0.f;
+#pragma unroll
+  for (int i = 0; i < kQuarters; ++i) {
+    const float4 v = q[i * stride];
+    two_sum_acc(hx, lx, v.x);
+    lx += v.y;
+    two_sum_acc(hy, ly, v.z);
+    ly += v.w;
+  }
   two_sum_acc(mx, lx, hx);
   two_sum_acc(my, ly, hy);
   ax = mx + lx;
   ay = my + ly;
 }
 
-template <bool kAlpha>
+// Per-block quarter partials: [quarter][slot], slot < 256 / kSplit.
+template <int kSplit>
+struct QuarterScratch {
+  float4 q[kQuarters][256 / kSplit];
+};
+
+// The quarters handled by wave-group g of kSplit, for the sub-pixel (tx, ty),
+// written to scratch.q[*][slot].
+template <int kSplit>
+__device__ __forceinline__ void subhalo_quarters(float tx, float ty, const SubRec* __restrict__ sub, int nloop,
+                                                 int g, int slot, QuarterScratch<kSplit>& scratch) {
+  constexpr int kPer = kQuarters / kSplit;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int q = g * kPer + i;
+    scratch.q[q][slot] = subhalo_range_sum(tx, ty, sub, quarter_bound(nloop, q), quarter_bound(nloop, q + 1));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Step 1 at explicit points.  Block = kSplit wave-groups x (256 / kSplit)
+// points; all groups see the same points.
+template <bool kAlpha, int kSplit>
 __global__ __launch_bounds__(256) void k_ray_shoot(int n, const float* __restrict__ x,
                                                   const float* __restrict__ y, MacroC mc,
-                                                  const SubRec* __restrict__ sub, int nsub,
+                                                  const SubRec* __restrict__ sub, int nloop,
                                                   float* __restrict__ ox, float* __restrict__ oy) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ QuarterScratch<kSplit> scratch;
+  constexpr int kW = 256 / kSplit;
+  // kW is a multiple of the wave size, so the group index is wave-uniform;
+  // readfirstlane lets the compiler keep the subhalo loop on scalar loads.
+  const int g = __builtin_amdgcn_readfirstlane(threadIdx.x / kW);
+  const int slot = threadIdx.x - g * kW;
+  const int i = blockIdx.x * kW + slot;
   const bool valid = i < n;
   const float tx = valid ? x[i] : 0.f;
   const float ty = valid ? y[i] : 0.f;
-  float ax, ay;
-  deflect_point(mc, sub, nsub, tx, ty, ax, ay);
-  if (valid) {
+  subhalo_quarters<kSplit>(tx, ty, sub, nloop, g, slot, scratch);
+  __syncthreads();
+  if (g == 0 && valid) {
+    float mx, my, ax, ay;
+    macro_deflection(mc, tx, ty, mx, my);
+    combine_deflection(mx, my, &scratch.q[0][slot], kW, ax, ay);
     ox[i] = kAlpha ? ax : tx - ax;
     oy[i] = kAlpha ? ay : ty - ay;
   }
@@ -100,14 +158,19 @@ __global__ __launch_bounds__(256) void k_source_sb(int n, const float* __restric
   sb[i] = v;
 }
 
-// One block covers g.ppb whole pixels; thread t handles sub-pixel (t mod s^2)
-// of local pixel (t / s^2).  Pixel values are reduced through LDS in a fixed
-// order.
-__global__ __launch_bounds__(256) void k_simulate(GridC g, MacroC mc,
-                                                 const SubRec* __restrict__ sub, int nsub,
-                                                 LightC src, LightC ll, float* __restrict__ img) {
+// Steps 1-2 and the supersample average, fused.  A block covers g.ppb whole
+// pixels (g.ppb * s^2 <= 256 / kSplit sub-pixel slots); slot t holds sub-pixel
+// (t mod s^2) of local pixel (t / s^2).  The kSplit wave-groups share the
+// subhalo quarters of the same slots; group 0 combines them, evaluates the
+// light, and the pixel values are reduced through LDS in a fixed order.
+template <int kSplit>
+__global__ __launch_bounds__(256) void k_simulate(GridC g, MacroC mc, const SubRec* __restrict__ sub,
+                                                 int nloop, LightC src, LightC ll, float* __restrict__ img) {
+  __shared__ QuarterScratch<kSplit> scratch;
   __shared__ float red[256];
-  const int t = threadIdx.x;
+  constexpr int kW = 256 / kSplit;
+  const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / kW);  // wave-uniform (kW % 64 == 0)
+  const int t = threadIdx.x - grp * kW;
   const int lp = t / g.s2;
   const int si = t - lp * g.s2;
   const int npix = g.nx * g.ny;
@@ -120,17 +183,22 @@ __global__ __launch_bounds__(256) void k_simulate(GridC g, MacroC mc,
   const int b = si - a * g.s;
   const float tx = (float)(g.ox + g.step * ((double)(col * g.s + b) + 0.5));
   const float ty = (float)(g.oy + g.step * ((double)(row * g.s + a) + 0.5));
-  float ax, ay;
-  deflect_point(mc, sub, nsub, tx, ty, ax, ay);
-  float v = sersic_sum(src, tx - ax, ty - ay);
-  if (ll.n > 0) v += sersic_sum(ll, tx, ty);
-  red[t] = v;
+  subhalo_quarters<kSplit>(tx, ty, sub, nloop, grp, t, scratch);
   __syncthreads();
-  if (t < g.ppb) {
-    const int q = blockIdx.x * g.ppb + t;
+  if (grp == 0) {
+    float mx, my, ax, ay;
+    macro_deflection(mc, tx, ty, mx, my);
+    combine_deflection(mx, my, &scratch.q[0][t], kW, ax, ay);
+    float v = sersic_sum(src, tx - ax, ty - ay);
+    if (ll.n > 0) v += sersic_sum(ll, tx, ty);
+    red[t] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < g.ppb) {
+    const int q = blockIdx.x * g.ppb + threadIdx.x;
     if (q < npix) {
       float acc = 0.f;
-      const float* r = red + t * g.s2;
+      const float* r = red + threadIdx.x * g.s2;
       for (int k = 0; k < g.s2; ++k) acc += r[k];
       img[q] = acc * g.area_over_s2;
     }
@@ -177,6 +245,21 @@ __global__ __launch_bounds__(256) void k_conv_direct(const float* __restrict__ i
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// Waves per block-column sharing one sub-pixel's subhalo quarters: enough
+// waves to give every SIMD of the 256 CUs several (about 16) to interleave,
+// while keeping whole pixels (`unit` sub-pixel slots each) in a wave-group.
+int pick_split(long points, int unit, int nloop) {
+  if (nloop < 64) return 1;
+  const long target = 16L * 1024 * 64;  // lanes for ~16 waves per SIMD
+  for (int split = 1; split < 4; split *= 2) {
+    const long w = 256 / split;
+    const long used = (w / unit) * unit;          // slots holding whole pixels
+    const long lanes = (points + used - 1) / used * 256;
+    if (lanes >= target) return split;
+    if (((256 / (split * 2)) / unit) < 1) return split;  // a pixel no longer fits
+  }
+  return 4;
+}
 hipError_t launch_prep_subhalos(int n, const float* x, const float* y, const float* rs,
                                 const float* ars, SubRec* out, hipStream_t st) {
   const int padded = subhalo_table_records(n);
@@ -186,13 +269,18 @@ hipError_t launch_prep_subhalos(int n, const float* x, const float* y, const flo
 }
 
 hipError_t launch_ray_shoot(bool alpha, int n, const float* x, const float* y, const MacroC& mc,
-                            const SubRec* sub, int nsub, float* ox, float* oy, hipStream_t st) {
+                            const SubRec* sub, int nloop, float* ox, float* oy, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  const dim3 grid((n + 255) / 256);
-  if (alpha)
-    hipLaunchKernelGGL(k_ray_shoot<true>, grid, dim3(256), 0, st, n, x, y, mc, sub, nsub, ox, oy);
-  else
-    hipLaunchKernelGGL(k_ray_shoot<false>, grid, dim3(256), 0, st, n, x, y, mc, sub, nsub, ox, oy);
+  const int split = pick_split(n, 1, nloop);
+  const int w = 256 / split;
+  const dim3 grid((n + w - 1) / w);
+#define JT_RAY(A, S) hipLaunchKernelGGL((k_ray_shoot<A, S>), grid, dim3(256), 0, st, n, x, y, mc, sub, nloop, ox, oy)
+  if (alpha) {
+    if (split == 1) JT_RAY(true, 1); else if (split == 2) JT_RAY(true, 2); else JT_RAY(true, 4);
+  } else {
+    if (split == 1) JT_RAY(false, 1); else if (split == 2) JT_RAY(false, 2); else JT_RAY(false, 4);
+  }
+#undef JT_RAY
   return hipGetLastError();
 }
 
@@ -203,11 +291,15 @@ hipError_t launch_source_sb(int n, const float* x, const float* y, const float* 
   return hipGetLastError();
 }
 
-hipError_t launch_simulate(const GridC& g, const MacroC& mc, const SubRec* sub, int nsub,
-                           const LightC& src, const LightC& ll, float* img, hipStream_t st) {
+hipError_t launch_simulate(GridC g, const MacroC& mc, const SubRec* sub, int nloop, const LightC& src,
+                           const LightC& ll, float* img, hipStream_t st) {
   const long npix = (long)g.nx * g.ny;
+  const int split = pick_split(npix * g.s2, g.s2, nloop);
+  g.ppb = (256 / split) / g.s2;
   const long blocks = (npix + g.ppb - 1) / g.ppb;
-  hipLaunchKernelGGL(k_simulate, dim3((unsigned)blocks), dim3(256), 0, st, g, mc, sub, nsub, src, ll, img);
+#define JT_SIM(S) hipLaunchKernelGGL((k_simulate<S>), dim3((unsigned)blocks), dim3(256), 0, st, g, mc, sub, nloop, src, ll, img)
+  if (split == 1) JT_SIM(1); else if (split == 2) JT_SIM(2); else JT_SIM(4);
+#undef JT_SIM
   return hipGetLastError();
 }
 
