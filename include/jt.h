@@ -3,10 +3,10 @@
  *
  * The library computes the paper's three-step image simulation (JAXtronomy,
  * section "Improvements over lenstronomy in image simulation"):
- *   1. a coordinate grid in the observer's angles is ray-traced through the
- *      deflectors to the source plane (deflection angles at each deflector);
- *   2. the source surface brightness is evaluated on the traced grid;
- *   3. the lensed image is convolved with the PSF.
+ *   1. every image-plane angle theta is mapped to the source plane,
+ *      beta = theta - sum of the deflections of all deflectors at theta;
+ *   2. the source light is evaluated at beta (lens light at theta);
+ *   3. the image is blurred by the point spread function.
  * The deflectors are those of the paper's deflector table that the path uses:
  * SIE (NIE with zero core; SIS as q = 1), external SHEAR and NFW (the subhalo
  * profile), plus a point mass used only by tests.  The light profile is the

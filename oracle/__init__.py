@@ -4,11 +4,11 @@ Only the test-suite, the package smoke check and the benchmark's CPU-baseline
 leg may import this package.  The HIP library never calls it and shares no
 code with it (no kernels, helpers, tables or constants).
 
-What it computes is the paper's three-step image simulation ("Improvements over
-lenstronomy in image simulation"): a coordinate grid in the observer's angles is
-ray-traced through the deflectors to the source plane, the source surface
-brightness is evaluated on the traced grid, and the lensed image is convolved
-with the PSF.  The paper gives no formulas; every profile below is the standard
+What it computes is the paper's three-step image simulation (section
+"Improvements over lenstronomy in image simulation"): image-plane angles are
+mapped back to the source plane by subtracting every deflector's deflection,
+the source light is evaluated at the mapped positions, and the resulting image
+is blurred by the PSF.  The paper gives no formulas; every profile below is the standard
 closed form from the lensing literature, named in its module, and evaluated in
 FP64 with branch forms that are well conditioned.  The direct sum over
 deflectors is an exact definition, so the oracle *is* that definition.

@@ -1,8 +1,8 @@
 """Image-plane coordinate grid and supersampling (oracle, FP64).
 
-The paper's first step starts from "a coordinate grid in the angles seen by the
-observer" (image-simulation section).  It does not fix the convention; the
-reading used here: pixel (i, j) has row i along +y and column j along +x, the
+The first step of the paper's image simulation (image-simulation section)
+starts from a grid of image-plane angles.  The paper does not fix its
+convention; the reading used here: pixel (i, j) has row i along +y and column j along +x, the
 grid is centred on (x0, y0), and each pixel is split into s x s equal
 sub-pixels evaluated at their centres.  A native pixel value is the mean of its
 sub-pixel surface brightness times the pixel area (flux per pixel).

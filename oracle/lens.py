@@ -1,9 +1,9 @@
 """Deflection angles of the deflector profiles on the path (oracle, FP64).
 
-The paper's first step ray-traces the observer's grid to the source plane,
-which "requires the calculation of light-ray deflection angles at each
-deflector" (image-simulation section); its deflector table lists NIE/SIE, SIS,
-SHEAR and NFW among others.  It states no formula, so each profile here is the
+Step one of the paper's image simulation (image-simulation section) maps every
+image-plane angle to the source plane, which needs the deflection of each
+deflector there; the paper's deflector table lists NIE/SIE, SIS, SHEAR and NFW
+among others.  It states no formula, so each profile here is the
 standard closed form from the literature, named per function.  All angles are in
 arcsec.  Single lens plane: beta = theta - sum_k alpha_k(theta).
 """

@@ -1,8 +1,8 @@
 """Elliptical Sersic surface brightness (oracle, FP64).
 
-The paper's second step evaluates "the surface brightness of the source ... on
-the ray-traced coordinate grid" (image-simulation section) and its flux table
-lists SERSIC, SERSIC_ELLIPSE and SERSIC_ELLIPSE_Q_PHI.  The profile is Sersic
+Step two of the paper's image simulation (image-simulation section) evaluates
+the source light at the source-plane positions of the grid; the paper's flux
+table lists SERSIC, SERSIC_ELLIPSE and SERSIC_ELLIPSE_Q_PHI.  The profile is Sersic
 (1968):  I(R) = amp * exp(-b_n [(R/R_sersic)^(1/n) - 1]), with the amplitude
 read as the surface brightness at R = R_sersic and the elliptical radius
 R = sqrt(q x'^2 + y'^2/q) (product average; x' along the major axis at angle

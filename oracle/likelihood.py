@@ -1,7 +1,6 @@
 """Image chi^2 log-likelihood (oracle, FP64).
 
-The paper names "a variety of log-likelihood functions" among the modelling
-features and uses autodiff for gradient-based fitting; it fixes neither the
+The paper lists several log-likelihood choices among the modelling features and uses autodiff for gradient-based fitting; it fixes neither the
 likelihood nor the noise model.  Reading: the Gaussian image likelihood
 
     log L = -1/2 sum_i (m_i - d_i)^2 / sigma_i^2,

@@ -1,8 +1,8 @@
 """The three-step lensed-image simulation (oracle, FP64).
 
-Steps in the paper's order (image-simulation section): observer grid ->
-ray-trace through the deflectors -> source surface brightness on the traced
-grid (plus unlensed lens light) -> supersample average -> PSF convolution.
+Steps in the paper's order (image-simulation section): image-plane grid ->
+source-plane positions after all deflections -> source light there (plus the
+unlensed lens light) -> supersample average -> PSF convolution.
 Reading: supersampled sub-pixels are averaged to native pixels before the
 native-resolution PSF is applied.
 """
