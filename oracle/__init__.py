@@ -24,6 +24,7 @@ from .light import sersic_bn, sersic, surface_brightness
 from .conv import convolve_same
 from .simulate import simulate_image, simulate_unconvolved
 from .likelihood import log_likelihood, noise_variance
+from .grad import chi2_gradient, macro_vector, macro_names
 
 # Functions whose result no independent pin fixes (see the test modules).
 PARITY_UNPINNED = ()
@@ -33,5 +34,5 @@ __all__ = [
     "shear_deflection", "nfw_g", "nfw_deflection", "nfw_kappa", "point_mass_deflection",
     "total_deflection", "ray_shoot", "sersic_bn", "sersic", "surface_brightness",
     "convolve_same", "simulate_image", "simulate_unconvolved", "log_likelihood",
-    "noise_variance", "PARITY_UNPINNED",
+    "noise_variance", "chi2_gradient", "macro_vector", "macro_names", "PARITY_UNPINNED",
 ]

@@ -1,0 +1,178 @@
+"""Gradient of the chi^2 image log-likelihood (oracle, FP64).
+
+The paper credits automatic differentiation with making gradient-based fitting
+possible (L-BFGS through autodiff, "Improvements over lenstronomy in lens
+modelling").  The oracle gradient is obtained the same way, but on the CPU in
+FP64: the forward model of `simulate.py` is restated with torch float64 CPU
+operations (same definitions and branch forms, checked equal to the NumPy
+oracle by the pins), and torch.autograd differentiates
+
+    log L = -1/2 sum_i (m_i - d_i)^2 w_i,   w_i = 1 / sigma_i^2 (data-based)
+
+with respect to the lens, shear, Sersic and subhalo parameters.  It shares no
+derivation with the GPU adjoint, which is written by hand.
+
+Parameter vector per draw (`macro`):
+  [theta_E, q, phi, cx, cy] of the SIE, [gamma1, gamma2] of the shear, then
+  [amp, R_sersic, n_sersic, q, phi, cx, cy] for every source component, then
+  the same seven for every lens-light component.
+Subhalo gradients: (x, y, alpha_Rs) per subhalo.  b_n is the Capaccioli fit
+1.9992 n - 0.3271 (its derivative in n is 1.9992).
+"""
+import math
+
+import numpy as np
+
+LN2 = math.log(2.0)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def macro_vector(lens, source, lens_light):
+    v = [lens.sie.theta_E, lens.sie.q, lens.sie.phi, lens.sie.cx, lens.sie.cy,
+         lens.shear.gamma1, lens.shear.gamma2]
+    for c in list(source) + list(lens_light):
+        v += [c.amp, c.R_sersic, c.n_sersic, c.q, c.phi, c.cx, c.cy]
+    return np.array(v, dtype=np.float64)
+
+
+def macro_names(n_source, n_lens_light):
+    names = ["sie.theta_E", "sie.q", "sie.phi", "sie.cx", "sie.cy", "shear.gamma1", "shear.gamma2"]
+    for tag, n in (("src", n_source), ("ll", n_lens_light)):
+        for k in range(n):
+            names += [f"{tag}{k}.{p}" for p in ("amp", "R_sersic", "n_sersic", "q", "phi", "cx", "cy")]
+    return names
+
+
+# ---------------------------------------------------------------- torch forward
+def _sie(t, x, y, te, q, phi, cx, cy):
+    c, s = t.cos(phi), t.sin(phi)
+    dx, dy = x - cx, y - cy
+    xp, yp = c * dx + s * dy, -s * dx + c * dy
+    f = t.sqrt((1 - q) * (1 + q))
+    psi = t.sqrt(q * q * xp * xp + yp * yp)
+    pref = te * t.sqrt(q)
+    if float(f.detach()) < 1e-3:
+        zx, zy = f * xp / psi, f * yp / psi
+        axp = pref * (xp / psi) * (1 - zx ** 2 / 3 + zx ** 4 / 5 - zx ** 6 / 7)
+        ayp = pref * (yp / psi) * (1 + zy ** 2 / 3 + zy ** 4 / 5 + zy ** 6 / 7)
+    else:
+        axp = pref / f * t.atan(f * xp / psi)
+        ayp = pref / f * t.atanh(f * yp / psi)
+    return c * axp - s * ayp, s * axp + c * ayp
+
+
+def _nfw_g(t, X):
+    """g(x) = ln(x/2) + F(x) with the oracle's branch forms (x > 0)."""
+    u = X * X - 1
+    near = u.abs() < 0.1
+    small = X < 0.5
+    # series in u near x = 1
+    us = t.where(near, u, t.zeros_like(u))
+    Fs = t.zeros_like(u)
+    p = t.ones_like(u)
+    for k in range(24):
+        Fs = Fs + p / (2 * k + 1)
+        p = p * (-us)
+    # direct forms, evaluated on safe arguments outside their branch
+    Xl = t.where((X < 1) & ~near, X, t.full_like(X, 0.5))
+    Fl = t.acosh(1 / Xl) / t.sqrt(1 - Xl * Xl)
+    Xh = t.where((X > 1) & ~near, X, t.full_like(X, 2.0))
+    Fh = t.acos(1 / Xh) / t.sqrt(Xh * Xh - 1)
+    F = t.where(near, Fs, t.where(X < 1, Fl, Fh))
+    g_rest = t.log(X / 2) + F
+    # stable small-x form
+    Xs = t.where(small, X, t.full_like(X, 0.25))
+    x2 = Xs * Xs
+    w = t.sqrt(1 - x2)
+    L = t.log(Xs / 2)
+    g_small = (-L * x2 / (1 + w) + t.log1p(-x2 / (2 * (1 + w)))) / w
+    return t.where(small, g_small, g_rest)
+
+
+def _nfw(t, x, y, rs, ars, sx, sy):
+    """Summed NFW deflection; x, y (P,), subhalo arrays (K,)."""
+    dx = x[:, None] - sx[None, :]
+    dy = y[:, None] - sy[None, :]
+    r2 = dx * dx + dy * dy
+    pos = r2 > 0                          # alpha = 0 at r = 0
+    r = t.sqrt(t.where(pos, r2, t.ones_like(r2)))
+    X = r / rs[None, :]
+    g = _nfw_g(t, X)
+    fac = t.where(pos, ars[None, :] / (1 - LN2) * g / X / r, t.zeros_like(r))
+    return (fac * dx).sum(1), (fac * dy).sum(1)
+
+
+def _sersic(t, x, y, amp, R, n, q, phi, cx, cy):
+    c, s = t.cos(phi), t.sin(phi)
+    dx, dy = x - cx, y - cy
+    xp, yp = c * dx + s * dy, -s * dx + c * dy
+    Rr = t.sqrt(q * xp * xp + yp * yp / q)
+    b = 1.9992 * n - 0.3271
+    return amp * t.exp(-b * ((Rr / R) ** (1 / n) - 1))
+
+
+def torch_forward(macro, sub_x, sub_y, sub_ars, sub_rs, grid, n_source, n_lens_light, psf):
+    """Model image (ny, nx) as a torch float64 tensor from torch parameters."""
+    t = _torch()
+    g = grid
+    d, s = float(g.pixel_scale), int(g.supersample)
+    j = t.arange(g.nx, dtype=t.float64)
+    i = t.arange(g.ny, dtype=t.float64)
+    b = t.arange(s, dtype=t.float64)
+    tx = (g.x0 + (j[None, :, None, None] - (g.nx - 1) / 2) * d
+          + ((b[None, None, None, :] + 0.5) / s - 0.5) * d).expand(g.ny, g.nx, s, s).reshape(-1)
+    ty = (g.y0 + (i[:, None, None, None] - (g.ny - 1) / 2) * d
+          + ((b[None, None, :, None] + 0.5) / s - 0.5) * d).expand(g.ny, g.nx, s, s).reshape(-1)
+    ax, ay = _sie(t, tx, ty, *[macro[k] for k in range(5)])
+    ax = ax + macro[5] * tx + macro[6] * ty
+    ay = ay + macro[6] * tx - macro[5] * ty
+    if sub_x is not None and sub_x.numel() > 0:
+        nx_, ny_ = _nfw(t, tx, ty, sub_rs, sub_ars, sub_x, sub_y)
+        ax, ay = ax + nx_, ay + ny_
+    bx, by = tx - ax, ty - ay
+    sb = t.zeros_like(tx)
+    for k in range(n_source):
+        sb = sb + _sersic(t, bx, by, *[macro[7 + 7 * k + m] for m in range(7)])
+    for k in range(n_lens_light):
+        o = 7 + 7 * (n_source + k)
+        sb = sb + _sersic(t, tx, ty, *[macro[o + m] for m in range(7)])
+    img = d * d * sb.reshape(g.ny, g.nx, s * s).mean(-1)
+    if psf is None:
+        return img
+    K = t.as_tensor(np.asarray(psf, dtype=np.float64))
+    k = K.shape[0]
+    # true convolution, zero padding, same size: conv2d correlates, so flip K
+    w = t.flip(K, dims=(0, 1))[None, None]
+    return t.nn.functional.conv2d(img[None, None], w, padding=(k - 1) // 2)[0, 0]
+
+
+def chi2_gradient(scene, data, inv_var):
+    """log L and its gradient for one scene.
+
+    Returns (logL, g_macro (P,), g_sub (N, 3) for (x, y, alpha_Rs))."""
+    t = _torch()
+    lens = scene.lens
+    macro = t.tensor(macro_vector(lens, scene.source, scene.lens_light), dtype=t.float64, requires_grad=True)
+    nfw = lens.nfw
+    if nfw is not None and nfw.n > 0:
+        sx = t.tensor(np.asarray(nfw.x, np.float64), requires_grad=True)
+        sy = t.tensor(np.asarray(nfw.y, np.float64), requires_grad=True)
+        sa = t.tensor(np.asarray(nfw.alpha_Rs, np.float64), requires_grad=True)
+        srs = t.tensor(np.asarray(nfw.Rs, np.float64))
+    else:
+        sx = sy = sa = srs = None
+    m = torch_forward(macro, sx, sy, sa, srs, scene.grid, len(scene.source), len(scene.lens_light), scene.psf)
+    dd = t.as_tensor(np.asarray(data, np.float64))
+    w = t.as_tensor(np.asarray(inv_var, np.float64))
+    logL = -0.5 * ((m - dd) ** 2 * w).sum()
+    logL.backward()
+    gm = macro.grad.numpy().copy()
+    if sx is not None:
+        gs = np.stack([sx.grad.numpy(), sy.grad.numpy(), sa.grad.numpy()], axis=1)
+    else:
+        gs = np.zeros((0, 3))
+    return float(logL.detach()), gm, gs
