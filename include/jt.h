@@ -167,6 +167,51 @@ jt_status jt_simulate_image(jt_ctx* ctx, const jt_grid* grid, const jt_lens* len
                             const float* psf, int k, float* out, hipStream_t stream);
 
 /* ----------------------------------------------------------------------
+ * Batches of parameter draws: forward images, the chi^2 log-likelihood and
+ * its gradient.  The paper names automatic differentiation as what makes
+ * gradient-based fitting possible (section "Improvements over lenstronomy in
+ * lens modelling", L-BFGS); here the gradient is a hand-written adjoint.
+ * -------------------------------------------------------------------- */
+/* B draws on one grid, each with an SIE, an external shear, n_sub NFW
+ * subhalos and n_src source + n_ll lens-light Sersic components (b_n from the
+ * Capaccioli fit).  Host arrays are read during the call; the subhalo SoA is
+ * device float32 [B][n_sub] (draw b at offset b * n_sub). */
+typedef struct {
+  int B;
+  const jt_sie* sie;                /* host [B] */
+  const jt_shear* shear;            /* host [B] */
+  int n_sub;                        /* >= 0 */
+  const float *sub_x, *sub_y, *sub_Rs, *sub_alpha_Rs;   /* device [B][n_sub] */
+  int n_src, n_ll;                  /* n_src + n_ll <= 3 for jt_chi2_grad */
+  const jt_sersic* src;             /* host [B][n_src] */
+  const jt_sersic* ll;              /* host [B][n_ll] (NULL when n_ll = 0) */
+} jt_draws;
+
+/* Forward images of every draw: out device float32 [B][ny][nx].  psf device
+ * [k][k] (odd k) or NULL with k = 0 (no convolution). */
+jt_status jt_simulate_batch(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws,
+                            const float* psf, int k, float* out, hipStream_t stream);
+
+/* log L_b = -1/2 sum_i w_i (m_b,i - d_i)^2 for every draw.  data, inv_var:
+ * device float32 [ny][nx] (inv_var = w = 1/sigma^2).  logL: device double [B]. */
+jt_status jt_chi2(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, const float* psf, int k,
+                  const float* data, const float* inv_var, double* logL, hipStream_t stream);
+
+/* log L and its gradient for every draw, by a hand-written adjoint that
+ * recomputes the traced positions instead of storing them.
+ * g_macro: device float32 [B][P], P = 7 + 7 (n_src + n_ll), in the order
+ *   (theta_E, q, phi, cx, cy) of the SIE, (gamma1, gamma2), then
+ *   (amp, R_sersic, n_sersic, q, phi, cx, cy) per source, then per lens-light
+ *   component.
+ * g_sub: device float32 [B][n_sub][3] = d log L / d(x, y, alpha_Rs) per
+ *   subhalo (may be NULL when n_sub = 0).
+ * logL: device double [B] (may be NULL).  Deterministic: fixed summation order.
+ * JT_EUNSUPPORTED when n_src + n_ll > 3. */
+jt_status jt_chi2_grad(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, const float* psf, int k,
+                       const float* data, const float* inv_var, double* logL, float* g_macro,
+                       float* g_sub, hipStream_t stream);
+
+/* ----------------------------------------------------------------------
  * Resident tables
  * -------------------------------------------------------------------- */
 /* Copy n subhalos (host float32 SoA) into a device-resident, pre-derived
@@ -189,7 +234,8 @@ typedef enum {
   JT_K_SB = 2,          /* surface brightness */
   JT_K_SIM = 3,         /* fused simulate kernel */
   JT_K_CONV = 4,        /* convolution */
-  JT_K_COUNT = 5
+  JT_K_GRAD = 5,        /* adjoint: residual, per-sub-pixel and subhalo passes */
+  JT_K_COUNT = 6
 } jt_kernel_id;
 /* Enable (1) or disable (0) event timing of every launch; resets the totals. */
 jt_status jt_profile_enable(jt_ctx* ctx, int on);

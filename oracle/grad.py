@@ -66,31 +66,35 @@ def _sie(t, x, y, te, q, phi, cx, cy):
 
 
 def _nfw_g(t, X):
-    """g(x) = ln(x/2) + F(x) with the oracle's branch forms (x > 0)."""
+    """g(x) = ln(x/2) + F(x) with the oracle's branch forms (x > 0); each
+    branch is evaluated on its own elements only."""
     u = X * X - 1
     near = u.abs() < 0.1
-    small = X < 0.5
-    # series in u near x = 1
-    us = t.where(near, u, t.zeros_like(u))
-    Fs = t.zeros_like(u)
-    p = t.ones_like(u)
-    for k in range(24):
-        Fs = Fs + p / (2 * k + 1)
-        p = p * (-us)
-    # direct forms, evaluated on safe arguments outside their branch
-    Xl = t.where((X < 1) & ~near, X, t.full_like(X, 0.5))
-    Fl = t.acosh(1 / Xl) / t.sqrt(1 - Xl * Xl)
-    Xh = t.where((X > 1) & ~near, X, t.full_like(X, 2.0))
-    Fh = t.acos(1 / Xh) / t.sqrt(Xh * Xh - 1)
-    F = t.where(near, Fs, t.where(X < 1, Fl, Fh))
-    g_rest = t.log(X / 2) + F
-    # stable small-x form
-    Xs = t.where(small, X, t.full_like(X, 0.25))
-    x2 = Xs * Xs
-    w = t.sqrt(1 - x2)
-    L = t.log(Xs / 2)
-    g_small = (-L * x2 / (1 + w) + t.log1p(-x2 / (2 * (1 + w)))) / w
-    return t.where(small, g_small, g_rest)
+    small = (X < 0.5) & ~near
+    lo = (X < 1) & ~near & ~small
+    hi = (X > 1) & ~near
+    out = t.zeros_like(X)
+    if bool(near.any()):
+        un = u[near]
+        F = t.zeros_like(un)
+        p = t.ones_like(un)
+        for k in range(24):
+            F = F + p / (2 * k + 1)
+            p = p * (-un)
+        out = out.index_put((near,), t.log(X[near] / 2) + F)
+    if bool(small.any()):
+        xs = X[small]
+        x2 = xs * xs
+        w = t.sqrt(1 - x2)
+        L = t.log(xs / 2)
+        out = out.index_put((small,), (-L * x2 / (1 + w) + t.log1p(-x2 / (2 * (1 + w)))) / w)
+    if bool(lo.any()):
+        xl = X[lo]
+        out = out.index_put((lo,), t.log(xl / 2) + t.acosh(1 / xl) / t.sqrt(1 - xl * xl))
+    if bool(hi.any()):
+        xh = X[hi]
+        out = out.index_put((hi,), t.log(xh / 2) + t.acos(1 / xh) / t.sqrt(xh * xh - 1))
+    return out
 
 
 def _nfw(t, x, y, rs, ars, sx, sy):

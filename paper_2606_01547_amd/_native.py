@@ -20,8 +20,9 @@ LIB_PATH = os.path.join(_HERE, "libjt.so")
 JT_OK, JT_EINVAL, JT_ENOMEM, JT_EDEVICE, JT_EUNSUPPORTED, JT_EBUSY, JT_ECANCELLED = range(7)
 STATUS_NAMES = {0: "JT_OK", 1: "JT_EINVAL", 2: "JT_ENOMEM", 3: "JT_EDEVICE", 4: "JT_EUNSUPPORTED",
                 5: "JT_EBUSY", 6: "JT_ECANCELLED"}
-JT_K_PREP, JT_K_RAY, JT_K_SB, JT_K_SIM, JT_K_CONV = range(5)
-KERNEL_IDS = {"prep": JT_K_PREP, "ray": JT_K_RAY, "sb": JT_K_SB, "sim": JT_K_SIM, "conv": JT_K_CONV}
+JT_K_PREP, JT_K_RAY, JT_K_SB, JT_K_SIM, JT_K_CONV, JT_K_GRAD = range(6)
+KERNEL_IDS = {"prep": JT_K_PREP, "ray": JT_K_RAY, "sb": JT_K_SB, "sim": JT_K_SIM, "conv": JT_K_CONV,
+              "grad": JT_K_GRAD}
 
 
 class JtError(RuntimeError):
@@ -66,6 +67,12 @@ class JtLight(ctypes.Structure):
     _fields_ = [("n", c_int), ("c", POINTER(JtSersic)), ("bn_exact", c_int)]
 
 
+class JtDraws(ctypes.Structure):
+    _fields_ = [("B", c_int), ("sie", POINTER(JtSie)), ("shear", POINTER(JtShear)), ("n_sub", c_int),
+                ("sub_x", c_void_p), ("sub_y", c_void_p), ("sub_Rs", c_void_p), ("sub_alpha_Rs", c_void_p),
+                ("n_src", c_int), ("n_ll", c_int), ("src", POINTER(JtSersic)), ("ll", POINTER(JtSersic))]
+
+
 # ---------------------------------------------------------------- library
 _LIB = None
 
@@ -89,6 +96,11 @@ _SIGS = {
     "jt_profile_enable": (c_int, [c_void_p, c_int]),
     "jt_profile_read": (c_int, [c_void_p, c_int, POINTER(c_double), POINTER(c_int)]),
     "jt_sersic_bn": (c_double, [c_double, c_int]),
+    "jt_simulate_batch": (c_int, [c_void_p, POINTER(JtGrid), POINTER(JtDraws), c_void_p, c_int, c_void_p, c_void_p]),
+    "jt_chi2": (c_int, [c_void_p, POINTER(JtGrid), POINTER(JtDraws), c_void_p, c_int, c_void_p, c_void_p, c_void_p,
+                        c_void_p]),
+    "jt_chi2_grad": (c_int, [c_void_p, POINTER(JtGrid), POINTER(JtDraws), c_void_p, c_int, c_void_p, c_void_p,
+                             c_void_p, c_void_p, c_void_p, c_void_p]),
 }
 
 
@@ -287,6 +299,93 @@ class Context:
         """simulate_image for a workloads.Scene-like object."""
         return self.simulate_image(scene.grid, scene.lens, scene.source, scene.lens_light,
                                    scene.psf if psf else None, getattr(scene, "bn_exact", False), **kw)
+
+    # ---- batches of parameter draws
+    def _draws(self, batch, keep):
+        """JtDraws from a DrawBatch (macro rows on the host, subhalo SoA on the device)."""
+        mac = np.ascontiguousarray(np.asarray(batch.macro, dtype=np.float64))
+        B, P = mac.shape
+        ns, nl = int(batch.n_src), int(batch.n_ll)
+        if P != 7 + 7 * (ns + nl):
+            raise ValueError("macro rows must hold 7 + 7 (n_src + n_ll) values")
+        sie = (JtSie * B)(*[JtSie(*row[:5]) for row in mac])
+        sh = (JtShear * B)(*[JtShear(*row[5:7]) for row in mac])
+        src = (JtSersic * max(1, B * ns))(*[JtSersic(*row[7 + 7 * k:14 + 7 * k]) for row in mac for k in range(ns)])
+        ll = (JtSersic * max(1, B * nl))(*[JtSersic(*row[7 + 7 * (ns + k):14 + 7 * (ns + k)])
+                                           for row in mac for k in range(nl)])
+        keep.extend([sie, sh, src, ll])
+        D = JtDraws()
+        D.B = B
+        D.sie = ctypes.cast(sie, POINTER(JtSie))
+        D.shear = ctypes.cast(sh, POINTER(JtShear))
+        D.n_src, D.n_ll = ns, nl
+        D.src = ctypes.cast(src, POINTER(JtSersic))
+        D.ll = ctypes.cast(ll, POINTER(JtSersic)) if nl else None
+        n = 0 if batch.sub_x is None else int(batch.sub_x.shape[-1])
+        D.n_sub = n
+        if n:
+            arrs = [_dev_f32(a, self.device, keep) for a in (batch.sub_x, batch.sub_y, batch.sub_Rs, batch.sub_alpha_Rs)]
+            for a in arrs:
+                if tuple(a.shape) != (B, n):
+                    raise ValueError("subhalo arrays must be [B, n_sub]")
+            D.sub_x, D.sub_y, D.sub_Rs, D.sub_alpha_Rs = [c_void_p(a.data_ptr()) for a in arrs]
+        return D, B, n, P
+
+    @staticmethod
+    def _grid(grid):
+        return JtGrid(int(grid.nx), int(grid.ny), int(grid.supersample), float(grid.pixel_scale),
+                      float(grid.x0), float(grid.y0))
+
+    def _psf(self, psf, keep):
+        if psf is None:
+            return c_void_p(), 0
+        pt = _dev_f32(psf, self.device, keep)
+        return c_void_p(pt.data_ptr()), int(pt.shape[0])
+
+    def simulate_batch(self, grid, batch, psf=None, out=None, stream=None):
+        """Forward images of every draw: [B, ny, nx]."""
+        keep = []
+        D, B, _, _ = self._draws(batch, keep)
+        G = self._grid(grid)
+        o = _require_out(out, (B, int(grid.ny), int(grid.nx)), self.device)
+        pp, k = self._psf(psf, keep)
+        _check(self._lib.jt_simulate_batch(self._ptr, byref(G), byref(D), pp, k, c_void_p(o.data_ptr()),
+                                           _stream_handle(stream)))
+        self._retain(keep, stream)
+        return o
+
+    def chi2(self, grid, batch, data, inv_var, psf=None, stream=None):
+        """log L of every draw (float64 [B])."""
+        torch = _torch()
+        keep = []
+        D, B, _, _ = self._draws(batch, keep)
+        G = self._grid(grid)
+        pp, k = self._psf(psf, keep)
+        dt = _dev_f32(data, self.device, keep)
+        wt = _dev_f32(inv_var, self.device, keep)
+        logL = torch.empty(B, dtype=torch.float64, device=self.device)
+        _check(self._lib.jt_chi2(self._ptr, byref(G), byref(D), pp, k, c_void_p(dt.data_ptr()),
+                                 c_void_p(wt.data_ptr()), c_void_p(logL.data_ptr()), _stream_handle(stream)))
+        self._retain(keep, stream)
+        return logL
+
+    def chi2_grad(self, grid, batch, data, inv_var, psf=None, stream=None):
+        """(log L [B] float64, d log L / d macro [B, P], d log L / d (x, y, alpha_Rs) [B, n, 3])."""
+        torch = _torch()
+        keep = []
+        D, B, n, P = self._draws(batch, keep)
+        G = self._grid(grid)
+        pp, k = self._psf(psf, keep)
+        dt = _dev_f32(data, self.device, keep)
+        wt = _dev_f32(inv_var, self.device, keep)
+        logL = torch.empty(B, dtype=torch.float64, device=self.device)
+        gm = torch.empty((B, P), dtype=torch.float32, device=self.device)
+        gs = torch.empty((B, n, 3), dtype=torch.float32, device=self.device)
+        _check(self._lib.jt_chi2_grad(self._ptr, byref(G), byref(D), pp, k, c_void_p(dt.data_ptr()),
+                                      c_void_p(wt.data_ptr()), c_void_p(logL.data_ptr()), c_void_p(gm.data_ptr()),
+                                      c_void_p(gs.data_ptr() if n else None), _stream_handle(stream)))
+        self._retain(keep, stream)
+        return logL, gm, gs
 
     # ---- resident tables
     def upload_subhalos(self, nfw) -> int:

@@ -1,0 +1,439 @@
+// Hand-written adjoint of the chi^2 image log-likelihood (gfx950, FP32).
+//
+//   log L = -1/2 sum_i w_i (m_i - d_i)^2,  m = K * U,  U = pixel-area mean of
+//   the sub-pixel surface brightness I(theta, beta(theta)).
+//
+// Reverse pass, per parameter draw:
+//   r = -w (m - d)                         k_residual (+ log L block partials)
+//   lambda_U = K correlated with r         k_conv_direct<flip>
+//   lambda   = lambda_U * d^2 / s^2 per sub-pixel; beta is recomputed (never
+//   stored by the forward), G = lambda * dI/dbeta; Sersic, SIE and shear
+//   parameter partials are reduced per block          k_grad_pixel
+//   subhalo (x, y, alpha_Rs) gradients: a subhalo-major pass over the
+//   sub-pixel records (theta, G)                      k_grad_subhalo
+//   fixed-order sums of the partials                  k_grad_finalize
+// Every sum has a fixed order (no atomics), so gradients are reproducible.
+#include "jt_device.hpp"
+#include "jt_kernels.hpp"
+#include "jt_sum.hpp"
+
+namespace jt {
+
+static_assert(kQuarters == kQuartersHost, "host and device quarter counts differ");
+
+constexpr float kCapaccioliSlope = 1.9992f;   // d b_n / d n of the Capaccioli fit
+
+// ---------------------------------------------------------------------------
+// Sersic value and its partials.  d[0..6] = dI / d(amp, R, n, q, phi, cx, cy);
+// (gx, gy) = dI / d(x, y) at the evaluation point.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float sersic_grad(const SersicC& c, float x, float y, float d[7], float& gx,
+                                             float& gy) {
+  const float dx = x - c.cx, dy = y - c.cy;
+  const float xp = fmaf(c.cphi, dx, c.sphi * dy);
+  const float yp = fmaf(c.cphi, dy, -c.sphi * dx);
+  const float R2 = fmaf(c.q, xp * xp, c.inv_q * (yp * yp));
+  const float lr = __builtin_amdgcn_logf(R2 * c.inv_r2);          // log2(R^2 / R_s^2)
+  const float t = __builtin_amdgcn_exp2f(c.e * lr);                // (R / R_s)^(1/n)
+  const float E = __builtin_amdgcn_exp2f(fmaf(-c.kb, t, c.kb));    // exp(-b (t - 1))
+  const float I = c.amp * E;
+  const bool pos = R2 > 0.f;
+  const float dIdR2 = pos ? -c.b * I * c.e * t / R2 : 0.f;         // dI/dt * dt/dR^2
+  d[0] = E;
+  d[1] = c.b * I * t / (c.n * c.R);
+  const float tl = pos ? t * lr * kLn2 : 0.f;                       // t ln(R^2/R_s^2)
+  d[2] = -I * (kCapaccioliSlope * (t - 1.0f) - c.b * tl * 0.5f / (c.n * c.n));
+  d[3] = dIdR2 * (xp * xp - yp * yp * c.inv_q * c.inv_q);
+  d[4] = dIdR2 * 2.0f * xp * yp * (c.q - c.inv_q);
+  gx = dIdR2 * 2.0f * (c.q * xp * c.cphi - yp * c.inv_q * c.sphi);
+  gy = dIdR2 * 2.0f * (c.q * xp * c.sphi + yp * c.inv_q * c.cphi);
+  d[5] = -gx;
+  d[6] = -gy;
+  return I;
+}
+
+// T(t) = atan(sqrt t)/sqrt t and dT/dt; Hh(s) = atanh(sqrt s)/sqrt s and
+// dHh/ds.  Series below 0.05 (truncation < 1e-9), closed forms above.
+__device__ __forceinline__ void atan_ratio(float t, float& T, float& dT) {
+  if (t < 0.05f) {
+    T = fmaf(t, fmaf(t, fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.0f / 13, -1.0f / 11), 1.0f / 9), -1.0f / 7), 1.0f / 5),
+                     -1.0f / 3), 1.0f);
+    dT = fmaf(t, fmaf(t, fmaf(t, fmaf(t, fmaf(t, 6.0f / 13, -5.0f / 11), 4.0f / 9), -3.0f / 7), 2.0f / 5),
+              -1.0f / 3);
+  } else {
+    const float r = sqrtf(t);
+    T = atanf(r) / r;
+    dT = (1.0f / (1.0f + t) - T) / (2.0f * t);
+  }
+}
+
+__device__ __forceinline__ void atanh_ratio(float s, float& H, float& dH) {
+  if (s < 0.05f) {
+    H = fmaf(s, fmaf(s, fmaf(s, fmaf(s, fmaf(s, fmaf(s, 1.0f / 13, 1.0f / 11), 1.0f / 9), 1.0f / 7), 1.0f / 5),
+                     1.0f / 3), 1.0f);
+    dH = fmaf(s, fmaf(s, fmaf(s, fmaf(s, fmaf(s, 6.0f / 13, 5.0f / 11), 4.0f / 9), 3.0f / 7), 2.0f / 5),
+              1.0f / 3);
+  } else {
+    const float r = sqrtf(s);
+    H = atanhf(r) / r;
+    dH = (1.0f / (1.0f - s) - H) / (2.0f * s);
+  }
+}
+
+// Contributions -G . d alpha_SIE / d p to d log L / d p for
+// p = (theta_E, q, phi, cx, cy), from the Jacobian of the primed-frame
+// deflection alpha'(u) = theta_E sqrt(q) (x'/psi T(t), y'/psi Hh(s)),
+// t = f^2 x'^2/psi^2, s = f^2 y'^2/psi^2:
+//   d alpha'/d u = theta_E sqrt(q)/(psi r^2) [[y'^2, -x'y'], [-x'y', x'^2]].
+__device__ __forceinline__ void sie_grad(const MacroC& m, float tx, float ty, float Gx, float Gy, float out[5]) {
+  const float dx = tx - m.cx, dy = ty - m.cy;
+  const float xp = fmaf(m.cphi, dx, m.sphi * dy);
+  const float yp = fmaf(m.cphi, dy, -m.sphi * dx);
+  const float psi2 = fmaf(m.q2, xp * xp, yp * yp);
+  const float r2 = fmaf(xp, xp, yp * yp);
+  if (!(psi2 > 0.f)) {
+    for (int i = 0; i < 5; ++i) out[i] = 0.f;
+    return;
+  }
+  const float psi = sqrtf(psi2);
+  const float ipsi = 1.0f / psi;
+  const float f2 = m.f * m.f;
+  const float t = f2 * xp * xp / psi2, s = f2 * yp * yp / psi2;
+  float T, dT, H, dH;
+  atan_ratio(t, T, dT);
+  atanh_ratio(s, H, dH);
+  // primed-frame G
+  const float Gpx = fmaf(m.cphi, Gx, m.sphi * Gy);
+  const float Gpy = fmaf(m.cphi, Gy, -m.sphi * Gx);
+  const float ax1 = m.sqrt_q * xp * ipsi * T;   // alpha'_x / theta_E
+  const float ay1 = m.sqrt_q * yp * ipsi * H;   // alpha'_y / theta_E
+  out[0] = -(Gpx * ax1 + Gpy * ay1);
+  // q
+  const float ipsi3 = ipsi * ipsi * ipsi;
+  const float lead = (psi2 - 2.0f * m.q2 * xp * xp) * ipsi3 * 0.5f / m.sqrt_q;
+  const float dts = -2.0f * m.q * r2 * ipsi3 * ipsi;   // d(t, s)/dq = dts * (x'^2, y'^2)
+  const float dax = m.theta_E * (xp * lead * T + m.sqrt_q * xp * ipsi * dT * dts * xp * xp);
+  const float day = m.theta_E * (yp * lead * H + m.sqrt_q * yp * ipsi * dH * dts * yp * yp);
+  out[1] = -(Gpx * dax + Gpy * day);
+  // phi: d alpha/d phi = R (J alpha' - H' J u), H' J u = theta_E sqrt(q)/psi (-y', x')
+  const float a = m.theta_E * m.sqrt_q * ipsi;
+  const float vx = -m.theta_E * ay1 + a * yp;
+  const float vy = m.theta_E * ax1 - a * xp;
+  out[2] = -(Gpx * vx + Gpy * vy);
+  // centre: d log L/d c = G . H e = G' . H' (R^T e)
+  const float k = m.theta_E * m.sqrt_q * ipsi / (r2 > 0.f ? r2 : 1.0f) * (Gpx * yp - Gpy * xp);
+  out[3] = k * fmaf(yp, m.cphi, xp * m.sphi);
+  out[4] = k * fmaf(yp, m.sphi, -xp * m.cphi);
+}
+
+// ---------------------------------------------------------------------------
+// residual weights and log-likelihood block partials
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_residual(int npix, const float* __restrict__ model,
+                                                 const float* __restrict__ data, const float* __restrict__ w,
+                                                 float* __restrict__ resid, float* __restrict__ part) {
+  __shared__ float red[256];
+  const int b = blockIdx.y;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  float v = 0.f;
+  if (i < npix) {
+    const float diff = model[(size_t)b * npix + i] - data[i];
+    resid[(size_t)b * npix + i] = -w[i] * diff;
+    v = -0.5f * w[i] * diff * diff;
+  }
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(size_t)b * gridDim.x + blockIdx.x] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// per-sub-pixel adjoint
+// ---------------------------------------------------------------------------
+constexpr int kGradMaxP = 7 + 7 * 3;   // SIE 5 + shear 2 + 7 per Sersic component (<= 3)
+
+// Deterministic sum of v over one wave (xor butterfly, fixed pattern).
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int kSplit>
+__global__ __launch_bounds__(256) void k_grad_pixel(const ImageDesc* __restrict__ descs, int bpi,
+                                                   const float* __restrict__ lamU, float4* __restrict__ rec,
+                                                   int rec_stride, float* __restrict__ part, int P) {
+  __shared__ QuarterScratch<kSplit> scratch;
+  __shared__ float wsum[4][kGradMaxP];
+  constexpr int kW = 256 / kSplit;
+  const int di = blockIdx.x / bpi;
+  const int blk = blockIdx.x - di * bpi;
+  const ImageDesc& d = descs[di];
+  const GridC& g = d.g;
+  const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / kW);
+  const int t = threadIdx.x - grp * kW;
+  const int lp = t / g.s2;
+  const int si = t - lp * g.s2;
+  const int npix = g.nx * g.ny;
+  const int p = blk * g.ppb + lp;
+  const bool valid = (lp < g.ppb) && (p < npix);
+  const int pp = valid ? p : 0;
+  const int row = pp / g.nx, col = pp - (pp / g.nx) * g.nx;
+  const int a = si / g.s, b = si - (si / g.s) * g.s;
+  const float tx = (float)(g.ox + g.step * ((double)(col * g.s + b) + 0.5));
+  const float ty = (float)(g.oy + g.step * ((double)(row * g.s + a) + 0.5));
+  subhalo_quarters<kSplit>(tx, ty, d.sub, d.nloop, grp, t, scratch);
+  __syncthreads();
+  float c[kGradMaxP];
+#pragma unroll
+  for (int i = 0; i < kGradMaxP; ++i) c[i] = 0.f;
+  if (grp == 0) {
+    float mx, my, ax, ay;
+    macro_deflection(d.mc, tx, ty, mx, my);
+    combine_deflection(mx, my, &scratch.q[0][t], kW, ax, ay);
+    const float bx = tx - ax, by = ty - ay;
+    const float lam = valid ? lamU[(size_t)di * npix + pp] * g.area_over_s2 : 0.f;
+    float Gx = 0.f, Gy = 0.f, dd[7], gx, gy;
+    const int ns = d.src.n, nl = d.ll.n;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (k < ns) {
+        sersic_grad(d.src.c[k], bx, by, dd, gx, gy);
+#pragma unroll
+        for (int m = 0; m < 7; ++m) c[7 + 7 * k + m] = lam * dd[m];
+        Gx = fmaf(lam, gx, Gx);
+        Gy = fmaf(lam, gy, Gy);
+      } else if (k < ns + nl) {
+        sersic_grad(d.ll.c[k - ns], tx, ty, dd, gx, gy);
+#pragma unroll
+        for (int m = 0; m < 7; ++m) c[7 + 7 * k + m] = lam * dd[m];
+      }
+    }
+    if (d.mc.has_sie) sie_grad(d.mc, tx, ty, Gx, Gy, c);
+    c[5] = -(Gx * tx - Gy * ty);
+    c[6] = -(Gx * ty + Gy * tx);
+    if (valid) rec[(size_t)di * rec_stride + (size_t)pp * g.s2 + si] = make_float4(tx, ty, Gx, Gy);
+  }
+  // padding records past the last sub-pixel: G = 0 and a finite x^2 for any
+  // subhalo, so they contribute exactly zero
+  if (blk == 0 && threadIdx.x < 8) {
+    const int first = npix * g.s2;
+    const int idx = first + threadIdx.x;
+    if (idx < rec_stride) rec[(size_t)di * rec_stride + idx] = make_float4(1e4f, 1e4f, 0.f, 0.f);
+  }
+  const int wave = threadIdx.x >> 6;
+  constexpr int kWaves0 = kW / 64;   // waves of group 0
+#pragma unroll
+  for (int i = 0; i < kGradMaxP; ++i) {
+    if (i < P && wave < kWaves0) {
+      const float s = wave_sum(c[i]);
+      if ((threadIdx.x & 63) == 0) wsum[wave][i] = s;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < P) {
+    float acc = 0.f;
+    for (int w = 0; w < kWaves0; ++w) acc += wsum[w][threadIdx.x];
+    part[((size_t)di * bpi + blk) * P + threadIdx.x] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// subhalo-major pass
+// ---------------------------------------------------------------------------
+// h = g/x^2 and dh/d(x^2) for the NFW term, X2 = x^2.  Far (X2 >= 1.2): the
+// fitted polynomial, F = psi + ln 2, dg/dX2 = (1 - F)/(2 (X2 - 1)).  Near:
+// series in u = X2 - 1 (X2 >= 0.81), the log1p form below, 0 at X2 = 0.
+__device__ __forceinline__ void nfw_h_dh_near(float X2, float& h, float& dh) {
+  if (!(X2 > 0.f)) {
+    h = 0.f;
+    dh = 0.f;
+    return;
+  }
+  const float l2 = __builtin_amdgcn_logf(X2);
+  const float L = fmaf(0.5f * kLn2, l2, -kLn2);
+  const float iX2 = __builtin_amdgcn_rcpf(X2);
+  if (X2 >= 0.81f) {
+    const float u = X2 - 1.0f;
+    float F = 1.0f / 25.0f;   // F = sum_{k=0..12} (-u)^k / (2k+1)
+    F = fmaf(F, -u, 1.0f / 23.0f);
+    F = fmaf(F, -u, 1.0f / 21.0f);
+    F = fmaf(F, -u, 1.0f / 19.0f);
+    F = fmaf(F, -u, 1.0f / 17.0f);
+    F = fmaf(F, -u, 1.0f / 15.0f);
+    F = fmaf(F, -u, 1.0f / 13.0f);
+    F = fmaf(F, -u, 1.0f / 11.0f);
+    F = fmaf(F, -u, 1.0f / 9.0f);
+    F = fmaf(F, -u, 1.0f / 7.0f);
+    F = fmaf(F, -u, 1.0f / 5.0f);
+    F = fmaf(F, -u, 1.0f / 3.0f);
+    F = fmaf(F, -u, 1.0f);
+    // S = (1 - F)/u = sum_{j=0..11} (-1)^j u^j / (2j+3)
+    float S = -1.0f / 25.0f;
+    S = fmaf(S, u, 1.0f / 23.0f);
+    S = fmaf(S, u, -1.0f / 21.0f);
+    S = fmaf(S, u, 1.0f / 19.0f);
+    S = fmaf(S, u, -1.0f / 17.0f);
+    S = fmaf(S, u, 1.0f / 15.0f);
+    S = fmaf(S, u, -1.0f / 13.0f);
+    S = fmaf(S, u, 1.0f / 11.0f);
+    S = fmaf(S, u, -1.0f / 9.0f);
+    S = fmaf(S, u, 1.0f / 7.0f);
+    S = fmaf(S, u, -1.0f / 5.0f);
+    S = fmaf(S, u, 1.0f / 3.0f);
+    h = (L + F) * iX2;
+    dh = (0.5f * S - h) * iX2;
+  } else {
+    const float w = __builtin_amdgcn_sqrtf(1.0f - X2);
+    const float ropw = __builtin_amdgcn_rcpf(1.0f + w);
+    const float tt = -0.5f * X2 * ropw;
+    const float uu = 1.0f + tt;
+    const float lp = (uu == 1.0f) ? tt : kLn2 * __builtin_amdgcn_logf(uu) * tt * __builtin_amdgcn_rcpf(uu - 1.0f);
+    const float iw = __builtin_amdgcn_rcpf(w);
+    const float g = fmaf(-L * X2, ropw, lp) * iw;
+    // F = atanh(w)/w = ln((1+w)^2 / X2) / (2 w)
+    const float F = kLn2 * (2.0f * __builtin_amdgcn_logf(1.0f + w) - l2) * 0.5f * iw;
+    h = g * iX2;
+    dh = ((1.0f - F) * 0.5f / (X2 - 1.0f) - h) * iX2;
+  }
+}
+
+__device__ __forceinline__ void nfw_h_dh(float X2, float& h, float& dh) {
+  const float y = __builtin_amdgcn_rsqf(X2);
+  const float l2 = __builtin_amdgcn_logf(X2);
+  float p = kNfwPsi[0];
+#pragma unroll
+  for (int i = 1; i <= JT_NFW_POLY_DEGREE; ++i) p = fmaf(p, y, kNfwPsi[i]);
+  const float y2 = y * y;
+  h = fmaf(l2, 0.5f * kLn2, p) * y2;
+  const float oneF = (1.0f - kLn2) - p;
+  dh = fmaf(oneF, 0.5f * __builtin_amdgcn_rcpf(X2 - 1.0f), -h) * y2;
+}
+
+// grid (ceil(n / 64), B, kQuarters); lane = subhalo.  Writes the quarter
+// partial (x, y, alpha_Rs) gradients to gpart[q][b][k][3].
+__global__ __launch_bounds__(64) void k_grad_subhalo(const ImageDesc* __restrict__ descs,
+                                                    const float4* __restrict__ rec, int rec_stride,
+                                                    int nrec_loop, int n, float* __restrict__ gpart) {
+  const int b = blockIdx.y, q = blockIdx.z, B = gridDim.y;
+  const int k = blockIdx.x * 64 + threadIdx.x;
+  const bool valid = k < n;
+  const SubRec s = descs[b].sub[valid ? k : 0];
+  const float c2n = sqrtf(s.c1) / (1.0f - kLn2);   // alpha / alpha_Rs = c2n * h * d
+  const float4* __restrict__ r = rec + (size_t)b * rec_stride;
+  const int kb = quarter_bound(nrec_loop, q), ke = quarter_bound(nrec_loop, q + 1);
+  float hx = 0.f, lx = 0.f, hy = 0.f, ly = 0.f, ha = 0.f, la = 0.f;
+  float4 n0 = r[kb], n1 = r[kb + 1], n2 = r[kb + 2], n3 = r[kb + 3];
+  for (int j0 = kb; j0 < ke; j0 += 64) {
+    const int jend = min(j0 + 64, ke);
+    float px = 0.f, py = 0.f, pa = 0.f;
+    for (int j = j0; j < jend; j += 4) {
+      const float4 rr[4] = {n0, n1, n2, n3};
+      n0 = r[j + 4];
+      n1 = r[j + 5];
+      n2 = r[j + 6];
+      n3 = r[j + 7];
+      float dx[4], dy[4], X[4], h[4], dh[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        dx[m] = rr[m].x - s.x;
+        dy[m] = rr[m].y - s.y;
+        X[m] = fmaf(dy[m], dy[m], dx[m] * dx[m]) * s.c1;
+        nfw_h_dh(X[m], h[m], dh[m]);
+      }
+      if (__builtin_expect(fminf(fminf(X[0], X[1]), fminf(X[2], X[3])) < 1.2f, 0)) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+          if (X[m] < 1.2f) nfw_h_dh_near(X[m], h[m], dh[m]);
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const float GD = fmaf(rr[m].z, dx[m], rr[m].w * dy[m]);
+        const float e = 2.0f * s.c1 * dh[m] * GD;
+        px = fmaf(s.c2, fmaf(h[m], rr[m].z, e * dx[m]), px);
+        py = fmaf(s.c2, fmaf(h[m], rr[m].w, e * dy[m]), py);
+        pa = fmaf(-c2n, h[m] * GD, pa);
+      }
+    }
+    two_sum_acc(hx, lx, px);
+    two_sum_acc(hy, ly, py);
+    two_sum_acc(ha, la, pa);
+  }
+  if (valid) {
+    float* o = gpart + (((size_t)q * B + b) * n + k) * 3;
+    o[0] = hx + lx;
+    o[1] = hy + ly;
+    o[2] = ha + la;
+  }
+}
+
+// Fixed-order final sums: macro partials over blocks (TwoSum), log L over
+// residual blocks (FP64), subhalo quarters in order.
+__global__ __launch_bounds__(256) void k_grad_finalize(int B, int P, int bpi, const float* __restrict__ part,
+                                                      float* __restrict__ g_macro, int nres,
+                                                      const float* __restrict__ lpart, double* __restrict__ logL,
+                                                      int n, const float* __restrict__ gpart,
+                                                      float* __restrict__ g_sub) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  const long nm = (long)B * P, nl = B, ns = (long)B * n * 3;
+  if (i < nm) {
+    const int b = (int)(i / P), p = (int)(i - (long)b * P);
+    float hi = 0.f, lo = 0.f;
+    for (int j = 0; j < bpi; ++j) two_sum_acc(hi, lo, part[((size_t)b * bpi + j) * P + p]);
+    g_macro[i] = hi + lo;
+  } else if (i < nm + nl) {
+    const int b = (int)(i - nm);
+    double acc = 0.0;
+    for (int j = 0; j < nres; ++j) acc += (double)lpart[(size_t)b * nres + j];
+    if (logL) logL[b] = acc;
+  } else if (i < nm + nl + ns && g_sub) {
+    const long e = i - nm - nl;
+    float hi = 0.f, lo = 0.f;
+    for (int q = 0; q < kQuarters; ++q) two_sum_acc(hi, lo, gpart[(size_t)q * ns + e]);
+    g_sub[e] = hi + lo;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_residual(int B, int npix, const float* model, const float* data, const float* w, float* resid,
+                           float* part, int* nblocks, hipStream_t st) {
+  const int nb = (npix + 255) / 256;
+  *nblocks = nb;
+  hipLaunchKernelGGL(k_residual, dim3(nb, B), dim3(256), 0, st, npix, model, data, w, resid, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_pixel(int split, int B, int bpi, const ImageDesc* descs, const float* lamU, float4* rec,
+                             int rec_stride, float* part, int P, hipStream_t st) {
+  const dim3 grid((unsigned)((long)B * bpi));
+#define JT_GP(S) hipLaunchKernelGGL((k_grad_pixel<S>), grid, dim3(256), 0, st, descs, bpi, lamU, rec, rec_stride, part, P)
+  if (split == 1) JT_GP(1); else if (split == 2) JT_GP(2); else JT_GP(4);
+#undef JT_GP
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_subhalo(int B, int n, const ImageDesc* descs, const float4* rec, int rec_stride,
+                               int nrec_loop, float* gpart, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_grad_subhalo, dim3((n + 63) / 64, B, kQuarters), dim3(64), 0, st, descs, rec, rec_stride,
+                     nrec_loop, n, gpart);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_finalize(int B, int P, int bpi, const float* part, float* g_macro, int nres,
+                                const float* lpart, double* logL, int n, const float* gpart, float* g_sub,
+                                hipStream_t st) {
+  const long total = (long)B * P + B + (long)B * n * 3;
+  hipLaunchKernelGGL(k_grad_finalize, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, B, P, bpi, part,
+                     g_macro, nres, lpart, logL, n, gpart, g_sub);
+  return hipGetLastError();
+}
+
+int grad_max_params() { return kGradMaxP; }
+
+}  // namespace jt

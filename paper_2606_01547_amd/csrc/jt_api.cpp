@@ -82,6 +82,30 @@ jt_status ctx_workspace(jt_ctx* ctx, hipStream_t stream, size_t bytes, void** ou
   return JT_OK;
 }
 
+jt_status ctx_upload(jt_ctx* ctx, hipStream_t stream, void* dev_dst, const void* host_src, size_t bytes) {
+  if (bytes == 0) return JT_OK;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  Staging& sg = ctx->stage[stream];
+  if (sg.pending) {
+    JT_TRY(check_hip(hipEventSynchronize(sg.done), "staging wait"));
+    sg.pending = false;
+  }
+  if (sg.bytes < bytes) {
+    if (sg.host) JT_TRY(check_hip(hipHostFree(sg.host), "hipHostFree"));
+    sg.host = nullptr;
+    sg.bytes = 0;
+    const size_t cap = std::max<size_t>(bytes, 1 << 16);
+    JT_TRY(check_hip(hipHostMalloc(&sg.host, cap, hipHostMallocDefault), "hipHostMalloc(staging)"));
+    sg.bytes = cap;
+  }
+  if (!sg.done) JT_TRY(check_hip(hipEventCreateWithFlags(&sg.done, hipEventDisableTiming), "hipEventCreate"));
+  std::memcpy(sg.host, host_src, bytes);
+  JT_TRY(check_hip(hipMemcpyAsync(dev_dst, sg.host, bytes, hipMemcpyHostToDevice, stream), "staged upload"));
+  JT_TRY(check_hip(hipEventRecord(sg.done, stream), "staging event"));
+  sg.pending = true;
+  return JT_OK;
+}
+
 hipEvent_t take_event(jt_ctx* ctx) {
   if (!ctx->free_events.empty()) {
     hipEvent_t e = ctx->free_events.back();
@@ -144,6 +168,10 @@ extern "C" void jt_destroy(jt_ctx* ctx) {
       if (kv.second.p) (void)hipFree(kv.second.p);
     for (auto& kv : ctx->handles)
       if (kv.second.dev) (void)hipFree(kv.second.dev);
+    for (auto& kv : ctx->stage) {
+      if (kv.second.host) (void)hipHostFree(kv.second.host);
+      if (kv.second.done) (void)hipEventDestroy(kv.second.done);
+    }
   }
   if (ctx->empty_table) (void)hipFree(ctx->empty_table);
   delete ctx;

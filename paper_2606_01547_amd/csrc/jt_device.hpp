@@ -24,6 +24,7 @@ struct MacroC {
   int has_sie, sie_series, has_shear, npm;
   // SIE: rotate into the major-axis frame about (cx, cy); psi = sqrt(q^2 x'^2 + y'^2)
   float cx, cy, cphi, sphi, q2, pref_f, f, pref;  // pref = theta_E sqrt(q); pref_f = pref / f
+  float theta_E, q, sqrt_q;                       // used by the adjoint
   float g1, g2;                                   // shear
   float pm_x[kMaxPointMass], pm_y[kMaxPointMass], pm_te2[kMaxPointMass];
 };
@@ -35,6 +36,7 @@ struct SersicC {
   float e;               // 1 / (2 n): (R/R_s)^(1/n) = exp2(e * log2(R^2 / R_s^2))
   float kb;              // b_n * log2(e): I = amp * exp2(kb * (1 - t))
   float amp;
+  float R, n, b;         // R_sersic, n, b_n (used by the adjoint)
 };
 
 struct LightC {
@@ -52,11 +54,25 @@ struct GridC {
   float area_over_s2;    // d^2 / s^2
 };
 
+// One image of a batched launch: grid, lens and light constants, its subhalo
+// table and its unconvolved output.  Read from device memory with
+// wave-uniform indices.
+struct ImageDesc;
+
 // Packed subhalo record: centre and the two derived constants of the pair term
 // alpha = c2 * g(x) / x^2 * (dx, dy), x^2 = r^2 c1, c1 = 1/Rs^2,
 // c2 = alpha_Rs / ((1 - ln 2) Rs).
 struct __align__(16) SubRec {
   float x, y, c1, c2;
+};
+
+struct ImageDesc {
+  GridC g;               // g.ppb matches the launch's wave split
+  MacroC mc;
+  LightC src, ll;
+  const SubRec* sub;     // subhalo_table_records(n) records
+  int nloop;             // loop count (multiple of 4)
+  float* img;            // unconvolved image [ny][nx]
 };
 
 // ---------------------------------------------------------------------------

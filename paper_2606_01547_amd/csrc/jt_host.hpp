@@ -28,6 +28,13 @@ struct Resident {
   int n = 0;     // subhalos (kind 1) or PSF side k (kind 2)
 };
 
+struct Staging {
+  void* host = nullptr;       // pinned
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;  // recorded after the last copy out of `host`
+  bool pending = false;
+};
+
 struct EventRec {
   hipEvent_t a, b;
   int id;
@@ -37,6 +44,7 @@ struct jt_ctx {
   int device = 0;
   std::mutex mu;
   std::map<hipStream_t, Buffer> ws;  // per-stream workspace
+  std::map<hipStream_t, Staging> stage;  // per-stream pinned upload buffer
   std::map<uint64_t, Resident> handles;
   uint64_t next_handle = 1;
   jt::SubRec* empty_table = nullptr;  // padding records for lenses without subhalos
@@ -53,6 +61,9 @@ jt_status fail(jt_status st, const char* fmt, ...);
 jt_status check_hip(hipError_t e, const char* what);
 jt_status ctx_enter(jt_ctx* ctx);
 jt_status ctx_workspace(jt_ctx* ctx, hipStream_t stream, size_t bytes, void** out);
+// Asynchronous host -> device copy of `bytes` through the stream's pinned
+// staging buffer (the previous copy out of it is waited for first).
+jt_status ctx_upload(jt_ctx* ctx, hipStream_t stream, void* dev_dst, const void* host_src, size_t bytes);
 jt_status ctx_subhalo_handle(jt_ctx* ctx, uint64_t h, const SubRec** table, int* n);
 const SubRec* ctx_empty_table(jt_ctx* ctx);
 hipEvent_t take_event(jt_ctx* ctx);

@@ -26,6 +26,30 @@ hipError_t launch_simulate(GridC g, const MacroC& mc, const SubRec* sub, int nlo
 // Wave-groups per block for `points` sub-pixels in whole units of `unit`.
 int pick_split(long points, int unit, int nloop);
 size_t conv_direct_lds_bytes(int k);
+// `batch` images at img + z * in_stride -> out + z * out_stride; flip = the
+// adjoint (correlation with the kernel).
+hipError_t launch_conv_direct_batched(bool flip, int batch, const float* img, long in_stride, int nx, int ny,
+                                      const float* psf, int k, float* out, long out_stride, hipStream_t st);
+// Batched fused simulation over image descriptors (see k_simulate_desc).
+hipError_t launch_simulate_desc(int split, const ImageDesc* descs, const int2* tiles, int nblocks,
+                                int blocks_per_image, hipStream_t st);
+// Per-draw subhalo tables from [B][n] SoA into B tables of
+// subhalo_table_records(n) records.
+hipError_t launch_prep_subhalos_batched(int B, int n, const float* x, const float* y, const float* rs,
+                                        const float* ars, SubRec* out, hipStream_t st);
+
+// ---- adjoint (adjoint.hip) ----
+constexpr int kQuartersHost = 4;   // == kQuarters of the canonical summation order
+hipError_t launch_residual(int B, int npix, const float* model, const float* data, const float* w, float* resid,
+                           float* part, int* nblocks, hipStream_t st);
+hipError_t launch_grad_pixel(int split, int B, int bpi, const ImageDesc* descs, const float* lamU, float4* rec,
+                             int rec_stride, float* part, int P, hipStream_t st);
+hipError_t launch_grad_subhalo(int B, int n, const ImageDesc* descs, const float4* rec, int rec_stride,
+                               int nrec_loop, float* gpart, hipStream_t st);
+hipError_t launch_grad_finalize(int B, int P, int bpi, const float* part, float* g_macro, int nres,
+                                const float* lpart, double* logL, int n, const float* gpart, float* g_sub,
+                                hipStream_t st);
+int grad_max_params();
 hipError_t launch_conv_direct(const float* img, int nx, int ny, const float* psf, int k, float* out,
                               hipStream_t st);
 

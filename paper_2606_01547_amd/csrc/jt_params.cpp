@@ -91,6 +91,9 @@ jt_status make_macro(const jt_lens* lens, MacroC& m) {
     m.f = (float)f;
     m.pref = (float)pref;
     m.pref_f = f > 0.0 ? (float)(pref / f) : 0.f;
+    m.theta_E = (float)s.theta_E;
+    m.q = (float)s.q;
+    m.sqrt_q = (float)std::sqrt(s.q);
   }
   if (lens->has_shear) {
     if (!finite(lens->shear.gamma1) || !finite(lens->shear.gamma2))
@@ -183,6 +186,9 @@ jt_status make_light(const jt_light* light, LightC& out, const char* which) {
     o.e = (float)(0.5 / c.n_sersic);
     o.kb = (float)(b / kLn2d);
     o.amp = (float)c.amp;
+    o.R = (float)c.R_sersic;
+    o.n = (float)c.n_sersic;
+    o.b = (float)b;
   }
   out.n = light->n;
   return JT_OK;

@@ -15,10 +15,9 @@
 // reproducible and independent of launch batching.
 #include "jt_device.hpp"
 #include "jt_kernels.hpp"
+#include "jt_sum.hpp"
 
 namespace jt {
-
-constexpr int kSubTile = 64;
 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_prep_subhalos(int n, int padded, const float* __restrict__ x,
@@ -38,83 +37,6 @@ __global__ __launch_bounds__(256) void k_prep_subhalos(int n, int padded, const 
   s.c1 = (float)(1.0 / (r * r));
   s.c2 = (float)((double)ars[i] / ((1.0 - 0.69314718055994530942) * r));
   out[i] = s;
-}
-
-// ---------------------------------------------------------------------------
-// Canonical subhalo summation order.  The nloop records (a multiple of 4) are
-// cut into kQuarters contiguous ranges with boundaries that are multiples of
-// 4; each range is summed in tiles of kSubTile pairs (plain FP32 inside a
-// tile, TwoSum across tiles), and the ranges are combined in index order.  A
-// launch may hand the ranges of one sub-pixel to 1, 2 or 4 waves (kSplit);
-// the arithmetic and its order do not change, so every launch shape gives
-// bitwise the same deflection.
-// ---------------------------------------------------------------------------
-constexpr int kQuarters = 4;
-
-__device__ __forceinline__ int quarter_bound(int nloop, int q) {
-  const int step = ((nloop + 15) / 16) * 4;  // ceil(nloop / 4) rounded up to a multiple of 4
-  return min(q * step, nloop);
-}
-
-// Sum of the pair terms over records [kb, ke) as (hi, lo) per component.  The
-// table holds 4 readable records past every range end (the next range, or
-// the padding at the end), so the next group is always prefetched.
-__device__ __forceinline__ float4 subhalo_range_sum(float tx, float ty, const SubRec* __restrict__ sub,
-                                                    int kb, int ke) {
-  float hx = 0.f, lx = 0.f, hy = 0.f, ly = 0.f;
-  SubRec n0 = sub[kb], n1 = sub[kb + 1], n2 = sub[kb + 2], n3 = sub[kb + 3];
-  for (int k0 = kb; k0 < ke; k0 += kSubTile) {
-    const int kend = min(k0 + kSubTile, ke);
-    float px = 0.f, py = 0.f;
-    for (int k = k0; k < kend; k += 4) {
-      const SubRec s0 = n0, s1 = n1, s2 = n2, s3 = n3;
-      n0 = sub[k + 4];
-      n1 = sub[k + 5];
-      n2 = sub[k + 6];
-      n3 = sub[k + 7];
-      nfw_pairs4(tx, ty, s0, s1, s2, s3, px, py);
-    }
-    two_sum_acc(hx, lx, px);
-    two_sum_acc(hy, ly, py);
-  }
-  return make_float4(hx, lx, hy, ly);
-}
-
-// macro + sum of the quarter partials, in quarter order.
-__device__ __forceinline__ void combine_deflection(float mx, float my, const float4* q, int stride,
-                                                   float& ax, float& ay) {
-  float hx = 0.f, lx = 0.f, hy = 0.f, ly = 0.f;
-#pragma unroll
-  for (int i = 0; i < kQuarters; ++i) {
-    const float4 v = q[i * stride];
-    two_sum_acc(hx, lx, v.x);
-    lx += v.y;
-    two_sum_acc(hy, ly, v.z);
-    ly += v.w;
-  }
-  two_sum_acc(mx, lx, hx);
-  two_sum_acc(my, ly, hy);
-  ax = mx + lx;
-  ay = my + ly;
-}
-
-// Per-block quarter partials: [quarter][slot], slot < 256 / kSplit.
-template <int kSplit>
-struct QuarterScratch {
-  float4 q[kQuarters][256 / kSplit];
-};
-
-// The quarters handled by wave-group g of kSplit, for the sub-pixel (tx, ty),
-// written to scratch.q[*][slot].
-template <int kSplit>
-__device__ __forceinline__ void subhalo_quarters(float tx, float ty, const SubRec* __restrict__ sub, int nloop,
-                                                 int g, int slot, QuarterScratch<kSplit>& scratch) {
-  constexpr int kPer = kQuarters / kSplit;
-#pragma unroll
-  for (int i = 0; i < kPer; ++i) {
-    const int q = g * kPer + i;
-    scratch.q[q][slot] = subhalo_range_sum(tx, ty, sub, quarter_bound(nloop, q), quarter_bound(nloop, q + 1));
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -158,45 +80,58 @@ __global__ __launch_bounds__(256) void k_source_sb(int n, const float* __restric
   sb[i] = v;
 }
 
-// Steps 1-2 and the supersample average, fused.  A block covers g.ppb whole
-// pixels (g.ppb * s^2 <= 256 / kSplit sub-pixel slots); slot t holds sub-pixel
-// (t mod s^2) of local pixel (t / s^2).  The kSplit wave-groups share the
-// subhalo quarters of the same slots; group 0 combines them, evaluates the
-// light, and the pixel values are reduced through LDS in a fixed order.
-template <int kSplit>
-__global__ __launch_bounds__(256) void k_simulate(GridC g, MacroC mc, const SubRec* __restrict__ sub,
-                                                 int nloop, LightC src, LightC ll, float* __restrict__ img) {
-  __shared__ QuarterScratch<kSplit> scratch;
-  __shared__ float red[256];
-  constexpr int kW = 256 / kSplit;
-  const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / kW);  // wave-uniform (kW % 64 == 0)
-  const int t = threadIdx.x - grp * kW;
+// Sub-pixel slot of a simulate block: slot t of wave-group 0..kSplit-1 holds
+// sub-pixel (t mod s^2) of local pixel (t / s^2) of the block's g.ppb pixels.
+struct SubPixel {
+  int pixel;             // global pixel index (0 when invalid)
+  bool valid;
+  float tx, ty;          // correctly rounded FP32 sub-pixel centre
+};
+
+__device__ __forceinline__ SubPixel subpixel_of(const GridC& g, int block, int t) {
+  SubPixel sp;
   const int lp = t / g.s2;
   const int si = t - lp * g.s2;
   const int npix = g.nx * g.ny;
-  const int p = blockIdx.x * g.ppb + lp;
-  const bool valid = (lp < g.ppb) && (p < npix);
-  const int pp = valid ? p : 0;
-  const int row = pp / g.nx;
-  const int col = pp - row * g.nx;
+  const int p = block * g.ppb + lp;
+  sp.valid = (lp < g.ppb) && (p < npix);
+  sp.pixel = sp.valid ? p : 0;
+  const int row = sp.pixel / g.nx;
+  const int col = sp.pixel - row * g.nx;
   const int a = si / g.s;
   const int b = si - a * g.s;
-  const float tx = (float)(g.ox + g.step * ((double)(col * g.s + b) + 0.5));
-  const float ty = (float)(g.oy + g.step * ((double)(row * g.s + a) + 0.5));
-  subhalo_quarters<kSplit>(tx, ty, sub, nloop, grp, t, scratch);
+  sp.tx = (float)(g.ox + g.step * ((double)(col * g.s + b) + 0.5));
+  sp.ty = (float)(g.oy + g.step * ((double)(row * g.s + a) + 0.5));
+  return sp;
+}
+
+// Steps 1-2 and the supersample average for pixel block `block` of one
+// image.  The kSplit wave-groups share the subhalo quarters of the same
+// slots; group 0 combines them, evaluates the light, and the pixel values are
+// reduced through LDS in a fixed order.
+template <int kSplit>
+__device__ __forceinline__ void simulate_block(const GridC& g, const MacroC& mc, const SubRec* __restrict__ sub,
+                                               int nloop, const LightC& src, const LightC& ll,
+                                               float* __restrict__ img, int block,
+                                               QuarterScratch<kSplit>& scratch, float* red) {
+  constexpr int kW = 256 / kSplit;
+  const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / kW);  // wave-uniform (kW % 64 == 0)
+  const int t = threadIdx.x - grp * kW;
+  const SubPixel sp = subpixel_of(g, block, t);
+  subhalo_quarters<kSplit>(sp.tx, sp.ty, sub, nloop, grp, t, scratch);
   __syncthreads();
   if (grp == 0) {
     float mx, my, ax, ay;
-    macro_deflection(mc, tx, ty, mx, my);
+    macro_deflection(mc, sp.tx, sp.ty, mx, my);
     combine_deflection(mx, my, &scratch.q[0][t], kW, ax, ay);
-    float v = sersic_sum(src, tx - ax, ty - ay);
-    if (ll.n > 0) v += sersic_sum(ll, tx, ty);
+    float v = sersic_sum(src, sp.tx - ax, sp.ty - ay);
+    if (ll.n > 0) v += sersic_sum(ll, sp.tx, sp.ty);
     red[t] = v;
   }
   __syncthreads();
   if (threadIdx.x < g.ppb) {
-    const int q = blockIdx.x * g.ppb + threadIdx.x;
-    if (q < npix) {
+    const int q = block * g.ppb + threadIdx.x;
+    if (q < g.nx * g.ny) {
       float acc = 0.f;
       const float* r = red + threadIdx.x * g.s2;
       for (int k = 0; k < g.s2; ++k) acc += r[k];
@@ -205,15 +140,49 @@ __global__ __launch_bounds__(256) void k_simulate(GridC g, MacroC mc, const SubR
   }
 }
 
+template <int kSplit>
+__global__ __launch_bounds__(256) void k_simulate(GridC g, MacroC mc, const SubRec* __restrict__ sub,
+                                                 int nloop, LightC src, LightC ll, float* __restrict__ img) {
+  __shared__ QuarterScratch<kSplit> scratch;
+  __shared__ float red[256];
+  simulate_block<kSplit>(g, mc, sub, nloop, src, ll, img, blockIdx.x, scratch, red);
+}
+
+// Batched images: block b works on image descs[b / blocks_per_image] when
+// every image has the same grid (tiles == nullptr), otherwise on the
+// (image, pixel block) pair tiles[b].
+template <int kSplit>
+__global__ __launch_bounds__(256) void k_simulate_desc(const ImageDesc* __restrict__ descs,
+                                                      const int2* __restrict__ tiles, int blocks_per_image) {
+  __shared__ QuarterScratch<kSplit> scratch;
+  __shared__ float red[256];
+  int di, blk;
+  if (tiles) {
+    const int2 tl = tiles[blockIdx.x];
+    di = tl.x;
+    blk = tl.y;
+  } else {
+    di = blockIdx.x / blocks_per_image;
+    blk = blockIdx.x - di * blocks_per_image;
+  }
+  const ImageDesc& d = descs[di];
+  simulate_block<kSplit>(d.g, d.mc, d.sub, d.nloop, d.src, d.ll, d.img, blk, scratch, red);
+}
+
 // Direct convolution: 32 x 8 outputs per block; the input window of a chunk of
 // up to kConvRows kernel rows is staged in LDS (dynamic size), kernel weights
 // are read with uniform indices (scalar loads).
 constexpr int kConvTX = 32, kConvTY = 8, kConvRows = 32;
 
-__global__ __launch_bounds__(256) void k_conv_direct(const float* __restrict__ img, int nx, int ny,
-                                                    const float* __restrict__ psf, int k,
-                                                    float* __restrict__ out) {
+// kFlip: correlate instead (the kernel read as psf[k-1-a][k-1-b]), which is the
+// adjoint of the convolution.  blockIdx.z selects an image of a batch.
+template <bool kFlip>
+__global__ __launch_bounds__(256) void k_conv_direct(const float* __restrict__ img, long in_stride, int nx, int ny,
+                                                    const float* __restrict__ psf, int k, float* __restrict__ out,
+                                                    long out_stride) {
   extern __shared__ float tile[];
+  img += blockIdx.z * in_stride;
+  out += blockIdx.z * out_stride;
   const int c = (k - 1) / 2;
   const int tx = threadIdx.x % kConvTX, ty = threadIdx.x / kConvTX;
   const int j0 = blockIdx.x * kConvTX, i0 = blockIdx.y * kConvTY;
@@ -232,10 +201,16 @@ __global__ __launch_bounds__(256) void k_conv_direct(const float* __restrict__ i
     }
     __syncthreads();
     for (int da = 0; da < ka; ++da) {
-      const float* __restrict__ w = psf + (a0 + da) * k;
+      const int arow = a0 + da;
       // input row i - a + c  ->  local row ty + (ka - 1 - da)
       const float* trow = tile + (ty + ka - 1 - da) * cols + tx + k - 1;
-      for (int bb = 0; bb < k; ++bb) acc = fmaf(w[bb], trow[-bb], acc);
+      if (kFlip) {
+        const float* __restrict__ w = psf + (k - 1 - arow) * k + (k - 1);
+        for (int bb = 0; bb < k; ++bb) acc = fmaf(w[-bb], trow[-bb], acc);
+      } else {
+        const float* __restrict__ w = psf + arow * k;
+        for (int bb = 0; bb < k; ++bb) acc = fmaf(w[bb], trow[-bb], acc);
+      }
     }
   }
   const int i = i0 + ty, j = j0 + tx;
@@ -310,8 +285,53 @@ size_t conv_direct_lds_bytes(int k) {
 
 hipError_t launch_conv_direct(const float* img, int nx, int ny, const float* psf, int k, float* out,
                               hipStream_t st) {
-  const dim3 grid((nx + kConvTX - 1) / kConvTX, (ny + kConvTY - 1) / kConvTY);
-  hipLaunchKernelGGL(k_conv_direct, grid, dim3(256), conv_direct_lds_bytes(k), st, img, nx, ny, psf, k, out);
+  return launch_conv_direct_batched(false, 1, img, 0, nx, ny, psf, k, out, 0, st);
+}
+
+hipError_t launch_conv_direct_batched(bool flip, int batch, const float* img, long in_stride, int nx, int ny,
+                                      const float* psf, int k, float* out, long out_stride, hipStream_t st) {
+  const dim3 grid((nx + kConvTX - 1) / kConvTX, (ny + kConvTY - 1) / kConvTY, batch);
+  const size_t lds = conv_direct_lds_bytes(k);
+  if (flip)
+    hipLaunchKernelGGL(k_conv_direct<true>, grid, dim3(256), lds, st, img, in_stride, nx, ny, psf, k, out, out_stride);
+  else
+    hipLaunchKernelGGL(k_conv_direct<false>, grid, dim3(256), lds, st, img, in_stride, nx, ny, psf, k, out, out_stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_simulate_desc(int split, const ImageDesc* descs, const int2* tiles, int nblocks,
+                                int blocks_per_image, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+#define JT_SIMD(S) hipLaunchKernelGGL((k_simulate_desc<S>), dim3((unsigned)nblocks), dim3(256), 0, st, descs, tiles, blocks_per_image)
+  if (split == 1) JT_SIMD(1); else if (split == 2) JT_SIMD(2); else JT_SIMD(4);
+#undef JT_SIMD
+  return hipGetLastError();
+}
+
+// grid (ceil(records / 256), B): draw b's SoA [b][n] -> table b of `records`.
+__global__ __launch_bounds__(256) void k_prep_subhalos_batched(int n, int records, const float* __restrict__ x,
+                                                              const float* __restrict__ y,
+                                                              const float* __restrict__ rs,
+                                                              const float* __restrict__ ars,
+                                                              SubRec* __restrict__ out) {
+  const int b = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= records) return;
+  SubRec* o = out + (size_t)b * records;
+  if (i >= n) {
+    o[i] = SubRec{1e18f, 1e18f, 1.0f, 0.0f};
+    return;
+  }
+  const size_t j = (size_t)b * n + i;
+  const double r = rs[j];
+  o[i] = SubRec{x[j], y[j], (float)(1.0 / (r * r)), (float)((double)ars[j] / ((1.0 - 0.69314718055994530942) * r))};
+}
+
+hipError_t launch_prep_subhalos_batched(int B, int n, const float* x, const float* y, const float* rs,
+                                        const float* ars, SubRec* out, hipStream_t st) {
+  const int records = subhalo_table_records(n);
+  hipLaunchKernelGGL(k_prep_subhalos_batched, dim3((records + 255) / 256, B), dim3(256), 0, st, n, records, x, y, rs,
+                     ars, out);
   return hipGetLastError();
 }
 

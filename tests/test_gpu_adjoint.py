@@ -1,0 +1,177 @@
+"""GPU parity of the batched forward, the chi^2 log-likelihood and its
+hand-written adjoint against the FP64 oracle (autograd of the oracle forward).
+
+Gradient bar per parameter group (macro; subhalo x; y; alpha_Rs):
+  max |g_gpu - g_orc| / max(|g_orc|, 1e-3 max_group |g_orc|) <= 1e-3.
+The GPU forward is FP32, so residuals carry ~1e-4 relative error and the
+gradient inherits it; 1e-3 leaves a factor ~10.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from parity import IMAGE_TOL, image_error
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GRAD_TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2606_01547_amd import Context
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.float64)
+
+
+def _batch(scenes):
+    from paper_2606_01547_amd.grad import DrawBatch, macro_row
+    macro = np.stack([macro_row(s.lens, s.source, s.lens_light) for s in scenes])
+    n = scenes[0].lens.nfw.n if scenes[0].lens.nfw is not None else 0
+    if n == 0:
+        return DrawBatch(macro, len(scenes[0].source), len(scenes[0].lens_light))
+    st = lambda a: np.stack([getattr(s.lens.nfw, a) for s in scenes]).astype(np.float32)
+    return DrawBatch(macro, len(scenes[0].source), len(scenes[0].lens_light), st("x"), st("y"), st("Rs"),
+                     st("alpha_Rs"))
+
+
+def _group_err(g, e):
+    g, e = np.asarray(g, np.float64), np.asarray(e, np.float64)
+    den = np.maximum(np.abs(e), 1e-3 * np.abs(e).max())
+    return float(np.max(np.abs(g - e) / den))
+
+
+def _data(truth, seed=0):
+    m = O.simulate_image(truth)
+    d = W.noisy_image(m, seed=seed)
+    w = (1.0 / O.noise_variance(d, 0.01, 1000.0)).astype(np.float32)
+    return d, w
+
+
+def test_batch_forward_equals_single_images(ctx):
+    truth, draws = W.config4_draws(B=5, n_sub=300)
+    out = _np(ctx.simulate_batch(truth.grid, _batch(draws), truth.psf))
+    for b, sc in enumerate(draws):
+        np.testing.assert_array_equal(out[b], _np(ctx.simulate_scene(sc)))
+    assert image_error(out[2], O.simulate_image(draws[2])) <= IMAGE_TOL
+
+
+def test_chi2_matches_oracle(ctx):
+    truth, draws = W.config4_draws(B=4, n_sub=200)
+    d, w = _data(truth)
+    logL = _np(ctx.chi2(truth.grid, _batch(draws), d, w, truth.psf))
+    models = _np(ctx.simulate_batch(truth.grid, _batch(draws), truth.psf))
+    for b, sc in enumerate(draws):
+        own = -0.5 * np.sum(w * (models[b] - d) ** 2)
+        assert logL[b] == pytest.approx(own, rel=1e-5)          # the reduction itself
+        ref = O.log_likelihood(O.simulate_image(sc), d, 0.01, 1000.0)
+        assert logL[b] == pytest.approx(ref, rel=1e-3)           # FP32 model vs FP64 model
+
+
+def _check_grad(ctx, truth, draws, d, w):
+    logL, gm, gs = ctx.chi2_grad(truth.grid, _batch(draws), d, w, truth.psf)
+    gm, gs = _np(gm), _np(gs)
+    for b, sc in enumerate(draws):
+        lo, em, es = O.chi2_gradient(sc, d.astype(np.float64), w.astype(np.float64))
+        assert _group_err(gm[b], em) <= GRAD_TOL, (b, gm[b], em)
+        if es.shape[0]:
+            for col in range(3):
+                assert _group_err(gs[b, :, col], es[:, col]) <= GRAD_TOL, (b, col)
+        assert float(_np(logL)[b]) == pytest.approx(lo, rel=1e-3)
+
+
+def test_chi2_grad_differentiation_case(ctx):
+    """100x100 px, s = 1, 1000 NFW, 21x21 PSF (the benchmark's gradient shape)."""
+    truth, draws = W.config4_draws(B=2)
+    d, w = _data(truth, seed=1)
+    _check_grad(ctx, truth, draws, d, w)
+
+
+def test_chi2_grad_supersampled_with_lens_light(ctx):
+    grid = W.Grid(nx=37, ny=29, pixel_scale=0.09, x0=0.04, y0=-0.03, supersample=2)
+    truth, draws = W.config4_draws(B=3, n_sub=150, grid=grid, lens_light=True, psf_size=7)
+    d, w = _data(truth, seed=2)
+    _check_grad(ctx, truth, draws, d, w)
+
+
+def test_chi2_grad_without_subhalos_or_psf(ctx):
+    grid = W.Grid(nx=31, ny=33, pixel_scale=0.1, supersample=3)
+    truth, draws = W.config4_draws(B=2, n_sub=1, grid=grid)
+    for sc in [truth] + draws:
+        sc.lens.nfw = None
+        sc.psf = None
+    d, w = _data(truth, seed=3)
+    logL, gm, gs = ctx.chi2_grad(truth.grid, _batch(draws), d, w, None)
+    for b, sc in enumerate(draws):
+        _, em, _ = O.chi2_gradient(sc, d.astype(np.float64), w.astype(np.float64))
+        assert _group_err(_np(gm)[b], em) <= GRAD_TOL
+    assert gs.numel() == 0
+
+
+def test_gradient_is_zero_at_the_gpu_model(ctx):
+    truth, draws = W.config4_draws(B=2, n_sub=100)
+    m = ctx.simulate_batch(truth.grid, _batch(draws[:1]), truth.psf)[0]
+    d = m.clone()
+    w = torch.ones_like(m)
+    logL, gm, gs = ctx.chi2_grad(truth.grid, _batch(draws[:1]), d, w, truth.psf)
+    assert _np(logL)[0] == 0.0
+    assert np.all(_np(gm) == 0.0) and np.all(_np(gs) == 0.0)
+
+
+def test_gradient_deterministic_and_batch_independent(ctx):
+    truth, draws = W.config4_draws(B=6, n_sub=400)
+    d, w = _data(truth, seed=4)
+    a = ctx.chi2_grad(truth.grid, _batch(draws), d, w, truth.psf)
+    b = ctx.chi2_grad(truth.grid, _batch(draws), d, w, truth.psf)
+    c = ctx.chi2_grad(truth.grid, _batch(draws[3:4]), d, w, truth.psf)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(_np(x), _np(y))
+    np.testing.assert_array_equal(_np(a[1])[3], _np(c[1])[0])
+    np.testing.assert_array_equal(_np(a[2])[3], _np(c[2])[0])
+
+
+def test_autograd_function_backward_is_the_adjoint(ctx):
+    from paper_2606_01547_amd.grad import chi2_loglike
+    truth, draws = W.config4_draws(B=3, n_sub=120)
+    d, w = _data(truth, seed=5)
+    bt = _batch(draws)
+    macro = torch.tensor(bt.macro, dtype=torch.float64, requires_grad=True)
+    dev = torch.device("cuda", 0)
+    sx = torch.tensor(bt.sub_x, device=dev, requires_grad=True)
+    sy = torch.tensor(bt.sub_y, device=dev, requires_grad=True)
+    sa = torch.tensor(bt.sub_alpha_Rs, device=dev, requires_grad=True)
+    srs = torch.tensor(bt.sub_Rs, device=dev)
+    logL = chi2_loglike(ctx, truth.grid, macro, sx, sy, srs, sa, bt.n_src, bt.n_ll, d, w, truth.psf)
+    scale = torch.tensor([1.0, -2.0, 0.5], dtype=torch.float64, device=logL.device)
+    (logL * scale).sum().backward()
+    _, gm, gs = ctx.chi2_grad(truth.grid, bt, d, w, truth.psf)
+    gm, gs = _np(gm), _np(gs)
+    s = np.array([1.0, -2.0, 0.5])
+    np.testing.assert_allclose(macro.grad.numpy(), gm * s[:, None], rtol=1e-6)
+    np.testing.assert_allclose(_np(sx.grad), gs[..., 0] * s[:, None], rtol=1e-6)
+    np.testing.assert_allclose(_np(sa.grad), gs[..., 2] * s[:, None], rtol=1e-6)
+
+
+def test_gradient_argument_errors(ctx):
+    from paper_2606_01547_amd import JtError
+    from paper_2606_01547_amd._native import JT_EUNSUPPORTED
+    grid = W.Grid(nx=16, ny=16, pixel_scale=0.1)
+    truth, draws = W.config4_draws(B=1, n_sub=10, grid=grid, lens_light=True)
+    for sc in draws:
+        sc.source = sc.source * 3
+    d, w = np.zeros((16, 16), np.float32), np.ones((16, 16), np.float32)
+    with pytest.raises(JtError) as e:
+        ctx.chi2_grad(grid, _batch(draws), d, w, truth.psf)
+    assert e.value.status == JT_EUNSUPPORTED
+    with pytest.raises(JtError):
+        ctx.chi2(grid, _batch(draws), d, w, np.ones((4, 4), np.float32))

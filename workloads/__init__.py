@@ -34,7 +34,7 @@ __all__ = [
     "Grid", "SIE", "Shear", "NFWTable", "PointMasses", "Sersic", "Lens", "Scene",
     "f32", "gaussian_psf", "airy_mix_psf", "nfw_params_from_mass",
     "config1_scene", "config2_scene", "config4_scene", "config5_scene",
-    "config3_requests", "random_points",
+    "config3_requests", "random_points", "noisy_image", "config4_draws",
 ]
 
 
@@ -332,6 +332,52 @@ def config3_requests(n_requests: int = 4096, seed: int = 1003, max_sub: int = 20
         out.append(config2_scene(seed=seed * 100000 + i, n_sub=nsub, npix=npx,
                                  supersample=s, psf_size=k))
     return out
+
+
+def noisy_image(model, sigma_bkg: float = 0.01, t_exp: float = 1000.0, seed: int = 0):
+    """Seeded mock data: Poisson counts of exposure t_exp on max(model, 0),
+    divided by t_exp, plus Gaussian background noise sigma_bkg (FP32)."""
+    rng = np.random.default_rng(seed)
+    m = np.asarray(model, dtype=np.float64)
+    d = rng.poisson(t_exp * np.maximum(m, 0.0)) / t_exp + rng.normal(0.0, sigma_bkg, m.shape)
+    return d.astype(np.float32)
+
+
+def config4_draws(B: int = 256, seed: int = 1004, n_sub: int = 1000, grid: Optional[Grid] = None,
+                  lens_light: bool = False, psf_size: int = 21):
+    """Differentiation case: the truth scene and B parameter draws around it.
+    Macro parameters scale by (1 + 0.01 N(0,1)) (q clipped to (0, 1]);
+    subhalo x, y move by N(0, 0.005"); alpha_Rs scales by (1 + 0.1 N(0,1))
+    (clipped at 0).  Returns (truth, [scene_b])."""
+    import copy
+    truth = config4_scene(seed=seed, n_sub=n_sub)
+    if grid is not None:
+        truth.grid = grid
+    if psf_size != 21:
+        truth.psf = gaussian_psf(psf_size, 0.1 / truth.grid.pixel_scale)
+    if lens_light:
+        truth.lens_light = [_lens_light(_rngs(seed + 7, 1)[0], truth.lens.sie)]
+    rng, = _rngs(seed + 1, 1)
+    out = []
+    for _ in range(B):
+        sc = copy.deepcopy(truth)
+        jit = lambda v: f32(v * (1.0 + 0.01 * rng.standard_normal()))
+        s = sc.lens.sie
+        sc.lens.sie = SIE(jit(s.theta_E), f32(min(1.0, jit(s.q))), jit(s.phi), jit(s.cx), jit(s.cy))
+        sc.lens.shear = Shear(jit(sc.lens.shear.gamma1), jit(sc.lens.shear.gamma2))
+        sc.source = [Sersic(jit(c.amp), jit(c.R_sersic), jit(c.n_sersic), f32(min(1.0, jit(c.q))), jit(c.phi),
+                            jit(c.cx), jit(c.cy)) for c in sc.source]
+        sc.lens_light = [Sersic(jit(c.amp), jit(c.R_sersic), jit(c.n_sersic), f32(min(1.0, jit(c.q))),
+                                jit(c.phi), jit(c.cx), jit(c.cy)) for c in sc.lens_light]
+        n = sc.lens.nfw
+        if n is not None and n.n > 0:
+            sc.lens.nfw = NFWTable(
+                x=(n.x + 0.005 * rng.standard_normal(n.n)).astype(np.float32),
+                y=(n.y + 0.005 * rng.standard_normal(n.n)).astype(np.float32),
+                Rs=n.Rs.copy(),
+                alpha_Rs=np.maximum(n.alpha_Rs * (1.0 + 0.1 * rng.standard_normal(n.n)), 0.0).astype(np.float32))
+        out.append(sc)
+    return truth, out
 
 
 def random_points(n: int, half_width: float, seed: int):
