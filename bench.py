@@ -80,6 +80,136 @@ def cpu_baseline(scene, rows):
             "seconds": round(t2 - t0, 2)}
 
 
+def serving_bench(ctx, n_requests, large_every, seed=1003):
+    """The request stream served by the continuous-batching server: a
+    saturated calibration pass (everything submitted at once), then Poisson
+    arrivals at 0.8x the saturated rate; the same stream through one
+    jt_simulate_image call per request (FIFO, one stream) for comparison."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2606_01547_amd import Server
+    t_gen = time.perf_counter()
+    scenes = W.config3_requests(n_requests, seed=seed)
+    if large_every:
+        for i in range(large_every - 1, n_requests, large_every):
+            scenes[i] = W.config5_scene(seed=1005 + i)
+    handles, outs, pairs = [], [], 0.0
+    for sc in scenes:
+        hs = ctx.upload_subhalos(sc.lens.nfw) if sc.lens.nfw.n > 0 else 0
+        hp = ctx.upload_psf(sc.psf)
+        handles.append((hs, hp))
+        outs.append(torch.empty((sc.grid.ny, sc.grid.nx), dtype=torch.float32, device="cuda"))
+        pairs += sc.grid.nx * sc.grid.ny * sc.grid.supersample ** 2 * sc.lens.nfw.n
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t_gen
+    cfg = dict(hbm_budget_bytes=4 << 30, max_batch_images=64, max_batch_pairs=4e9, max_inflight_batches=4,
+               n_streams=4)
+
+    def run(arrivals):
+        srv = Server(ctx, **cfg)
+        t0 = time.perf_counter()
+        tickets = []
+        for sc, (hs, hp), o, ta in zip(scenes, handles, outs, arrivals):
+            while True:
+                dt = t0 + ta - time.perf_counter()
+                if dt <= 0:
+                    break
+                time.sleep(min(dt, 2e-3))
+            tickets.append(srv.submit(sc.grid, sc.lens, sc.source, sc.lens_light, out=o, subhalo_handle=hs,
+                                      psf_handle=hp))
+        lat = np.array([srv.wait(t) for t in tickets])
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return lat, wall, st
+
+    lat_sat, wall_sat, st_sat = run(np.zeros(n_requests))
+    rate_sat = n_requests / wall_sat
+    lam = 0.8 * rate_sat
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, n_requests))
+    arrivals -= arrivals[0]
+    lat, wall, st = run(arrivals)
+
+    # per-image launches: one jt_simulate_image per request, FIFO, waiting for each
+    pimg = []
+    t0 = time.perf_counter()
+    for sc, o, ta in zip(scenes, outs, arrivals):
+        while True:
+            dt = t0 + ta - time.perf_counter()
+            if dt <= 0:
+                break
+            time.sleep(min(dt, 2e-3))
+        ctx.simulate_scene(sc, out=o)
+        torch.cuda.synchronize()
+        pimg.append(time.perf_counter() - (t0 + ta))
+    wall_pi = time.perf_counter() - t0
+    pimg = np.array(pimg)
+    for hs, hp in handles:
+        for h in (hs, hp):
+            if h:
+                ctx.release(h)
+    pct = lambda a, q: round(1e3 * float(np.percentile(a, q)), 3)
+    return {
+        "workload": (f"{n_requests} seeded requests: grid from {{64,100,200,400}}^2, s from {{1,3}}, "
+                     f"log-uniform 0-20000 NFW, PSF 21 or 41" +
+                     (f"; every {large_every}th a 1000^2, s=5, 50000-NFW, 101^2-PSF image" if large_every else "")),
+        "pairs": pairs, "generation_s": round(gen_s, 2),
+        "saturated": {"images_per_s": round(rate_sat, 2), "p50_ms": pct(lat_sat, 50), "p99_ms": pct(lat_sat, 99),
+                      "batches": int(st_sat["batches"])},
+        "poisson": {"arrival_rate_per_s": round(lam, 2), "images_per_s": round(n_requests / wall, 2),
+                    "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "batches": int(st["batches"]),
+                    "arena_peak_bytes": int(st["arena_peak"])},
+        "per_image_launches": {"images_per_s": round(n_requests / wall_pi, 2), "p50_ms": pct(pimg, 50),
+                               "p99_ms": pct(pimg, 99)},
+        "server_config": cfg,
+    }
+
+
+def adjoint_bench(ctx, draws, reps):
+    """Gradient of the chi^2 log-likelihood for a batch of parameter draws
+    (100x100 px, 1000 NFW, 21x21 PSF) against the forward alone and the plain
+    per-image path."""
+    import numpy as np
+    import torch
+    import oracle as O
+    import workloads as W
+    from paper_2606_01547_amd.grad import DrawBatch, macro_row
+    truth, scenes = W.config4_draws(B=draws)
+    macro = np.stack([macro_row(s.lens, s.source, s.lens_light) for s in scenes])
+    st = lambda a: torch.from_numpy(np.stack([getattr(s.lens.nfw, a) for s in scenes])).cuda()
+    batch = DrawBatch(macro, 1, 0, st("x"), st("y"), st("Rs"), st("alpha_Rs"))
+    m = ctx.simulate_scene(truth)
+    torch.cuda.synchronize()
+    d = W.noisy_image(m.cpu().numpy(), seed=1)
+    w = (1.0 / (0.01 ** 2 + np.maximum(d, 0) / 1000.0)).astype(np.float32)
+    dt, wt, psf = torch.from_numpy(d).cuda(), torch.from_numpy(w).cuda(), torch.from_numpy(truth.psf).cuda()
+
+    def timeit(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_grad = timeit(lambda: ctx.chi2_grad(truth.grid, batch, dt, wt, psf))
+    t_fwd = timeit(lambda: ctx.chi2(truth.grid, batch, dt, wt, psf))
+    out = torch.empty((truth.grid.ny, truth.grid.nx), dtype=torch.float32, device="cuda")
+
+    def per_image():
+        for sc in scenes:
+            ctx.simulate_scene(sc, out=out)
+    t_pi = timeit(per_image)
+    return {"workload": f"{draws} draws of 100x100 px, s=1, SIE + shear + 1000 NFW, 1 source, 21x21 PSF",
+            "gradient_ms_per_batch": round(1e3 * t_grad, 3), "forward_ms_per_batch": round(1e3 * t_fwd, 3),
+            "per_image_forward_ms_per_batch": round(1e3 * t_pi, 3),
+            "gradients_per_s": round(draws / t_grad, 1), "adjoint_over_forward": round(t_grad / t_fwd, 3),
+            "params_per_draw": int(macro.shape[1] + 3 * scenes[0].lens.nfw.n)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +217,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--latency-samples", type=int, default=200)
     ap.add_argument("--cpu-rows", type=int, default=10, help="pixel rows of the oracle sample (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=4096, help="serving stream length (0 = skip)")
+    ap.add_argument("--serve-large-every", type=int, default=512,
+                    help="every n-th request is a large 1000x1000 image (0 = none)")
+    ap.add_argument("--adjoint-draws", type=int, default=256, help="parameter draws per gradient (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (3 times), to calibrate "
                          "the FETCH_SIZE / WRITE_SIZE counters")
@@ -176,6 +310,10 @@ def main():
                        "prep": round(prep_ms / max(prep_n, 1), 4)},
         "roofline": roofline,
     }
+    if args.adjoint_draws > 0:
+        result["adjoint"] = adjoint_bench(ctx, args.adjoint_draws, reps=10)
+    if args.serve_requests > 0:
+        result["serving"] = serving_bench(ctx, args.serve_requests, args.serve_large_every)
     if args.cpu_rows > 0:
         result["cpu_baseline"] = cpu_baseline(scene, args.cpu_rows)
     ctx.close()

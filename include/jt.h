@@ -226,6 +226,72 @@ jt_status jt_psf_pointer(jt_ctx* ctx, uint64_t handle, const float** dev_psf, in
 jt_status jt_release(jt_ctx* ctx, uint64_t handle);
 
 /* ----------------------------------------------------------------------
+ * Serving: continuous batching of heterogeneous simulation requests.
+ * The paper notes that the pipeline's run time varies strongly with the
+ * deflector and light models, the grid and the PSF size (image-simulation
+ * section), and that per-call overhead can dominate simple profiles; the
+ * server therefore packs whatever requests are waiting into one launch of the
+ * fused kernel over a (request, pixel block) tile list, keeps subhalo tables
+ * and PSFs resident, admits requests by device-memory footprint, and keeps
+ * several batches in flight on separate streams.
+ * -------------------------------------------------------------------- */
+typedef struct jt_server jt_server;
+
+typedef struct {
+  size_t hbm_budget_bytes;   /* device arena for in-flight request buffers (> 0) */
+  int max_batch_images;      /* requests per batch (>= 1) */
+  double max_batch_pairs;    /* work cap per batch in (sub-pixel, subhalo) pairs; a
+                                larger request runs in a batch of its own (> 0) */
+  int max_inflight_batches;  /* batches on the device at once (>= 1) */
+  int n_streams;             /* streams the batches rotate over (>= 1) */
+} jt_server_cfg;
+
+/* One image to simulate.  Lens and light parameters are copied at submit;
+ * the resident subhalo table and PSF must outlive the ticket. */
+typedef struct {
+  jt_grid grid;
+  int has_sie, has_shear;
+  jt_sie sie;
+  jt_shear shear;
+  uint64_t subhalo_handle;   /* from jt_upload_subhalos; 0 = no subhalos */
+  jt_light src, lens_light;  /* host arrays, read during jt_server_submit */
+  uint64_t psf_handle;       /* from jt_upload_psf; 0 = no convolution */
+  float* out;                /* device float32 [ny][nx], written when the ticket completes */
+} jt_request;
+
+typedef enum { JT_TICKET_QUEUED = 0, JT_TICKET_RUNNING = 1, JT_TICKET_DONE = 2, JT_TICKET_CANCELLED = 3,
+               JT_TICKET_FAILED = 4 } jt_ticket_state;
+
+typedef struct {
+  uint64_t submitted, completed, cancelled, failed, batches;
+  uint64_t arena_bytes, arena_in_use, arena_peak;
+  double device_seconds;     /* simulated executor: modelled device time */
+} jt_server_stats;
+
+/* Server on the device of ctx; starts its scheduling thread. */
+jt_status jt_server_create(jt_ctx* ctx, const jt_server_cfg* cfg, jt_server** out);
+/* Server with a simulated device (no GPU): a batch "runs" for
+ * (sum of its pairs) / pairs_per_second seconds.  Requests then read
+ * subhalo_handle as the subhalo count and psf_handle as the PSF side; `out` is
+ * never touched.  For tests of the scheduler. */
+jt_status jt_server_create_simulated(const jt_server_cfg* cfg, double pairs_per_second, jt_server** out);
+/* Queue a request: JT_EINVAL (bad request), JT_ENOMEM (can never fit the
+ * arena), JT_OK (*ticket set). */
+jt_status jt_server_submit(jt_server* srv, const jt_request* req, uint64_t* ticket);
+/* Current state (jt_ticket_state) of a ticket. */
+jt_status jt_server_poll(jt_server* srv, uint64_t ticket, int* state);
+/* Wait until the ticket leaves the queue and the device (timeout_s < 0: no
+ * limit).  JT_OK when done (latency_s = completion - submission, may be NULL),
+ * JT_ECANCELLED, JT_EDEVICE (failed), JT_EBUSY (timed out).  Once it has
+ * returned a final state the ticket is forgotten (later calls: JT_EINVAL). */
+jt_status jt_server_wait(jt_server* srv, uint64_t ticket, double timeout_s, double* latency_s);
+/* Cancel a queued ticket (JT_EBUSY once it runs). */
+jt_status jt_server_cancel(jt_server* srv, uint64_t ticket);
+jt_status jt_server_get_stats(jt_server* srv, jt_server_stats* stats);
+/* Stop scheduling, cancel queued tickets, wait for running batches, free. */
+void jt_server_destroy(jt_server* srv);
+
+/* ----------------------------------------------------------------------
  * Kernel timing (HIP events recorded on the launch stream)
  * -------------------------------------------------------------------- */
 typedef enum {

@@ -73,6 +73,26 @@ class JtDraws(ctypes.Structure):
                 ("n_src", c_int), ("n_ll", c_int), ("src", POINTER(JtSersic)), ("ll", POINTER(JtSersic))]
 
 
+class JtServerCfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_batch_images", c_int), ("max_batch_pairs", c_double),
+                ("max_inflight_batches", c_int), ("n_streams", c_int)]
+
+
+class JtRequest(ctypes.Structure):
+    _fields_ = [("grid", JtGrid), ("has_sie", c_int), ("has_shear", c_int), ("sie", JtSie), ("shear", JtShear),
+                ("subhalo_handle", c_uint64), ("src", JtLight), ("lens_light", JtLight), ("psf_handle", c_uint64),
+                ("out", c_void_p)]
+
+
+class JtServerStats(ctypes.Structure):
+    _fields_ = [("submitted", c_uint64), ("completed", c_uint64), ("cancelled", c_uint64), ("failed", c_uint64),
+                ("batches", c_uint64), ("arena_bytes", c_uint64), ("arena_in_use", c_uint64),
+                ("arena_peak", c_uint64), ("device_seconds", c_double)]
+
+
+TICKET_QUEUED, TICKET_RUNNING, TICKET_DONE, TICKET_CANCELLED, TICKET_FAILED = range(5)
+
+
 # ---------------------------------------------------------------- library
 _LIB = None
 
@@ -101,6 +121,14 @@ _SIGS = {
                         c_void_p]),
     "jt_chi2_grad": (c_int, [c_void_p, POINTER(JtGrid), POINTER(JtDraws), c_void_p, c_int, c_void_p, c_void_p,
                              c_void_p, c_void_p, c_void_p, c_void_p]),
+    "jt_server_create": (c_int, [c_void_p, POINTER(JtServerCfg), POINTER(c_void_p)]),
+    "jt_server_create_simulated": (c_int, [POINTER(JtServerCfg), c_double, POINTER(c_void_p)]),
+    "jt_server_submit": (c_int, [c_void_p, POINTER(JtRequest), POINTER(c_uint64)]),
+    "jt_server_poll": (c_int, [c_void_p, c_uint64, POINTER(c_int)]),
+    "jt_server_wait": (c_int, [c_void_p, c_uint64, c_double, POINTER(c_double)]),
+    "jt_server_cancel": (c_int, [c_void_p, c_uint64]),
+    "jt_server_get_stats": (c_int, [c_void_p, POINTER(JtServerStats)]),
+    "jt_server_destroy": (None, [c_void_p]),
 }
 
 
@@ -427,3 +455,83 @@ class Context:
         for t in keep:
             if isinstance(t, torch.Tensor) and t.device.type == "cuda":
                 t.record_stream(s)
+
+
+# ---------------------------------------------------------------- serving
+class Server:
+    """Continuous-batching server (jt_server_*).  `ctx=None` builds the
+    simulated-device server used to test the scheduler without a GPU; its
+    requests carry the subhalo count and PSF side in place of handles."""
+
+    def __init__(self, ctx=None, hbm_budget_bytes=1 << 30, max_batch_images=64, max_batch_pairs=2e9,
+                 max_inflight_batches=4, n_streams=4, simulated_pairs_per_s=None):
+        self._lib = load_library()
+        self.ctx = ctx
+        cfg = JtServerCfg(int(hbm_budget_bytes), int(max_batch_images), float(max_batch_pairs),
+                          int(max_inflight_batches), int(n_streams))
+        self._ptr = c_void_p()
+        if ctx is None:
+            _check(self._lib.jt_server_create_simulated(byref(cfg), float(simulated_pairs_per_s or 1e12),
+                                                        byref(self._ptr)))
+        else:
+            _check(self._lib.jt_server_create(ctx._ptr, byref(cfg), byref(self._ptr)))
+
+    def close(self):
+        if self._ptr:
+            self._lib.jt_server_destroy(self._ptr)
+            self._ptr = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, grid, lens, source, lens_light=(), out=None, subhalo_handle=0, psf_handle=0, bn_exact=False):
+        """Queue one image; returns its ticket.  `out` is a device float32
+        [ny, nx] tensor (any non-null address for the simulated server)."""
+        keep = []
+        R = JtRequest()
+        R.grid = JtGrid(int(grid.nx), int(grid.ny), int(grid.supersample), float(grid.pixel_scale),
+                        float(grid.x0), float(grid.y0))
+        sie = getattr(lens, "sie", None)
+        if sie is not None:
+            R.has_sie = 1
+            R.sie = JtSie(sie.theta_E, sie.q, sie.phi, sie.cx, sie.cy)
+        sh = getattr(lens, "shear", None)
+        if sh is not None:
+            R.has_shear = 1
+            R.shear = JtShear(sh.gamma1, sh.gamma2)
+        R.subhalo_handle = int(subhalo_handle)
+        R.psf_handle = int(psf_handle)
+        R.src = Context._light(source, bn_exact, keep)
+        R.lens_light = Context._light(lens_light, bn_exact, keep)
+        if out is None:
+            R.out = c_void_p(1)
+        elif isinstance(out, int):
+            R.out = c_void_p(out)
+        else:
+            R.out = c_void_p(out.data_ptr())
+        t = c_uint64()
+        _check(self._lib.jt_server_submit(self._ptr, byref(R), byref(t)))
+        return int(t.value)
+
+    def poll(self, ticket):
+        st = c_int()
+        _check(self._lib.jt_server_poll(self._ptr, c_uint64(ticket), byref(st)))
+        return st.value
+
+    def wait(self, ticket, timeout=-1.0):
+        """Seconds from submission to completion; raises JtError when the
+        ticket was cancelled, failed or is still pending at the timeout."""
+        lat = c_double()
+        _check(self._lib.jt_server_wait(self._ptr, c_uint64(ticket), float(timeout), byref(lat)))
+        return lat.value
+
+    def cancel(self, ticket):
+        _check(self._lib.jt_server_cancel(self._ptr, c_uint64(ticket)))
+
+    def stats(self):
+        s = JtServerStats()
+        _check(self._lib.jt_server_get_stats(self._ptr, byref(s)))
+        return {f: getattr(s, f) for f, _ in JtServerStats._fields_}

@@ -75,6 +75,14 @@ struct ImageDesc {
   float* img;            // unconvolved image [ny][nx]
 };
 
+// One convolution of a heterogeneous batch: out = psf * img ([ny][nx], odd k).
+struct ConvDesc {
+  const float* img;
+  float* out;
+  const float* psf;
+  int nx, ny, k, pad;
+};
+
 // ---------------------------------------------------------------------------
 // macro lens
 // ---------------------------------------------------------------------------

@@ -174,18 +174,16 @@ __global__ __launch_bounds__(256) void k_simulate_desc(const ImageDesc* __restri
 // are read with uniform indices (scalar loads).
 constexpr int kConvTX = 32, kConvTY = 8, kConvRows = 32;
 
-// kFlip: correlate instead (the kernel read as psf[k-1-a][k-1-b]), which is the
-// adjoint of the convolution.  blockIdx.z selects an image of a batch.
+// One 32 x 8 output tile: the input window of each chunk of up to kConvRows
+// kernel rows is staged in LDS; kernel weights are read with uniform indices
+// (scalar loads).  kFlip: correlate instead (the kernel read as
+// psf[k-1-a][k-1-b]), which is the adjoint of the convolution.
 template <bool kFlip>
-__global__ __launch_bounds__(256) void k_conv_direct(const float* __restrict__ img, long in_stride, int nx, int ny,
-                                                    const float* __restrict__ psf, int k, float* __restrict__ out,
-                                                    long out_stride) {
-  extern __shared__ float tile[];
-  img += blockIdx.z * in_stride;
-  out += blockIdx.z * out_stride;
+__device__ __forceinline__ void conv_tile(const float* __restrict__ img, int nx, int ny, const float* __restrict__ psf,
+                                          int k, float* __restrict__ out, int tile_x, int tile_y, float* tile) {
   const int c = (k - 1) / 2;
   const int tx = threadIdx.x % kConvTX, ty = threadIdx.x / kConvTX;
-  const int j0 = blockIdx.x * kConvTX, i0 = blockIdx.y * kConvTY;
+  const int j0 = tile_x * kConvTX, i0 = tile_y * kConvTY;
   const int cols = kConvTX + k - 1;
   const int colmin = j0 + c - (k - 1);
   float acc = 0.f;
@@ -215,6 +213,25 @@ __global__ __launch_bounds__(256) void k_conv_direct(const float* __restrict__ i
   }
   const int i = i0 + ty, j = j0 + tx;
   if (i < ny && j < nx) out[i * nx + j] = acc;
+}
+
+// blockIdx.z selects an image of a batch (strided images, one PSF).
+template <bool kFlip>
+__global__ __launch_bounds__(256) void k_conv_direct(const float* __restrict__ img, long in_stride, int nx, int ny,
+                                                    const float* __restrict__ psf, int k, float* __restrict__ out,
+                                                    long out_stride) {
+  extern __shared__ float tile[];
+  conv_tile<kFlip>(img + blockIdx.z * in_stride, nx, ny, psf, k, out + blockIdx.z * out_stride, blockIdx.x,
+                   blockIdx.y, tile);
+}
+
+// Heterogeneous batch: block b convolves tile (tiles[b].y, tiles[b].z) of
+// image descs[tiles[b].x]; the dynamic LDS fits the batch's largest kernel.
+__global__ __launch_bounds__(256) void k_conv_desc(const ConvDesc* __restrict__ descs, const int4* __restrict__ tiles) {
+  extern __shared__ float tile[];
+  const int4 tl = tiles[blockIdx.x];
+  const ConvDesc& d = descs[tl.x];
+  conv_tile<false>(d.img, d.nx, d.ny, d.psf, d.k, d.out, tl.y, tl.z, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -298,6 +315,15 @@ hipError_t launch_conv_direct_batched(bool flip, int batch, const float* img, lo
     hipLaunchKernelGGL(k_conv_direct<false>, grid, dim3(256), lds, st, img, in_stride, nx, ny, psf, k, out, out_stride);
   return hipGetLastError();
 }
+
+hipError_t launch_conv_desc(const ConvDesc* descs, const int4* tiles, int ntiles, int kmax, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_conv_desc, dim3((unsigned)ntiles), dim3(256), conv_direct_lds_bytes(kmax), st, descs, tiles);
+  return hipGetLastError();
+}
+
+int conv_tiles_x(int nx) { return (nx + kConvTX - 1) / kConvTX; }
+int conv_tiles_y(int ny) { return (ny + kConvTY - 1) / kConvTY; }
 
 hipError_t launch_simulate_desc(int split, const ImageDesc* descs, const int2* tiles, int nblocks,
                                 int blocks_per_image, hipStream_t st) {

@@ -1,0 +1,106 @@
+"""The continuous-batching server on the GPU: every request's image is
+bitwise the same as the same request simulated alone (fixed summation order,
+shared convolution code), and matches the oracle; requests of very different
+sizes share launches and streams."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from parity import IMAGE_TOL, image_error
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2606_01547_amd import Context
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.float64)
+
+
+def _requests(n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        npx = int(rng.choice([17, 32, 50, 64, 100]))
+        s = int(rng.choice([1, 3]))
+        nsub = int(rng.choice([0, 5, 300, 2000]))
+        k = int(rng.choice([0, 11, 21]))
+        sc = W.config2_scene(seed=seed * 1000 + i, n_sub=max(nsub, 1), npix=npx, supersample=s,
+                             psf_size=k if k else 11)
+        if nsub == 0:
+            sc.lens.nfw = None
+        if k == 0:
+            sc.psf = None
+        out.append(sc)
+    return out
+
+
+def _serve(ctx, scenes, gaps=None, **cfg):
+    from paper_2606_01547_amd import Server
+    srv = Server(ctx, **cfg)
+    handles, outs, tickets = [], [], []
+    for i, sc in enumerate(scenes):
+        hs = ctx.upload_subhalos(sc.lens.nfw) if sc.lens.nfw is not None else 0
+        hp = ctx.upload_psf(sc.psf) if sc.psf is not None else 0
+        handles += [h for h in (hs, hp) if h]
+        o = torch.full((sc.grid.ny, sc.grid.nx), float("nan"), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        outs.append(o)
+        tickets.append(srv.submit(sc.grid, sc.lens, sc.source, sc.lens_light, out=o, subhalo_handle=hs,
+                                  psf_handle=hp))
+        if gaps is not None:
+            time.sleep(gaps[i])
+    lat = [srv.wait(t, timeout=60.0) for t in tickets]
+    stats = srv.stats()
+    srv.close()
+    for h in handles:
+        ctx.release(h)
+    return outs, lat, stats
+
+
+def test_mixed_stream_equals_single_requests(ctx):
+    scenes = _requests(40, seed=7)
+    gaps = np.random.default_rng(1).exponential(2e-4, len(scenes))
+    outs, lat, st = _serve(ctx, scenes, gaps, hbm_budget_bytes=256 << 20, max_batch_images=16,
+                           max_batch_pairs=5e8, max_inflight_batches=3, n_streams=3)
+    assert st["completed"] == 40 and st["arena_in_use"] == 0 and st["failed"] == 0
+    assert min(lat) > 0
+    for sc, o in zip(scenes, outs):
+        alone = ctx.simulate_scene(sc)
+        np.testing.assert_array_equal(_np(o), _np(alone))
+    for sc, o in list(zip(scenes, outs))[:6]:
+        assert image_error(_np(o), O.simulate_image(sc)) <= IMAGE_TOL
+
+
+def test_large_request_in_the_mix(ctx):
+    big = W.config2_scene()                                  # 200x200, s = 3, 10k NFW, 41x41 PSF
+    small = _requests(12, seed=9)
+    scenes = small[:6] + [big] + small[6:]
+    outs, lat, st = _serve(ctx, scenes, None, hbm_budget_bytes=512 << 20, max_batch_images=8,
+                           max_batch_pairs=2e8, max_inflight_batches=4, n_streams=4)
+    assert st["completed"] == len(scenes)
+    np.testing.assert_array_equal(_np(outs[6]), _np(ctx.simulate_scene(big)))
+    for sc, o in zip(scenes, outs):
+        np.testing.assert_array_equal(_np(o), _np(ctx.simulate_scene(sc)))
+
+
+def test_tight_arena_serialises_but_completes(ctx):
+    scenes = _requests(10, seed=11)
+    outs, lat, st = _serve(ctx, scenes, None, hbm_budget_bytes=1 << 20, max_batch_images=4,
+                           max_batch_pairs=1e12, max_inflight_batches=2, n_streams=2)
+    assert st["completed"] == 10 and st["arena_peak"] <= (1 << 20)
+    for sc, o in zip(scenes, outs):
+        np.testing.assert_array_equal(_np(o), _np(ctx.simulate_scene(sc)))

@@ -1,0 +1,148 @@
+"""The serving scheduler on the simulated device (no GPU): admission by arena
+footprint, FIFO order, work-capped batches, several batches in flight,
+cancellation, invalid and never-fitting requests, concurrent submitters and
+shutdown with work pending."""
+import threading
+import time
+
+import pytest
+
+import workloads as W
+
+
+def _srv(**kw):
+    from paper_2606_01547_amd import Server
+    cfg = dict(hbm_budget_bytes=64 << 20, max_batch_images=16, max_batch_pairs=5e8, max_inflight_batches=2,
+               n_streams=2, simulated_pairs_per_s=1e11)
+    cfg.update(kw)
+    return Server(None, **cfg)
+
+
+def _sc(n=64, s=1):
+    sc = W.config1_scene()
+    sc.grid = W.Grid(nx=n, ny=n, pixel_scale=0.05, supersample=s)
+    return sc
+
+
+def _submit(srv, sc, nsub=100, k=11):
+    return srv.submit(sc.grid, sc.lens, sc.source, sc.lens_light, subhalo_handle=nsub, psf_handle=k)
+
+
+def test_all_requests_complete_in_fifo_order():
+    # ~5 ms per job, so every request is queued before the first completes
+    srv = _srv(max_inflight_batches=1, max_batch_images=1, simulated_pairs_per_s=1e8)
+    sc = _sc()
+    tickets = [_submit(srv, sc) for _ in range(20)]
+    lat = [srv.wait(t) for t in tickets]
+    assert all(b > a for a, b in zip(lat, lat[1:]))   # equal jobs served one at a time, in order
+    st = srv.stats()
+    assert st["completed"] == 20 and st["batches"] == 20 and st["arena_in_use"] == 0
+    srv.close()
+
+
+def test_batches_pack_waiting_requests_up_to_the_caps():
+    srv = _srv(max_batch_images=8, max_inflight_batches=1)
+    sc = _sc()
+    first = _submit(srv, sc, nsub=20000)          # occupies the device
+    rest = [_submit(srv, sc, nsub=10) for _ in range(16)]
+    srv.wait(first)
+    for t in rest:
+        srv.wait(t)
+    st = srv.stats()
+    assert st["completed"] == 17
+    assert st["batches"] <= 4                      # 16 small requests in batches of <= 8
+    srv.close()
+
+
+def test_work_cap_keeps_large_requests_alone():
+    srv = _srv(max_batch_pairs=1e7, max_inflight_batches=1)
+    big = _sc(200, 3)
+    ts = [_submit(srv, big, nsub=2000) for _ in range(3)]
+    for t in ts:
+        srv.wait(t)
+    assert srv.stats()["batches"] == 3
+    srv.close()
+
+
+def test_admission_waits_for_arena_space():
+    sc = _sc(400, 3)
+    from paper_2606_01547_amd import Server
+    one = 4 * 400 * 400 + (400 * 400 // 7) * 8 + 13 * 50 * 16 + 4096
+    srv = Server(None, hbm_budget_bytes=int(1.5 * one), max_batch_images=8, max_batch_pairs=1e15,
+                 max_inflight_batches=4, n_streams=4, simulated_pairs_per_s=1e13)
+    ts = [_submit(srv, sc, nsub=100, k=41) for _ in range(5)]
+    for t in ts:
+        srv.wait(t)
+    st = srv.stats()
+    assert st["batches"] == 5                       # one at a time fits the arena
+    assert st["arena_peak"] <= st["arena_bytes"]
+    srv.close()
+
+
+def test_never_fitting_and_invalid_requests_are_rejected():
+    from paper_2606_01547_amd import JtError
+    from paper_2606_01547_amd._native import JT_EINVAL, JT_ENOMEM
+    srv = _srv(hbm_budget_bytes=1 << 16)
+    with pytest.raises(JtError) as e:
+        _submit(srv, _sc(400, 3), k=41)
+    assert e.value.status == JT_ENOMEM
+    bad = _sc()
+    bad.lens.sie = W.SIE(1.0, 1.5, 0.0, 0.0, 0.0)
+    with pytest.raises(JtError) as e:
+        _submit(srv, bad)
+    assert e.value.status == JT_EINVAL
+    with pytest.raises(JtError) as e:
+        _submit(srv, _sc(), k=4)
+    assert e.value.status == JT_EINVAL
+    with pytest.raises(JtError):
+        srv.wait(12345)
+    srv.close()
+
+
+def test_cancel_queued_ticket():
+    from paper_2606_01547_amd import JtError
+    from paper_2606_01547_amd._native import JT_ECANCELLED, TICKET_QUEUED
+    srv = _srv(max_inflight_batches=1, max_batch_images=1, simulated_pairs_per_s=1e9)
+    sc = _sc(200, 3)
+    a = _submit(srv, sc, nsub=5000)
+    b = _submit(srv, sc, nsub=5000)
+    assert srv.poll(b) == TICKET_QUEUED
+    srv.cancel(b)
+    with pytest.raises(JtError) as e:
+        srv.wait(b)
+    assert e.value.status == JT_ECANCELLED
+    srv.wait(a)
+    assert srv.stats()["cancelled"] == 1
+    srv.close()
+
+
+def test_concurrent_submitters():
+    srv = _srv(max_batch_images=32, max_inflight_batches=3)
+    sc = _sc()
+    out = []
+    lock = threading.Lock()
+
+    def worker():
+        mine = [_submit(srv, sc, nsub=50) for _ in range(25)]
+        for t in mine:
+            srv.wait(t)
+        with lock:
+            out.extend(mine)
+
+    th = [threading.Thread(target=worker) for _ in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert len(set(out)) == 100 and srv.stats()["completed"] == 100
+    srv.close()
+
+
+def test_destroy_with_pending_work_cancels_the_queue():
+    srv = _srv(max_inflight_batches=1, max_batch_images=1, simulated_pairs_per_s=1e9)
+    sc = _sc(200, 3)
+    for _ in range(10):
+        _submit(srv, sc, nsub=2000)
+    t0 = time.time()
+    srv.close()
+    assert time.time() - t0 < 5.0
