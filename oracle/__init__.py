@@ -21,7 +21,7 @@ from .grid import subpixel_coords, supersample_reduce
 from .lens import (sie_deflection, sie_kappa, shear_deflection, nfw_g, nfw_deflection,
                    nfw_kappa, point_mass_deflection, total_deflection, ray_shoot)
 from .light import sersic_bn, sersic, surface_brightness
-from .conv import convolve_same
+from .conv import convolve_at, convolve_same
 from .simulate import simulate_image, simulate_unconvolved
 from .likelihood import log_likelihood, noise_variance
 from .grad import chi2_gradient, macro_vector, macro_names
@@ -33,6 +33,6 @@ __all__ = [
     "subpixel_coords", "supersample_reduce", "sie_deflection", "sie_kappa",
     "shear_deflection", "nfw_g", "nfw_deflection", "nfw_kappa", "point_mass_deflection",
     "total_deflection", "ray_shoot", "sersic_bn", "sersic", "surface_brightness",
-    "convolve_same", "simulate_image", "simulate_unconvolved", "log_likelihood",
+    "convolve_at", "convolve_same", "simulate_image", "simulate_unconvolved", "log_likelihood",
     "noise_variance", "chi2_gradient", "macro_vector", "macro_names", "PARITY_UNPINNED",
 ]

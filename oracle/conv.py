@@ -31,3 +31,25 @@ def convolve_same(img, K):
             if w != 0.0:
                 out += w * pad[2 * c - a:2 * c - a + ny, 2 * c - b:2 * c - b + nx]
     return out
+
+
+def convolve_at(img, K, rows, cols):
+    """The same convolution evaluated only at the pixels (rows[t], cols[t]),
+    each as its own sum over the kernel taps that land inside the image; for
+    checking very large images on a sample of outputs."""
+    img = np.asarray(img, dtype=np.float64)
+    K = np.asarray(K, dtype=np.float64)
+    k = K.shape[0]
+    c = (k - 1) // 2
+    ny, nx = img.shape
+    out = np.empty(len(rows), dtype=np.float64)
+    for t, (i, j) in enumerate(zip(rows, cols)):
+        a0, a1 = max(0, i + c - (ny - 1)), min(k - 1, i + c)
+        b0, b1 = max(0, j + c - (nx - 1)), min(k - 1, j + c)
+        acc = 0.0
+        for a in range(a0, a1 + 1):
+            # taps K[a, b0..b1] meet img[i - a + c, j - b + c] for b = b0..b1
+            seg = img[i - a + c, j - b1 + c:j - b0 + c + 1][::-1]
+            acc += float(np.dot(K[a, b0:b1 + 1], seg))
+        out[t] = acc
+    return out

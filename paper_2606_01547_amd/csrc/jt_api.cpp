@@ -63,9 +63,19 @@ jt_status ctx_enter(jt_ctx* ctx) {
 
 // Workspace of at least `bytes` for `stream`; grows (after synchronising the
 // stream) when too small.
+static jt_status grow_buffer(Buffer& b, hipStream_t stream, size_t bytes, void** out);
+
 jt_status ctx_workspace(jt_ctx* ctx, hipStream_t stream, size_t bytes, void** out) {
   std::lock_guard<std::mutex> lk(ctx->mu);
-  Buffer& b = ctx->ws[stream];
+  return grow_buffer(ctx->ws[stream], stream, bytes, out);
+}
+
+jt_status ctx_workspace_aux(jt_ctx* ctx, hipStream_t stream, size_t bytes, void** out) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  return grow_buffer(ctx->ws_aux[stream], stream, bytes, out);
+}
+
+static jt_status grow_buffer(Buffer& b, hipStream_t stream, size_t bytes, void** out) {
   if (b.bytes < bytes) {
     if (b.p) {
       JT_TRY(check_hip(hipStreamSynchronize(stream), "workspace sync"));
@@ -103,6 +113,30 @@ jt_status ctx_upload(jt_ctx* ctx, hipStream_t stream, void* dev_dst, const void*
   JT_TRY(check_hip(hipMemcpyAsync(dev_dst, sg.host, bytes, hipMemcpyHostToDevice, stream), "staged upload"));
   JT_TRY(check_hip(hipEventRecord(sg.done, stream), "staging event"));
   sg.pending = true;
+  return JT_OK;
+}
+
+jt_status ctx_twiddles(jt_ctx* ctx, int N, const double2** out) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = ctx->twiddles.find(N);
+  if (it == ctx->twiddles.end()) {
+    std::vector<double2> tw(N / 2);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int t = 0; t < N / 2; ++t) {
+      const double a = two_pi * (double)t / (double)N;
+      tw[t] = make_double2(std::cos(a), -std::sin(a));
+    }
+    void* dev = nullptr;
+    JT_TRY(check_hip(hipMalloc(&dev, sizeof(double2) * tw.size()), "hipMalloc(twiddles)"));
+    jt_status st = check_hip(hipMemcpy(dev, tw.data(), sizeof(double2) * tw.size(), hipMemcpyHostToDevice),
+                             "hipMemcpy(twiddles)");
+    if (st != JT_OK) {
+      (void)hipFree(dev);
+      return st;
+    }
+    it = ctx->twiddles.emplace(N, dev).first;
+  }
+  *out = (const double2*)it->second;
   return JT_OK;
 }
 
@@ -166,8 +200,11 @@ extern "C" void jt_destroy(jt_ctx* ctx) {
     for (auto e : ctx->free_events) (void)hipEventDestroy(e);
     for (auto& kv : ctx->ws)
       if (kv.second.p) (void)hipFree(kv.second.p);
+    for (auto& kv : ctx->ws_aux)
+      if (kv.second.p) (void)hipFree(kv.second.p);
     for (auto& kv : ctx->handles)
       if (kv.second.dev) (void)hipFree(kv.second.dev);
+    for (auto& kv : ctx->twiddles) (void)hipFree(kv.second);
     for (auto& kv : ctx->stage) {
       if (kv.second.host) (void)hipHostFree(kv.second.host);
       if (kv.second.done) (void)hipEventDestroy(kv.second.done);

@@ -43,8 +43,10 @@ struct EventRec {
 struct jt_ctx {
   int device = 0;
   std::mutex mu;
-  std::map<hipStream_t, Buffer> ws;  // per-stream workspace
+  std::map<hipStream_t, Buffer> ws;      // per-stream workspace
+  std::map<hipStream_t, Buffer> ws_aux;  // per-stream second workspace (FFT buffers)
   std::map<hipStream_t, Staging> stage;  // per-stream pinned upload buffer
+  std::map<int, void*> twiddles;         // FFT length -> device exp(-2 pi i t / N), t < N/2
   std::map<uint64_t, Resident> handles;
   uint64_t next_handle = 1;
   jt::SubRec* empty_table = nullptr;  // padding records for lenses without subhalos
@@ -61,9 +63,14 @@ jt_status fail(jt_status st, const char* fmt, ...);
 jt_status check_hip(hipError_t e, const char* what);
 jt_status ctx_enter(jt_ctx* ctx);
 jt_status ctx_workspace(jt_ctx* ctx, hipStream_t stream, size_t bytes, void** out);
+// A second per-stream workspace, independent of the first (a call can hold
+// both: e.g. the unconvolved image in one and FFT buffers in the other).
+jt_status ctx_workspace_aux(jt_ctx* ctx, hipStream_t stream, size_t bytes, void** out);
 // Asynchronous host -> device copy of `bytes` through the stream's pinned
 // staging buffer (the previous copy out of it is waited for first).
 jt_status ctx_upload(jt_ctx* ctx, hipStream_t stream, void* dev_dst, const void* host_src, size_t bytes);
+// Device twiddle table of an FFT length (built on first use, kept by ctx).
+jt_status ctx_twiddles(jt_ctx* ctx, int N, const double2** out);
 jt_status ctx_subhalo_handle(jt_ctx* ctx, uint64_t h, const SubRec** table, int* n);
 const SubRec* ctx_empty_table(jt_ctx* ctx);
 hipEvent_t take_event(jt_ctx* ctx);

@@ -43,6 +43,22 @@ hipError_t launch_simulate_desc(int split, const ImageDesc* descs, const int2* t
 hipError_t launch_prep_subhalos_batched(int B, int n, const float* x, const float* y, const float* rs,
                                         const float* ars, SubRec* out, hipStream_t st);
 
+// ---- FFT convolution (fft.hip) ----
+// Cost model of the direct/FFT choice (method 0): direct FMAs per second,
+// padded FFT points per second and a fixed launch cost of the FFT pipeline.
+constexpr double kConvDirectFmaPerS = 3.0e13;
+constexpr double kConvFftPointsPerS = 2.0e10;
+constexpr double kConvFftFixedS = 30e-6;
+bool conv_prefers_fft(int nx, int ny, int k);
+constexpr int kFftMinN = 16, kFftMaxN = 2048;
+// Padded power-of-two length for an image side n and kernel side k.
+int fft_size_for(int n, int k);
+size_t fft_workspace_bytes(int nx, int ny, int k);
+// tw_x, tw_y: tables exp(-2 pi i t / N), t < N/2, for N = fft_size_for(nx, k)
+// and fft_size_for(ny, k); ws: fft_workspace_bytes.
+hipError_t launch_fft_convolve(const float* img, int nx, int ny, const float* psf, int k, float* out, void* ws,
+                               const double2* tw_x, const double2* tw_y, hipStream_t st);
+
 // ---- adjoint (adjoint.hip) ----
 constexpr int kQuartersHost = 4;   // == kQuarters of the canonical summation order
 hipError_t launch_residual(int B, int npix, const float* model, const float* data, const float* w, float* resid,

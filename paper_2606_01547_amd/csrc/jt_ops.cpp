@@ -41,13 +41,44 @@ jt_status check_conv_args(const float* img, int nx, int ny, const float* psf, in
   return JT_OK;
 }
 
+}  // namespace
+
+namespace jt {
+// Direct or FFT for method 0: the FFT path once its modelled time is lower
+// (direct: n_x n_y k^2 FMAs; FFT: ~8 padded transforms' worth of passes over
+// Nx Ny complex values), or when the direct path cannot take k.
+bool conv_prefers_fft(int nx, int ny, int k) {
+  const bool fft_ok = fft_size_for(nx, k) <= kFftMaxN && fft_size_for(ny, k) <= kFftMaxN;
+  if (!fft_ok) return false;
+  if (k > JT_MAX_PSF) return true;
+  const double direct_s = (double)nx * ny * k * (double)k / kConvDirectFmaPerS;
+  const double N2 = (double)fft_size_for(nx, k) * fft_size_for(ny, k);
+  const double fft_s = kConvFftFixedS + N2 / kConvFftPointsPerS;
+  return fft_s < direct_s;
+}
+}  // namespace jt
+
+namespace {
+
 jt_status convolve_on(jt_ctx* ctx, const float* img, int nx, int ny, const float* psf, int k, int method,
                       float* out, hipStream_t st) {
-  if (method == 2) return fail(JT_EUNSUPPORTED, "convolve: FFT method not available in this build");
-  if (method != 0 && method != 1) return fail(JT_EINVAL, "convolve: method %d", method);
-  if (k > JT_MAX_PSF) return fail(JT_EUNSUPPORTED, "convolve: direct path supports k <= %d", JT_MAX_PSF);
+  if (method < 0 || method > 2) return fail(JT_EINVAL, "convolve: method %d", method);
+  if (method == 0) method = conv_prefers_fft(nx, ny, k) ? 2 : 1;
+  if (method == 1) {
+    if (k > JT_MAX_PSF) return fail(JT_EUNSUPPORTED, "convolve: direct path supports k <= %d", JT_MAX_PSF);
+    return timed_launch(ctx, JT_K_CONV, st,
+                        [&] { return launch_conv_direct(img, nx, ny, psf, k, out, st); }, "conv_direct");
+  }
+  const int Nx = fft_size_for(nx, k), Ny = fft_size_for(ny, k);
+  if (Nx > kFftMaxN || Ny > kFftMaxN)
+    return fail(JT_EUNSUPPORTED, "convolve: FFT path supports padded sizes up to %d", kFftMaxN);
+  const double2 *twx = nullptr, *twy = nullptr;
+  JT_TRY(ctx_twiddles(ctx, Nx, &twx));
+  JT_TRY(ctx_twiddles(ctx, Ny, &twy));
+  void* ws = nullptr;
+  JT_TRY(ctx_workspace_aux(ctx, st, fft_workspace_bytes(nx, ny, k), &ws));
   return timed_launch(ctx, JT_K_CONV, st,
-                      [&] { return launch_conv_direct(img, nx, ny, psf, k, out, st); }, "conv_direct");
+                      [&] { return launch_fft_convolve(img, nx, ny, psf, k, out, ws, twx, twy, st); }, "conv_fft");
 }
 
 }  // namespace

@@ -172,23 +172,46 @@ __global__ __launch_bounds__(256) void k_simulate_desc(const ImageDesc* __restri
 // Direct convolution: 32 x 8 outputs per block; the input window of a chunk of
 // up to kConvRows kernel rows is staged in LDS (dynamic size), kernel weights
 // are read with uniform indices (scalar loads).
-constexpr int kConvTX = 32, kConvTY = 8, kConvRows = 32;
+// Direct convolution tiles: 64 x 4 outputs per 256-thread block.  Thread
+// (q, r, w) computes the four outputs (i0 + r, j0 + 4q .. 4q + 3) over the
+// kernel rows a = w, w + 4, ... of each staged chunk: wave w owns a quarter of
+// the kernel rows, so the weights it reads are wave-uniform (scalar loads), and
+// a sliding window of four input values in registers feeds four FMAs per LDS
+// read.  The four per-wave partials are added in wave order at the end.
+constexpr int kConvTX = 64, kConvTY = 4, kConvQ = 4, kConvW = 4;
+constexpr size_t kConvLdsCap = 48 * 1024;
 
-// One 32 x 8 output tile: the input window of each chunk of up to kConvRows
-// kernel rows is staged in LDS; kernel weights are read with uniform indices
-// (scalar loads).  kFlip: correlate instead (the kernel read as
-// psf[k-1-a][k-1-b]), which is the adjoint of the convolution.
+// Kernel rows staged per chunk so that the input window fits kConvLdsCap.
+int conv_rows_per_chunk(int k) {
+  const long cols = kConvTX + k - 1;
+  long rb = (long)(kConvLdsCap / (sizeof(float) * cols)) - (kConvTY - 1);
+  if (rb > k) rb = k;
+  if (rb < 1) rb = 1;
+  return (int)rb;
+}
+
+size_t conv_direct_lds_bytes(int k) {
+  return sizeof(float) * (size_t)(kConvTY + conv_rows_per_chunk(k) - 1) * (size_t)(kConvTX + k - 1);
+}
+
+// kFlip: correlate instead (the kernel read as psf[k-1-a][k-1-b]), which is the
+// adjoint of the convolution.  rb: kernel rows per staged chunk (the launch's
+// LDS holds (kConvTY + rb - 1) x (kConvTX + k - 1) floats).
 template <bool kFlip>
 __device__ __forceinline__ void conv_tile(const float* __restrict__ img, int nx, int ny, const float* __restrict__ psf,
-                                          int k, float* __restrict__ out, int tile_x, int tile_y, float* tile) {
+                                          int k, int rb, float* __restrict__ out, int tile_x, int tile_y, float* tile) {
+  __shared__ float part[kConvW][kConvTY][kConvTX];
+  const int q = threadIdx.x % (kConvTX / kConvQ);
+  const int r = (threadIdx.x / (kConvTX / kConvQ)) % kConvTY;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);  // wave index, uniform
   const int c = (k - 1) / 2;
-  const int tx = threadIdx.x % kConvTX, ty = threadIdx.x / kConvTX;
   const int j0 = tile_x * kConvTX, i0 = tile_y * kConvTY;
   const int cols = kConvTX + k - 1;
   const int colmin = j0 + c - (k - 1);
-  float acc = 0.f;
-  for (int a0 = 0; a0 < k; a0 += kConvRows) {
-    const int ka = min(kConvRows, k - a0);
+  const int base = kConvQ * q;
+  float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
+  for (int a0 = 0; a0 < k; a0 += rb) {
+    const int ka = min(rb, k - a0);
     const int rows = kConvTY + ka - 1;
     const int rowmin = i0 + c - (a0 + ka - 1);
     __syncthreads();
@@ -198,40 +221,57 @@ __device__ __forceinline__ void conv_tile(const float* __restrict__ img, int nx,
       tile[e] = (gi >= 0 && gi < ny && gj >= 0 && gj < nx) ? img[gi * nx + gj] : 0.f;
     }
     __syncthreads();
-    for (int da = 0; da < ka; ++da) {
+    for (int da = w; da < ka; da += kConvW) {
       const int arow = a0 + da;
-      // input row i - a + c  ->  local row ty + (ka - 1 - da)
-      const float* trow = tile + (ty + ka - 1 - da) * cols + tx + k - 1;
-      if (kFlip) {
-        const float* __restrict__ w = psf + (k - 1 - arow) * k + (k - 1);
-        for (int bb = 0; bb < k; ++bb) acc = fmaf(w[-bb], trow[-bb], acc);
-      } else {
-        const float* __restrict__ w = psf + arow * k;
-        for (int bb = 0; bb < k; ++bb) acc = fmaf(w[bb], trow[-bb], acc);
+      // input row i - a + c  ->  local row r + (ka - 1 - da); output 4q + t at
+      // kernel column b reads local column 4q + t + (k - 1 - b)
+      const float* trow = tile + (r + ka - 1 - da) * cols + base;
+      const float* __restrict__ wrow = kFlip ? psf + (k - 1 - arow) * k : psf + arow * k;
+      float x0 = trow[0], x1 = trow[1], x2 = trow[2];
+#pragma unroll 4
+      for (int m = 0; m < k; ++m) {
+        const float x3 = trow[m + 3];
+        const float wv = kFlip ? wrow[m] : wrow[k - 1 - m];
+        acc0 = fmaf(wv, x0, acc0);
+        acc1 = fmaf(wv, x1, acc1);
+        acc2 = fmaf(wv, x2, acc2);
+        acc3 = fmaf(wv, x3, acc3);
+        x0 = x1;
+        x1 = x2;
+        x2 = x3;
       }
     }
   }
-  const int i = i0 + ty, j = j0 + tx;
-  if (i < ny && j < nx) out[i * nx + j] = acc;
+  part[w][r][base] = acc0;
+  part[w][r][base + 1] = acc1;
+  part[w][r][base + 2] = acc2;
+  part[w][r][base + 3] = acc3;
+  __syncthreads();
+  // threadIdx < 256 covers the 64 x 4 outputs once
+  const int oc = threadIdx.x % kConvTX, orow = threadIdx.x / kConvTX;
+  const float v = ((part[0][orow][oc] + part[1][orow][oc]) + part[2][orow][oc]) + part[3][orow][oc];
+  const int i = i0 + orow, j = j0 + oc;
+  if (i < ny && j < nx) out[i * nx + j] = v;
 }
 
 // blockIdx.z selects an image of a batch (strided images, one PSF).
 template <bool kFlip>
 __global__ __launch_bounds__(256) void k_conv_direct(const float* __restrict__ img, long in_stride, int nx, int ny,
-                                                    const float* __restrict__ psf, int k, float* __restrict__ out,
+                                                    const float* __restrict__ psf, int k, int rb, float* __restrict__ out,
                                                     long out_stride) {
   extern __shared__ float tile[];
-  conv_tile<kFlip>(img + blockIdx.z * in_stride, nx, ny, psf, k, out + blockIdx.z * out_stride, blockIdx.x,
+  conv_tile<kFlip>(img + blockIdx.z * in_stride, nx, ny, psf, k, rb, out + blockIdx.z * out_stride, blockIdx.x,
                    blockIdx.y, tile);
 }
 
 // Heterogeneous batch: block b convolves tile (tiles[b].y, tiles[b].z) of
 // image descs[tiles[b].x]; the dynamic LDS fits the batch's largest kernel.
-__global__ __launch_bounds__(256) void k_conv_desc(const ConvDesc* __restrict__ descs, const int4* __restrict__ tiles) {
+__global__ __launch_bounds__(256) void k_conv_desc(const ConvDesc* __restrict__ descs, const int4* __restrict__ tiles,
+                                                  int rb) {
   extern __shared__ float tile[];
   const int4 tl = tiles[blockIdx.x];
   const ConvDesc& d = descs[tl.x];
-  conv_tile<false>(d.img, d.nx, d.ny, d.psf, d.k, d.out, tl.y, tl.z, tile);
+  conv_tile<false>(d.img, d.nx, d.ny, d.psf, d.k, min(rb, d.k), d.out, tl.y, tl.z, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -295,10 +335,6 @@ hipError_t launch_simulate(GridC g, const MacroC& mc, const SubRec* sub, int nlo
   return hipGetLastError();
 }
 
-size_t conv_direct_lds_bytes(int k) {
-  const int ka = k < kConvRows ? k : kConvRows;
-  return sizeof(float) * (size_t)(kConvTY + ka - 1) * (size_t)(kConvTX + k - 1);
-}
 
 hipError_t launch_conv_direct(const float* img, int nx, int ny, const float* psf, int k, float* out,
                               hipStream_t st) {
@@ -309,16 +345,18 @@ hipError_t launch_conv_direct_batched(bool flip, int batch, const float* img, lo
                                       const float* psf, int k, float* out, long out_stride, hipStream_t st) {
   const dim3 grid((nx + kConvTX - 1) / kConvTX, (ny + kConvTY - 1) / kConvTY, batch);
   const size_t lds = conv_direct_lds_bytes(k);
+  const int rb = conv_rows_per_chunk(k);
   if (flip)
-    hipLaunchKernelGGL(k_conv_direct<true>, grid, dim3(256), lds, st, img, in_stride, nx, ny, psf, k, out, out_stride);
+    hipLaunchKernelGGL(k_conv_direct<true>, grid, dim3(256), lds, st, img, in_stride, nx, ny, psf, k, rb, out, out_stride);
   else
-    hipLaunchKernelGGL(k_conv_direct<false>, grid, dim3(256), lds, st, img, in_stride, nx, ny, psf, k, out, out_stride);
+    hipLaunchKernelGGL(k_conv_direct<false>, grid, dim3(256), lds, st, img, in_stride, nx, ny, psf, k, rb, out, out_stride);
   return hipGetLastError();
 }
 
 hipError_t launch_conv_desc(const ConvDesc* descs, const int4* tiles, int ntiles, int kmax, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_conv_desc, dim3((unsigned)ntiles), dim3(256), conv_direct_lds_bytes(kmax), st, descs, tiles);
+  hipLaunchKernelGGL(k_conv_desc, dim3((unsigned)ntiles), dim3(256), conv_direct_lds_bytes(kmax), st, descs, tiles,
+                     conv_rows_per_chunk(kmax));
   return hipGetLastError();
 }
 

@@ -218,6 +218,54 @@ def test_convolve_direct(ctx, shape, k):
     assert image_error(_np(out), ref) <= (2e-5 if k <= 41 else IMAGE_TOL)
 
 
+@pytest.mark.parametrize("shape,k", [((53, 77), 1), ((53, 77), 11), ((200, 200), 41), ((64, 64), 101),
+                                     ((300, 33), 129), ((9, 300), 255), ((1, 1), 5), ((3, 1998), 101)])
+def test_convolve_fft(ctx, shape, k):
+    """FP64 transforms: only the FP32 rounding of the output remains."""
+    rng = np.random.default_rng(k + 7)
+    img = rng.uniform(0, 1, shape).astype(np.float32)
+    psf = rng.uniform(0, 1, (k, k))
+    psf[:, -1] *= 4.0         # asymmetric along x
+    psf[0, :] *= 3.0          # and along y
+    psf = (psf / psf.sum()).astype(np.float32)
+    out = ctx.convolve(img, psf, method=2)
+    assert image_error(_np(out), O.convolve_same(img, psf)) <= 1e-6
+
+
+def test_convolve_large_image_both_paths(ctx):
+    """1000 x 1000 px with a 101 x 101 PSF (the largest workload): both paths
+    on 4000 sampled pixels (every border and corner included) against the
+    oracle one pixel at a time, and against each other on every pixel; method
+    0 returns one of the two bit for bit."""
+    rng = np.random.default_rng(5)
+    n, k = 1000, 101
+    img = rng.uniform(0, 1, (n, n)).astype(np.float32)
+    psf = W.gaussian_psf(k, 12.0)
+    psf[k // 2 + 3, :] += 1e-3     # a ridge off the centre row breaks the symmetry
+    psf = (psf / psf.sum()).astype(np.float32)
+    rows = np.concatenate([rng.integers(0, n, 3600), [0, 0, n - 1, n - 1], rng.integers(0, n, 396)])
+    cols = np.concatenate([rng.integers(0, n, 3600), [0, n - 1, 0, n - 1], np.zeros(198, int),
+                           np.full(198, n - 1)])
+    ref = O.convolve_at(img, psf, rows, cols)
+    direct = _np(ctx.convolve(img, psf, method=1))
+    fft = _np(ctx.convolve(img, psf, method=2))
+    for got in (direct, fft):
+        assert image_error(got[rows, cols], ref) <= 2e-5
+    assert image_error(direct, fft) <= 2e-5
+    auto = _np(ctx.convolve(img, psf, method=0))
+    assert np.array_equal(auto, direct) or np.array_equal(auto, fft)
+
+
+def test_convolve_fft_size_limit(ctx):
+    from paper_2606_01547_amd import JtError
+    img = np.ones((1, 2000), np.float32)
+    psf = np.full((101, 101), 1.0 / 101**2, np.float32)
+    with pytest.raises(JtError):
+        ctx.convolve(img, psf, method=2)      # padded row of 2050 > 2048
+    out = _np(ctx.convolve(img, psf, method=0))   # auto falls back to the direct path
+    assert image_error(out, O.convolve_same(img, psf)) <= 2e-5
+
+
 def test_convolve_delta_is_identity(ctx):
     img = np.random.default_rng(0).standard_normal((70, 90)).astype(np.float32)
     psf = np.zeros((9, 9), np.float32)

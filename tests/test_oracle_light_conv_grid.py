@@ -120,6 +120,17 @@ def test_convolution_matches_scipy(k, shape):
     np.testing.assert_allclose(out, ref, rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("k,shape", [(3, (9, 6)), (11, (8, 8)), (15, (6, 9)), (21, (40, 13))])
+def test_sampled_convolution_matches_scipy(k, shape):
+    rng = np.random.default_rng(k + 100)
+    img = rng.standard_normal(shape)
+    K = rng.uniform(0, 1, (k, k))
+    K[:, 0] *= 5.0
+    ref = convolve2d(img, K, mode="same", boundary="fill", fillvalue=0.0)
+    rows, cols = np.divmod(np.arange(img.size), shape[1])
+    np.testing.assert_allclose(O.convolve_at(img, K, rows, cols), ref.ravel(), rtol=1e-12, atol=1e-12)
+
+
 def test_convolution_delta_and_flux():
     rng = np.random.default_rng(0)
     img = rng.uniform(0, 1, (30, 40))
