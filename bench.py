@@ -30,7 +30,7 @@ PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector, published
 # rsq + log2 2; degree-8 polynomial 16; g 2; g/x^2 2; * c2 1; accumulate 4.
 FLOP_PER_PAIR = 33
 KERNEL_SOURCES = ["paper_2606_01547_amd/csrc/kernels.hip", "paper_2606_01547_amd/csrc/jt_device.hpp",
-                  "paper_2606_01547_amd/csrc/nfw_poly.inc"]
+                  "paper_2606_01547_amd/csrc/nfw_poly.inc", "paper_2606_01547_amd/csrc/jt_sum.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_simulate_headline_traffic.json")
 
 
@@ -167,6 +167,77 @@ def serving_bench(ctx, n_requests, large_every, seed=1003):
     }
 
 
+def conv_sweep(ctx, reps=10):
+    """Direct against FFT convolution, kernel time from the library's HIP
+    events, on 200^2 and 1000^2 images for PSF sides 21..101, and the path
+    method 0 picks."""
+    import numpy as np
+    import torch
+    from paper_2606_01547_amd import convolve_auto_method
+    rng = np.random.default_rng(7)
+    rows = []
+    for n in (200, 1000):
+        img = torch.from_numpy(rng.uniform(0, 1, (n, n)).astype(np.float32)).cuda()
+        out = torch.empty_like(img)
+        for k in (21, 41, 61, 81, 101):
+            psf = rng.uniform(0, 1, (k, k))
+            psf = torch.from_numpy((psf / psf.sum()).astype(np.float32)).cuda()
+            us = {}
+            for name, m in (("direct", 1), ("fft", 2)):
+                ctx.convolve(img, psf, method=m, out=out)
+                torch.cuda.synchronize()
+                ctx.profile_enable(True)
+                ms0, n0 = ctx.profile_read("conv")
+                for _ in range(reps):
+                    ctx.convolve(img, psf, method=m, out=out)
+                torch.cuda.synchronize()
+                ms1, n1 = ctx.profile_read("conv")
+                ctx.profile_enable(False)
+                us[name] = round(1e3 * (ms1 - ms0) / (n1 - n0), 2)
+            rows.append({"n": n, "k": k, "direct_us": us["direct"], "fft_us": us["fft"],
+                         "direct_tflops": round(2.0 * n * n * k * k / us["direct"] / 1e6, 2),
+                         "auto": {1: "direct", 2: "fft"}[convolve_auto_method(n, n, k)]})
+    return rows
+
+
+def large_image_bench(ctx, reps):
+    """One 1000x1000 px image at s = 5 with 50,000 NFW subhalos, four Sersic
+    components and a 101x101 PSF (the largest workload)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    sc = W.config5_scene()
+    g = sc.grid
+    nfw = sc.lens.nfw
+    dev_nfw = W.NFWTable(*[torch.from_numpy(np.asarray(a)).cuda() for a in (nfw.x, nfw.y, nfw.Rs, nfw.alpha_Rs)])
+    lens = W.Lens(sie=sc.lens.sie, shear=sc.lens.shear, nfw=dev_nfw)
+    psf = torch.from_numpy(sc.psf).cuda()
+    out = torch.empty((g.ny, g.nx), dtype=torch.float32, device="cuda")
+    step = lambda: ctx.simulate_image(g, lens, sc.source, sc.lens_light, psf, sc.bn_exact, out=out)
+    step()
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    base = {k: ctx.profile_read(k) for k in ("sim", "conv")}
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    per = {}
+    for k in ("sim", "conv"):
+        ms, n = ctx.profile_read(k)
+        per[k] = (ms - base[k][0]) / max(n - base[k][1], 1)
+    ctx.profile_enable(False)
+    pairs = g.nx * g.ny * g.supersample ** 2 * nfw.n
+    achieved = FLOP_PER_PAIR * pairs / (1e-3 * per["sim"]) / 1e12
+    return {"workload": "1000x1000 px at 0.11\"/px, s=5, SIE + shear + 50000 NFW, 1 lens-light + 3 source Sersic, "
+                        "101x101 PSF (seed 1005)",
+            "reps": reps, "ms_per_image": round(1e3 * wall, 2), "simulate_ms": round(per["sim"], 2),
+            "convolve_ms": round(per["conv"], 3), "pairs": pairs,
+            "pairs_per_s": round(pairs / (1e-3 * per["sim"]), 1),
+            "simulate_frac_fp32_peak": round(achieved / PEAK_FP32_TFLOPS, 4)}
+
+
 def adjoint_bench(ctx, draws, reps):
     """Gradient of the chi^2 log-likelihood for a batch of parameter draws
     (100x100 px, 1000 NFW, 21x21 PSF) against the forward alone and the plain
@@ -221,6 +292,8 @@ def main():
     ap.add_argument("--serve-large-every", type=int, default=512,
                     help="every n-th request is a large 1000x1000 image (0 = none)")
     ap.add_argument("--adjoint-draws", type=int, default=256, help="parameter draws per gradient (0 = skip)")
+    ap.add_argument("--large-reps", type=int, default=3, help="timed 1000^2-px images (0 = skip)")
+    ap.add_argument("--conv-sweep", type=int, default=1, help="direct/FFT convolution sweep (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (3 times), to calibrate "
                          "the FETCH_SIZE / WRITE_SIZE counters")
@@ -310,6 +383,10 @@ def main():
                        "prep": round(prep_ms / max(prep_n, 1), 4)},
         "roofline": roofline,
     }
+    if args.conv_sweep:
+        result["conv_sweep"] = conv_sweep(ctx)
+    if args.large_reps > 0:
+        result["large_image"] = large_image_bench(ctx, args.large_reps)
     if args.adjoint_draws > 0:
         result["adjoint"] = adjoint_bench(ctx, args.adjoint_draws, reps=10)
     if args.serve_requests > 0:

@@ -155,6 +155,10 @@ jt_status jt_source_sb(jt_ctx* ctx, int n, const float* x, const float* y,
 jt_status jt_convolve(jt_ctx* ctx, const float* img, int nx, int ny, const float* psf,
                       int k, int method, float* out, hipStream_t stream);
 
+/* The method (1 direct, 2 FFT) that method 0 selects for an nx x ny image
+ * and a k x k PSF; 0 when neither path takes the shape.  Host only. */
+int jt_convolve_auto_method(int nx, int ny, int k);
+
 /* ----------------------------------------------------------------------
  * Fused simulation: steps 1-2 and the supersample average in one kernel,
  * then step 3.

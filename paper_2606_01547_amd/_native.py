@@ -107,6 +107,7 @@ _SIGS = {
     "jt_source_sb": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(JtLight),
                              POINTER(JtLight), c_void_p, c_void_p]),
     "jt_convolve": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_int, c_void_p, c_void_p]),
+    "jt_convolve_auto_method": (c_int, [c_int, c_int, c_int]),
     "jt_simulate_image": (c_int, [c_void_p, POINTER(JtGrid), POINTER(JtLens), POINTER(JtLight), POINTER(JtLight),
                                   c_void_p, c_int, c_void_p, c_void_p]),
     "jt_upload_subhalos": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_uint64)]),
@@ -156,6 +157,11 @@ def _check(status):
 def sersic_bn(n: float, exact: bool = False) -> float:
     """b_n as the library computes it on the host (FP64)."""
     return float(load_library().jt_sersic_bn(float(n), int(bool(exact))))
+
+
+def convolve_auto_method(nx: int, ny: int, k: int) -> int:
+    """The convolution path method 0 takes: 1 direct, 2 FFT, 0 none."""
+    return int(load_library().jt_convolve_auto_method(int(nx), int(ny), int(k)))
 
 
 # ---------------------------------------------------------------- helpers

@@ -30,7 +30,7 @@ size_t conv_direct_lds_bytes(int k);
 // adjoint (correlation with the kernel).
 hipError_t launch_conv_direct_batched(bool flip, int batch, const float* img, long in_stride, int nx, int ny,
                                       const float* psf, int k, float* out, long out_stride, hipStream_t st);
-// Heterogeneous convolutions: tiles (desc, tile_x, tile_y, -) over 32 x 8
+// Heterogeneous convolutions: tiles (desc, tile_x, tile_y, -) over 64 x 4
 // output tiles; kmax = largest kernel side in the batch.
 hipError_t launch_conv_desc(const ConvDesc* descs, const int4* tiles, int ntiles, int kmax, hipStream_t st);
 int conv_tiles_x(int nx);

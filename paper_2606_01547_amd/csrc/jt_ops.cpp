@@ -119,6 +119,12 @@ extern "C" jt_status jt_convolve(jt_ctx* ctx, const float* img, int nx, int ny, 
   return convolve_on(ctx, img, nx, ny, psf, k, method, out, stream);
 }
 
+extern "C" int jt_convolve_auto_method(int nx, int ny, int k) {
+  if (nx < 1 || ny < 1 || k < 1 || k % 2 == 0) return 0;
+  if (conv_prefers_fft(nx, ny, k)) return 2;
+  return k <= JT_MAX_PSF ? 1 : 0;
+}
+
 extern "C" jt_status jt_simulate_image(jt_ctx* ctx, const jt_grid* grid, const jt_lens* lens,
                                        const jt_light* src, const jt_light* lens_light, const float* psf,
                                        int k, float* out, hipStream_t stream) {

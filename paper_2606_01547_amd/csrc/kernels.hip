@@ -172,13 +172,15 @@ __global__ __launch_bounds__(256) void k_simulate_desc(const ImageDesc* __restri
 // Direct convolution: 32 x 8 outputs per block; the input window of a chunk of
 // up to kConvRows kernel rows is staged in LDS (dynamic size), kernel weights
 // are read with uniform indices (scalar loads).
-// Direct convolution tiles: 64 x 4 outputs per 256-thread block.  Thread
+// Direct convolution tiles: 64 x 4 outputs per block of kW waves.  Thread
 // (q, r, w) computes the four outputs (i0 + r, j0 + 4q .. 4q + 3) over the
-// kernel rows a = w, w + 4, ... of each staged chunk: wave w owns a quarter of
-// the kernel rows, so the weights it reads are wave-uniform (scalar loads), and
-// a sliding window of four input values in registers feeds four FMAs per LDS
-// read.  The four per-wave partials are added in wave order at the end.
-constexpr int kConvTX = 64, kConvTY = 4, kConvQ = 4, kConvW = 4;
+// kernel rows a = w, w + kW, ... of each staged chunk: wave w owns 1/kW of the
+// kernel rows, so the weights it reads are wave-uniform (scalar loads), and a
+// sliding window of four input values in registers feeds four FMAs per LDS
+// read.  The kW per-wave partials are added in wave order at the end.  Small
+// images (too few tiles to fill the chip) use kW = 16 so that each CU still
+// runs enough waves to hide the LDS latency.
+constexpr int kConvTX = 64, kConvTY = 4, kConvQ = 4;
 constexpr size_t kConvLdsCap = 48 * 1024;
 
 // Kernel rows staged per chunk so that the input window fits kConvLdsCap.
@@ -190,6 +192,10 @@ int conv_rows_per_chunk(int k) {
   return (int)rb;
 }
 
+// 16-wave blocks when the tiles alone would leave CUs short of waves and the
+// kernel has enough rows to share out.
+bool conv_wide_blocks(long tiles, int k) { return k >= 16 && tiles < 4L * 256; }
+
 size_t conv_direct_lds_bytes(int k) {
   return sizeof(float) * (size_t)(kConvTY + conv_rows_per_chunk(k) - 1) * (size_t)(kConvTX + k - 1);
 }
@@ -197,10 +203,11 @@ size_t conv_direct_lds_bytes(int k) {
 // kFlip: correlate instead (the kernel read as psf[k-1-a][k-1-b]), which is the
 // adjoint of the convolution.  rb: kernel rows per staged chunk (the launch's
 // LDS holds (kConvTY + rb - 1) x (kConvTX + k - 1) floats).
-template <bool kFlip>
+template <bool kFlip, int kW>
 __device__ __forceinline__ void conv_tile(const float* __restrict__ img, int nx, int ny, const float* __restrict__ psf,
                                           int k, int rb, float* __restrict__ out, int tile_x, int tile_y, float* tile) {
-  __shared__ float part[kConvW][kConvTY][kConvTX];
+  static_assert(kW == 4 || kW == 16, "4 or 16 waves per block");
+  __shared__ float part[kW][kConvTY][kConvTX];
   const int q = threadIdx.x % (kConvTX / kConvQ);
   const int r = (threadIdx.x / (kConvTX / kConvQ)) % kConvTY;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);  // wave index, uniform
@@ -221,7 +228,7 @@ __device__ __forceinline__ void conv_tile(const float* __restrict__ img, int nx,
       tile[e] = (gi >= 0 && gi < ny && gj >= 0 && gj < nx) ? img[gi * nx + gj] : 0.f;
     }
     __syncthreads();
-    for (int da = w; da < ka; da += kConvW) {
+    for (int da = w; da < ka; da += kW) {
       const int arow = a0 + da;
       // input row i - a + c  ->  local row r + (ka - 1 - da); output 4q + t at
       // kernel column b reads local column 4q + t + (k - 1 - b)
@@ -247,31 +254,35 @@ __device__ __forceinline__ void conv_tile(const float* __restrict__ img, int nx,
   part[w][r][base + 2] = acc2;
   part[w][r][base + 3] = acc3;
   __syncthreads();
-  // threadIdx < 256 covers the 64 x 4 outputs once
+  // the first 256 threads cover the 64 x 4 outputs once
+  if (threadIdx.x >= kConvTX * kConvTY) return;
   const int oc = threadIdx.x % kConvTX, orow = threadIdx.x / kConvTX;
-  const float v = ((part[0][orow][oc] + part[1][orow][oc]) + part[2][orow][oc]) + part[3][orow][oc];
+  float v = part[0][orow][oc];
+#pragma unroll
+  for (int u = 1; u < kW; ++u) v += part[u][orow][oc];
   const int i = i0 + orow, j = j0 + oc;
   if (i < ny && j < nx) out[i * nx + j] = v;
 }
 
 // blockIdx.z selects an image of a batch (strided images, one PSF).
-template <bool kFlip>
-__global__ __launch_bounds__(256) void k_conv_direct(const float* __restrict__ img, long in_stride, int nx, int ny,
-                                                    const float* __restrict__ psf, int k, int rb, float* __restrict__ out,
-                                                    long out_stride) {
+template <bool kFlip, int kW>
+__global__ __launch_bounds__(kW * 64) void k_conv_direct(const float* __restrict__ img, long in_stride, int nx, int ny,
+                                                        const float* __restrict__ psf, int k, int rb,
+                                                        float* __restrict__ out, long out_stride) {
   extern __shared__ float tile[];
-  conv_tile<kFlip>(img + blockIdx.z * in_stride, nx, ny, psf, k, rb, out + blockIdx.z * out_stride, blockIdx.x,
-                   blockIdx.y, tile);
+  conv_tile<kFlip, kW>(img + blockIdx.z * in_stride, nx, ny, psf, k, rb, out + blockIdx.z * out_stride, blockIdx.x,
+                       blockIdx.y, tile);
 }
 
 // Heterogeneous batch: block b convolves tile (tiles[b].y, tiles[b].z) of
 // image descs[tiles[b].x]; the dynamic LDS fits the batch's largest kernel.
-__global__ __launch_bounds__(256) void k_conv_desc(const ConvDesc* __restrict__ descs, const int4* __restrict__ tiles,
-                                                  int rb) {
+template <int kW>
+__global__ __launch_bounds__(kW * 64) void k_conv_desc(const ConvDesc* __restrict__ descs,
+                                                      const int4* __restrict__ tiles, int rb) {
   extern __shared__ float tile[];
   const int4 tl = tiles[blockIdx.x];
   const ConvDesc& d = descs[tl.x];
-  conv_tile<false>(d.img, d.nx, d.ny, d.psf, d.k, min(rb, d.k), d.out, tl.y, tl.z, tile);
+  conv_tile<false, kW>(d.img, d.nx, d.ny, d.psf, d.k, min(rb, d.k), d.out, tl.y, tl.z, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -346,17 +357,26 @@ hipError_t launch_conv_direct_batched(bool flip, int batch, const float* img, lo
   const dim3 grid((nx + kConvTX - 1) / kConvTX, (ny + kConvTY - 1) / kConvTY, batch);
   const size_t lds = conv_direct_lds_bytes(k);
   const int rb = conv_rows_per_chunk(k);
-  if (flip)
-    hipLaunchKernelGGL(k_conv_direct<true>, grid, dim3(256), lds, st, img, in_stride, nx, ny, psf, k, rb, out, out_stride);
-  else
-    hipLaunchKernelGGL(k_conv_direct<false>, grid, dim3(256), lds, st, img, in_stride, nx, ny, psf, k, rb, out, out_stride);
+  const bool wide = conv_wide_blocks((long)grid.x * grid.y * grid.z, k);
+#define JT_CONV(F, W) hipLaunchKernelGGL((k_conv_direct<F, W>), grid, dim3(W * 64), lds, st, img, in_stride, nx, ny, \
+                                         psf, k, rb, out, out_stride)
+  if (flip) {
+    if (wide) JT_CONV(true, 16); else JT_CONV(true, 4);
+  } else {
+    if (wide) JT_CONV(false, 16); else JT_CONV(false, 4);
+  }
+#undef JT_CONV
   return hipGetLastError();
 }
 
 hipError_t launch_conv_desc(const ConvDesc* descs, const int4* tiles, int ntiles, int kmax, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_conv_desc, dim3((unsigned)ntiles), dim3(256), conv_direct_lds_bytes(kmax), st, descs, tiles,
-                     conv_rows_per_chunk(kmax));
+  const size_t lds = conv_direct_lds_bytes(kmax);
+  const int rb = conv_rows_per_chunk(kmax);
+  if (conv_wide_blocks(ntiles, kmax))
+    hipLaunchKernelGGL(k_conv_desc<16>, dim3((unsigned)ntiles), dim3(1024), lds, st, descs, tiles, rb);
+  else
+    hipLaunchKernelGGL(k_conv_desc<4>, dim3((unsigned)ntiles), dim3(256), lds, st, descs, tiles, rb);
   return hipGetLastError();
 }
 

@@ -110,3 +110,13 @@ def test_create_without_gpu_fails_cleanly():
     with pytest.raises(nat.JtError) as ei:
         nat.Context(0)
     assert ei.value.status in (nat.JT_EDEVICE, nat.JT_EINVAL)
+
+
+def test_convolve_auto_method_host_rule():
+    _, nat = _lib()
+    assert nat.convolve_auto_method(200, 200, 3) == 1        # tiny kernel: direct
+    assert nat.convolve_auto_method(64, 64, 301) == 2        # beyond the direct limit: FFT
+    assert nat.convolve_auto_method(3000, 10, 301) == 0      # neither path takes it
+    assert nat.convolve_auto_method(2000, 2000, 101) == 1    # FFT size over 2048: direct
+    assert nat.convolve_auto_method(10, 10, 4) == 0          # even kernel
+    assert nat.convolve_auto_method(0, 10, 3) == 0

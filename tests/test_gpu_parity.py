@@ -327,6 +327,43 @@ def test_simulate_headline_full_size_sampled(ctx):
     assert image_error(full, O.convolve_same(un, sc.psf)) <= 2e-5
 
 
+def _oracle_pixels_direct(sc, rows, cols):
+    """Sampled pixels of a large grid without forming its whole sub-pixel
+    array: pixel (i, j) is the 1 x 1 grid centred on that pixel."""
+    g = sc.grid
+    out = np.empty(len(rows))
+    for t, (i, j) in enumerate(zip(rows, cols)):
+        x0 = g.x0 + (j - (g.nx - 1) / 2.0) * g.pixel_scale
+        y0 = g.y0 + (i - (g.ny - 1) / 2.0) * g.pixel_scale
+        tx, ty = O.subpixel_coords(1, 1, g.pixel_scale, x0, y0, g.supersample)
+        bx, by = O.ray_shoot(tx, ty, sc.lens)
+        sb = O.surface_brightness(tx, ty, bx, by, sc.source, sc.lens_light, sc.bn_exact)
+        out[t] = g.pixel_scale ** 2 * sb.mean()
+    return out
+
+
+def test_simulate_large_image_sampled(ctx):
+    """1000x1000 px, s = 5, 50,000 NFW, four Sersic components, 101x101 PSF
+    (the largest workload): the unconvolved image on sampled pixels against the
+    oracle pixel by pixel; the convolution stage on sampled outputs."""
+    sc = W.config5_scene()
+    n = sc.grid.nx
+    un = _np(ctx.simulate_scene(sc, psf=False))
+    rng = np.random.default_rng(1)
+    flat = np.argsort(un.reshape(-1))[-40:]
+    rows = np.concatenate([rng.integers(0, n, 56), [0, n - 1], flat // n])
+    cols = np.concatenate([rng.integers(0, n, 56), [n - 1, 0], flat % n])
+    ref = _oracle_pixels_direct(sc, rows, cols)
+    floor = 1e-3 * np.abs(un).max()
+    assert np.max(np.abs(un[rows, cols] - ref) / np.maximum(np.abs(ref), floor)) <= IMAGE_TOL
+    full = _np(ctx.simulate_scene(sc))
+    np.testing.assert_array_equal(full, _np(ctx.convolve(un.astype(np.float32), sc.psf)))
+    r2, c2 = rng.integers(0, n, 300), rng.integers(0, n, 300)
+    conv_ref = O.convolve_at(un.astype(np.float32), sc.psf, r2, c2)
+    fl2 = 1e-3 * np.abs(full).max()
+    assert np.max(np.abs(full[r2, c2] - conv_ref) / np.maximum(np.abs(conv_ref), fl2)) <= 2e-5
+
+
 def test_simulate_is_deterministic(ctx):
     sc = W.config2_scene(npix=64, n_sub=3000)
     a = _np(ctx.simulate_scene(sc))
