@@ -183,18 +183,18 @@ __global__ __launch_bounds__(256) void k_grad_pixel(const ImageDesc* __restrict_
   const int pp = valid ? p : 0;
   const int row = pp / g.nx, col = pp - (pp / g.nx) * g.nx;
   const int a = si / g.s, b = si - (si / g.s) * g.s;
-  const float tx = (float)(g.ox + g.step * ((double)(col * g.s + b) + 0.5));
-  const float ty = (float)(g.oy + g.step * ((double)(row * g.s + a) + 0.5));
+  const double tx64 = g.ox + g.step * ((double)(col * g.s + b) + 0.5);
+  const double ty64 = g.oy + g.step * ((double)(row * g.s + a) + 0.5);
+  const float tx = (float)tx64, ty = (float)ty64;
   subhalo_quarters<kSplit>(tx, ty, d.sub, d.nloop, grp, t, scratch);
   __syncthreads();
   float c[kGradMaxP];
 #pragma unroll
   for (int i = 0; i < kGradMaxP; ++i) c[i] = 0.f;
   if (grp == 0) {
-    float mx, my, ax, ay;
-    macro_deflection(d.mc, tx, ty, mx, my);
-    combine_deflection(mx, my, &scratch.q[0][t], kW, ax, ay);
-    const float bx = tx - ax, by = ty - ay;
+    double ax, ay;
+    total_deflection64(d.mc, tx64, ty64, &scratch.q[0][t], kW, ax, ay);
+    const float bx = (float)(tx64 - ax), by = (float)(ty64 - ay);
     const float lam = valid ? lamU[(size_t)di * npix + pp] * g.area_over_s2 : 0.f;
     float Gx = 0.f, Gy = 0.f, dd[7], gx, gy;
     const int ns = d.src.n, nl = d.ll.n;
@@ -244,17 +244,22 @@ __global__ __launch_bounds__(256) void k_grad_pixel(const ImageDesc* __restrict_
 // ---------------------------------------------------------------------------
 // subhalo-major pass
 // ---------------------------------------------------------------------------
-// h = g/x^2 and dh/d(x^2) for the NFW term, X2 = x^2.  Far (X2 >= 1.2): the
-// fitted polynomial, F = psi + ln 2, dg/dX2 = (1 - F)/(2 (X2 - 1)).  Near:
-// series in u = X2 - 1 (X2 >= 0.81), the log1p form below, 0 at X2 = 0.
+// h = g/x^2 and dh/d(x^2) for the NFW term, X2 = x^2, in the forward's units
+// (g divided by kNfwRecScale, which each record's c2 carries).  Far
+// (X2 >= 1.2): the fitted polynomial, psi = (ln2/2)(1 - kLog2Bias) P,
+// F = psi + ln 2 and dg/dX2 = (1 - F)/(2 (X2 - 1)).  Near: series in
+// u = X2 - 1 (X2 >= 0.81), the log1p form below, 0 at X2 = 0; both in units
+// of ln2/2, then rescaled by kNfwNearScale.
 __device__ __forceinline__ void nfw_h_dh_near(float X2, float& h, float& dh) {
   if (!(X2 > 0.f)) {
     h = 0.f;
     dh = 0.f;
     return;
   }
+  constexpr float kInvA = (float)(2.0 / kLn2d);    // 1 / (ln2/2)
+  constexpr float kInvLn2 = (float)(1.0 / kLn2d);
   const float l2 = __builtin_amdgcn_logf(X2);
-  const float L = fmaf(0.5f * kLn2, l2, -kLn2);
+  const float Lp = l2 - 2.0f;                       // ln(x/2) / (ln2/2)
   const float iX2 = __builtin_amdgcn_rcpf(X2);
   if (X2 >= 0.81f) {
     const float u = X2 - 1.0f;
@@ -284,33 +289,39 @@ __device__ __forceinline__ void nfw_h_dh_near(float X2, float& h, float& dh) {
     S = fmaf(S, u, 1.0f / 7.0f);
     S = fmaf(S, u, -1.0f / 5.0f);
     S = fmaf(S, u, 1.0f / 3.0f);
-    h = (L + F) * iX2;
-    dh = (0.5f * S - h) * iX2;
+    h = fmaf(F, kInvA, Lp) * iX2;
+    dh = fmaf(S, kInvLn2, -h) * iX2;
+    h *= kNfwNearScale;
+    dh *= kNfwNearScale;
   } else {
     const float w = __builtin_amdgcn_sqrtf(1.0f - X2);
     const float ropw = __builtin_amdgcn_rcpf(1.0f + w);
     const float tt = -0.5f * X2 * ropw;
     const float uu = 1.0f + tt;
-    const float lp = (uu == 1.0f) ? tt : kLn2 * __builtin_amdgcn_logf(uu) * tt * __builtin_amdgcn_rcpf(uu - 1.0f);
+    const float lp = (uu == 1.0f) ? tt * kInvA : 2.0f * __builtin_amdgcn_logf(uu) * tt * __builtin_amdgcn_rcpf(uu - 1.0f);
     const float iw = __builtin_amdgcn_rcpf(w);
-    const float g = fmaf(-L * X2, ropw, lp) * iw;
+    const float g = fmaf(-Lp * X2, ropw, lp) * iw;
     // F = atanh(w)/w = ln((1+w)^2 / X2) / (2 w)
     const float F = kLn2 * (2.0f * __builtin_amdgcn_logf(1.0f + w) - l2) * 0.5f * iw;
     h = g * iX2;
-    dh = ((1.0f - F) * 0.5f / (X2 - 1.0f) - h) * iX2;
+    dh = ((1.0f - F) * kInvLn2 / (X2 - 1.0f) - h) * iX2;
+    h *= kNfwNearScale;
+    dh *= kNfwNearScale;
   }
 }
 
 __device__ __forceinline__ void nfw_h_dh(float X2, float& h, float& dh) {
+  constexpr float kA1 = (float)(0.5 * kLn2d * (1.0 - kLog2Bias));   // psi = kA1 * P
+  constexpr float kInv2U = (float)(0.5 / kNfwRecScale);
   const float y = __builtin_amdgcn_rsqf(X2);
   const float l2 = __builtin_amdgcn_logf(X2);
-  float p = kNfwPsi[0];
+  float p = kNfwP[0];
 #pragma unroll
-  for (int i = 1; i <= JT_NFW_POLY_DEGREE; ++i) p = fmaf(p, y, kNfwPsi[i]);
+  for (int i = 1; i <= JT_NFW_POLY_DEGREE; ++i) p = fmaf(p, y, kNfwP[i]);
   const float y2 = y * y;
-  h = fmaf(l2, 0.5f * kLn2, p) * y2;
-  const float oneF = (1.0f - kLn2) - p;
-  dh = fmaf(oneF, 0.5f * __builtin_amdgcn_rcpf(X2 - 1.0f), -h) * y2;
+  h = (l2 + p) * y2;
+  const float oneF = fmaf(-kA1, p, (float)(1.0 - kLn2d));           // 1 - F
+  dh = fmaf(oneF * kInv2U, __builtin_amdgcn_rcpf(X2 - 1.0f), -h) * y2;
 }
 
 // grid (ceil(n / 64), B, kQuarters); lane = subhalo.  Writes the quarter
@@ -322,7 +333,8 @@ __global__ __launch_bounds__(64) void k_grad_subhalo(const ImageDesc* __restrict
   const int k = blockIdx.x * 64 + threadIdx.x;
   const bool valid = k < n;
   const SubRec s = descs[b].sub[valid ? k : 0];
-  const float c2n = sqrtf(s.c1) / (1.0f - kLn2);   // alpha / alpha_Rs = c2n * h * d
+  // alpha / alpha_Rs = c2n * h * d  (h in units of ln2/2)
+  const float c2n = sqrtf(s.c1) * (float)(kNfwRecScale / (1.0 - kLn2d));
   const float4* __restrict__ r = rec + (size_t)b * rec_stride;
   const int kb = quarter_bound(nrec_loop, q), ke = quarter_bound(nrec_loop, q + 1);
   float hx = 0.f, lx = 0.f, hy = 0.f, ly = 0.f, ha = 0.f, la = 0.f;

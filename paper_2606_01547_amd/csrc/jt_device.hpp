@@ -1,9 +1,10 @@
-// Device-side building blocks of the lensed-image simulation (gfx950, FP32).
+// Device-side building blocks of the lensed-image simulation (gfx950).
 //
 // Everything here is evaluated per image-plane (sub-)pixel: the macro-lens
-// deflection (SIE + external shear + test point masses), the NFW subhalo pair
-// term, and the elliptical Sersic surface brightness.  Kernel-constant structs
-// are filled on the host in FP64 and rounded once to FP32.
+// deflection (SIE + external shear + test point masses, FP64, once per
+// sub-pixel), the NFW subhalo pair term (FP32, the hot loop), and the
+// elliptical Sersic surface brightness (FP32).  Kernel-constant structs are
+// filled on the host in FP64; the FP32 ones are rounded once.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,19 +15,37 @@ namespace jt {
 constexpr int kMaxSersic = 8;
 constexpr int kMaxPointMass = 16;
 constexpr float kLn2 = 0.69314718055994530942f;
+constexpr double kLn2d = 0.69314718055994530942;
 
 #include "nfw_poly.inc"
+
+// Mean relative errors of gfx950's log2 and rsq instructions (measured over 4M
+// arguments in [1e-6, 1e6]: log2 sits 0.466 ulp low).  Their products with a
+// sum of tens of thousands of same-signed NFW terms would otherwise bias the
+// deflection by ~5e-8 of its size.  The subhalo record's amplitude carries
+// kNfwRecScale = (ln2/2)(1 - kLog2Bias)(1 - 2 kRsqBias) and the far-field
+// polynomial is fitted to P/(1 - kLog2Bias), which removes both means at no
+// cost; the near-field forms are rescaled by kNfwNearScale to the same units.
+constexpr double kLog2Bias = -4.08e-8;
+constexpr double kRsqBias = -7.4e-9;
+constexpr double kNfwRecScale = 0.5 * kLn2d * (1.0 - kLog2Bias) * (1.0 - 2.0 * kRsqBias);
+constexpr float kNfwNearScale = (float)(1.0 / ((1.0 - kLog2Bias) * (1.0 - 2.0 * kRsqBias)));
 
 // ---------------------------------------------------------------------------
 // kernel constants
 // ---------------------------------------------------------------------------
 struct MacroC {
   int has_sie, sie_series, has_shear, npm;
-  // SIE: rotate into the major-axis frame about (cx, cy); psi = sqrt(q^2 x'^2 + y'^2)
-  float cx, cy, cphi, sphi, q2, pref_f, f, pref;  // pref = theta_E sqrt(q); pref_f = pref / f
-  float theta_E, q, sqrt_q;                       // used by the adjoint
-  float g1, g2;                                   // shear
-  float pm_x[kMaxPointMass], pm_y[kMaxPointMass], pm_te2[kMaxPointMass];
+  // FP32 copies for the adjoint's SIE and shear partials
+  float cx, cy, cphi, sphi, q2, f;
+  float theta_E, q, sqrt_q;
+  float g1, g2;
+  // FP64 constants of the deflection.  SIE: rotate into the major-axis frame
+  // about (cx, cy); psi = sqrt(q^2 x'^2 + y'^2); pref = theta_E sqrt(q),
+  // pref_f = pref / f, f = sqrt(1 - q^2)
+  double dcx, dcy, dcphi, dsphi, dq2, df, dpref, dpref_f;
+  double dg1, dg2;
+  double pm_x[kMaxPointMass], pm_y[kMaxPointMass], pm_te2[kMaxPointMass];
 };
 
 struct SersicC {
@@ -60,8 +79,11 @@ struct GridC {
 struct ImageDesc;
 
 // Packed subhalo record: centre and the two derived constants of the pair term
-// alpha = c2 * g(x) / x^2 * (dx, dy), x^2 = r^2 c1, c1 = 1/Rs^2,
-// c2 = alpha_Rs / ((1 - ln 2) Rs).
+// alpha = c2 * g'(x) / x^2 * (dx, dy), x^2 = r^2 c1, c1 = 1/Rs^2, with g in
+// units of ln2/2 (g' = g / (ln2/2)) and the factor carried by
+// c2 = kNfwRecScale alpha_Rs / ((1 - ln 2) Rs).  Folding the constant into c2
+// (one FP64 product rounded per subhalo) keeps its FP32 rounding from biasing
+// every term the same way.
 struct __align__(16) SubRec {
   float x, y, c1, c2;
 };
@@ -86,92 +108,99 @@ struct ConvDesc {
 // ---------------------------------------------------------------------------
 // macro lens
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void macro_deflection(const MacroC& m, float tx, float ty,
-                                                 float& ax, float& ay) {
-  ax = 0.f;
-  ay = 0.f;
+// FP64, once per sub-pixel: the FP32 representation of angles of tens of
+// arcseconds (|theta|, |alpha| up to ~20") would otherwise dominate the error
+// of beta = theta - alpha.
+__device__ __forceinline__ void macro_deflection64(const MacroC& m, double tx, double ty, double& ax, double& ay) {
+  ax = 0.0;
+  ay = 0.0;
   if (m.has_sie) {
-    const float dx = tx - m.cx, dy = ty - m.cy;
-    const float xp = fmaf(m.cphi, dx, m.sphi * dy);
-    const float yp = fmaf(m.cphi, dy, -m.sphi * dx);
-    const float psi = sqrtf(fmaf(m.q2, xp * xp, yp * yp));
-    float axp = 0.f, ayp = 0.f;
-    if (psi > 0.f) {
-      const float ipsi = 1.0f / psi;
+    const double dx = tx - m.dcx, dy = ty - m.dcy;
+    const double xp = m.dcphi * dx + m.dsphi * dy;
+    const double yp = m.dcphi * dy - m.dsphi * dx;
+    const double psi = sqrt(m.dq2 * xp * xp + yp * yp);
+    double axp = 0.0, ayp = 0.0;
+    if (psi > 0.0) {
+      const double ipsi = 1.0 / psi;
       if (m.sie_series) {
-        // atan(z)/z and atanh(z)/z by their Taylor series for f < 1e-2 (|z| < f)
-        const float zx = m.f * xp * ipsi, zy = m.f * yp * ipsi;
-        const float zx2 = zx * zx, zy2 = zy * zy;
-        axp = m.pref * xp * ipsi * fmaf(zx2, fmaf(zx2, 0.2f, -1.0f / 3.0f), 1.0f);
-        ayp = m.pref * yp * ipsi * fmaf(zy2, fmaf(zy2, 0.2f, 1.0f / 3.0f), 1.0f);
+        // atan(z)/z and atanh(z)/z by their Taylor series for f < 1e-3 (|z| < f)
+        const double zx = m.df * xp * ipsi, zy = m.df * yp * ipsi;
+        const double zx2 = zx * zx, zy2 = zy * zy;
+        axp = m.dpref * xp * ipsi * (1.0 + zx2 * (-1.0 / 3.0 + zx2 * (0.2 - zx2 / 7.0)));
+        ayp = m.dpref * yp * ipsi * (1.0 + zy2 * (1.0 / 3.0 + zy2 * (0.2 + zy2 / 7.0)));
       } else {
-        axp = m.pref_f * atanf(m.f * xp * ipsi);
-        ayp = m.pref_f * atanhf(m.f * yp * ipsi);
+        axp = m.dpref_f * atan(m.df * xp * ipsi);
+        ayp = m.dpref_f * atanh(m.df * yp * ipsi);
       }
     }
-    ax = fmaf(m.cphi, axp, -m.sphi * ayp);
-    ay = fmaf(m.sphi, axp, m.cphi * ayp);
+    ax = m.dcphi * axp - m.dsphi * ayp;
+    ay = m.dsphi * axp + m.dcphi * ayp;
   }
   if (m.has_shear) {
-    ax = fmaf(m.g1, tx, fmaf(m.g2, ty, ax));
-    ay = fmaf(m.g2, tx, fmaf(-m.g1, ty, ay));
+    ax += m.dg1 * tx + m.dg2 * ty;
+    ay += m.dg2 * tx - m.dg1 * ty;
   }
   for (int k = 0; k < m.npm; ++k) {
-    const float dx = tx - m.pm_x[k], dy = ty - m.pm_y[k];
-    const float r2 = fmaf(dx, dx, dy * dy);
-    const float fac = r2 > 0.f ? m.pm_te2[k] / r2 : 0.f;
-    ax = fmaf(fac, dx, ax);
-    ay = fmaf(fac, dy, ay);
+    const double dx = tx - m.pm_x[k], dy = ty - m.pm_y[k];
+    const double r2 = dx * dx + dy * dy;
+    const double fac = r2 > 0.0 ? m.pm_te2[k] / r2 : 0.0;
+    ax += fac * dx;
+    ay += fac * dy;
   }
 }
 
 // ---------------------------------------------------------------------------
 // NFW pair term
 // ---------------------------------------------------------------------------
-// g(x)/x^2 for x^2 = X2 < 1 (rare near-field pairs), from l2 = log2(X2), with
-// hardware transcendentals and forms that avoid cancellation:
+// g'(x)/x^2 = g(x)/((ln2/2) x^2) for x^2 = X2 < 1 (rare near-field pairs), from
+// l2 = log2(X2), with hardware transcendentals and forms that avoid
+// cancellation.  In these units ln(x/2) = (ln2/2)(l2 - 2) exactly:
 //   X2 >= 0.81: F = sum_k (-u)^k/(2k+1), u = X2 - 1 in [-0.19, 0), and
-//               g = ln(x/2) + F;
+//               g' = (l2 - 2) + F / (ln2/2);
 //   X2 <  0.81: g = [-L X2/(1+w) + log1p(-X2/(2(1+w)))]/w, L = ln(x/2),
 //               w = sqrt(1 - X2), with log1p(t) = t ln(1+t)/((1+t) - 1)
 //               (exact t when 1 + t rounds to 1);
 // 0 at X2 = 0.
 __device__ __forceinline__ float nfw_near_g_over_x2(float X2, float l2) {
-  const float L = fmaf(0.5f * kLn2, l2, -kLn2);   // ln(x/2)
+  constexpr float kInvA = (float)(2.0 / kLn2d);   // 1 / (ln2/2)
+  const float Lp = l2 - 2.0f;                      // ln(x/2) / (ln2/2)
   float g;
   if (X2 >= 0.81f) {
     const float u = X2 - 1.0f;
-    float F = 1.0f / 21.0f;
-    F = fmaf(F, -u, 1.0f / 19.0f);
-    F = fmaf(F, -u, 1.0f / 17.0f);
-    F = fmaf(F, -u, 1.0f / 15.0f);
-    F = fmaf(F, -u, 1.0f / 13.0f);
-    F = fmaf(F, -u, 1.0f / 11.0f);
-    F = fmaf(F, -u, 1.0f / 9.0f);
-    F = fmaf(F, -u, 1.0f / 7.0f);
-    F = fmaf(F, -u, 1.0f / 5.0f);
-    F = fmaf(F, -u, 1.0f / 3.0f);
-    F = fmaf(F, -u, 1.0f);
-    g = L + F;
+    // F / (ln2/2): coefficients (2/ln2)/(2k+1), each rounded once
+    float F = (float)(2.0 / kLn2d / 21.0);
+    F = fmaf(F, -u, (float)(2.0 / kLn2d / 19.0));
+    F = fmaf(F, -u, (float)(2.0 / kLn2d / 17.0));
+    F = fmaf(F, -u, (float)(2.0 / kLn2d / 15.0));
+    F = fmaf(F, -u, (float)(2.0 / kLn2d / 13.0));
+    F = fmaf(F, -u, (float)(2.0 / kLn2d / 11.0));
+    F = fmaf(F, -u, (float)(2.0 / kLn2d / 9.0));
+    F = fmaf(F, -u, (float)(2.0 / kLn2d / 7.0));
+    F = fmaf(F, -u, (float)(2.0 / kLn2d / 5.0));
+    F = fmaf(F, -u, (float)(2.0 / kLn2d / 3.0));
+    F = fmaf(F, -u, kInvA);
+    g = Lp + F;
   } else {
     const float w = __builtin_amdgcn_sqrtf(1.0f - X2);
     const float ropw = __builtin_amdgcn_rcpf(1.0f + w);
     const float t = -0.5f * X2 * ropw;
     const float u = 1.0f + t;
-    const float lp = (u == 1.0f) ? t : kLn2 * __builtin_amdgcn_logf(u) * t * __builtin_amdgcn_rcpf(u - 1.0f);
-    g = fmaf(-L * X2, ropw, lp) * __builtin_amdgcn_rcpf(w);
+    // log1p(t) / (ln2/2) = 2 log2(1+t) t / ((1+t) - 1)
+    const float lp = (u == 1.0f) ? t * kInvA : 2.0f * __builtin_amdgcn_logf(u) * t * __builtin_amdgcn_rcpf(u - 1.0f);
+    g = fmaf(-Lp * X2, ropw, lp) * __builtin_amdgcn_rcpf(w);
   }
-  return X2 > 0.f ? g * __builtin_amdgcn_rcpf(X2) : 0.f;
+  return X2 > 0.f ? g * kNfwNearScale * __builtin_amdgcn_rcpf(X2) : 0.f;
 }
 
-// Far-field g(x)/x^2 for x^2 = X2 >= 1 and l2 = log2(X2): with y = rsq(X2),
-// g = (ln2/2) log2(X2) + psi(y), psi the fitted polynomial, and g/x^2 = g y^2.
+// Far-field g'(x)/x^2 for x^2 = X2 >= 1 and l2 = log2(X2): with y = rsq(X2),
+// g' = log2(X2) + P(y), P ~ psi/(ln2/2) the fitted polynomial (P(0) ~ -2),
+// and g'/x^2 = g' y^2.
 __device__ __forceinline__ float nfw_far_g_over_x2(float X2, float l2) {
   const float y = __builtin_amdgcn_rsqf(X2);
-  float p = kNfwPsi[0];
+  float p = kNfwP[0];
 #pragma unroll
-  for (int i = 1; i <= JT_NFW_POLY_DEGREE; ++i) p = fmaf(p, y, kNfwPsi[i]);
-  return fmaf(l2, 0.5f * kLn2, p) * (y * y);
+  for (int i = 1; i <= JT_NFW_POLY_DEGREE; ++i) p = fmaf(p, y, kNfwP[i]);
+  return (l2 + p) * (y * y);
 }
 
 // Four (sub-pixel, subhalo) pairs: adds alpha_k, k = 0..3, to (sx, sy).  All

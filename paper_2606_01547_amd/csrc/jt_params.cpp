@@ -11,8 +11,6 @@
 namespace jt {
 
 namespace {
-constexpr double kLn2d = 0.69314718055994530942;
-
 bool finite(double v) { return std::isfinite(v); }
 }  // namespace
 
@@ -82,15 +80,21 @@ jt_status make_macro(const jt_lens* lens, MacroC& m) {
     const double f = std::sqrt((1.0 - s.q) * (1.0 + s.q));
     const double pref = s.theta_E * std::sqrt(s.q);
     m.has_sie = 1;
-    m.sie_series = f < 1e-2;
+    m.sie_series = f < 1e-3;
     m.cx = (float)s.cx;
     m.cy = (float)s.cy;
     m.cphi = (float)std::cos(s.phi);
     m.sphi = (float)std::sin(s.phi);
     m.q2 = (float)(s.q * s.q);
     m.f = (float)f;
-    m.pref = (float)pref;
-    m.pref_f = f > 0.0 ? (float)(pref / f) : 0.f;
+    m.dcx = s.cx;
+    m.dcy = s.cy;
+    m.dcphi = std::cos(s.phi);
+    m.dsphi = std::sin(s.phi);
+    m.dq2 = s.q * s.q;
+    m.df = f;
+    m.dpref = pref;
+    m.dpref_f = f > 0.0 ? pref / f : 0.0;
     m.theta_E = (float)s.theta_E;
     m.q = (float)s.q;
     m.sqrt_q = (float)std::sqrt(s.q);
@@ -101,6 +105,8 @@ jt_status make_macro(const jt_lens* lens, MacroC& m) {
     m.has_shear = 1;
     m.g1 = (float)lens->shear.gamma1;
     m.g2 = (float)lens->shear.gamma2;
+    m.dg1 = lens->shear.gamma1;
+    m.dg2 = lens->shear.gamma2;
   }
   const jt_point_masses& pm = lens->pm;
   if (pm.n < 0 || pm.n > JT_MAX_POINT_MASS)
@@ -109,9 +115,9 @@ jt_status make_macro(const jt_lens* lens, MacroC& m) {
   for (int k = 0; k < pm.n; ++k) {
     if (!finite(pm.x[k]) || !finite(pm.y[k]) || !finite(pm.theta_E[k]))
       return fail(JT_EINVAL, "point mass %d: non-finite parameter", k);
-    m.pm_x[k] = (float)pm.x[k];
-    m.pm_y[k] = (float)pm.y[k];
-    m.pm_te2[k] = (float)(pm.theta_E[k] * pm.theta_E[k]);
+    m.pm_x[k] = pm.x[k];
+    m.pm_y[k] = pm.y[k];
+    m.pm_te2[k] = pm.theta_E[k] * pm.theta_E[k];
   }
   m.npm = pm.n;
   if (lens->nfw.n < 0) return fail(JT_EINVAL, "NFW: n = %d", lens->nfw.n);
@@ -129,7 +135,7 @@ jt_status pack_subhalos_host(int n, const float* x, const float* y, const float*
       return fail(JT_EINVAL, "subhalo %d: non-finite parameter", i);
     if (!(rs[i] > 0.0f) || !std::isfinite(rs[i])) return fail(JT_EINVAL, "subhalo %d: Rs = %g", i, (double)rs[i]);
     const double r = rs[i];
-    out[i] = SubRec{x[i], y[i], (float)(1.0 / (r * r)), (float)((double)ars[i] / ((1.0 - kLn2d) * r))};
+    out[i] = SubRec{x[i], y[i], (float)(1.0 / (r * r)), (float)(kNfwRecScale * (double)ars[i] / ((1.0 - kLn2d) * r))};
   }
   return JT_OK;
 }

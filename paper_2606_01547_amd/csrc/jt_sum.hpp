@@ -57,22 +57,20 @@ __device__ __forceinline__ float4 subhalo_range_sum(float tx, float ty, const Su
   return make_float4(hx, lx, hy, ly);
 }
 
-// macro + sum of the quarter partials, in quarter order.
-__device__ __forceinline__ void combine_deflection(float mx, float my, const float4* q, int stride,
-                                                   float& ax, float& ay) {
-  float hx = 0.f, lx = 0.f, hy = 0.f, ly = 0.f;
+// Total deflection in FP64 at the sub-pixel (tx, ty): the macro lens plus the
+// (hi, lo) quarter partials of the subhalo sum, added in quarter order.
+__device__ __forceinline__ void total_deflection64(const MacroC& mc, double tx, double ty, const float4* q,
+                                                   int stride, double& ax, double& ay) {
+  macro_deflection64(mc, tx, ty, ax, ay);
+  double sx = 0.0, sy = 0.0;
 #pragma unroll
   for (int i = 0; i < kQuarters; ++i) {
     const float4 v = q[i * stride];
-    two_sum_acc(hx, lx, v.x);
-    lx += v.y;
-    two_sum_acc(hy, ly, v.z);
-    ly += v.w;
+    sx += (double)v.x + (double)v.y;
+    sy += (double)v.z + (double)v.w;
   }
-  two_sum_acc(mx, lx, hx);
-  two_sum_acc(my, ly, hy);
-  ax = mx + lx;
-  ay = my + ly;
+  ax += sx;
+  ay += sy;
 }
 
 // Per-block quarter partials: [quarter][slot], slot < 256 / kSplit.

@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256) void k_prep_subhalos(int n, int padded, const 
   s.x = x[i];
   s.y = y[i];
   s.c1 = (float)(1.0 / (r * r));
-  s.c2 = (float)((double)ars[i] / ((1.0 - 0.69314718055994530942) * r));
+  s.c2 = (float)(kNfwRecScale * (double)ars[i] / ((1.0 - kLn2d) * r));
   out[i] = s;
 }
 
@@ -60,11 +60,10 @@ __global__ __launch_bounds__(256) void k_ray_shoot(int n, const float* __restric
   subhalo_quarters<kSplit>(tx, ty, sub, nloop, g, slot, scratch);
   __syncthreads();
   if (g == 0 && valid) {
-    float mx, my, ax, ay;
-    macro_deflection(mc, tx, ty, mx, my);
-    combine_deflection(mx, my, &scratch.q[0][slot], kW, ax, ay);
-    ox[i] = kAlpha ? ax : tx - ax;
-    oy[i] = kAlpha ? ay : ty - ay;
+    double ax, ay;
+    total_deflection64(mc, tx, ty, &scratch.q[0][slot], kW, ax, ay);
+    ox[i] = (float)(kAlpha ? ax : (double)tx - ax);
+    oy[i] = (float)(kAlpha ? ay : (double)ty - ay);
   }
 }
 
@@ -85,7 +84,8 @@ __global__ __launch_bounds__(256) void k_source_sb(int n, const float* __restric
 struct SubPixel {
   int pixel;             // global pixel index (0 when invalid)
   bool valid;
-  float tx, ty;          // correctly rounded FP32 sub-pixel centre
+  double dx, dy;         // sub-pixel centre (FP64)
+  float tx, ty;          // its correctly rounded FP32 value (pair loop, lens light)
 };
 
 __device__ __forceinline__ SubPixel subpixel_of(const GridC& g, int block, int t) {
@@ -100,8 +100,10 @@ __device__ __forceinline__ SubPixel subpixel_of(const GridC& g, int block, int t
   const int col = sp.pixel - row * g.nx;
   const int a = si / g.s;
   const int b = si - a * g.s;
-  sp.tx = (float)(g.ox + g.step * ((double)(col * g.s + b) + 0.5));
-  sp.ty = (float)(g.oy + g.step * ((double)(row * g.s + a) + 0.5));
+  sp.dx = g.ox + g.step * ((double)(col * g.s + b) + 0.5);
+  sp.dy = g.oy + g.step * ((double)(row * g.s + a) + 0.5);
+  sp.tx = (float)sp.dx;
+  sp.ty = (float)sp.dy;
   return sp;
 }
 
@@ -121,10 +123,9 @@ __device__ __forceinline__ void simulate_block(const GridC& g, const MacroC& mc,
   subhalo_quarters<kSplit>(sp.tx, sp.ty, sub, nloop, grp, t, scratch);
   __syncthreads();
   if (grp == 0) {
-    float mx, my, ax, ay;
-    macro_deflection(mc, sp.tx, sp.ty, mx, my);
-    combine_deflection(mx, my, &scratch.q[0][t], kW, ax, ay);
-    float v = sersic_sum(src, sp.tx - ax, sp.ty - ay);
+    double ax, ay;
+    total_deflection64(mc, sp.dx, sp.dy, &scratch.q[0][t], kW, ax, ay);
+    float v = sersic_sum(src, (float)(sp.dx - ax), (float)(sp.dy - ay));
     if (ll.n > 0) v += sersic_sum(ll, sp.tx, sp.ty);
     red[t] = v;
   }
@@ -169,9 +170,6 @@ __global__ __launch_bounds__(256) void k_simulate_desc(const ImageDesc* __restri
   simulate_block<kSplit>(d.g, d.mc, d.sub, d.nloop, d.src, d.ll, d.img, blk, scratch, red);
 }
 
-// Direct convolution: 32 x 8 outputs per block; the input window of a chunk of
-// up to kConvRows kernel rows is staged in LDS (dynamic size), kernel weights
-// are read with uniform indices (scalar loads).
 // Direct convolution tiles: 64 x 4 outputs per block of kW waves.  Thread
 // (q, r, w) computes the four outputs (i0 + r, j0 + 4q .. 4q + 3) over the
 // kernel rows a = w, w + kW, ... of each staged chunk: wave w owns 1/kW of the
@@ -408,7 +406,7 @@ __global__ __launch_bounds__(256) void k_prep_subhalos_batched(int n, int record
   }
   const size_t j = (size_t)b * n + i;
   const double r = rs[j];
-  o[i] = SubRec{x[j], y[j], (float)(1.0 / (r * r)), (float)((double)ars[j] / ((1.0 - 0.69314718055994530942) * r))};
+  o[i] = SubRec{x[j], y[j], (float)(1.0 / (r * r)), (float)(kNfwRecScale * (double)ars[j] / ((1.0 - kLn2d) * r))};
 }
 
 hipError_t launch_prep_subhalos_batched(int B, int n, const float* x, const float* y, const float* rs,
