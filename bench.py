@@ -103,7 +103,7 @@ def serving_bench(ctx, n_requests, large_every, seed=1003):
         pairs += sc.grid.nx * sc.grid.ny * sc.grid.supersample ** 2 * sc.lens.nfw.n
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t_gen
-    cfg = dict(hbm_budget_bytes=4 << 30, max_batch_images=64, max_batch_pairs=4e9, max_inflight_batches=4,
+    cfg = dict(hbm_budget_bytes=4 << 30, max_batch_images=64, max_batch_pairs=4e9, max_inflight_batches=8,
                n_streams=4)
 
     def run(arrivals):

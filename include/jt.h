@@ -244,8 +244,10 @@ typedef struct jt_server jt_server;
 typedef struct {
   size_t hbm_budget_bytes;   /* device arena for in-flight request buffers (> 0) */
   int max_batch_images;      /* requests per batch (>= 1) */
-  double max_batch_pairs;    /* work cap per batch in (sub-pixel, subhalo) pairs; a
-                                larger request runs in a batch of its own (> 0) */
+  double max_batch_pairs;    /* work cap per batch in (sub-pixel, subhalo) pairs (> 0);
+                                a larger request runs in chunks of its pixel blocks of
+                                at most this much work, one such request at a time,
+                                while later requests are batched beside it */
   int max_inflight_batches;  /* batches on the device at once (>= 1) */
   int n_streams;             /* streams the batches rotate over (>= 1) */
 } jt_server_cfg;
@@ -270,6 +272,9 @@ typedef struct {
   uint64_t submitted, completed, cancelled, failed, batches;
   uint64_t arena_bytes, arena_in_use, arena_peak;
   double device_seconds;     /* simulated executor: modelled device time */
+  double wait_seconds;       /* sum over finished requests of submission -> launch */
+  double run_seconds;        /* sum over finished requests of launch -> completion */
+  double max_wait_seconds;   /* longest submission -> launch */
 } jt_server_stats;
 
 /* Server on the device of ctx; starts its scheduling thread. */

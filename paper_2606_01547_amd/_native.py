@@ -87,7 +87,8 @@ class JtRequest(ctypes.Structure):
 class JtServerStats(ctypes.Structure):
     _fields_ = [("submitted", c_uint64), ("completed", c_uint64), ("cancelled", c_uint64), ("failed", c_uint64),
                 ("batches", c_uint64), ("arena_bytes", c_uint64), ("arena_in_use", c_uint64),
-                ("arena_peak", c_uint64), ("device_seconds", c_double)]
+                ("arena_peak", c_uint64), ("device_seconds", c_double), ("wait_seconds", c_double),
+                ("run_seconds", c_double), ("max_wait_seconds", c_double)]
 
 
 TICKET_QUEUED, TICKET_RUNNING, TICKET_DONE, TICKET_CANCELLED, TICKET_FAILED = range(5)

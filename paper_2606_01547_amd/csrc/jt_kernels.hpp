@@ -44,11 +44,16 @@ hipError_t launch_prep_subhalos_batched(int B, int n, const float* x, const floa
                                         const float* ars, SubRec* out, hipStream_t st);
 
 // ---- FFT convolution (fft.hip) ----
-// Cost model of the direct/FFT choice (method 0): direct FMAs per second,
-// padded FFT points per second and a fixed launch cost of the FFT pipeline.
-constexpr double kConvDirectFmaPerS = 3.0e13;
-constexpr double kConvFftPointsPerS = 2.0e10;
+// Cost model of the direct/FFT choice (method 0), fitted to kernel times on
+// MI355X (images 100^2..1000^2, k = 3..255):
+//   direct: kConvDirectFixedS + nx ny k^2 / min(kConvDirectFmaPerS, tiles * kConvDirectFmaPerTileS)
+//           (small images have too few 64 x 4 tiles to fill the chip)
+//   FFT:    kConvFftFixedS + Nx Ny / kConvFftPointsPerS (padded power-of-two sizes)
+constexpr double kConvDirectFixedS = 6e-6;
+constexpr double kConvDirectFmaPerS = 1.55e13;
+constexpr double kConvDirectFmaPerTileS = 5e10;
 constexpr double kConvFftFixedS = 30e-6;
+constexpr double kConvFftPointsPerS = 1.45e10;
 bool conv_prefers_fft(int nx, int ny, int k);
 constexpr int kFftMinN = 16, kFftMaxN = 2048;
 // Padded power-of-two length for an image side n and kernel side k.

@@ -1,6 +1,7 @@
 // The compute entry points of the C ABI: ray shooting, surface brightness,
 // convolution and the fused simulation.  Each validates its arguments (no
 // launch on error) and enqueues kernels on the caller's stream.
+#include <algorithm>
 #include <cmath>
 
 #include "jt_host.hpp"
@@ -44,14 +45,15 @@ jt_status check_conv_args(const float* img, int nx, int ny, const float* psf, in
 }  // namespace
 
 namespace jt {
-// Direct or FFT for method 0: the FFT path once its modelled time is lower
-// (direct: n_x n_y k^2 FMAs; FFT: ~8 padded transforms' worth of passes over
-// Nx Ny complex values), or when the direct path cannot take k.
+// Direct or FFT for method 0: the FFT path once its modelled time is lower,
+// or when the direct path cannot take k.
 bool conv_prefers_fft(int nx, int ny, int k) {
   const bool fft_ok = fft_size_for(nx, k) <= kFftMaxN && fft_size_for(ny, k) <= kFftMaxN;
   if (!fft_ok) return false;
   if (k > JT_MAX_PSF) return true;
-  const double direct_s = (double)nx * ny * k * (double)k / kConvDirectFmaPerS;
+  const double tiles = (double)conv_tiles_x(nx) * conv_tiles_y(ny);
+  const double rate = std::min(kConvDirectFmaPerS, tiles * kConvDirectFmaPerTileS);
+  const double direct_s = kConvDirectFixedS + (double)nx * ny * k * (double)k / rate;
   const double N2 = (double)fft_size_for(nx, k) * fft_size_for(ny, k);
   const double fft_s = kConvFftFixedS + N2 / kConvFftPointsPerS;
   return fft_s < direct_s;

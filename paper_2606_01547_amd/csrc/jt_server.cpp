@@ -3,6 +3,18 @@
 // (one launch of the fused kernel over a (request, pixel block) tile list and
 // one convolution launch per batch).  Several batches are in flight on
 // separate streams; new requests keep being admitted while others run.
+//
+// A request whose work exceeds the per-batch cap and that has more than two
+// minimum chunks of pixel blocks runs in chunks instead (a smaller one over
+// the cap forms a batch of its own): each chunk is a launch of at least
+// kChunkMinBlocks blocks
+// (two rounds of wave slots) and otherwise about the cap, all on one stream
+// with two chunks queued at a time, and the convolution follows as a launch of
+// its own once every chunk has completed.  The hardware dispatches every
+// workgroup of a queued kernel before it turns to another queue, but switches
+// at kernel boundaries of one queue: batches of the requests behind a large
+// one therefore start at the next chunk boundary instead of after the whole
+// image.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -26,6 +38,15 @@ using Clock = std::chrono::steady_clock;
 namespace {
 
 size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Smallest chunk of a chunked request: 4096 blocks of 4 waves, two full rounds
+// of wave slots on 256 CUs at 8 waves per SIMD.
+constexpr int kChunkMinBlocks = 4096;
+
+// Pinned host memory for the batches' descriptor uploads.  Each batch keeps its
+// own slice until it completes, so forming a batch never waits for a copy
+// queued behind earlier work on the same stream.
+constexpr size_t kStagingBytes = 64u << 20;
 
 // First-fit allocator over [0, size).
 struct Arena {
@@ -80,18 +101,35 @@ struct Req {
   size_t footprint = 0;
   double pairs = 0;
   int state = JT_TICKET_QUEUED;
-  Clock::time_point t_submit, t_done;
+  Clock::time_point t_submit, t_launch, t_done;
+  // chunked (large) requests
+  bool chunked = false;
+  int split = 1, ppb = 1;          // fixed block shape of all its chunks
+  int blocks = 0, next_block = 0;  // pixel blocks in all, first not yet launched
+  int chunk_blocks = 1;            // blocks per chunk
+  int chunks_inflight = 0;
+  bool conv_launched = false;
+  bool failed = false;
+  int stream = 0;                  // every chunk runs on this stream
+  size_t img_off = 0, img_bytes = 0;  // arena block of its unconvolved image
 };
 
 struct Batch {
-  std::vector<Req*> reqs;
+  size_t st_off = 0, st_bytes = 0; // slice of the pinned staging arena
+  std::vector<Req*> reqs;          // whole requests, or the one chunked request
+  bool chunk = false;              // a chunk of reqs[0]: blocks [blk0, blk1)
+  int blk0 = 0, blk1 = 0;
+  bool conv = false;               // the convolution of chunked request reqs[0]
   size_t off = 0, bytes = 0;
   double pairs = 0;
   int stream = 0;
-  std::atomic<bool> done{false};
+  hipEvent_t ev = nullptr;         // recorded after the batch's last kernel
+  bool done = false;               // set when the launch failed
   bool failed = false;
   Clock::time_point t_done;
-  Clock::time_point sim_done;
+  Clock::time_point sim_done;      // simulated device: completion time once known
+  double sim_left = 0;             // simulated device: seconds of work left alone on the device
+  bool sim_fin = false;
   jt_server* srv = nullptr;
 };
 
@@ -107,6 +145,22 @@ size_t request_footprint(const GridC& g, int k) {
 
 double request_pairs(const GridC& g, int nloop) {
   return (double)g.nx * g.ny * g.s2 * (double)(nloop + 16);
+}
+
+// Host-side header of a request inside a batch: its footprint without the
+// unconvolved image (descriptors and tile lists, uploaded through staging).
+size_t header_bytes(const Req* r) {
+  return r->footprint - (r->k ? a256(4 * (size_t)r->g.nx * r->g.ny) : 0);
+}
+
+// Device bytes of one chunk batch (descriptor and tile list) and of the
+// convolution batch of a chunked request (descriptor and tiles).
+size_t chunk_footprint(int chunk_blocks) {
+  return a256(sizeof(ImageDesc)) + a256(8 * (size_t)chunk_blocks);
+}
+
+size_t conv_footprint(const GridC& g) {
+  return a256(sizeof(ConvDesc)) + a256(16 * (size_t)conv_tiles_x(g.nx) * conv_tiles_y(g.ny));
 }
 
 }  // namespace
@@ -125,33 +179,38 @@ struct jt_server {
   char* arena_dev = nullptr;
   std::vector<hipStream_t> streams;
   int next_stream = 0;
+  std::vector<Req*> active;         // chunked requests in progress
+  size_t rr = 0;                    // round robin over them
+  int chunk_batches = 0;            // their chunk and convolution batches in flight
+  Arena stage;                      // offsets into stage_host
+  char* stage_host = nullptr;
+  std::vector<hipEvent_t> events;   // completion events not in use
   uint64_t next_ticket = 1;
   jt_server_stats st{};
-  Clock::time_point sim_free;
+  Clock::time_point sim_last;       // simulated device: last advance
   bool stop = false;
   std::thread thread;
 
   void run();
+  void sim_advance(Clock::time_point now);
+  double sim_next_completion();
   void launch_ready();
   void complete_finished();
+  void finish_request(Req* r, bool failed, Clock::time_point t);
+  bool launch_batch(std::unique_ptr<Batch> bp);
   jt_status launch_hip(Batch& b);
+  jt_status launch_chunk_hip(Batch& b);
+  jt_status launch_conv_hip(Batch& b);
+  jt_status upload(Batch& b, const char* host, size_t bytes, void* dev, hipStream_t s);
+  int small_stream();
 };
 
-namespace {
-
-// Runs on a HIP runtime thread when the stream reaches the end of the batch.
-// The batch may be freed by the scheduler as soon as `done` is set, so it is
-// not touched afterwards; the server outlives the callback because
-// jt_server_destroy synchronises every stream before freeing it.
-void on_batch_done(void* p) {
-  Batch* b = (Batch*)p;
-  jt_server* srv = b->srv;
-  b->t_done = Clock::now();
-  b->done.store(true, std::memory_order_release);
-  srv->cv.notify_all();
+// Copies the batch's header bytes through its staging slice.
+jt_status jt_server::upload(Batch& b, const char* host, size_t bytes, void* dev, hipStream_t s) {
+  if (bytes > b.st_bytes) return fail(JT_EDEVICE, "server: staging slice too small (internal)");
+  std::memcpy(stage_host + b.st_off, host, bytes);
+  return check_hip(hipMemcpyAsync(dev, stage_host + b.st_off, bytes, hipMemcpyHostToDevice, s), "hipMemcpyAsync(batch)");
 }
-
-}  // namespace
 
 jt_status jt_server::launch_hip(Batch& b) {
   JT_TRY(ctx_enter(ctx));
@@ -222,7 +281,7 @@ jt_status jt_server::launch_hip(Batch& b) {
   if (ncon) std::memcpy(host.data() + o_cd, cdescs.data(), sizeof(ConvDesc) * ncon);
   std::memcpy(host.data() + o_t, tiles.data(), sizeof(int2) * ntiles);
   if (nctiles) std::memcpy(host.data() + o_ct, ctiles.data(), sizeof(int4) * nctiles);
-  JT_TRY(ctx_upload(ctx, s, base, host.data(), o_img));
+  JT_TRY(upload(b, host.data(), o_img, base, s));
   JT_TRY(timed_launch(ctx, JT_K_SIM, s, [&] {
     return launch_simulate_desc(split, (const ImageDesc*)base, (const int2*)(base + o_t), (int)ntiles, 0, s);
   }, "server simulate"));
@@ -230,88 +289,376 @@ jt_status jt_server::launch_hip(Batch& b) {
     JT_TRY(timed_launch(ctx, JT_K_CONV, s, [&] {
       return launch_conv_desc((const ConvDesc*)(base + o_cd), (const int4*)(base + o_ct), (int)nctiles, kmax, s);
     }, "server convolve"));
-  return check_hip(hipLaunchHostFunc(s, on_batch_done, &b), "hipLaunchHostFunc");
+  return check_hip(hipEventRecord(b.ev, s), "hipEventRecord(batch)");
+}
+
+jt_status jt_server::launch_chunk_hip(Batch& b) {
+  JT_TRY(ctx_enter(ctx));
+  Req* r = b.reqs[0];
+  hipStream_t s = streams[b.stream];
+  const int nt = b.blk1 - b.blk0;
+  const size_t o_t = a256(sizeof(ImageDesc));
+  const size_t end = o_t + a256(sizeof(int2) * (size_t)nt);
+  if (end > b.bytes) return fail(JT_EDEVICE, "server: chunk block too small (internal)");
+  char* base = arena_dev + b.off;
+  std::vector<char> host(end, 0);
+  ImageDesc& D = *(ImageDesc*)host.data();
+  D.g = r->g;
+  D.g.ppb = r->ppb;
+  D.mc = r->mc;
+  D.src = r->src;
+  D.ll = r->ll;
+  D.sub = r->table ? r->table : ctx_empty_table(ctx);
+  D.nloop = r->nloop;
+  D.img = r->k ? (float*)(arena_dev + r->img_off) : r->out;
+  int2* tl = (int2*)(host.data() + o_t);
+  for (int i = 0; i < nt; ++i) tl[i] = make_int2(0, b.blk0 + i);
+  JT_TRY(upload(b, host.data(), end, base, s));
+  JT_TRY(timed_launch(ctx, JT_K_SIM, s, [&] {
+    return launch_simulate_desc(r->split, (const ImageDesc*)base, (const int2*)(base + o_t), nt, 0, s);
+  }, "server simulate chunk"));
+  return check_hip(hipEventRecord(b.ev, s), "hipEventRecord(batch)");
+}
+
+jt_status jt_server::launch_conv_hip(Batch& b) {
+  JT_TRY(ctx_enter(ctx));
+  Req* r = b.reqs[0];
+  hipStream_t s = streams[b.stream];
+  const long nct = (long)conv_tiles_x(r->g.nx) * conv_tiles_y(r->g.ny);
+  const size_t o_ct = a256(sizeof(ConvDesc));
+  const size_t end = o_ct + a256(sizeof(int4) * (size_t)nct);
+  if (end > b.bytes) return fail(JT_EDEVICE, "server: convolution block too small (internal)");
+  char* base = arena_dev + b.off;
+  std::vector<char> host(end, 0);
+  *(ConvDesc*)host.data() = ConvDesc{(const float*)(arena_dev + r->img_off), r->out, r->psf, r->g.nx, r->g.ny, r->k, 0};
+  int4* ct = (int4*)(host.data() + o_ct);
+  long j = 0;
+  for (int ty = 0; ty < conv_tiles_y(r->g.ny); ++ty)
+    for (int tx = 0; tx < conv_tiles_x(r->g.nx); ++tx) ct[j++] = make_int4(0, tx, ty, 0);
+  JT_TRY(upload(b, host.data(), end, base, s));
+  JT_TRY(timed_launch(ctx, JT_K_CONV, s, [&] {
+    return launch_conv_desc((const ConvDesc*)base, (const int4*)(base + o_ct), (int)nct, r->k, s);
+  }, "server convolve"));
+  return check_hip(hipEventRecord(b.ev, s), "hipEventRecord(batch)");
+}
+
+// Simulated device, called with mu held: the first unfinished batch of each
+// stream runs, and the running batches share the device equally (a stream's
+// batches run in order, different streams overlap).
+void jt_server::sim_advance(Clock::time_point now) {
+  double dt = std::chrono::duration<double>(now - sim_last).count();
+  auto at = sim_last;
+  sim_last = now;
+  for (;;) {
+    std::vector<Batch*> run;
+    std::vector<int> seen;
+    for (auto& bp : inflight) {
+      Batch* b = bp.get();
+      if (b->sim_fin || std::find(seen.begin(), seen.end(), b->stream) != seen.end()) {
+        if (!b->sim_fin) continue;
+        continue;
+      }
+      seen.push_back(b->stream);
+      run.push_back(b);
+    }
+    if (run.empty() || dt <= 0) return;
+    const double n = (double)run.size();
+    double first = run[0]->sim_left;
+    for (Batch* b : run) first = std::min(first, b->sim_left);
+    const double t_first = first * n;          // wall time until the first finishes
+    const double step = std::min(t_first, dt);
+    for (Batch* b : run) b->sim_left -= step / n;
+    at += std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(step));
+    dt -= step;
+    bool any = false;
+    for (Batch* b : run)
+      if (b->sim_left <= 1e-12) {
+        b->sim_fin = true;
+        b->sim_done = at;
+        any = true;
+      }
+    if (!any) return;
+  }
+}
+
+// Simulated device: wall seconds until the next running batch finishes.
+double jt_server::sim_next_completion() {
+  std::vector<int> seen;
+  double best = 1.0, n = 0;
+  std::vector<double> left;
+  for (auto& bp : inflight) {
+    Batch* b = bp.get();
+    if (b->sim_fin || std::find(seen.begin(), seen.end(), b->stream) != seen.end()) continue;
+    seen.push_back(b->stream);
+    left.push_back(b->sim_left);
+  }
+  n = (double)left.size();
+  for (double l : left) best = std::min(best, l * n);
+  return left.empty() ? 1e-3 : best;
+}
+
+// Called with mu held: a request leaves the device.
+void jt_server::finish_request(Req* r, bool failed, Clock::time_point t) {
+  r->state = failed ? JT_TICKET_FAILED : JT_TICKET_DONE;
+  r->t_done = t;
+  if (failed) ++st.failed; else ++st.completed;
+  const double w = std::chrono::duration<double>(r->t_launch - r->t_submit).count();
+  st.wait_seconds += w;
+  st.max_wait_seconds = std::max(st.max_wait_seconds, w);
+  st.run_seconds += std::chrono::duration<double>(t - r->t_launch).count();
 }
 
 // Called with mu held.
 void jt_server::complete_finished() {
   const auto now = Clock::now();
+  if (!ctx) sim_advance(now);
   bool any = false;
   for (auto it = inflight.begin(); it != inflight.end();) {
     Batch& b = **it;
-    const bool fin = ctx ? b.done.load(std::memory_order_acquire) : (now >= b.sim_done);
+    bool fin = false;
+    if (!ctx) {
+      fin = b.sim_fin;
+    } else if (b.done) {
+      fin = true;
+    } else {
+      // completion is polled from the stream's event: a host callback on the
+      // stream was seen to wait for the other streams' queued work
+      const hipError_t q = hipEventQuery(b.ev);
+      if (q == hipSuccess) {
+        fin = true;
+        b.t_done = now;
+      } else if (q != hipErrorNotReady) {
+        (void)hipGetLastError();
+        fin = true;
+        b.failed = true;
+        b.t_done = now;
+      }
+    }
     if (!fin) {
       ++it;
       continue;
     }
+    if (b.ev) events.push_back(b.ev);
     const auto t = ctx ? b.t_done : b.sim_done;
-    for (Req* r : b.reqs) {
-      r->state = b.failed ? JT_TICKET_FAILED : JT_TICKET_DONE;
-      r->t_done = t;
-      if (b.failed) ++st.failed; else ++st.completed;
+    if (b.chunk || b.conv) {
+      --chunk_batches;
+      Req* r = b.reqs[0];
+      if (b.chunk) --r->chunks_inflight;
+      if (b.failed) r->failed = true;
+      // done after its convolution (or last chunk without a PSF), or after a
+      // failure once nothing of it runs
+      const bool chunks_done = r->next_block == r->blocks && r->chunks_inflight == 0;
+      const bool over = b.conv || (r->failed && r->chunks_inflight == 0) || (chunks_done && !r->k);
+      if (over) {
+        finish_request(r, r->failed, t);
+        if (r->img_bytes) arena.release(r->img_off, r->img_bytes);
+        active.erase(std::find(active.begin(), active.end(), r));
+      }
+    } else {
+      for (Req* r : b.reqs) finish_request(r, b.failed, t);
     }
     arena.release(b.off, b.bytes);
+    if (b.st_bytes) stage.release(b.st_off, b.st_bytes);
     it = inflight.erase(it);
     any = true;
   }
   if (any) done_cv.notify_all();
 }
 
-// Called with mu held: forms batches from the queue head while slots and
-// arena space allow.
+// Stream of the next batch of whole requests: round robin, avoiding the
+// streams of chunked requests in progress when another is free.
+int jt_server::small_stream() {
+  const int n = std::max(1, cfg.n_streams);
+  int sidx = next_stream;
+  for (int t = 0; t < n; ++t) {
+    const int c = (next_stream + t) % n;
+    bool used = false;
+    for (Req* a : active) used |= a->stream == c;
+    if (!used) {
+      sidx = c;
+      break;
+    }
+  }
+  next_stream = (sidx + 1) % n;
+  return sidx;
+}
+
+// Called with mu held: launches (or, on the simulated device, schedules) a
+// formed batch; false when the launch failed.
+bool jt_server::launch_batch(std::unique_ptr<Batch> bp) {
+  Batch& b = *bp;
+  b.srv = this;
+  ++st.batches;
+  bool ok = true;
+  if (ctx) {
+    if (!events.empty()) {
+      b.ev = events.back();
+      events.pop_back();
+    } else if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) {
+      b.ev = nullptr;
+    }
+  }
+  if (ctx && !b.ev) {
+    b.failed = true;
+    b.t_done = Clock::now();
+    b.done = true;
+    ok = false;
+  } else if (ctx) {
+    if ((b.chunk ? launch_chunk_hip(b) : b.conv ? launch_conv_hip(b) : launch_hip(b)) != JT_OK) {
+      // no completion callback was queued: let whatever was launched finish
+      // before the batch's arena block can be reused
+      (void)hipStreamSynchronize(streams[b.stream]);
+      b.failed = true;
+      b.t_done = Clock::now();
+      b.done = true;
+      ok = false;
+    }
+  } else {
+    const auto now = Clock::now();
+    const double dur = b.pairs / sim_rate + 20e-6;
+    sim_advance(now);
+    b.sim_left = dur;
+    st.device_seconds += dur;
+  }
+  inflight.push_back(std::move(bp));
+  return ok;
+}
+
+// Called with mu held: forms batches while slots and arena space allow.
+// Chunked requests in progress get their next chunks first (round robin, at
+// most two queued each, leaving one slot for batches of whole requests); then
+// whole requests are taken from the queue head up to the caps (a request over
+// the work cap that is not chunked forms a batch of its own).  A chunked
+// request at the head is started while fewer than max(1, n_streams - 1) are
+// in progress, and otherwise waits there (FIFO).
 void jt_server::launch_ready() {
-  while (!stop && (int)inflight.size() < cfg.max_inflight_batches && !queue.empty()) {
+  // staging slices exist only on a real device
+  auto take_stage = [&](size_t n, size_t* o) { return !ctx || n == 0 || stage.alloc(n, o); };
+  const int n_streams = std::max(1, cfg.n_streams);
+  const int max_active = std::max(1, n_streams - 1);
+  const int max_chunk_batches = std::max(1, cfg.max_inflight_batches - 1);
+  while (!stop && (int)inflight.size() < cfg.max_inflight_batches) {
+    // next chunk of a chunked request, or its convolution once every chunk
+    // has completed
+    Req* r = nullptr;
+    bool conv = false;
+    if (chunk_batches < max_chunk_batches) {
+      for (size_t i = 0; i < active.size() && !r; ++i) {
+        Req* a = active[(rr + i) % active.size()];
+        if (a->failed) continue;
+        if (a->next_block < a->blocks && a->chunks_inflight < 2) {
+          r = a;
+        } else if (a->k && !a->conv_launched && a->next_block == a->blocks && a->chunks_inflight == 0) {
+          r = a;
+          conv = true;
+        }
+        if (r) rr = (rr + i + 1) % active.size();
+      }
+    }
+    if (r) {
+      const int b0 = r->next_block, b1 = conv ? b0 : std::min(r->blocks, b0 + r->chunk_blocks);
+      const size_t bytes = conv ? conv_footprint(r->g) : chunk_footprint(b1 - b0);
+      size_t off = 0, so = 0;
+      if (!arena.alloc(bytes, &off)) return;
+      if (!take_stage(bytes, &so)) {
+        arena.release(off, bytes);
+        return;
+      }
+      auto bp = std::make_unique<Batch>();
+      bp->st_off = so;
+      bp->st_bytes = ctx ? bytes : 0;
+      bp->reqs = {r};
+      bp->off = off;
+      bp->bytes = bytes;
+      bp->stream = r->stream;
+      if (conv) {
+        bp->conv = true;
+        r->conv_launched = true;
+      } else {
+        bp->chunk = true;
+        bp->blk0 = b0;
+        bp->blk1 = b1;
+        bp->pairs = r->pairs * (double)(b1 - b0) / r->blocks;
+        r->next_block = b1;
+        ++r->chunks_inflight;
+      }
+      ++chunk_batches;
+      if (!launch_batch(std::move(bp))) r->failed = true;
+      continue;
+    }
+    if (queue.empty()) return;
+    Req* head = queue.front();
+    if (head->chunked) {
+      if ((int)active.size() >= max_active) return;  // FIFO behind it
+      // start the chunked request: its image block and stream
+      size_t off = 0;
+      const size_t img = head->k ? a256(4 * (size_t)head->g.nx * head->g.ny) : 0;
+      if (img && !arena.alloc(img, &off)) return;
+      head->img_off = off;
+      head->img_bytes = img;
+      // a stream no other chunked request uses
+      int sidx = next_stream;
+      for (int t = 0; t < n_streams; ++t) {
+        const int c = (next_stream + t) % n_streams;
+        bool used = false;
+        for (Req* a : active) used |= a->stream == c;
+        if (!used) {
+          sidx = c;
+          break;
+        }
+      }
+      head->stream = sidx;
+      next_stream = (sidx + 1) % n_streams;
+      head->state = JT_TICKET_RUNNING;
+      head->t_launch = Clock::now();
+      queue.pop_front();
+      active.push_back(head);
+      continue;
+    }
     std::vector<Req*> pick;
     double pairs = 0;
-    size_t bytes = 0;
+    size_t bytes = 0, hbytes = 0;
     for (Req* r : queue) {
       if ((int)pick.size() >= cfg.max_batch_images) break;
+      if (r->chunked) break;  // it waits at its place
       if (!pick.empty() && pairs + r->pairs > cfg.max_batch_pairs) break;
       pick.push_back(r);
       pairs += r->pairs;
       bytes += r->footprint;
+      hbytes += header_bytes(r);
     }
-    size_t off = 0;
-    while (!pick.empty() && !arena.alloc(bytes, &off)) {
+    size_t off = 0, so = 0;
+    while (!pick.empty()) {
+      if (arena.alloc(bytes, &off)) {
+        if (take_stage(hbytes, &so)) break;
+        arena.release(off, bytes);
+      }
       bytes -= pick.back()->footprint;
+      hbytes -= header_bytes(pick.back());
       pairs -= pick.back()->pairs;
       pick.pop_back();
     }
     if (pick.empty()) return;  // the head does not fit yet: wait for completions
     for (size_t i = 0; i < pick.size(); ++i) queue.pop_front();
     auto bp = std::make_unique<Batch>();
-    Batch& b = *bp;
-    b.reqs = pick;
-    b.off = off;
-    b.bytes = bytes;
-    b.pairs = pairs;
-    b.srv = this;
-    b.stream = next_stream;
-    next_stream = (next_stream + 1) % std::max(1, (int)streams.size());
-    for (Req* r : pick) r->state = JT_TICKET_RUNNING;
-    ++st.batches;
-    if (ctx) {
-      if (launch_hip(b) != JT_OK) {
-        // no completion callback was queued: let whatever was launched finish
-        // before the batch's arena block can be reused
-        (void)hipStreamSynchronize(streams[b.stream]);
-        b.failed = true;
-        b.t_done = Clock::now();
-        b.done.store(true);
-      }
-    } else {
-      const auto now = Clock::now();
-      const double dur = pairs / sim_rate + 20e-6;
-      const auto start = std::max(now, sim_free);
-      b.sim_done = start + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(dur));
-      sim_free = b.sim_done;
-      st.device_seconds += dur;
+    bp->st_off = so;
+    bp->st_bytes = ctx ? hbytes : 0;
+    bp->reqs = pick;
+    bp->off = off;
+    bp->bytes = bytes;
+    bp->pairs = pairs;
+    bp->stream = small_stream();
+    const auto tl = Clock::now();
+    for (Req* r : pick) {
+      r->state = JT_TICKET_RUNNING;
+      r->t_launch = tl;
     }
-    inflight.push_back(std::move(bp));
+    launch_batch(std::move(bp));
   }
 }
 
 void jt_server::run() {
+  if (ctx) (void)hipSetDevice(ctx->device);
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
     complete_finished();
@@ -320,13 +667,11 @@ void jt_server::run() {
     if (inflight.empty()) {
       cv.wait(lk, [&] { return stop || !queue.empty(); });
     } else if (!ctx) {
-      auto next = inflight.front()->sim_done;
-      for (auto& b : inflight) next = std::min(next, b->sim_done);
-      cv.wait_until(lk, next);
+      const double dt = sim_next_completion();
+      cv.wait_for(lk, std::chrono::duration<double>(std::max(dt, 1e-6)));
     } else {
-      // woken by batch callbacks and submissions; the timeout covers a
-      // notification that lands between the check and the wait
-      cv.wait_for(lk, std::chrono::microseconds(500));
+      // woken by submissions; in-flight batches are polled every 200 us
+      cv.wait_for(lk, std::chrono::microseconds(200));
     }
   }
 }
@@ -343,8 +688,9 @@ jt_status check_cfg(const jt_server_cfg* c) {
 
 jt_status start(jt_server* s) {
   s->arena.init(s->cfg.hbm_budget_bytes);
+  s->stage.init(kStagingBytes);
   s->st.arena_bytes = s->cfg.hbm_budget_bytes;
-  s->sim_free = Clock::now();
+  s->sim_last = Clock::now();
   s->thread = std::thread([s] { s->run(); });
   return JT_OK;
 }
@@ -359,12 +705,19 @@ extern "C" jt_status jt_server_create(jt_ctx* ctx, const jt_server_cfg* cfg, jt_
   s->ctx = ctx;
   s->cfg = *cfg;
   JT_TRY(check_hip(hipMalloc((void**)&s->arena_dev, cfg->hbm_budget_bytes), "hipMalloc(server arena)"));
+  jt_status hs = check_hip(hipHostMalloc((void**)&s->stage_host, kStagingBytes, hipHostMallocDefault),
+                           "hipHostMalloc(server staging)");
+  if (hs != JT_OK) {
+    (void)hipFree(s->arena_dev);
+    return hs;
+  }
   for (int i = 0; i < cfg->n_streams; ++i) {
     hipStream_t st = nullptr;
     jt_status e = check_hip(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
     if (e != JT_OK) {
       for (auto x : s->streams) (void)hipStreamDestroy(x);
       (void)hipFree(s->arena_dev);
+      (void)hipHostFree(s->stage_host);
       return e;
     }
     s->streams.push_back(st);
@@ -410,8 +763,26 @@ extern "C" jt_status jt_server_submit(jt_server* srv, const jt_request* req, uin
   }
   if (r->k > JT_MAX_PSF) return fail(JT_EUNSUPPORTED, "server submit: PSF side %d > %d", r->k, JT_MAX_PSF);
   r->nloop = subhalo_loop_count(r->nsub);
-  r->footprint = request_footprint(r->g, r->k);
   r->pairs = request_pairs(r->g, r->nloop);
+  // block shape as the request would run alone; chunked when over the work
+  // cap and large enough for more than two minimum chunks, otherwise a
+  // request over the cap runs as a batch of its own
+  r->split = pick_split((long)r->g.nx * r->g.ny * r->g.s2, r->g.s2, r->nloop);
+  r->ppb = (256 / r->split) / r->g.s2;
+  r->blocks = (int)(((long)r->g.nx * r->g.ny + r->ppb - 1) / r->ppb);
+  r->chunked = r->pairs > srv->cfg.max_batch_pairs && r->blocks > 2 * kChunkMinBlocks;
+  if (r->chunked) {
+    const double per_block = r->pairs / r->blocks;
+    r->chunk_blocks = (int)std::max((double)kChunkMinBlocks, std::floor(srv->cfg.max_batch_pairs / per_block));
+    r->footprint = (r->k ? a256(4 * (size_t)r->g.nx * r->g.ny) : 0) +
+                   std::max(2 * chunk_footprint(std::min(r->blocks, r->chunk_blocks)), r->k ? conv_footprint(r->g) : 0);
+  } else {
+    r->footprint = request_footprint(r->g, r->k);
+  }
+  const size_t hdr = r->chunked ? (r->k ? conv_footprint(r->g) : 0) : header_bytes(r.get());
+  if (hdr > kStagingBytes)
+    return fail(JT_ENOMEM, "server submit: request descriptors need %zu bytes of staging, %zu available", hdr,
+                kStagingBytes);
   if (r->footprint > srv->arena.size)
     return fail(JT_ENOMEM, "server submit: request needs %zu bytes, arena holds %zu", r->footprint, srv->arena.size);
   std::lock_guard<std::mutex> lk(srv->mu);
@@ -502,7 +873,9 @@ extern "C" void jt_server_destroy(jt_server* srv) {
       (void)hipStreamSynchronize(s);
       (void)hipStreamDestroy(s);
     }
+    for (auto e : srv->events) (void)hipEventDestroy(e);
     if (srv->arena_dev) (void)hipFree(srv->arena_dev);
+    if (srv->stage_host) (void)hipHostFree(srv->stage_host);
   }
   delete srv;
 }

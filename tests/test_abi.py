@@ -64,6 +64,7 @@ int main(void) {
   P(jt_lens); O(jt_lens, sie); O(jt_lens, shear); O(jt_lens, nfw); O(jt_lens, subhalo_handle); O(jt_lens, pm);
   P(jt_sersic); P(jt_light); O(jt_light, c); O(jt_light, bn_exact);
   P(jt_draws); O(jt_draws, sie); O(jt_draws, n_sub); O(jt_draws, sub_alpha_Rs); O(jt_draws, n_ll); O(jt_draws, ll);
+  P(jt_server_stats); O(jt_server_stats, device_seconds); O(jt_server_stats, max_wait_seconds);
   return 0;
 }
 """
@@ -80,7 +81,7 @@ def test_ctypes_structs_match_c_layout(tmp_path):
                                                               check=True).stdout.splitlines())
     m = {"jt_grid": nat.JtGrid, "jt_sie": nat.JtSie, "jt_shear": nat.JtShear, "jt_nfw": nat.JtNfw,
          "jt_point_masses": nat.JtPointMasses, "jt_lens": nat.JtLens, "jt_sersic": nat.JtSersic,
-         "jt_light": nat.JtLight, "jt_draws": nat.JtDraws}
+         "jt_light": nat.JtLight, "jt_draws": nat.JtDraws, "jt_server_stats": nat.JtServerStats}
     for key, val in got.items():
         if "." in key:
             t, f = key.split(".")

@@ -97,6 +97,22 @@ def test_large_request_in_the_mix(ctx):
         np.testing.assert_array_equal(_np(o), _np(ctx.simulate_scene(sc)))
 
 
+def test_chunked_requests_equal_single_requests(ctx):
+    """Requests over the work cap run as chunks of pixel blocks on one stream;
+    the image (with and without a PSF) is the same as the request alone."""
+    big1 = W.config2_scene(seed=21, n_sub=2000, npix=500, supersample=3, psf_size=21)   # 8929 blocks
+    big2 = W.config2_scene(seed=22, n_sub=3000, npix=520, supersample=3)                # 9658 blocks
+    big2.psf = None
+    small = _requests(6, seed=13)
+    scenes = [big1] + small[:3] + [big2] + small[3:]
+    outs, lat, st = _serve(ctx, scenes, None, hbm_budget_bytes=256 << 20, max_batch_images=8,
+                           max_batch_pairs=2e7, max_inflight_batches=4, n_streams=4)
+    assert st["completed"] == len(scenes) and st["failed"] == 0 and st["arena_in_use"] == 0
+    assert st["batches"] >= 3 + 1 + 3                # chunks of 4096 blocks, one convolution
+    for sc, o in zip(scenes, outs):
+        np.testing.assert_array_equal(_np(o), _np(ctx.simulate_scene(sc)))
+
+
 def test_tight_arena_serialises_but_completes(ctx):
     scenes = _requests(10, seed=11)
     outs, lat, st = _serve(ctx, scenes, None, hbm_budget_bytes=1 << 20, max_batch_images=4,

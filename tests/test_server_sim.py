@@ -54,10 +54,55 @@ def test_batches_pack_waiting_requests_up_to_the_caps():
     srv.close()
 
 
-def test_work_cap_keeps_large_requests_alone():
-    srv = _srv(max_batch_pairs=1e7, max_inflight_batches=1)
-    big = _sc(200, 3)
-    ts = [_submit(srv, big, nsub=2000) for _ in range(3)]
+def test_large_request_runs_in_chunks_beside_small_ones():
+    # 2.6e10 pairs over a 1e7 cap: 51 429 blocks of 28 pixels in chunks of
+    # 4096 blocks (13 chunks) and a convolution launch; the small requests
+    # queued behind it are batched while its chunks run (this simulated device
+    # runs batches one after another, so they wait for at most the chunks
+    # already queued), long before it ends
+    srv = _srv(max_batch_pairs=1e7, max_inflight_batches=3)
+    t_big = _submit(srv, _sc(1200, 3), nsub=2000)
+    small = [_submit(srv, _sc(), nsub=10) for _ in range(5)]
+    lat_small = [srv.wait(t) for t in small]
+    lat_big = srv.wait(t_big)
+    st = srv.stats()
+    assert st["completed"] == 6 and st["arena_in_use"] == 0
+    assert st["batches"] >= 13 + 1 + 1
+    assert max(lat_small) < 0.3 * lat_big
+    srv.close()
+
+
+def test_chunked_requests_beyond_the_stream_limit_wait_in_fifo_order():
+    # with 2 streams one chunked request runs at a time: a second waits at the
+    # head until the first is done, and the small request behind it waits too
+    srv = _srv(max_batch_pairs=1e7, max_inflight_batches=3, n_streams=2)
+    big1 = _submit(srv, _sc(600, 3), nsub=2000)     # 12 858 blocks: chunked
+    big2 = _submit(srv, _sc(600, 3), nsub=2000)
+    small = _submit(srv, _sc(), nsub=10)
+    l1, l2, ls = srv.wait(big1), srv.wait(big2), srv.wait(small)
+    assert 0.5 * l1 < ls < l2          # it waited for the first large request, not the second
+    assert srv.stats()["completed"] == 3
+    srv.close()
+
+
+def test_several_chunked_requests_run_together():
+    # with 4 streams up to 3 chunked requests are in progress at once, so the
+    # small request behind two of them is not held until they finish
+    srv = _srv(max_batch_pairs=1e7, max_inflight_batches=4, n_streams=4)
+    big = [_submit(srv, _sc(600, 3), nsub=2000) for _ in range(2)]
+    small = _submit(srv, _sc(), nsub=10)
+    ls = srv.wait(small)
+    lb = [srv.wait(t) for t in big]
+    assert ls < 0.5 * min(lb)
+    assert srv.stats()["completed"] == 3 and srv.stats()["arena_in_use"] == 0
+    srv.close()
+
+
+def test_request_over_the_cap_with_few_blocks_runs_alone():
+    # 200^2, s = 3: 5715 blocks, too few to chunk; over the cap it forms a
+    # batch of its own instead of joining the small ones
+    srv = _srv(max_batch_pairs=1e7, max_inflight_batches=1, max_batch_images=16)
+    ts = [_submit(srv, _sc(200, 3), nsub=2000) for _ in range(3)]
     for t in ts:
         srv.wait(t)
     assert srv.stats()["batches"] == 3
