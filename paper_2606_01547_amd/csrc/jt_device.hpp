@@ -192,20 +192,35 @@ __device__ __forceinline__ float nfw_near_g_over_x2(float X2, float l2) {
   return X2 > 0.f ? g * kNfwNearScale * __builtin_amdgcn_rcpf(X2) : 0.f;
 }
 
-// Far-field g'(x)/x^2 for x^2 = X2 >= 1 and l2 = log2(X2): with y = rsq(X2),
-// g' = log2(X2) + P(y), P ~ psi/(ln2/2) the fitted polynomial (P(0) ~ -2),
-// and g'/x^2 = g' y^2.
-__device__ __forceinline__ float nfw_far_g_over_x2(float X2, float l2) {
-  const float y = __builtin_amdgcn_rsqf(X2);
+// Far-field g'(x)/x^2 for x^2 = X2 >= 1, l2 = log2(X2) and y = rsq(X2):
+// g' = l2 + P(y), P ~ psi/(ln2/2) the fitted polynomial (P(0) ~ -2), and
+// g'/x^2 = g' y^2.  The short form uses the polynomial fitted on
+// [0, kNfwFastY] only.
+__device__ __forceinline__ float nfw_far_h(float l2, float y) {
   float p = kNfwP[0];
 #pragma unroll
   for (int i = 1; i <= JT_NFW_POLY_DEGREE; ++i) p = fmaf(p, y, kNfwP[i]);
   return (l2 + p) * (y * y);
 }
 
-// Four (sub-pixel, subhalo) pairs: adds alpha_k, k = 0..3, to (sx, sy).  All
-// four far-field terms are formed first; a single wave-level branch then
-// recomputes the rare near-field (X2 < 1) terms.
+__device__ __forceinline__ float nfw_far_h_short(float l2, float y) {
+  float p = kNfwPFast[0];
+#pragma unroll
+  for (int i = 1; i <= JT_NFW_FAST_DEGREE; ++i) p = fmaf(p, y, kNfwPFast[i]);
+  return (l2 + p) * (y * y);
+}
+
+__device__ __forceinline__ float nfw_far_g_over_x2(float X2, float l2) {
+  return nfw_far_h(l2, __builtin_amdgcn_rsqf(X2));
+}
+
+// Four (sub-pixel, subhalo) pairs: adds alpha_k, k = 0..3, to (sx, sy).
+// When y = Rs/r < kNfwFastY for all four (distant subhalos: nearly every
+// group) the short polynomial is used; otherwise the full one, and a second
+// branch recomputes the rare near-field (X2 < 1) terms.  The choice is made
+// per lane from its own four pairs, so a sub-pixel's result does not depend
+// on which sub-pixels share its wave; in practice the lanes of a wave agree
+// and the branches are uniform.
 __device__ __forceinline__ void nfw_pairs4(float tx, float ty, const SubRec& s0, const SubRec& s1,
                                            const SubRec& s2, const SubRec& s3, float& sx,
                                            float& sy) {
@@ -221,15 +236,27 @@ __device__ __forceinline__ void nfw_pairs4(float tx, float ty, const SubRec& s0,
   const float l1 = __builtin_amdgcn_logf(X1);
   const float l2 = __builtin_amdgcn_logf(X2);
   const float l3 = __builtin_amdgcn_logf(X3);
-  float h0 = nfw_far_g_over_x2(X0, l0);
-  float h1 = nfw_far_g_over_x2(X1, l1);
-  float h2 = nfw_far_g_over_x2(X2, l2);
-  float h3 = nfw_far_g_over_x2(X3, l3);
-  if (__builtin_expect(fminf(fminf(X0, X1), fminf(X2, X3)) < 1.0f, 0)) {
-    if (X0 < 1.0f) h0 = nfw_near_g_over_x2(X0, l0);
-    if (X1 < 1.0f) h1 = nfw_near_g_over_x2(X1, l1);
-    if (X2 < 1.0f) h2 = nfw_near_g_over_x2(X2, l2);
-    if (X3 < 1.0f) h3 = nfw_near_g_over_x2(X3, l3);
+  const float y0 = __builtin_amdgcn_rsqf(X0);
+  const float y1 = __builtin_amdgcn_rsqf(X1);
+  const float y2 = __builtin_amdgcn_rsqf(X2);
+  const float y3 = __builtin_amdgcn_rsqf(X3);
+  float h0, h1, h2, h3;
+  if (fmaxf(fmaxf(y0, y1), fmaxf(y2, y3)) < kNfwFastY) {
+    h0 = nfw_far_h_short(l0, y0);
+    h1 = nfw_far_h_short(l1, y1);
+    h2 = nfw_far_h_short(l2, y2);
+    h3 = nfw_far_h_short(l3, y3);
+  } else {
+    h0 = nfw_far_h(l0, y0);
+    h1 = nfw_far_h(l1, y1);
+    h2 = nfw_far_h(l2, y2);
+    h3 = nfw_far_h(l3, y3);
+    if (fminf(fminf(X0, X1), fminf(X2, X3)) < 1.0f) {
+      if (X0 < 1.0f) h0 = nfw_near_g_over_x2(X0, l0);
+      if (X1 < 1.0f) h1 = nfw_near_g_over_x2(X1, l1);
+      if (X2 < 1.0f) h2 = nfw_near_g_over_x2(X2, l2);
+      if (X3 < 1.0f) h3 = nfw_near_g_over_x2(X3, l3);
+    }
   }
   sx = fmaf(h0 * s0.c2, dx0, sx);
   sy = fmaf(h0 * s0.c2, dy0, sy);
