@@ -291,7 +291,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--latency-samples", type=int, default=200)
-    ap.add_argument("--cpu-rows", type=int, default=10, help="pixel rows of the oracle sample (0 = skip)")
+    ap.add_argument("--cpu-rows", type=int, default=30, help="pixel rows of the oracle sample (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=4096, help="serving stream length (0 = skip)")
     ap.add_argument("--serve-large-every", type=int, default=512,
                     help="every n-th request is a large 1000x1000 image (0 = none)")
