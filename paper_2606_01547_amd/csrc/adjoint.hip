@@ -19,7 +19,8 @@
 
 namespace jt {
 
-static_assert(kQuarters == kQuartersHost, "host and device quarter counts differ");
+// Parts of the subhalo-major pass over sub-pixel records (summed in order).
+constexpr int kRecParts = kRecPartsHost;
 
 constexpr float kCapaccioliSlope = 1.9992f;   // d b_n / d n of the Capaccioli fit
 
@@ -163,12 +164,13 @@ __device__ __forceinline__ float wave_sum(float v) {
 }
 
 template <int kSplit>
-__global__ __launch_bounds__(256) void k_grad_pixel(const ImageDesc* __restrict__ descs, int bpi,
-                                                   const float* __restrict__ lamU, float4* __restrict__ rec,
-                                                   int rec_stride, float* __restrict__ part, int P) {
-  __shared__ QuarterScratch<kSplit> scratch;
+__global__ __launch_bounds__(split_threads(kSplit)) void k_grad_pixel(const ImageDesc* __restrict__ descs, int bpi,
+                                                                     const float* __restrict__ lamU,
+                                                                     float4* __restrict__ rec, int rec_stride,
+                                                                     float* __restrict__ part, int P) {
+  __shared__ RangeScratch<kSplit> scratch;
   __shared__ float wsum[4][kGradMaxP];
-  constexpr int kW = 256 / kSplit;
+  constexpr int kW = split_lanes(kSplit);
   const int di = blockIdx.x / bpi;
   const int blk = blockIdx.x - di * bpi;
   const ImageDesc& d = descs[di];
@@ -186,14 +188,15 @@ __global__ __launch_bounds__(256) void k_grad_pixel(const ImageDesc* __restrict_
   const double tx64 = g.ox + g.step * ((double)(col * g.s + b) + 0.5);
   const double ty64 = g.oy + g.step * ((double)(row * g.s + a) + 0.5);
   const float tx = (float)tx64, ty = (float)ty64;
-  subhalo_quarters<kSplit>(tx, ty, d.sub, d.nloop, grp, t, scratch);
+  double sx = 0.0, sy = 0.0;
+  subhalo_ranges<kSplit>(tx, ty, d.sub, d.nloop, grp, t, scratch, sx, sy);
   __syncthreads();
   float c[kGradMaxP];
 #pragma unroll
   for (int i = 0; i < kGradMaxP; ++i) c[i] = 0.f;
   if (grp == 0) {
     double ax, ay;
-    total_deflection64(d.mc, tx64, ty64, &scratch.q[0][t], kW, ax, ay);
+    total_deflection64<kSplit>(d.mc, tx64, ty64, scratch, t, sx, sy, ax, ay);
     const float bx = (float)(tx64 - ax), by = (float)(ty64 - ay);
     const float lam = valid ? lamU[(size_t)di * npix + pp] * g.area_over_s2 : 0.f;
     float Gx = 0.f, Gy = 0.f, dd[7], gx, gy;
@@ -324,7 +327,7 @@ __device__ __forceinline__ void nfw_h_dh(float X2, float& h, float& dh) {
   dh = fmaf(oneF * kInv2U, __builtin_amdgcn_rcpf(X2 - 1.0f), -h) * y2;
 }
 
-// grid (ceil(n / 64), B, kQuarters); lane = subhalo.  Writes the quarter
+// grid (ceil(n / 64), B, kRecParts); lane = subhalo.  Writes the part
 // partial (x, y, alpha_Rs) gradients to gpart[q][b][k][3].
 __global__ __launch_bounds__(64) void k_grad_subhalo(const ImageDesc* __restrict__ descs,
                                                     const float4* __restrict__ rec, int rec_stride,
@@ -336,7 +339,7 @@ __global__ __launch_bounds__(64) void k_grad_subhalo(const ImageDesc* __restrict
   // alpha / alpha_Rs = c2n * h * d  (h in units of ln2/2)
   const float c2n = sqrtf(s.c1) * (float)(kNfwRecScale / (1.0 - kLn2d));
   const float4* __restrict__ r = rec + (size_t)b * rec_stride;
-  const int kb = quarter_bound(nrec_loop, q), ke = quarter_bound(nrec_loop, q + 1);
+  const int kb = part_bound(nrec_loop, kRecParts, q), ke = part_bound(nrec_loop, kRecParts, q + 1);
   float hx = 0.f, lx = 0.f, hy = 0.f, ly = 0.f, ha = 0.f, la = 0.f;
   float4 n0 = r[kb], n1 = r[kb + 1], n2 = r[kb + 2], n3 = r[kb + 3];
   for (int j0 = kb; j0 < ke; j0 += 64) {
@@ -404,7 +407,7 @@ __global__ __launch_bounds__(256) void k_grad_finalize(int B, int P, int bpi, co
   } else if (i < nm + nl + ns && g_sub) {
     const long e = i - nm - nl;
     float hi = 0.f, lo = 0.f;
-    for (int q = 0; q < kQuarters; ++q) two_sum_acc(hi, lo, gpart[(size_t)q * ns + e]);
+    for (int q = 0; q < kRecParts; ++q) two_sum_acc(hi, lo, gpart[(size_t)q * ns + e]);
     g_sub[e] = hi + lo;
   }
 }
@@ -423,8 +426,9 @@ hipError_t launch_residual(int B, int npix, const float* model, const float* dat
 hipError_t launch_grad_pixel(int split, int B, int bpi, const ImageDesc* descs, const float* lamU, float4* rec,
                              int rec_stride, float* part, int P, hipStream_t st) {
   const dim3 grid((unsigned)((long)B * bpi));
-#define JT_GP(S) hipLaunchKernelGGL((k_grad_pixel<S>), grid, dim3(256), 0, st, descs, bpi, lamU, rec, rec_stride, part, P)
-  if (split == 1) JT_GP(1); else if (split == 2) JT_GP(2); else JT_GP(4);
+#define JT_GP(S) hipLaunchKernelGGL((k_grad_pixel<S>), grid, dim3(split_threads(S)), 0, st, descs, bpi, lamU, rec, \
+                                    rec_stride, part, P)
+  if (split == 1) JT_GP(1); else if (split == 2) JT_GP(2); else if (split == 4) JT_GP(4); else JT_GP(8);
 #undef JT_GP
   return hipGetLastError();
 }
@@ -432,7 +436,7 @@ hipError_t launch_grad_pixel(int split, int B, int bpi, const ImageDesc* descs, 
 hipError_t launch_grad_subhalo(int B, int n, const ImageDesc* descs, const float4* rec, int rec_stride,
                                int nrec_loop, float* gpart, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_grad_subhalo, dim3((n + 63) / 64, B, kQuarters), dim3(64), 0, st, descs, rec, rec_stride,
+  hipLaunchKernelGGL(k_grad_subhalo, dim3((n + 63) / 64, B, kRecParts), dim3(64), 0, st, descs, rec, rec_stride,
                      nrec_loop, n, gpart);
   return hipGetLastError();
 }

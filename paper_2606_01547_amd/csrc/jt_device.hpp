@@ -31,6 +31,13 @@ constexpr double kRsqBias = -7.4e-9;
 constexpr double kNfwRecScale = 0.5 * kLn2d * (1.0 - kLog2Bias) * (1.0 - 2.0 * kRsqBias);
 constexpr float kNfwNearScale = (float)(1.0 / ((1.0 - kLog2Bias) * (1.0 - 2.0 * kRsqBias)));
 
+// Launch shape of the subhalo sum: `split` wave-groups share the records of
+// one set of sub-pixels; a group has split_lanes(split) lanes (a multiple of
+// the wave size, so record reads are wave-uniform) and a block
+// split_threads(split) threads.
+__host__ __device__ constexpr int split_lanes(int split) { return split <= 4 ? 256 / split : 64; }
+__host__ __device__ constexpr int split_threads(int split) { return split <= 4 ? 256 : 64 * split; }
+
 // ---------------------------------------------------------------------------
 // kernel constants
 // ---------------------------------------------------------------------------
@@ -68,7 +75,7 @@ struct LightC {
 // correctly rounded FP32 value of the exact grid.
 struct GridC {
   int nx, ny, s, s2;
-  int ppb;               // whole pixels per 256-thread block: floor(256 / s^2)
+  int ppb;               // whole pixels per wave-group: floor(split_lanes(split) / s^2)
   double ox, oy, step;   // ox = x0 - d nx / 2, step = d / s
   float area_over_s2;    // d^2 / s^2
 };

@@ -58,7 +58,7 @@ jt_status make_batch(const jt_grid* grid, const jt_draws* d, bool for_grad, Batc
   bt.nsubpix = bt.npix * bt.g.s2;
   if ((double)bt.B * bt.nsubpix > 2147483647.0) return fail(JT_EUNSUPPORTED, "batch: too many sub-pixels");
   bt.split = pick_split((long)bt.B * bt.nsubpix, bt.g.s2, bt.nloop);
-  bt.g.ppb = (256 / bt.split) / bt.g.s2;
+  bt.g.ppb = split_lanes(bt.split) / bt.g.s2;
   bt.bpi = (bt.npix + bt.g.ppb - 1) / bt.g.ppb;
   bt.P = 7 + 7 * (d->n_src + d->n_ll);
   bt.descs.resize(bt.B);
@@ -155,7 +155,7 @@ jt_status chi2_common(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, c
   if (grad)
     bytes += align256(sizeof(float) * BN) + align256(sizeof(float4) * (size_t)bt.B * rec_stride) +
              align256(sizeof(float) * (size_t)bt.B * bt.bpi * bt.P) +
-             align256(sizeof(float) * (size_t)kQuartersHost * bt.B * bt.n * 3);
+             align256(sizeof(float) * (size_t)kRecPartsHost * bt.B * bt.n * 3);
   void* ws = nullptr;
   JT_TRY(ctx_workspace(ctx, st, bytes, &ws));
   Carve cv{(char*)ws};
@@ -177,7 +177,7 @@ jt_status chi2_common(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, c
   float* lamU = psf ? cv.take<float>(BN) : resid;
   float4* rec = cv.take<float4>((size_t)bt.B * rec_stride);
   float* part = cv.take<float>((size_t)bt.B * bt.bpi * bt.P);
-  float* gpart = cv.take<float>((size_t)kQuartersHost * bt.B * bt.n * 3);
+  float* gpart = cv.take<float>((size_t)kRecPartsHost * bt.B * bt.n * 3);
   if (psf)
     JT_TRY(timed_launch(ctx, JT_K_CONV, st, [&] {
       return launch_conv_direct_batched(true, bt.B, resid, bt.npix, bt.g.nx, bt.g.ny, psf, k, lamU, bt.npix, st);

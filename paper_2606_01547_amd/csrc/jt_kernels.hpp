@@ -65,7 +65,7 @@ hipError_t launch_fft_convolve(const float* img, int nx, int ny, const float* ps
                                const double2* tw_x, const double2* tw_y, hipStream_t st);
 
 // ---- adjoint (adjoint.hip) ----
-constexpr int kQuartersHost = 4;   // == kQuarters of the canonical summation order
+constexpr int kRecPartsHost = 4;  // parts of the adjoint's subhalo-major pass
 hipError_t launch_residual(int B, int npix, const float* model, const float* data, const float* w, float* resid,
                            float* part, int* nblocks, hipStream_t st);
 hipError_t launch_grad_pixel(int split, int B, int bpi, const ImageDesc* descs, const float* lamU, float4* rec,

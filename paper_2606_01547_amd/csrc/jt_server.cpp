@@ -238,7 +238,7 @@ jt_status jt_server::launch_hip(Batch& b) {
   for (Req* r : order) img_total += r->k ? a256(4 * (size_t)r->g.nx * r->g.ny) : 0;
   size_t ntiles = 0, nctiles = 0, ncon = 0;
   for (Req* r : order) {
-    const int ppb = (256 / split) / r->g.s2;
+    const int ppb = split_lanes(split) / r->g.s2;
     ntiles += ((long)r->g.nx * r->g.ny + ppb - 1) / ppb;
     if (r->k) {
       nctiles += (size_t)conv_tiles_x(r->g.nx) * conv_tiles_y(r->g.ny);
@@ -257,7 +257,7 @@ jt_status jt_server::launch_hip(Batch& b) {
     ImageDesc& D = descs[i];
     std::memset(&D, 0, sizeof(D));
     D.g = r->g;
-    D.g.ppb = (256 / split) / r->g.s2;
+    D.g.ppb = split_lanes(split) / r->g.s2;
     D.mc = r->mc;
     D.src = r->src;
     D.ll = r->ll;
@@ -768,7 +768,7 @@ extern "C" jt_status jt_server_submit(jt_server* srv, const jt_request* req, uin
   // cap and large enough for more than two minimum chunks, otherwise a
   // request over the cap runs as a batch of its own
   r->split = pick_split((long)r->g.nx * r->g.ny * r->g.s2, r->g.s2, r->nloop);
-  r->ppb = (256 / r->split) / r->g.s2;
+  r->ppb = split_lanes(r->split) / r->g.s2;
   r->blocks = (int)(((long)r->g.nx * r->g.ny + r->ppb - 1) / r->ppb);
   r->chunked = r->pairs > srv->cfg.max_batch_pairs && r->blocks > 2 * kChunkMinBlocks;
   if (r->chunked) {

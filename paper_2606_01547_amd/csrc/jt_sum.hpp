@@ -19,18 +19,26 @@ __device__ __forceinline__ SubRec load_rec(SubTable t, int k) {
 
 // ---------------------------------------------------------------------------
 // Canonical subhalo summation order.  The nloop records (a multiple of 4) are
-// cut into kQuarters contiguous ranges with boundaries that are multiples of
-// 4; each range is summed in tiles of kSubTile pairs (plain FP32 inside a
-// tile, TwoSum across tiles), and the ranges are combined in index order.  A
-// launch may hand the ranges of one sub-pixel to 1, 2 or 4 waves (kSplit);
-// the arithmetic and its order do not change, so every launch shape gives
-// bitwise the same deflection.
+// cut into kRanges contiguous ranges with boundaries that are multiples of 4;
+// each range is summed in tiles of kSubTile pairs (plain FP32 inside a tile,
+// TwoSum across tiles) into (hi, lo), and the ranges are added in FP64 in
+// index order, hi + lo of one range at a time.  A launch hands the ranges of
+// one sub-pixel to 1, 2, 4 or 8 wave-groups (kSplit) that leave them in LDS
+// for group 0 (one group adds them as it goes); the arithmetic and its order
+// do not change, so every launch shape gives bitwise the same deflection.
 // ---------------------------------------------------------------------------
-constexpr int kQuarters = 4;
+constexpr int kRanges = 8;
 
-__host__ __device__ __forceinline__ int quarter_bound(int nloop, int q) {
-  const int step = ((nloop + 15) / 16) * 4;  // ceil(nloop / 4) rounded up to a multiple of 4
-  return min(q * step, nloop);
+__host__ __device__ __forceinline__ int range_bound(int nloop, int e) {
+  const int step = ((nloop + 4 * kRanges - 1) / (4 * kRanges)) * 4;  // ceil(nloop / kRanges), multiple of 4
+  return min(e * step, nloop);
+}
+
+// Boundaries of `parts` contiguous parts of n records, multiples of 4 (the
+// adjoint's sums over sub-pixel records).
+__host__ __device__ __forceinline__ int part_bound(int n, int parts, int q) {
+  const int step = ((n + 4 * parts - 1) / (4 * parts)) * 4;
+  return min(q * step, n);
 }
 
 // Sum of the pair terms over records [kb, ke) as (hi, lo) per component.  The
@@ -57,39 +65,53 @@ __device__ __forceinline__ float4 subhalo_range_sum(float tx, float ty, const Su
   return make_float4(hx, lx, hy, ly);
 }
 
-// Total deflection in FP64 at the sub-pixel (tx, ty): the macro lens plus the
-// (hi, lo) quarter partials of the subhalo sum, added in quarter order.
-__device__ __forceinline__ void total_deflection64(const MacroC& mc, double tx, double ty, const float4* q,
-                                                   int stride, double& ax, double& ay) {
-  macro_deflection64(mc, tx, ty, ax, ay);
-  double sx = 0.0, sy = 0.0;
-#pragma unroll
-  for (int i = 0; i < kQuarters; ++i) {
-    const float4 v = q[i * stride];
-    sx += (double)v.x + (double)v.y;
-    sy += (double)v.z + (double)v.w;
-  }
-  ax += sx;
-  ay += sy;
-}
-
-// Per-block quarter partials: [quarter][slot], slot < 256 / kSplit.
+// Range partials of a block's sub-pixels, [range][slot], slot <
+// split_lanes(kSplit).  With one group the ranges are added as they are
+// computed and nothing is stored.
 template <int kSplit>
-struct QuarterScratch {
-  float4 q[kQuarters][256 / kSplit];
+struct RangeScratch {
+  float4 r[kSplit == 1 ? 1 : kRanges][split_lanes(kSplit)];
 };
 
-// The quarters handled by wave-group g of kSplit, for the sub-pixel (tx, ty),
-// written to scratch.q[*][slot].
+// The ranges of wave-group g for the sub-pixel (tx, ty).  With one group they
+// are added to (sx, sy) in FP64 as they are computed; otherwise each group
+// stores its ranges for group 0, which adds them after the block's barrier.
 template <int kSplit>
-__device__ __forceinline__ void subhalo_quarters(float tx, float ty, const SubRec* __restrict__ sub, int nloop,
-                                                 int g, int slot, QuarterScratch<kSplit>& scratch) {
-  constexpr int kPer = kQuarters / kSplit;
-#pragma unroll
-  for (int i = 0; i < kPer; ++i) {
-    const int q = g * kPer + i;
-    scratch.q[q][slot] = subhalo_range_sum(tx, ty, sub, quarter_bound(nloop, q), quarter_bound(nloop, q + 1));
+__device__ __forceinline__ void subhalo_ranges(float tx, float ty, const SubRec* __restrict__ sub, int nloop, int g,
+                                               int slot, RangeScratch<kSplit>& scratch, double& sx, double& sy) {
+  constexpr int kOwn = kRanges / kSplit;
+#pragma unroll 1
+  for (int i = 0; i < kOwn; ++i) {
+    const int e = g * kOwn + i;
+    const float4 v = subhalo_range_sum(tx, ty, sub, range_bound(nloop, e), range_bound(nloop, e + 1));
+    if (kSplit == 1) {
+      sx += (double)v.x + (double)v.y;
+      sy += (double)v.z + (double)v.w;
+    } else {
+      scratch.r[e][slot] = v;
+    }
   }
+}
+
+// Group 0, after the block's barrier: the stored ranges in order, then the
+// total deflection in FP64 at the sub-pixel (tx, ty) = macro lens + subhalos.
+template <int kSplit>
+__device__ __forceinline__ void total_deflection64(const MacroC& mc, double tx, double ty,
+                                                   const RangeScratch<kSplit>& scratch, int slot, double sx, double sy,
+                                                   double& ax, double& ay) {
+  if (kSplit > 1) {
+    // one range at a time: this epilogue must not raise the kernel's
+    // register count above the pair loop's
+#pragma unroll 1
+    for (int e = 0; e < kRanges; ++e) {
+      const float4 v = scratch.r[e][slot];
+      sx += (double)v.x + (double)v.y;
+      sy += (double)v.z + (double)v.w;
+    }
+  }
+  macro_deflection64(mc, tx, ty, ax, ay);
+  ax += sx;
+  ay += sy;
 }
 
 }  // namespace jt

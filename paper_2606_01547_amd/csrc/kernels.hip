@@ -40,15 +40,15 @@ __global__ __launch_bounds__(256) void k_prep_subhalos(int n, int padded, const 
 }
 
 // ---------------------------------------------------------------------------
-// Step 1 at explicit points.  Block = kSplit wave-groups x (256 / kSplit)
+// Step 1 at explicit points.  Block = kSplit wave-groups x split_lanes(kSplit)
 // points; all groups see the same points.
 template <bool kAlpha, int kSplit>
-__global__ __launch_bounds__(256) void k_ray_shoot(int n, const float* __restrict__ x,
-                                                  const float* __restrict__ y, MacroC mc,
-                                                  const SubRec* __restrict__ sub, int nloop,
-                                                  float* __restrict__ ox, float* __restrict__ oy) {
-  __shared__ QuarterScratch<kSplit> scratch;
-  constexpr int kW = 256 / kSplit;
+__global__ __launch_bounds__(split_threads(kSplit)) void k_ray_shoot(int n, const float* __restrict__ x,
+                                                                    const float* __restrict__ y, MacroC mc,
+                                                                    const SubRec* __restrict__ sub, int nloop,
+                                                                    float* __restrict__ ox, float* __restrict__ oy) {
+  __shared__ RangeScratch<kSplit> scratch;
+  constexpr int kW = split_lanes(kSplit);
   // kW is a multiple of the wave size, so the group index is wave-uniform;
   // readfirstlane lets the compiler keep the subhalo loop on scalar loads.
   const int g = __builtin_amdgcn_readfirstlane(threadIdx.x / kW);
@@ -57,11 +57,12 @@ __global__ __launch_bounds__(256) void k_ray_shoot(int n, const float* __restric
   const bool valid = i < n;
   const float tx = valid ? x[i] : 0.f;
   const float ty = valid ? y[i] : 0.f;
-  subhalo_quarters<kSplit>(tx, ty, sub, nloop, g, slot, scratch);
+  double sx = 0.0, sy = 0.0;
+  subhalo_ranges<kSplit>(tx, ty, sub, nloop, g, slot, scratch, sx, sy);
   __syncthreads();
   if (g == 0 && valid) {
     double ax, ay;
-    total_deflection64(mc, tx, ty, &scratch.q[0][slot], kW, ax, ay);
+    total_deflection64<kSplit>(mc, tx, ty, scratch, slot, sx, sy, ax, ay);
     ox[i] = (float)(kAlpha ? ax : (double)tx - ax);
     oy[i] = (float)(kAlpha ? ay : (double)ty - ay);
   }
@@ -115,16 +116,17 @@ template <int kSplit>
 __device__ __forceinline__ void simulate_block(const GridC& g, const MacroC& mc, const SubRec* __restrict__ sub,
                                                int nloop, const LightC& src, const LightC& ll,
                                                float* __restrict__ img, int block,
-                                               QuarterScratch<kSplit>& scratch, float* red) {
-  constexpr int kW = 256 / kSplit;
+                                               RangeScratch<kSplit>& scratch, float* red) {
+  constexpr int kW = split_lanes(kSplit);
   const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / kW);  // wave-uniform (kW % 64 == 0)
   const int t = threadIdx.x - grp * kW;
   const SubPixel sp = subpixel_of(g, block, t);
-  subhalo_quarters<kSplit>(sp.tx, sp.ty, sub, nloop, grp, t, scratch);
+  double sx = 0.0, sy = 0.0;
+  subhalo_ranges<kSplit>(sp.tx, sp.ty, sub, nloop, grp, t, scratch, sx, sy);
   __syncthreads();
   if (grp == 0) {
     double ax, ay;
-    total_deflection64(mc, sp.dx, sp.dy, &scratch.q[0][t], kW, ax, ay);
+    total_deflection64<kSplit>(mc, sp.dx, sp.dy, scratch, t, sx, sy, ax, ay);
     float v = sersic_sum(src, (float)(sp.dx - ax), (float)(sp.dy - ay));
     if (ll.n > 0) v += sersic_sum(ll, sp.tx, sp.ty);
     red[t] = v;
@@ -142,10 +144,11 @@ __device__ __forceinline__ void simulate_block(const GridC& g, const MacroC& mc,
 }
 
 template <int kSplit>
-__global__ __launch_bounds__(256) void k_simulate(GridC g, MacroC mc, const SubRec* __restrict__ sub,
-                                                 int nloop, LightC src, LightC ll, float* __restrict__ img) {
-  __shared__ QuarterScratch<kSplit> scratch;
-  __shared__ float red[256];
+__global__ __launch_bounds__(split_threads(kSplit)) void k_simulate(GridC g, MacroC mc, const SubRec* __restrict__ sub,
+                                                                   int nloop, LightC src, LightC ll,
+                                                                   float* __restrict__ img) {
+  __shared__ RangeScratch<kSplit> scratch;
+  __shared__ float red[split_lanes(kSplit)];
   simulate_block<kSplit>(g, mc, sub, nloop, src, ll, img, blockIdx.x, scratch, red);
 }
 
@@ -153,10 +156,11 @@ __global__ __launch_bounds__(256) void k_simulate(GridC g, MacroC mc, const SubR
 // every image has the same grid (tiles == nullptr), otherwise on the
 // (image, pixel block) pair tiles[b].
 template <int kSplit>
-__global__ __launch_bounds__(256) void k_simulate_desc(const ImageDesc* __restrict__ descs,
-                                                      const int2* __restrict__ tiles, int blocks_per_image) {
-  __shared__ QuarterScratch<kSplit> scratch;
-  __shared__ float red[256];
+__global__ __launch_bounds__(split_threads(kSplit)) void k_simulate_desc(const ImageDesc* __restrict__ descs,
+                                                                        const int2* __restrict__ tiles,
+                                                                        int blocks_per_image) {
+  __shared__ RangeScratch<kSplit> scratch;
+  __shared__ float red[split_lanes(kSplit)];
   int di, blk;
   if (tiles) {
     const int2 tl = tiles[blockIdx.x];
@@ -286,21 +290,23 @@ __global__ __launch_bounds__(kW * 64) void k_conv_desc(const ConvDesc* __restric
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-// Waves per block-column sharing one sub-pixel's subhalo quarters: enough
-// waves to give every SIMD of the 256 CUs several (about 16) to interleave,
-// while keeping whole pixels (`unit` sub-pixel slots each) in a wave-group.
+// Wave-groups sharing one sub-pixel's subhalo ranges: enough waves to give
+// every SIMD of the 256 CUs about 32 over the launch (four rounds of wave
+// slots, so the last, partly filled round costs little), while keeping whole
+// pixels (`unit` sub-pixel slots each) in a wave-group.
 int pick_split(long points, int unit, int nloop) {
   if (nloop < 64) return 1;
-  const long target = 16L * 1024 * 64;  // lanes for ~16 waves per SIMD
-  for (int split = 1; split < 4; split *= 2) {
-    const long w = 256 / split;
+  const long target = 32L * 1024 * 64;
+  for (int split = 1; split < 8; split *= 2) {
+    const long w = split_lanes(split);
     const long used = (w / unit) * unit;          // slots holding whole pixels
-    const long lanes = (points + used - 1) / used * 256;
+    const long lanes = (points + used - 1) / used * split_threads(split);
     if (lanes >= target) return split;
-    if (((256 / (split * 2)) / unit) < 1) return split;  // a pixel no longer fits
+    if (split_lanes(split * 2) / unit < 1) return split;  // a pixel no longer fits a group
   }
-  return 4;
+  return 8;
 }
+
 hipError_t launch_prep_subhalos(int n, const float* x, const float* y, const float* rs,
                                 const float* ars, SubRec* out, hipStream_t st) {
   const int padded = subhalo_table_records(n);
@@ -313,13 +319,16 @@ hipError_t launch_ray_shoot(bool alpha, int n, const float* x, const float* y, c
                             const SubRec* sub, int nloop, float* ox, float* oy, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const int split = pick_split(n, 1, nloop);
-  const int w = 256 / split;
+  const int w = split_lanes(split);
   const dim3 grid((n + w - 1) / w);
-#define JT_RAY(A, S) hipLaunchKernelGGL((k_ray_shoot<A, S>), grid, dim3(256), 0, st, n, x, y, mc, sub, nloop, ox, oy)
+#define JT_RAY(A, S) hipLaunchKernelGGL((k_ray_shoot<A, S>), grid, dim3(split_threads(S)), 0, st, n, x, y, mc, sub, \
+                                        nloop, ox, oy)
   if (alpha) {
-    if (split == 1) JT_RAY(true, 1); else if (split == 2) JT_RAY(true, 2); else JT_RAY(true, 4);
+    if (split == 1) JT_RAY(true, 1); else if (split == 2) JT_RAY(true, 2); else if (split == 4) JT_RAY(true, 4);
+    else JT_RAY(true, 8);
   } else {
-    if (split == 1) JT_RAY(false, 1); else if (split == 2) JT_RAY(false, 2); else JT_RAY(false, 4);
+    if (split == 1) JT_RAY(false, 1); else if (split == 2) JT_RAY(false, 2); else if (split == 4) JT_RAY(false, 4);
+    else JT_RAY(false, 8);
   }
 #undef JT_RAY
   return hipGetLastError();
@@ -336,10 +345,11 @@ hipError_t launch_simulate(GridC g, const MacroC& mc, const SubRec* sub, int nlo
                            const LightC& ll, float* img, hipStream_t st) {
   const long npix = (long)g.nx * g.ny;
   const int split = pick_split(npix * g.s2, g.s2, nloop);
-  g.ppb = (256 / split) / g.s2;
+  g.ppb = split_lanes(split) / g.s2;
   const long blocks = (npix + g.ppb - 1) / g.ppb;
-#define JT_SIM(S) hipLaunchKernelGGL((k_simulate<S>), dim3((unsigned)blocks), dim3(256), 0, st, g, mc, sub, nloop, src, ll, img)
-  if (split == 1) JT_SIM(1); else if (split == 2) JT_SIM(2); else JT_SIM(4);
+#define JT_SIM(S) hipLaunchKernelGGL((k_simulate<S>), dim3((unsigned)blocks), dim3(split_threads(S)), 0, st, g, mc, \
+                                     sub, nloop, src, ll, img)
+  if (split == 1) JT_SIM(1); else if (split == 2) JT_SIM(2); else if (split == 4) JT_SIM(4); else JT_SIM(8);
 #undef JT_SIM
   return hipGetLastError();
 }
@@ -384,8 +394,9 @@ int conv_tiles_y(int ny) { return (ny + kConvTY - 1) / kConvTY; }
 hipError_t launch_simulate_desc(int split, const ImageDesc* descs, const int2* tiles, int nblocks,
                                 int blocks_per_image, hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
-#define JT_SIMD(S) hipLaunchKernelGGL((k_simulate_desc<S>), dim3((unsigned)nblocks), dim3(256), 0, st, descs, tiles, blocks_per_image)
-  if (split == 1) JT_SIMD(1); else if (split == 2) JT_SIMD(2); else JT_SIMD(4);
+#define JT_SIMD(S) hipLaunchKernelGGL((k_simulate_desc<S>), dim3((unsigned)nblocks), dim3(split_threads(S)), 0, st, \
+                                      descs, tiles, blocks_per_image)
+  if (split == 1) JT_SIMD(1); else if (split == 2) JT_SIMD(2); else if (split == 4) JT_SIMD(4); else JT_SIMD(8);
 #undef JT_SIMD
   return hipGetLastError();
 }
