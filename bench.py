@@ -59,36 +59,87 @@ def counters():
     return t
 
 
-def cpu_baseline(scene, rows):
-    """The FP64 oracle on `rows` pixel rows of the image (every sub-pixel of
-    them through the full deflector sum and light), plus the full-image PSF
-    convolution; extrapolated to one whole image."""
+def _oracle_rows(job):
+    """The FP64 oracle on pixel rows [r0, r1) of a scene: every sub-pixel of
+    them through the full deflector sum and light, then the supersample mean.
+    Returns the seconds it took."""
+    import oracle as O
+    scene, r0, r1 = job
+    g = scene.grid
+    t0 = time.perf_counter()
+    tx, ty = O.subpixel_coords(g.nx, g.ny, g.pixel_scale, g.x0, g.y0, g.supersample)
+    tx, ty = tx[r0:r1], ty[r0:r1]
+    bx, by = O.ray_shoot(tx, ty, scene.lens)
+    sb = O.surface_brightness(tx, ty, bx, by, scene.source, scene.lens_light, scene.bn_exact)
+    O.supersample_reduce(sb, g.pixel_scale)
+    return time.perf_counter() - t0
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(scene, rows, workers, rows_per_worker=4):
+    """The FP64 oracle timed on this host, extrapolated to one whole image:
+    (i) one process on `rows` pixel rows; (ii) `workers` spawned processes,
+    each on `rows_per_worker` rows, timed by the wall clock around the pool
+    (start-up included).  Both add one full-image PSF convolution.  The value
+    is the faster of the two."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
     import numpy as np
     import oracle as O
     g = scene.grid
     t0 = time.perf_counter()
-    tx, ty = O.subpixel_coords(g.nx, g.ny, g.pixel_scale, g.x0, g.y0, g.supersample)
-    tx, ty = tx[:rows], ty[:rows]
-    bx, by = O.ray_shoot(tx, ty, scene.lens)
-    sb = O.surface_brightness(tx, ty, bx, by, scene.source, scene.lens_light, scene.bn_exact)
-    part = O.supersample_reduce(sb, g.pixel_scale)
-    t1 = time.perf_counter()
-    O.convolve_same(np.zeros((g.ny, g.nx)) + part.mean(), scene.psf)
-    t2 = time.perf_counter()
-    per_image = (t1 - t0) * g.ny / rows + (t2 - t1)
-    pairs = rows * g.nx * g.supersample ** 2 * scene.lens.nfw.n
-    return {"value": 1.0 / per_image, "unit": "images/s", "cores": 1, "kind": "oracle",
-            "sample": (f"{rows} of {g.ny} pixel rows ({pairs:.3g} sub-pixel x subhalo pairs) through the FP64 "
-                       f"oracle in {t1 - t0:.1f} s plus one full-image convolution ({t2 - t1:.2f} s), "
-                       f"extrapolated to a whole image; single NumPy process"),
-            "seconds": round(t2 - t0, 2)}
+    O.convolve_same(np.zeros((g.ny, g.nx)), scene.psf)
+    t_conv = time.perf_counter() - t0
+    pairs_row = g.nx * g.supersample ** 2 * scene.lens.nfw.n
+    t_single = _oracle_rows((scene, 0, rows))
+    single = 1.0 / (t_single * g.ny / rows + t_conv)
+    model, avail = host_cpu()
+    out = {"value": single, "unit": "images/s", "cores": 1, "kind": "oracle",
+           "sample": (f"{rows} of {g.ny} pixel rows ({rows * pairs_row:.3g} sub-pixel x subhalo pairs) through the "
+                      f"FP64 oracle in {t_single:.1f} s in one NumPy process, plus one full-image convolution "
+                      f"({t_conv:.2f} s), extrapolated to a whole image"),
+           "seconds": round(t_single + t_conv, 2), "host_cpu": model, "host_cores_available": avail,
+           "single_process_images_per_s": single}
+    workers = min(workers, avail, g.ny // rows_per_worker)
+    if workers > 1:
+        jobs = [(scene, w * rows_per_worker, (w + 1) * rows_per_worker) for w in range(workers)]
+        t0 = time.perf_counter()
+        with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+            busy = list(ex.map(_oracle_rows, jobs))
+        wall = time.perf_counter() - t0
+        done = workers * rows_per_worker
+        pooled = 1.0 / (wall * g.ny / done + t_conv)
+        out["pool"] = {"images_per_s": pooled, "processes": workers, "rows": done, "wall_s": round(wall, 2),
+                       "mean_worker_busy_s": round(sum(busy) / workers, 2)}
+        if pooled > single:
+            out["value"] = pooled
+            out["cores"] = workers
+            out["sample"] = (f"{done} of {g.ny} pixel rows ({done * pairs_row:.3g} sub-pixel x subhalo pairs) "
+                             f"through the FP64 oracle on {workers} spawned NumPy processes ({rows_per_worker} rows "
+                             f"each) in {wall:.1f} s wall, plus one full-image convolution ({t_conv:.2f} s), "
+                             f"extrapolated to a whole image; one process alone on {rows} rows: "
+                             f"{single:.4g} images/s")
+    return out
 
 
-def serving_bench(ctx, n_requests, large_every, seed=1003):
+def serving_bench(ctx, n_requests, large_every, seed=1003, loads=(0.5, 0.8, 1.0)):
     """The request stream served by the continuous-batching server: a
     saturated calibration pass (everything submitted at once), then Poisson
-    arrivals at 0.8x the saturated rate; the same stream through one
-    jt_simulate_image call per request (FIFO, one stream) for comparison."""
+    arrivals at each of `loads` times the saturated rate, each schedule also
+    served by one jt_simulate_image call per request (FIFO, one stream) for
+    comparison."""
     import numpy as np
     import torch
     import workloads as W
@@ -128,33 +179,42 @@ def serving_bench(ctx, n_requests, large_every, seed=1003):
         srv.close()
         return lat, wall, st
 
+    def run_per_image(arrivals):
+        # one jt_simulate_image per request, FIFO, waiting for each
+        lat = []
+        t0 = time.perf_counter()
+        for sc, o, ta in zip(scenes, outs, arrivals):
+            while True:
+                dt = t0 + ta - time.perf_counter()
+                if dt <= 0:
+                    break
+                time.sleep(min(dt, 2e-3))
+            ctx.simulate_scene(sc, out=o)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - (t0 + ta))
+        return np.array(lat), time.perf_counter() - t0
+
+    pct = lambda a, q: round(1e3 * float(np.percentile(a, q)), 3)
     lat_sat, wall_sat, st_sat = run(np.zeros(n_requests))
     rate_sat = n_requests / wall_sat
-    lam = 0.8 * rate_sat
-    rng = np.random.default_rng(seed)
-    arrivals = np.cumsum(rng.exponential(1.0 / lam, n_requests))
-    arrivals -= arrivals[0]
-    lat, wall, st = run(arrivals)
-
-    # per-image launches: one jt_simulate_image per request, FIFO, waiting for each
-    pimg = []
-    t0 = time.perf_counter()
-    for sc, o, ta in zip(scenes, outs, arrivals):
-        while True:
-            dt = t0 + ta - time.perf_counter()
-            if dt <= 0:
-                break
-            time.sleep(min(dt, 2e-3))
-        ctx.simulate_scene(sc, out=o)
-        torch.cuda.synchronize()
-        pimg.append(time.perf_counter() - (t0 + ta))
-    wall_pi = time.perf_counter() - t0
-    pimg = np.array(pimg)
+    poisson = {}
+    for load in loads:
+        lam = load * rate_sat
+        rng = np.random.default_rng(seed)
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, n_requests))
+        arrivals -= arrivals[0]
+        lat, wall, st = run(arrivals)
+        pimg, wall_pi = run_per_image(arrivals)
+        poisson[f"{load:g}"] = {
+            "arrival_rate_per_s": round(lam, 2),
+            "server": {"images_per_s": round(n_requests / wall, 2), "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+                       "batches": int(st["batches"]), "arena_peak_bytes": int(st["arena_peak"])},
+            "per_image_launches": {"images_per_s": round(n_requests / wall_pi, 2), "p50_ms": pct(pimg, 50),
+                                   "p99_ms": pct(pimg, 99)}}
     for hs, hp in handles:
         for h in (hs, hp):
             if h:
                 ctx.release(h)
-    pct = lambda a, q: round(1e3 * float(np.percentile(a, q)), 3)
     return {
         "workload": (f"{n_requests} seeded requests: grid from {{64,100,200,400}}^2, s from {{1,3}}, "
                      f"log-uniform 0-20000 NFW, PSF 21 or 41" +
@@ -162,11 +222,7 @@ def serving_bench(ctx, n_requests, large_every, seed=1003):
         "pairs": pairs, "generation_s": round(gen_s, 2),
         "saturated": {"images_per_s": round(rate_sat, 2), "p50_ms": pct(lat_sat, 50), "p99_ms": pct(lat_sat, 99),
                       "batches": int(st_sat["batches"])},
-        "poisson": {"arrival_rate_per_s": round(lam, 2), "images_per_s": round(n_requests / wall, 2),
-                    "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "batches": int(st["batches"]),
-                    "arena_peak_bytes": int(st["arena_peak"])},
-        "per_image_launches": {"images_per_s": round(n_requests / wall_pi, 2), "p50_ms": pct(pimg, 50),
-                               "p99_ms": pct(pimg, 99)},
+        "poisson_by_load": poisson,
         "server_config": cfg,
     }
 
@@ -292,6 +348,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--latency-samples", type=int, default=200)
     ap.add_argument("--cpu-rows", type=int, default=30, help="pixel rows of the oracle sample (0 = skip)")
+    ap.add_argument("--cpu-workers", type=int, default=16, help="oracle processes of the pooled baseline")
     ap.add_argument("--serve-requests", type=int, default=4096, help="serving stream length (0 = skip)")
     ap.add_argument("--serve-large-every", type=int, default=512,
                     help="every n-th request is a large 1000x1000 image (0 = none)")
@@ -401,7 +458,7 @@ def main():
     if args.serve_requests > 0:
         result["serving"] = serving_bench(ctx, args.serve_requests, args.serve_large_every)
     if args.cpu_rows > 0:
-        result["cpu_baseline"] = cpu_baseline(scene, args.cpu_rows)
+        result["cpu_baseline"] = cpu_baseline(scene, args.cpu_rows, args.cpu_workers)
     ctx.close()
     print(json.dumps(result), flush=True)
 
