@@ -2,8 +2,8 @@
 
 Step one of the paper's image simulation (image-simulation section) maps every
 image-plane angle to the source plane, which needs the deflection of each
-deflector there; the paper's deflector table lists NIE/SIE, SIS, SHEAR and NFW
-among others.  It states no formula, so each profile here is the
+deflector there; the paper's deflector table lists NIE/SIE, SIS, EPL, SHEAR,
+NFW and TNFW among others.  It states no formula, so each profile here is the
 standard closed form from the literature, named per function.  All angles are in
 arcsec.  Single lens plane: beta = theta - sum_k alpha_k(theta).
 """
@@ -58,6 +58,44 @@ def sie_deflection(x, y, theta_E, q, phi, cx, cy):
         ayp = pref / f * np.arctanh(f * yp / safe)
     axp = np.where(psi > 0.0, axp, 0.0)
     ayp = np.where(psi > 0.0, ayp, 0.0)
+    return c * axp - s * ayp, s * axp + c * ayp
+
+
+# --------------------------------------------------------------------------
+# EPL: elliptical power law  (Tessore & Metcalf 2015)
+# --------------------------------------------------------------------------
+def epl_kappa(x, y, theta_E, gamma, q, phi, cx, cy):
+    """Convergence kappa = (3 - gamma)/2 * (theta_E / sqrt(q x'^2 + y'^2/q))^(gamma - 1):
+    gamma is the slope of the 3-D density (gamma = 2 is the SIE of `sie_kappa`);
+    theta_E is in the same product-average normalisation."""
+    xp, yp, _, _ = _rotate_in(x, y, phi, cx, cy)
+    return 0.5 * (3.0 - gamma) * (theta_E / np.sqrt(q * xp * xp + yp * yp / q)) ** (gamma - 1.0)
+
+
+def epl_deflection(x, y, theta_E, gamma, q, phi, cx, cy):
+    """EPL deflection for the convergence of `epl_kappa`, by the closed form of
+    Tessore & Metcalf (2015) with the Gauss hypergeometric function.
+
+    With t = gamma - 1, b = theta_E sqrt(q) and, in the frame of the major
+    axis, the elliptical radius R = sqrt(q^2 x'^2 + y'^2) and angle
+    e^{i varphi} = (q x' + i y') / R, the complex deflection is
+        alpha' = 2 b / (1 + q) * (b / R)^(t - 1) * e^{i varphi}
+                 * 2F1(1, t/2; 2 - t/2; -(1 - q)/(1 + q) e^{2 i varphi}),
+    rotated back by +phi.  alpha = 0 at the centre (R = 0) and for theta_E = 0.
+    """
+    from scipy.special import hyp2f1
+    xp, yp, c, s = _rotate_in(x, y, phi, cx, cy)
+    t = gamma - 1.0
+    b = theta_E * math.sqrt(q)
+    R = np.sqrt(q * q * xp * xp + yp * yp)
+    ok = (R > 0.0) & (theta_E > 0.0)
+    safe = np.where(ok, R, 1.0)
+    eiv = (q * xp + 1j * yp) / safe
+    z = -(1.0 - q) / (1.0 + q) * eiv * eiv
+    with np.errstate(invalid="ignore", divide="ignore"):
+        a = 2.0 * b / (1.0 + q) * (b / safe) ** (t - 1.0) * eiv * hyp2f1(1.0, 0.5 * t, 2.0 - 0.5 * t, z)
+    axp = np.where(ok, a.real, 0.0)
+    ayp = np.where(ok, a.imag, 0.0)
     return c * axp - s * ayp, s * axp + c * ayp
 
 
@@ -210,7 +248,7 @@ def point_mass_deflection(x, y, theta_E, cx, cy):
 # --------------------------------------------------------------------------
 def total_deflection(x, y, lens):
     """Sum of the deflections of every deflector in `lens` (attributes sie,
-    shear, nfw, point_masses; any may be None)."""
+    epl, shear, nfw, point_masses; any may be None or absent)."""
     x = np.asarray(x, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     ax = np.zeros_like(x)
@@ -218,6 +256,11 @@ def total_deflection(x, y, lens):
     if getattr(lens, "sie", None) is not None:
         s = lens.sie
         dx, dy = sie_deflection(x, y, s.theta_E, s.q, s.phi, s.cx, s.cy)
+        ax += dx
+        ay += dy
+    if getattr(lens, "epl", None) is not None:
+        e = lens.epl
+        dx, dy = epl_deflection(x, y, e.theta_E, e.gamma, e.q, e.phi, e.cx, e.cy)
         ax += dx
         ay += dy
     if getattr(lens, "shear", None) is not None:

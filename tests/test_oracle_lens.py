@@ -7,6 +7,9 @@ own deflection formulas.
   (Keeton 2001 catalogue) evaluated by quadrature from the convergence alone;
   div alpha = 2 kappa and curl alpha = 0 by central differences; continuity of
   the q -> 1 series branch.
+* EPL: the same homoeoid integral for the power-law convergence; the circular
+  case |alpha| = theta_E^(gamma-1) r^(2-gamma); div alpha = 2 kappa, curl
+  alpha = 0; gamma = 2 is the SIE.
 * Shear: the complex form alpha = gamma * conj(z) and its constant Hessian.
 * NFW: kappa against a numerical line-of-sight projection of the 3-D NFW
   density; alpha against the enclosed-mass integral of kappa; 50-digit mpmath
@@ -106,6 +109,79 @@ def test_sie_series_branch_is_continuous():
     np.testing.assert_allclose(a_ser[0], a_sis[0], atol=2e-7)
     np.testing.assert_allclose(a_dir[0], a_ser[0], atol=2e-6)
     np.testing.assert_allclose(a_dir[1], a_ser[1], atol=2e-6)
+
+
+# ---------------------------------------------------------------- EPL
+def _schramm_power_law(xp, yp, theta_E, gamma, q):
+    """alpha in the major-axis frame of the homoeoidal convergence
+    kappa(xi) = (3 - gamma)/2 * (theta_E / (sqrt(q) xi))^(gamma - 1),
+    xi^2 = x^2 + y^2/q^2, by the same one-dimensional integrals as
+    `_schramm`: along the path kappa(xi(u)) carries u^(-(gamma-1)/2), taken as
+    the quadrature weight."""
+    e = 1.0 - q * q
+    p = gamma - 1.0
+
+    def h(u, n):
+        d = 1.0 - e * u
+        return (0.5 * (3.0 - gamma) * (theta_E / math.sqrt(q)) ** p
+                * (xp * xp + yp * yp / d) ** (-0.5 * p) / d ** (n + 0.5))
+
+    j0, _ = quad(h, 0.0, 1.0, args=(0,), weight="alg", wvar=(-0.5 * p, 0.0), epsabs=1e-14, epsrel=1e-13)
+    j1, _ = quad(h, 0.0, 1.0, args=(1,), weight="alg", wvar=(-0.5 * p, 0.0), epsabs=1e-14, epsrel=1e-13)
+    return q * xp * j0, q * yp * j1
+
+
+@pytest.mark.parametrize("gamma,q", [(1.5, 0.5), (2.0, 0.7), (2.4, 0.85), (1.8, 0.3)])
+def test_epl_matches_homoeoid_quadrature(gamma, q):
+    theta_E, phi, cx, cy = 1.05, 0.9, -0.06, 0.04
+    rng = np.random.default_rng(int(gamma * 10 + q * 100))
+    pts = rng.uniform(-2.5, 2.5, (10, 2))
+    c, s = math.cos(phi), math.sin(phi)
+    for px, py in pts:
+        ax, ay = O.epl_deflection(np.array([px]), np.array([py]), theta_E, gamma, q, phi, cx, cy)
+        dx, dy = px - cx, py - cy
+        xp, yp = c * dx + s * dy, -s * dx + c * dy
+        axp, ayp = _schramm_power_law(xp, yp, theta_E, gamma, q)
+        ex, ey = c * axp - s * ayp, s * axp + c * ayp
+        assert abs(ax[0] - ex) < 1e-9 * max(1.0, abs(ex)) and abs(ay[0] - ey) < 1e-9 * max(1.0, abs(ey))
+
+
+@pytest.mark.parametrize("gamma", [1.3, 2.0, 2.7])
+def test_epl_circular_is_power_law(gamma):
+    rng = np.random.default_rng(11)
+    x, y = rng.uniform(-3, 3, (2, 300))
+    ax, ay = O.epl_deflection(x, y, 0.9, gamma, 1.0, 0.4, 0.1, -0.2)
+    r = np.hypot(x - 0.1, y + 0.2)
+    np.testing.assert_allclose(np.hypot(ax, ay), 0.9 ** (gamma - 1.0) * r ** (2.0 - gamma), rtol=1e-13)
+    np.testing.assert_allclose(ax * (y + 0.2) - ay * (x - 0.1), 0.0, atol=1e-12)
+
+
+@pytest.mark.parametrize("gamma,q", [(1.6, 0.4), (2.3, 0.75), (1.2, 0.2)])
+def test_epl_divergence_and_curl(gamma, q):
+    theta_E, phi, cx, cy = 1.1, 0.7, 0.2, 0.1
+    rng = np.random.default_rng(5)
+    x, y = rng.uniform(-2, 2, (2, 80))
+    keep = np.hypot(x - cx, y - cy) > 0.2
+    x, y = x[keep], y[keep]
+    fun = lambda a, b: O.epl_deflection(a, b, theta_E, gamma, q, phi, cx, cy)
+    div, curl = _div_curl(fun, x, y, 1e-5)
+    kap = O.epl_kappa(x, y, theta_E, gamma, q, phi, cx, cy)
+    np.testing.assert_allclose(div, 2 * kap, rtol=1e-7)
+    assert np.max(np.abs(curl) / kap) < 1e-6
+
+
+def test_epl_gamma_two_is_sie_and_centre_is_zero():
+    rng = np.random.default_rng(2)
+    x, y = rng.uniform(-2, 2, (2, 100))
+    for q in (0.45, 0.9, 1.0):
+        a = O.epl_deflection(x, y, 1.2, 2.0, q, 0.4, 0.1, -0.05)
+        b = O.sie_deflection(x, y, 1.2, q, 0.4, 0.1, -0.05)
+        np.testing.assert_allclose(a[0], b[0], atol=1e-13)
+        np.testing.assert_allclose(a[1], b[1], atol=1e-13)
+    ax, ay = O.epl_deflection(np.array([0.1]), np.array([-0.05]), 1.2, 2.5, 0.6, 0.4, 0.1, -0.05)
+    assert ax[0] == 0.0 and ay[0] == 0.0
+    ax, ay = O.epl_deflection(x, y, 0.0, 1.5, 0.6, 0.4, 0.1, -0.05)
+    assert not np.any(ax) and not np.any(ay)
 
 
 # ---------------------------------------------------------------- shear
