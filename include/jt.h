@@ -83,6 +83,16 @@ typedef struct {
  * theta_E > 0, q in (0, 1], centre (cx, cy). */
 typedef struct { double theta_E, q, phi, cx, cy; } jt_sie;
 
+/* EPL, elliptical power-law main deflector (Tessore & Metcalf 2015; in the
+ * paper's deflector table):
+ * kappa = (3 - gamma)/2 (theta_E / sqrt(q x'^2 + y'^2/q))^(gamma - 1), gamma the
+ * slope of the 3-D density (gamma = 2 is the SIE above).  theta_E >= 0,
+ * gamma in (1, 3), q in [0.05, 1], position angle phi, centre (cx, cy).  The
+ * deflection is the hypergeometric closed form, summed as its power series in
+ * FP64 to full double precision (more terms as q falls: about 30 at q = 0.6,
+ * 400 at q = 0.05). */
+typedef struct { double theta_E, gamma, q, phi, cx, cy; } jt_epl;
+
 /* External shear about the origin: alpha = (g1 x + g2 y, g2 x - g1 y). */
 typedef struct { double gamma1, gamma2; } jt_shear;
 
@@ -103,6 +113,8 @@ typedef struct {
   jt_nfw nfw;                /* n = 0: no subhalos */
   uint64_t subhalo_handle;   /* nonzero: a table from jt_upload_subhalos, `nfw` ignored */
   jt_point_masses pm;        /* n = 0: none */
+  int has_epl;               /* adds an EPL (with or without the SIE) */
+  jt_epl epl;
 } jt_lens;
 
 /* Elliptical Sersic: I = amp exp(-b_n [(R/R_sersic)^(1/n) - 1]),
@@ -263,6 +275,8 @@ typedef struct {
   jt_light src, lens_light;  /* host arrays, read during jt_server_submit */
   uint64_t psf_handle;       /* from jt_upload_psf; 0 = no convolution */
   float* out;                /* device float32 [ny][nx], written when the ticket completes */
+  int has_epl;               /* EPL main deflector, as in jt_lens */
+  jt_epl epl;
 } jt_request;
 
 typedef enum { JT_TICKET_QUEUED = 0, JT_TICKET_RUNNING = 1, JT_TICKET_DONE = 2, JT_TICKET_CANCELLED = 3,

@@ -53,9 +53,19 @@ class JtPointMasses(ctypes.Structure):
     _fields_ = [("n", c_int), ("x", POINTER(c_double)), ("y", POINTER(c_double)), ("theta_E", POINTER(c_double))]
 
 
+class JtEpl(ctypes.Structure):
+    _fields_ = [("theta_E", c_double), ("gamma", c_double), ("q", c_double), ("phi", c_double), ("cx", c_double),
+                ("cy", c_double)]
+
+
+def _epl(e):
+    return JtEpl(e.theta_E, e.gamma, e.q, e.phi, e.cx, e.cy)
+
+
 class JtLens(ctypes.Structure):
     _fields_ = [("has_sie", c_int), ("has_shear", c_int), ("sie", JtSie), ("shear", JtShear),
-                ("nfw", JtNfw), ("subhalo_handle", c_uint64), ("pm", JtPointMasses)]
+                ("nfw", JtNfw), ("subhalo_handle", c_uint64), ("pm", JtPointMasses),
+                ("has_epl", c_int), ("epl", JtEpl)]
 
 
 class JtSersic(ctypes.Structure):
@@ -81,7 +91,7 @@ class JtServerCfg(ctypes.Structure):
 class JtRequest(ctypes.Structure):
     _fields_ = [("grid", JtGrid), ("has_sie", c_int), ("has_shear", c_int), ("sie", JtSie), ("shear", JtShear),
                 ("subhalo_handle", c_uint64), ("src", JtLight), ("lens_light", JtLight), ("psf_handle", c_uint64),
-                ("out", c_void_p)]
+                ("out", c_void_p), ("has_epl", c_int), ("epl", JtEpl)]
 
 
 class JtServerStats(ctypes.Structure):
@@ -235,6 +245,10 @@ class Context:
         if sh is not None:
             L.has_shear = 1
             L.shear = JtShear(sh.gamma1, sh.gamma2)
+        epl = getattr(lens, "epl", None)
+        if epl is not None:
+            L.has_epl = 1
+            L.epl = _epl(epl)
         handle = getattr(lens, "subhalo_handle", 0) or 0
         nfw = getattr(lens, "nfw", None)
         if handle:
@@ -509,6 +523,10 @@ class Server:
         if sh is not None:
             R.has_shear = 1
             R.shear = JtShear(sh.gamma1, sh.gamma2)
+        epl = getattr(lens, "epl", None)
+        if epl is not None:
+            R.has_epl = 1
+            R.epl = _epl(epl)
         R.subhalo_handle = int(subhalo_handle)
         R.psf_handle = int(psf_handle)
         R.src = Context._light(source, bn_exact, keep)

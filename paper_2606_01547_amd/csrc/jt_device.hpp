@@ -42,7 +42,7 @@ __host__ __device__ constexpr int split_threads(int split) { return split <= 4 ?
 // kernel constants
 // ---------------------------------------------------------------------------
 struct MacroC {
-  int has_sie, sie_series, has_shear, npm;
+  int has_sie, sie_series, has_shear, npm, has_epl;
   // FP32 copies for the adjoint's SIE and shear partials
   float cx, cy, cphi, sphi, q2, f;
   float theta_E, q, sqrt_q;
@@ -52,6 +52,10 @@ struct MacroC {
   // pref_f = pref / f, f = sqrt(1 - q^2)
   double dcx, dcy, dcphi, dsphi, dq2, df, dpref, dpref_f;
   double dg1, dg2;
+  // EPL: the same rotation about (ecx, ecy); R = sqrt(q^2 x'^2 + y'^2);
+  // alpha' = epref (eb / R)^etm1 * Omega, Omega the series of the
+  // hypergeometric factor with ratio -ef (2n - e2mt)/(2n + e2mt) e^{2 i varphi}
+  double ecx, ecy, ecphi, esphi, eq, ef, e2mt, eb, etm1, epref;
   double pm_x[kMaxPointMass], pm_y[kMaxPointMass], pm_te2[kMaxPointMass];
 };
 
@@ -118,6 +122,43 @@ struct ConvDesc {
 // FP64, once per sub-pixel: the FP32 representation of angles of tens of
 // arcseconds (|theta|, |alpha| up to ~20") would otherwise dominate the error
 // of beta = theta - alpha.
+// EPL deflection (Tessore & Metcalf 2015) in FP64, in the major-axis frame:
+// with e^{i varphi} = (q x' + i y')/R, alpha' = 2b/(1+q) (b/R)^(t-1) Omega,
+// Omega = sum_n w_n, w_0 = e^{i varphi},
+// w_n = -f (2n - (2-t))/(2n + (2-t)) e^{2 i varphi} w_{n-1}, f = (1-q)/(1+q):
+// the power series of the Gauss hypergeometric factor, summed until a term no
+// longer changes the sum in double precision.  0 at R = 0.
+constexpr int kEplMaxTerms = 1000;
+
+__device__ __forceinline__ void epl_deflection64(const MacroC& m, double tx, double ty, double& ax, double& ay) {
+  const double dx = tx - m.ecx, dy = ty - m.ecy;
+  const double xp = m.ecphi * dx + m.esphi * dy;
+  const double yp = m.ecphi * dy - m.esphi * dx;
+  const double qx = m.eq * xp;
+  const double R = sqrt(qx * qx + yp * yp);
+  ax = 0.0;
+  ay = 0.0;
+  if (!(R > 0.0)) return;
+  const double iR = 1.0 / R;
+  const double c = qx * iR, s = yp * iR;
+  const double c2 = c * c - s * s, s2 = 2.0 * c * s;
+  double wr = c, wi = s, sr = c, si = s;
+  for (int n = 1; n < kEplMaxTerms; ++n) {
+    const double k = -m.ef * (2.0 * n - m.e2mt) / (2.0 * n + m.e2mt);
+    const double nr = k * (c2 * wr - s2 * wi);
+    const double ni = k * (s2 * wr + c2 * wi);
+    wr = nr;
+    wi = ni;
+    sr += nr;
+    si += ni;
+    if (fabs(nr) + fabs(ni) <= 0x1p-56 * (fabs(sr) + fabs(si))) break;
+  }
+  const double a = m.epref * pow(m.eb * iR, m.etm1);
+  const double axp = a * sr, ayp = a * si;
+  ax = m.ecphi * axp - m.esphi * ayp;
+  ay = m.esphi * axp + m.ecphi * ayp;
+}
+
 __device__ __forceinline__ void macro_deflection64(const MacroC& m, double tx, double ty, double& ax, double& ay) {
   ax = 0.0;
   ay = 0.0;
@@ -142,6 +183,12 @@ __device__ __forceinline__ void macro_deflection64(const MacroC& m, double tx, d
     }
     ax = m.dcphi * axp - m.dsphi * ayp;
     ay = m.dsphi * axp + m.dcphi * ayp;
+  }
+  if (m.has_epl) {
+    double ex, ey;
+    epl_deflection64(m, tx, ty, ex, ey);
+    ax += ex;
+    ay += ey;
   }
   if (m.has_shear) {
     ax += m.dg1 * tx + m.dg2 * ty;

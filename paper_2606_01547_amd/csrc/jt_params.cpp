@@ -99,6 +99,27 @@ jt_status make_macro(const jt_lens* lens, MacroC& m) {
     m.q = (float)s.q;
     m.sqrt_q = (float)std::sqrt(s.q);
   }
+  if (lens->has_epl) {
+    const jt_epl& e = lens->epl;
+    if (!finite(e.theta_E) || !finite(e.gamma) || !finite(e.q) || !finite(e.phi) || !finite(e.cx) || !finite(e.cy))
+      return fail(JT_EINVAL, "EPL: non-finite parameter");
+    if (e.theta_E < 0.0) return fail(JT_EINVAL, "EPL: theta_E = %g < 0", e.theta_E);
+    if (!(e.gamma > 1.0 && e.gamma < 3.0)) return fail(JT_EINVAL, "EPL: gamma = %g not in (1, 3)", e.gamma);
+    if (!(e.q > 0.0 && e.q <= 1.0)) return fail(JT_EINVAL, "EPL: q = %g not in (0, 1]", e.q);
+    if (e.q < 0.05) return fail(JT_EUNSUPPORTED, "EPL: q = %g below 0.05 (series too long)", e.q);
+    const double t = e.gamma - 1.0, b = e.theta_E * std::sqrt(e.q);
+    m.has_epl = e.theta_E > 0.0;
+    m.ecx = e.cx;
+    m.ecy = e.cy;
+    m.ecphi = std::cos(e.phi);
+    m.esphi = std::sin(e.phi);
+    m.eq = e.q;
+    m.ef = (1.0 - e.q) / (1.0 + e.q);
+    m.e2mt = 2.0 - t;
+    m.eb = b;
+    m.etm1 = t - 1.0;
+    m.epref = 2.0 * b / (1.0 + e.q);
+  }
   if (lens->has_shear) {
     if (!finite(lens->shear.gamma1) || !finite(lens->shear.gamma2))
       return fail(JT_EINVAL, "shear: non-finite parameter");

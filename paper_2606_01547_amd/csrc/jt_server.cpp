@@ -748,6 +748,8 @@ extern "C" jt_status jt_server_submit(jt_server* srv, const jt_request* req, uin
   lens.sie = req->sie;
   lens.has_shear = req->has_shear;
   lens.shear = req->shear;
+  lens.has_epl = req->has_epl;
+  lens.epl = req->epl;
   JT_TRY(make_macro(&lens, r->mc));
   JT_TRY(make_light(&req->src, r->src, "source"));
   JT_TRY(make_light(&req->lens_light, r->ll, "lens light"));

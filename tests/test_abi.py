@@ -61,7 +61,11 @@ int main(void) {
   P(jt_sie); P(jt_shear);
   P(jt_nfw); O(jt_nfw, x); O(jt_nfw, alpha_Rs);
   P(jt_point_masses); O(jt_point_masses, theta_E);
+  P(jt_epl); O(jt_epl, gamma); O(jt_epl, cy);
   P(jt_lens); O(jt_lens, sie); O(jt_lens, shear); O(jt_lens, nfw); O(jt_lens, subhalo_handle); O(jt_lens, pm);
+  O(jt_lens, has_epl); O(jt_lens, epl);
+  P(jt_request); O(jt_request, sie); O(jt_request, subhalo_handle); O(jt_request, src); O(jt_request, lens_light);
+  O(jt_request, psf_handle); O(jt_request, out); O(jt_request, has_epl); O(jt_request, epl);
   P(jt_sersic); P(jt_light); O(jt_light, c); O(jt_light, bn_exact);
   P(jt_draws); O(jt_draws, sie); O(jt_draws, n_sub); O(jt_draws, sub_alpha_Rs); O(jt_draws, n_ll); O(jt_draws, ll);
   P(jt_server_stats); O(jt_server_stats, device_seconds); O(jt_server_stats, max_wait_seconds);
@@ -81,7 +85,8 @@ def test_ctypes_structs_match_c_layout(tmp_path):
                                                               check=True).stdout.splitlines())
     m = {"jt_grid": nat.JtGrid, "jt_sie": nat.JtSie, "jt_shear": nat.JtShear, "jt_nfw": nat.JtNfw,
          "jt_point_masses": nat.JtPointMasses, "jt_lens": nat.JtLens, "jt_sersic": nat.JtSersic,
-         "jt_light": nat.JtLight, "jt_draws": nat.JtDraws, "jt_server_stats": nat.JtServerStats}
+         "jt_light": nat.JtLight, "jt_draws": nat.JtDraws, "jt_server_stats": nat.JtServerStats,
+         "jt_epl": nat.JtEpl, "jt_request": nat.JtRequest}
     for key, val in got.items():
         if "." in key:
             t, f = key.split(".")

@@ -113,6 +113,21 @@ def test_chunked_requests_equal_single_requests(ctx):
         np.testing.assert_array_equal(_np(o), _np(ctx.simulate_scene(sc)))
 
 
+def test_epl_requests_equal_single_requests(ctx):
+    """Requests with an elliptical power-law main deflector batch beside SIE
+    requests and give the same image as alone."""
+    epl = [W.epl_scene(seed=30 + i, n_sub=n, npix=p, supersample=s, psf_size=21)
+           for i, (n, p, s) in enumerate([(1, 40, 3), (500, 64, 1), (2000, 50, 3)])]
+    scenes = _requests(4, seed=15)
+    scenes = scenes[:2] + epl + scenes[2:]
+    outs, lat, st = _serve(ctx, scenes, None, hbm_budget_bytes=256 << 20, max_batch_images=8,
+                           max_batch_pairs=5e8, max_inflight_batches=3, n_streams=2)
+    assert st["completed"] == len(scenes) and st["failed"] == 0
+    for sc, o in zip(scenes, outs):
+        np.testing.assert_array_equal(_np(o), _np(ctx.simulate_scene(sc)))
+    assert image_error(_np(outs[2]), O.simulate_image(epl[0])) <= IMAGE_TOL
+
+
 def test_tight_arena_serialises_but_completes(ctx):
     scenes = _requests(10, seed=11)
     outs, lat, st = _serve(ctx, scenes, None, hbm_budget_bytes=1 << 20, max_batch_images=4,

@@ -71,6 +71,19 @@ class SIE:
 
 
 @dataclass
+class EPL:
+    """Elliptical power-law main deflector: Einstein radius theta_E (arcsec),
+    3-D density slope gamma in (1, 3) (2 = SIE), axis ratio q, position angle
+    phi, centre (cx, cy)."""
+    theta_E: float
+    gamma: float
+    q: float
+    phi: float
+    cx: float
+    cy: float
+
+
+@dataclass
 class Shear:
     """External shear (gamma1, gamma2), centred on the coordinate origin."""
     gamma1: float
@@ -115,6 +128,7 @@ class Sersic:
 @dataclass
 class Lens:
     sie: Optional[SIE] = None
+    epl: Optional[EPL] = None
     shear: Optional[Shear] = None
     nfw: Optional[NFWTable] = None
     point_masses: Optional[PointMasses] = None
@@ -230,6 +244,14 @@ def _macro(rng: np.random.Generator):
     return sie, shear
 
 
+def _macro_epl(rng: np.random.Generator):
+    epl = EPL(theta_E=f32(rng.uniform(0.8, 1.5)), gamma=f32(rng.uniform(1.8, 2.2)),
+              q=f32(rng.uniform(0.6, 1.0)), phi=f32(rng.uniform(0.0, math.pi)),
+              cx=f32(rng.normal(0.0, 0.05)), cy=f32(rng.normal(0.0, 0.05)))
+    shear = Shear(gamma1=f32(rng.normal(0.0, 0.03)), gamma2=f32(rng.normal(0.0, 0.03)))
+    return epl, shear
+
+
 def _source(rng: np.random.Generator, amp: float) -> Sersic:
     return Sersic(amp=f32(amp), R_sersic=f32(rng.uniform(0.1, 0.4)),
                   n_sersic=f32(rng.uniform(1.0, 4.0)), q=f32(rng.uniform(0.6, 1.0)),
@@ -237,7 +259,7 @@ def _source(rng: np.random.Generator, amp: float) -> Sersic:
                   cy=f32(rng.normal(0.0, 0.1)))
 
 
-def _lens_light(rng: np.random.Generator, sie: SIE) -> Sersic:
+def _lens_light(rng: np.random.Generator, sie) -> Sersic:
     return Sersic(amp=f32(5.0), R_sersic=f32(rng.uniform(0.5, 1.5)),
                   n_sersic=f32(rng.uniform(2.0, 4.0)), q=f32(rng.uniform(0.6, 1.0)),
                   phi=f32(rng.uniform(0.0, math.pi)), cx=sie.cx, cy=sie.cy)
@@ -284,6 +306,23 @@ def config2_scene(seed: int = 1002, n_sub: int = 10000, npix: int = 200,
     grid = Grid(nx=npix, ny=npix, pixel_scale=0.05, supersample=supersample)
     psf = airy_mix_psf(psf_size, 2.0, 3.0, 0.01, r_psf)
     return Scene(grid=grid, lens=Lens(sie=sie, shear=shear, nfw=nfw), source=srcs,
+                 lens_light=[ll], psf=psf)
+
+
+def epl_scene(seed: int = 1006, n_sub: int = 10000, npix: int = 200,
+              supersample: int = 3, psf_size: int = 41) -> Scene:
+    """The headline image with an elliptical power-law main deflector in place
+    of the SIE (slope gamma uniform in [1.8, 2.2], the other priors as the
+    SIE's): 200x200 px at 0.05"/px, s = 3, EPL + shear + 10,000 NFW, one
+    lens-light and two source Sersic components, 41x41 PSF."""
+    r_macro, r_sub, r_ll, r_s1, r_s2, r_psf = _rngs(seed, 6)
+    epl, shear = _macro_epl(r_macro)
+    nfw = _subhalos(r_sub, n_sub, 1e6, 1e9, 3.0, epl.cx, epl.cy)
+    ll = _lens_light(r_ll, epl)
+    srcs = [_source(r_s1, 10.0), _source(r_s2, 5.0)]
+    grid = Grid(nx=npix, ny=npix, pixel_scale=0.05, supersample=supersample)
+    psf = airy_mix_psf(psf_size, 2.0, 3.0, 0.01, r_psf)
+    return Scene(grid=grid, lens=Lens(epl=epl, shear=shear, nfw=nfw), source=srcs,
                  lens_light=[ll], psf=psf)
 
 
