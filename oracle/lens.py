@@ -224,6 +224,69 @@ def nfw_deflection(x, y, Rs, alpha_Rs, cx, cy, chunk_points=4096, chunk_sub=1024
 
 
 # --------------------------------------------------------------------------
+# TNFW: truncated NFW  (Baltz, Marshall & Oguri 2009, truncation exponent 1)
+# --------------------------------------------------------------------------
+def tnfw_G(X, tau):
+    """Projected mass inside x = R/Rs of the density
+    rho_NFW(r) tau^2 / (tau^2 + (r/Rs)^2), tau = r_trunc/Rs, in the units in
+    which the untruncated profile's is `nfw_g`:
+        G = tau^2/(tau^2+1)^2 [ (tau^2 + 1 + 2(x^2 - 1)) F(x) + pi tau
+                                + (tau^2 - 1) ln tau
+                                + sqrt(tau^2 + x^2) (-pi + (tau^2 - 1)/tau L(x)) ],
+        L(x) = ln( x / (sqrt(tau^2 + x^2) + tau) ),
+    with F of `nfw_g`.  X and tau broadcast."""
+    X = np.asarray(X, dtype=np.float64)
+    tau = np.asarray(tau, dtype=np.float64)
+    X, tau = np.broadcast_arrays(X, tau)
+    t2 = tau * tau
+    s = np.sqrt(t2 + X * X)
+    F = _nfw_F(X.reshape(-1)).reshape(X.shape)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        L = np.log(X / (s + tau))
+        return t2 / (t2 + 1.0) ** 2 * ((t2 + 1.0 + 2.0 * (X * X - 1.0)) * F + np.pi * tau
+                                       + (t2 - 1.0) * np.log(tau) + s * (-np.pi + (t2 - 1.0) / tau * L))
+
+
+def tnfw_deflection(x, y, Rs, alpha_Rs, r_trunc, cx, cy, chunk_points=4096, chunk_sub=1024):
+    """Sum of TNFW deflections over subhalos k, normalised like the NFW (alpha_Rs
+    is the untruncated profile's deflection at r = Rs, so both share rho_0):
+        alpha_k = alpha_Rs,k / (1 - ln 2) * G(r/Rs,k, tau_k) / (r/Rs,k) * (dx, dy)/r,
+    tau_k = r_trunc,k / Rs,k; alpha_k = 0 at r = 0."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    shape = x.shape
+    xf = x.reshape(-1)
+    yf = y.reshape(-1)
+    Rs = np.atleast_1d(np.asarray(Rs, dtype=np.float64))
+    aRs = np.atleast_1d(np.asarray(alpha_Rs, dtype=np.float64))
+    tau = np.atleast_1d(np.asarray(r_trunc, dtype=np.float64)) / Rs
+    cx = np.atleast_1d(np.asarray(cx, dtype=np.float64))
+    cy = np.atleast_1d(np.asarray(cy, dtype=np.float64))
+    ax = np.zeros_like(xf)
+    ay = np.zeros_like(yf)
+    nsub = Rs.shape[0]
+    for p0 in range(0, xf.shape[0], chunk_points):
+        px = xf[p0:p0 + chunk_points, None]
+        py = yf[p0:p0 + chunk_points, None]
+        sx = np.zeros(px.shape[0])
+        sy = np.zeros(px.shape[0])
+        for k0 in range(0, nsub, chunk_sub):
+            sl = slice(k0, k0 + chunk_sub)
+            dx = px - cx[None, sl]
+            dy = py - cy[None, sl]
+            r = np.hypot(dx, dy)
+            X = r / Rs[None, sl]
+            G = tnfw_G(np.where(r > 0.0, X, 1.0), tau[None, sl])
+            with np.errstate(invalid="ignore", divide="ignore"):
+                fac = np.where(r > 0.0, aRs[None, sl] / (1.0 - LN2) * G / X / r, 0.0)
+            sx += np.sum(fac * dx, axis=1)
+            sy += np.sum(fac * dy, axis=1)
+        ax[p0:p0 + chunk_points] = sx
+        ay[p0:p0 + chunk_points] = sy
+    return ax.reshape(shape), ay.reshape(shape)
+
+
+# --------------------------------------------------------------------------
 # point mass (test profile)
 # --------------------------------------------------------------------------
 def point_mass_deflection(x, y, theta_E, cx, cy):
@@ -268,7 +331,11 @@ def total_deflection(x, y, lens):
         ax += dx
         ay += dy
     nfw = getattr(lens, "nfw", None)
-    if nfw is not None and nfw.x.shape[0] > 0:
+    if nfw is not None and nfw.x.shape[0] > 0 and getattr(nfw, "r_trunc", None) is not None:
+        dx, dy = tnfw_deflection(x, y, nfw.Rs, nfw.alpha_Rs, nfw.r_trunc, nfw.x, nfw.y)
+        ax += dx
+        ay += dy
+    elif nfw is not None and nfw.x.shape[0] > 0:
         dx, dy = nfw_deflection(x, y, nfw.Rs, nfw.alpha_Rs, nfw.x, nfw.y)
         ax += dx
         ay += dy

@@ -14,6 +14,10 @@ own deflection formulas.
 * NFW: kappa against a numerical line-of-sight projection of the 3-D NFW
   density; alpha against the enclosed-mass integral of kappa; 50-digit mpmath
   values of g(x); |alpha(Rs)| = alpha_Rs; div alpha = 2 kappa; linearity.
+* TNFW: alpha against the mass of the truncated 3-D density inside the
+  cylinder of radius r (one-dimensional quadrature over spherical shells); the
+  untruncated limit is the NFW; the far-field limit is the total mass of the
+  density; zero at the centre, linear in alpha_Rs.
 * Point mass: the two image positions of the quadratic lens equation.
 """
 import math
@@ -290,6 +294,66 @@ def test_nfw_zero_at_centre_and_chunking_invariant():
     a1 = O.nfw_deflection(x, y, Rs, aRs, cx, cy)
     a2 = O.nfw_deflection(x, y, Rs, aRs, cx, cy, chunk_points=5, chunk_sub=1)
     np.testing.assert_allclose(a1[0], a2[0], rtol=1e-14)
+
+
+# ---------------------------------------------------------------- TNFW
+def _tnfw_rho(xi, tau):
+    """Truncated NFW density in units of rho_0 at r = xi Rs."""
+    return 1.0 / (xi * (1.0 + xi) ** 2) * tau * tau / (tau * tau + xi * xi)
+
+
+def _cylinder_mass(X, tau):
+    """Mass of the density inside the cylinder of radius X (units rho_0 Rs^3 / 4 pi):
+    a shell of radius xi lies inside for xi <= X, otherwise the fraction
+    1 - sqrt(1 - X^2/xi^2) of it does."""
+    f = lambda xi: xi * xi * _tnfw_rho(xi, tau)
+    a, _ = quad(f, 0.0, X, epsabs=0, epsrel=1e-12, limit=400)
+    b, _ = quad(lambda xi: f(xi) * (1.0 - math.sqrt(1.0 - (X / xi) ** 2)), X, np.inf, epsabs=0, epsrel=1e-12,
+                limit=400)
+    return a + b
+
+
+@pytest.mark.parametrize("tau", [0.4, 1.0, 3.0, 25.0])
+@pytest.mark.parametrize("X", [0.01, 0.5, 0.97, 1.0, 1.03, 4.0, 60.0])
+def test_tnfw_alpha_is_cylinder_mass(X, tau):
+    # alpha(R) = M_cyl(R) / (pi R) with rho_0 = alpha_Rs / (4 Rs^2 (1 - ln 2))
+    Rs, aRs = 0.2, 3e-3
+    r = X * Rs
+    ax, ay = O.tnfw_deflection(np.array([r]), np.array([0.0]), Rs, aRs, tau * Rs, 0.0, 0.0)
+    rho0 = aRs / (4.0 * Rs * Rs * (1.0 - math.log(2.0)))
+    expect = 4.0 * math.pi * rho0 * Rs ** 3 * _cylinder_mass(X, tau) / (math.pi * r)
+    assert abs(ax[0] - expect) <= 1e-9 * expect
+    assert ay[0] == 0.0
+
+
+def test_tnfw_untruncated_limit_is_nfw():
+    rng = np.random.default_rng(8)
+    x, y = rng.uniform(-2, 2, (2, 300))
+    Rs = np.array([0.05, 0.3, 0.9])
+    aRs = np.array([1e-3, 4e-3, 2e-2])
+    sx, sy = np.array([0.2, -0.5, 1.0]), np.array([0.1, 0.7, -0.4])
+    a = O.tnfw_deflection(x, y, Rs, aRs, 1e7 * Rs, sx, sy)
+    b = O.nfw_deflection(x, y, Rs, aRs, sx, sy)
+    np.testing.assert_allclose(a[0], b[0], rtol=1e-8, atol=1e-15)
+    np.testing.assert_allclose(a[1], b[1], rtol=1e-8, atol=1e-15)
+
+
+@pytest.mark.parametrize("tau", [0.5, 2.0, 15.0])
+def test_tnfw_far_field_is_total_mass(tau):
+    m, _ = quad(lambda xi: xi * xi * _tnfw_rho(xi, tau), 0.0, np.inf, epsabs=0, epsrel=1e-12, limit=400)
+    G = O.tnfw_G(1e5, tau)
+    assert abs(G - m) <= 1e-4 * m                 # the mass outside x falls as x^-2
+
+
+def test_tnfw_zero_at_centre_and_linear_in_alpha_Rs():
+    rng = np.random.default_rng(4)
+    x, y = rng.uniform(-1, 1, (2, 50))
+    x[0], y[0] = 0.3, -0.2
+    a1 = O.tnfw_deflection(x, y, 0.1, 1e-3, 0.8, 0.3, -0.2)
+    a3 = O.tnfw_deflection(x, y, 0.1, 3e-3, 0.8, 0.3, -0.2)
+    assert a1[0][0] == 0.0 and a1[1][0] == 0.0
+    np.testing.assert_allclose(a3[0], 3.0 * a1[0], rtol=1e-14)
+    np.testing.assert_allclose(a3[1], 3.0 * a1[1], rtol=1e-14)
 
 
 # ---------------------------------------------------------------- point mass

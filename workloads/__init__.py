@@ -93,11 +93,14 @@ class Shear:
 @dataclass
 class NFWTable:
     """NFW subhalos as a structure of FP32 arrays (arcsec): centres (x, y),
-    scale radius Rs and alpha_Rs, the deflection at r = Rs."""
+    scale radius Rs and alpha_Rs, the deflection at r = Rs; with `r_trunc`
+    (truncation radii) they are truncated NFW (TNFW) subhalos of the same
+    inner density."""
     x: np.ndarray
     y: np.ndarray
     Rs: np.ndarray
     alpha_Rs: np.ndarray
+    r_trunc: Optional[np.ndarray] = None
 
     @property
     def n(self) -> int:
@@ -323,6 +326,25 @@ def epl_scene(seed: int = 1006, n_sub: int = 10000, npix: int = 200,
     grid = Grid(nx=npix, ny=npix, pixel_scale=0.05, supersample=supersample)
     psf = airy_mix_psf(psf_size, 2.0, 3.0, 0.01, r_psf)
     return Scene(grid=grid, lens=Lens(epl=epl, shear=shear, nfw=nfw), source=srcs,
+                 lens_light=[ll], psf=psf)
+
+
+def tnfw_scene(seed: int = 1007, n_sub: int = 10000, npix: int = 200,
+               supersample: int = 3, psf_size: int = 41, tau_lo: float = 3.0, tau_hi: float = 30.0) -> Scene:
+    """The headline image with truncated subhalos: the same priors, and each
+    subhalo truncated at r_trunc = tau Rs with tau log-uniform in
+    [tau_lo, tau_hi]; 200x200 px, s = 3, SIE + shear + 10,000 TNFW, one
+    lens-light and two source Sersic components, 41x41 PSF."""
+    r_macro, r_sub, r_ll, r_s1, r_s2, r_psf, r_tau = _rngs(seed, 7)
+    sie, shear = _macro(r_macro)
+    nfw = _subhalos(r_sub, n_sub, 1e6, 1e9, 3.0, sie.cx, sie.cy)
+    tau = 10.0 ** r_tau.uniform(math.log10(tau_lo), math.log10(tau_hi), size=n_sub)
+    nfw.r_trunc = (tau * nfw.Rs.astype(np.float64)).astype(np.float32)
+    ll = _lens_light(r_ll, sie)
+    srcs = [_source(r_s1, 10.0), _source(r_s2, 5.0)]
+    grid = Grid(nx=npix, ny=npix, pixel_scale=0.05, supersample=supersample)
+    psf = airy_mix_psf(psf_size, 2.0, 3.0, 0.01, r_psf)
+    return Scene(grid=grid, lens=Lens(sie=sie, shear=shear, nfw=nfw), source=srcs,
                  lens_light=[ll], psf=psf)
 
 
