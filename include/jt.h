@@ -99,8 +99,14 @@ typedef struct { double gamma1, gamma2; } jt_shear;
 /* NFW subhalos as device float32 structure-of-arrays of length n (arcsec):
  * centre (x, y), scale radius Rs > 0 and alpha_Rs = |alpha| at r = Rs.
  * alpha_k = alpha_Rs/(1 - ln 2) * g(r/Rs)/(r/Rs) * (dx, dy)/r with
- * g(x) = ln(x/2) + F(x) (Bartelmann 1996; Golse & Kneib 2002). */
-typedef struct { int n; const float *x, *y, *Rs, *alpha_Rs; } jt_nfw;
+ * g(x) = ln(x/2) + F(x) (Bartelmann 1996; Golse & Kneib 2002).
+ * r_trunc != NULL (device float32[n], each > 0): truncated NFW (TNFW, in the
+ * paper's deflector table) in the form of Baltz, Marshall & Oguri (2009) with
+ * truncation exponent 1, density rho_NFW tau^2/(tau^2 + (r/Rs)^2),
+ * tau = r_trunc/Rs, and the same rho_0 as the NFW of this alpha_Rs, so that
+ * alpha_k = alpha_Rs/(1 - ln 2) * G(r/Rs, tau)/(r/Rs) * (dx, dy)/r with G the
+ * projected mass in the units of g.  Device arrays are not validated. */
+typedef struct { int n; const float *x, *y, *Rs, *alpha_Rs, *r_trunc; } jt_nfw;
 
 /* Point masses (test profile), host float64 arrays of length n <= 16:
  * alpha = theta_E^2 (dx, dy) / r^2. */
@@ -111,7 +117,7 @@ typedef struct {
   jt_sie sie;
   jt_shear shear;
   jt_nfw nfw;                /* n = 0: no subhalos */
-  uint64_t subhalo_handle;   /* nonzero: a table from jt_upload_subhalos, `nfw` ignored */
+  uint64_t subhalo_handle;   /* nonzero: a table from jt_upload_subhalos or jt_upload_tnfw, `nfw` ignored */
   jt_point_masses pm;        /* n = 0: none */
   int has_epl;               /* adds an EPL (with or without the SIE) */
   jt_epl epl;
@@ -234,6 +240,11 @@ jt_status jt_chi2_grad(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, 
  * table owned by ctx (n = 0 allowed).  *handle != 0 on success. */
 jt_status jt_upload_subhalos(jt_ctx* ctx, int n, const float* x, const float* y,
                              const float* Rs, const float* alpha_Rs, uint64_t* handle);
+/* The same for truncated subhalos (r_trunc, host float32[n], each > 0; see
+ * jt_nfw).  The continuous-batching server does not take such tables
+ * (JT_EUNSUPPORTED at submit); the single-image calls do. */
+jt_status jt_upload_tnfw(jt_ctx* ctx, int n, const float* x, const float* y, const float* Rs,
+                         const float* alpha_Rs, const float* r_trunc, uint64_t* handle);
 /* Copy a host float32 [k][k] PSF (odd k) into device memory owned by ctx. */
 jt_status jt_upload_psf(jt_ctx* ctx, const float* psf, int k, uint64_t* handle);
 /* Device pointer of a resident PSF (valid until released). */

@@ -46,7 +46,8 @@ class JtShear(ctypes.Structure):
 
 
 class JtNfw(ctypes.Structure):
-    _fields_ = [("n", c_int), ("x", c_void_p), ("y", c_void_p), ("Rs", c_void_p), ("alpha_Rs", c_void_p)]
+    _fields_ = [("n", c_int), ("x", c_void_p), ("y", c_void_p), ("Rs", c_void_p), ("alpha_Rs", c_void_p),
+                ("r_trunc", c_void_p)]
 
 
 class JtPointMasses(ctypes.Structure):
@@ -122,6 +123,8 @@ _SIGS = {
     "jt_simulate_image": (c_int, [c_void_p, POINTER(JtGrid), POINTER(JtLens), POINTER(JtLight), POINTER(JtLight),
                                   c_void_p, c_int, c_void_p, c_void_p]),
     "jt_upload_subhalos": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_uint64)]),
+    "jt_upload_tnfw": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                               POINTER(c_uint64)]),
     "jt_upload_psf": (c_int, [c_void_p, c_void_p, c_int, POINTER(c_uint64)]),
     "jt_psf_pointer": (c_int, [c_void_p, c_uint64, POINTER(c_void_p), POINTER(c_int)]),
     "jt_release": (c_int, [c_void_p, c_uint64]),
@@ -254,7 +257,9 @@ class Context:
         if handle:
             L.subhalo_handle = int(handle)
         elif nfw is not None and len(nfw.x) > 0:
-            arrs = [_dev_f32(a, self.device, keep) for a in (nfw.x, nfw.y, nfw.Rs, nfw.alpha_Rs)]
+            rt = getattr(nfw, "r_trunc", None)
+            fields = (nfw.x, nfw.y, nfw.Rs, nfw.alpha_Rs) + ((rt,) if rt is not None else ())
+            arrs = [_dev_f32(a, self.device, keep) for a in fields]
             L.nfw = JtNfw(int(arrs[0].numel()), *[c_void_p(a.data_ptr()) for a in arrs])
         pm = getattr(lens, "point_masses", None)
         if pm is not None and np.size(pm.x) > 0:
@@ -438,10 +443,14 @@ class Context:
 
     # ---- resident tables
     def upload_subhalos(self, nfw) -> int:
-        cols = [np.ascontiguousarray(np.asarray(v, dtype=np.float32)) for v in (nfw.x, nfw.y, nfw.Rs, nfw.alpha_Rs)]
+        """Resident table of NFW subhalos, or of truncated ones when
+        `nfw.r_trunc` is set."""
+        rt = getattr(nfw, "r_trunc", None)
+        fields = (nfw.x, nfw.y, nfw.Rs, nfw.alpha_Rs) + ((rt,) if rt is not None else ())
+        cols = [np.ascontiguousarray(np.asarray(v, dtype=np.float32)) for v in fields]
         h = c_uint64()
-        _check(self._lib.jt_upload_subhalos(self._ptr, int(cols[0].size), *[c_void_p(c.ctypes.data) for c in cols],
-                                            byref(h)))
+        fn = self._lib.jt_upload_tnfw if rt is not None else self._lib.jt_upload_subhalos
+        _check(fn(self._ptr, int(cols[0].size), *[c_void_p(c.ctypes.data) for c in cols], byref(h)))
         return int(h.value)
 
     def upload_psf(self, psf) -> int:

@@ -246,6 +246,29 @@ extern "C" jt_status jt_upload_subhalos(jt_ctx* ctx, int n, const float* x, cons
   return JT_OK;
 }
 
+extern "C" jt_status jt_upload_tnfw(jt_ctx* ctx, int n, const float* x, const float* y, const float* Rs,
+                                    const float* alpha_Rs, const float* r_trunc, uint64_t* handle) {
+  JT_TRY(ctx_enter(ctx));
+  if (!handle) return fail(JT_EINVAL, "jt_upload_tnfw: null handle pointer");
+  if (n < 0) return fail(JT_EINVAL, "jt_upload_tnfw: n = %d", n);
+  if (n > 0 && (!x || !y || !Rs || !alpha_Rs || !r_trunc)) return fail(JT_EINVAL, "jt_upload_tnfw: null array");
+  std::vector<TRec> tab;
+  JT_TRY(pack_tnfw_host(n, x, y, Rs, alpha_Rs, r_trunc, tab));
+  void* dev = nullptr;
+  JT_TRY(check_hip(hipMalloc(&dev, tab.size() * sizeof(TRec)), "hipMalloc(tnfw)"));
+  jt_status st = check_hip(hipMemcpy(dev, tab.data(), tab.size() * sizeof(TRec), hipMemcpyHostToDevice),
+                           "hipMemcpy(tnfw)");
+  if (st != JT_OK) {
+    (void)hipFree(dev);
+    return st;
+  }
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  const uint64_t h = ctx->next_handle++;
+  ctx->handles[h] = Resident{3, dev, n};
+  *handle = h;
+  return JT_OK;
+}
+
 extern "C" jt_status jt_upload_psf(jt_ctx* ctx, const float* psf, int k, uint64_t* handle) {
   JT_TRY(ctx_enter(ctx));
   if (!handle || !psf) return fail(JT_EINVAL, "jt_upload_psf: null pointer");
@@ -292,13 +315,14 @@ extern "C" jt_status jt_release(jt_ctx* ctx, uint64_t handle) {
 }
 
 namespace jt {
-jt_status ctx_subhalo_handle(jt_ctx* ctx, uint64_t h, const SubRec** table, int* n) {
+jt_status ctx_subhalo_handle(jt_ctx* ctx, uint64_t h, const void** table, int* n, bool* tnfw) {
   std::lock_guard<std::mutex> lk(ctx->mu);
   auto it = ctx->handles.find(h);
-  if (it == ctx->handles.end() || it->second.kind != 1)
+  if (it == ctx->handles.end() || (it->second.kind != 1 && it->second.kind != 3))
     return fail(JT_EINVAL, "unknown subhalo handle %llu", (unsigned long long)h);
-  *table = (const SubRec*)it->second.dev;
+  *table = it->second.dev;
   *n = it->second.n;
+  *tnfw = it->second.kind == 3;
   return JT_OK;
 }
 

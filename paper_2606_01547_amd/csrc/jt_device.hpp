@@ -99,6 +99,13 @@ struct __align__(16) SubRec {
   float x, y, c1, c2;
 };
 
+// Truncated NFW record (Baltz, Marshall & Oguri 2009, truncation exponent 1):
+// centre, c1 = 1/Rs^2, c2 = alpha_Rs/((1 - ln 2) Rs) * tau^2/(tau^2 + 1)^2 and
+// tau = r_trunc/Rs with tau^2, tau^2 - 1, tau^2 + 1, each rounded once from FP64.
+struct __align__(16) TRec {
+  float x, y, c1, c2, tau, t2, t2m1, t2p1;
+};
+
 struct ImageDesc {
   GridC g;               // g.ppb matches the launch's wave split
   MacroC mc;
@@ -320,6 +327,67 @@ __device__ __forceinline__ void nfw_pairs4(float tx, float ty, const SubRec& s0,
   sy = fmaf(h2 * s2.c2, dy2, sy);
   sx = fmaf(h3 * s3.c2, dx3, sx);
   sy = fmaf(h3 * s3.c2, dy3, sy);
+}
+
+// ---------------------------------------------------------------------------
+// TNFW pair term
+// ---------------------------------------------------------------------------
+// With x^2 = X2, s = sqrt(tau^2 + x^2), sp = s + tau, the projected mass of
+// the truncated profile regrouped so that no step cancels catastrophically:
+//   G/x^2 = A [ (tau^2 - 1) P1 + P2 ],  A = tau^2/(tau^2 + 1)^2 (in c2),
+//   P1 = (g - ln((sp)/(2 tau))) / x^2 + L / (tau sp),
+//   P2 = 2F - pi/sp,
+// g = ln(x/2) + F the NFW function, L = ln(x/sp) = -log1p((tau + tau^2/(s+x))/x)
+// and ln(sp/(2 tau)) = log1p(x^2/(2 tau sp)).  F and g by branch:
+//   x^2 < 0.8:  g = [-ln(x/2) x^2/(1+w) + log1p(-x^2/(2(1+w)))]/w, w = sqrt(1-x^2);
+//   x^2 < 1.2:  F = sum_k (-v)^k/(2k+1), v = x^2 - 1;
+//   otherwise:  u = sqrt(x^2 - 1), a = atan(1/u), F = (pi/2 - a)/u, and
+//               P2 = pi (tau + (tau^2+1)/(s+u)) / (u sp) - 2a/u, which avoids
+//               the cancellation of 2F against pi/sp far from the centre.
+// 0 at the centre (X2 = 0).
+__device__ __forceinline__ void tnfw_pair(float tx, float ty, const TRec& r, float& sx, float& sy) {
+  constexpr float kPi = 3.14159265358979323846f;
+  constexpr float kHalfPi = 1.57079632679489661923f;
+  const float dx = tx - r.x, dy = ty - r.y;
+  const float X2 = fmaf(dy, dy, dx * dx) * r.c1;
+  if (!(X2 > 0.0f)) return;
+  const float x = sqrtf(X2);
+  const float s = sqrtf(r.t2 + X2);
+  const float sp = s + r.tau;
+  const float Lh = 0.5f * logf(X2) - kLn2;   // ln(x/2)
+  float F, g, P2;
+  if (X2 < 0.8f) {
+    const float w = sqrtf(1.0f - X2);
+    g = (-Lh * X2 / (1.0f + w) + log1pf(-X2 / (2.0f * (1.0f + w)))) / w;
+    F = g - Lh;
+    P2 = 2.0f * F - kPi / sp;
+  } else if (X2 < 1.2f) {
+    const float v = -(X2 - 1.0f);
+    F = 1.0f / 21.0f;
+    F = fmaf(F, v, 1.0f / 19.0f);
+    F = fmaf(F, v, 1.0f / 17.0f);
+    F = fmaf(F, v, 1.0f / 15.0f);
+    F = fmaf(F, v, 1.0f / 13.0f);
+    F = fmaf(F, v, 1.0f / 11.0f);
+    F = fmaf(F, v, 1.0f / 9.0f);
+    F = fmaf(F, v, 1.0f / 7.0f);
+    F = fmaf(F, v, 1.0f / 5.0f);
+    F = fmaf(F, v, 1.0f / 3.0f);
+    F = fmaf(F, v, 1.0f);
+    g = Lh + F;
+    P2 = 2.0f * F - kPi / sp;
+  } else {
+    const float u = sqrtf(X2 - 1.0f);
+    const float a = atanf(1.0f / u);
+    F = (kHalfPi - a) / u;
+    g = Lh + F;
+    P2 = kPi * (r.tau + r.t2p1 / (s + u)) / (u * sp) - 2.0f * a / u;
+  }
+  const float L = -log1pf((r.tau + r.t2 / (s + x)) / x);
+  const float P1 = (g - log1pf(X2 / (2.0f * r.tau * sp))) / X2 + L / (r.tau * sp);
+  const float h = r.c2 * fmaf(r.t2m1, P1, P2);
+  sx = fmaf(h, dx, sx);
+  sy = fmaf(h, dy, sy);
 }
 
 // Knuth's TwoSum: s + e == a + b exactly.

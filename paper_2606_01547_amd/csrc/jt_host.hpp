@@ -23,7 +23,7 @@ struct Buffer {
 };
 
 struct Resident {
-  int kind = 0;  // 1 = subhalo table, 2 = PSF
+  int kind = 0;  // 1 = NFW subhalo table, 2 = PSF, 3 = TNFW subhalo table
   void* dev = nullptr;
   int n = 0;     // subhalos (kind 1) or PSF side k (kind 2)
 };
@@ -71,7 +71,8 @@ jt_status ctx_workspace_aux(jt_ctx* ctx, hipStream_t stream, size_t bytes, void*
 jt_status ctx_upload(jt_ctx* ctx, hipStream_t stream, void* dev_dst, const void* host_src, size_t bytes);
 // Device twiddle table of an FFT length (built on first use, kept by ctx).
 jt_status ctx_twiddles(jt_ctx* ctx, int N, const double2** out);
-jt_status ctx_subhalo_handle(jt_ctx* ctx, uint64_t h, const SubRec** table, int* n);
+// A resident subhalo table: records (SubRec, or TRec when *tnfw), count.
+jt_status ctx_subhalo_handle(jt_ctx* ctx, uint64_t h, const void** table, int* n, bool* tnfw);
 const SubRec* ctx_empty_table(jt_ctx* ctx);
 hipEvent_t take_event(jt_ctx* ctx);
 void drain_events(jt_ctx* ctx);
@@ -113,11 +114,17 @@ double gamma_p(double a, double x);
 // Packed subhalo table (with padding records) from host FP32 SoA; validates.
 jt_status pack_subhalos_host(int n, const float* x, const float* y, const float* rs, const float* ars,
                              std::vector<SubRec>& out);
+// The same for truncated subhalos (r_trunc > 0).
+jt_status pack_tnfw_host(int n, const float* x, const float* y, const float* rs, const float* ars, const float* rt,
+                         std::vector<TRec>& out);
+// Bytes of the packed table the device SoA of `lens` needs (0 with a handle or
+// no subhalos), 256-byte aligned.
+size_t subhalo_scratch_bytes(const jt_lens* lens);
 
 // Resolves the subhalo table of a lens: resident handle, or device SoA packed
 // into `scratch` (room for subhalo_table_records(n) records) by the prep
 // kernel, or the context's empty table.  *nloop = loop count (multiple of 4).
-jt_status resolve_subhalos(jt_ctx* ctx, const jt_lens* lens, SubRec* scratch, hipStream_t st,
-                           const SubRec** table, int* nloop);
+jt_status resolve_subhalos(jt_ctx* ctx, const jt_lens* lens, void* scratch, hipStream_t st,
+                           const void** table, int* nloop, bool* tnfw);
 
 }  // namespace jt

@@ -16,12 +16,16 @@ inline int subhalo_table_records(int n) { return subhalo_loop_count(n) + 4; }
 // Writes all subhalo_table_records(n) records (padding included).
 hipError_t launch_prep_subhalos(int n, const float* x, const float* y, const float* rs,
                                 const float* ars, SubRec* out, hipStream_t st);
-hipError_t launch_ray_shoot(bool alpha, int n, const float* x, const float* y, const MacroC& mc,
-                            const SubRec* sub, int nloop, float* ox, float* oy, hipStream_t st);
+// The same for truncated subhalos (TRec records; padding has c2 = 0).
+hipError_t launch_prep_tnfw(int n, const float* x, const float* y, const float* rs, const float* ars,
+                            const float* rt, TRec* out, hipStream_t st);
+// `sub` holds SubRec records, or TRec records when tnfw is set.
+hipError_t launch_ray_shoot(bool alpha, bool tnfw, int n, const float* x, const float* y, const MacroC& mc,
+                            const void* sub, int nloop, float* ox, float* oy, hipStream_t st);
 hipError_t launch_source_sb(int n, const float* x, const float* y, const float* bx, const float* by,
                             const LightC& src, const LightC& ll, float* sb, hipStream_t st);
 // g.ppb is set by the launcher from the chosen split.
-hipError_t launch_simulate(GridC g, const MacroC& mc, const SubRec* sub, int nloop, const LightC& src,
+hipError_t launch_simulate(GridC g, const MacroC& mc, bool tnfw, const void* sub, int nloop, const LightC& src,
                            const LightC& ll, float* img, hipStream_t st);
 // Wave-groups per block for `points` sub-pixels in whole units of `unit`.
 int pick_split(long points, int unit, int nloop);

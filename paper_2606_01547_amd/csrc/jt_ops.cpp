@@ -20,17 +20,16 @@ jt_status ray_common(bool alpha, jt_ctx* ctx, int n, const float* x, const float
   if (n == 0) return JT_OK;
   if (!x || !y || !ox || !oy) return fail(JT_EINVAL, "ray_shoot: null array");
   if (ox == x || ox == y || oy == x || oy == y || ox == oy) return fail(JT_EINVAL, "ray_shoot: outputs alias inputs");
-  SubRec* scratch = nullptr;
-  if (!lens->subhalo_handle && lens->nfw.n > 0) {
-    void* ws = nullptr;
-    JT_TRY(ctx_workspace(ctx, st, sizeof(SubRec) * (size_t)subhalo_table_records(lens->nfw.n), &ws));
-    scratch = (SubRec*)ws;
-  }
-  const SubRec* tab = nullptr;
+  void* scratch = nullptr;
+  const size_t tab_bytes = subhalo_scratch_bytes(lens);
+  if (tab_bytes) JT_TRY(ctx_workspace(ctx, st, tab_bytes, &scratch));
+  const void* tab = nullptr;
   int nloop = 0;
-  JT_TRY(resolve_subhalos(ctx, lens, scratch, st, &tab, &nloop));
+  bool tnfw = false;
+  JT_TRY(resolve_subhalos(ctx, lens, scratch, st, &tab, &nloop, &tnfw));
   return timed_launch(ctx, JT_K_RAY, st,
-                      [&] { return launch_ray_shoot(alpha, n, x, y, mc, tab, nloop, ox, oy, st); }, "ray_shoot");
+                      [&] { return launch_ray_shoot(alpha, tnfw, n, x, y, mc, tab, nloop, ox, oy, st); },
+                      "ray_shoot");
 }
 
 jt_status check_conv_args(const float* img, int nx, int ny, const float* psf, int k, const float* out) {
@@ -142,8 +141,7 @@ extern "C" jt_status jt_simulate_image(jt_ctx* ctx, const jt_grid* grid, const j
   if ((psf == nullptr) != (k == 0)) return fail(JT_EINVAL, "simulate: psf and k must be given together");
   if (psf && (k < 1 || k % 2 == 0)) return fail(JT_EINVAL, "simulate: PSF side %d must be odd", k);
   // workspace: [subhalo table][unconvolved image]
-  const bool pack = !lens->subhalo_handle && lens->nfw.n > 0;
-  const size_t tab_bytes = pack ? ((sizeof(SubRec) * (size_t)subhalo_table_records(lens->nfw.n) + 255) & ~size_t(255)) : 0;
+  const size_t tab_bytes = subhalo_scratch_bytes(lens);
   const size_t img_bytes = psf ? sizeof(float) * (size_t)g.nx * g.ny : 0;
   char* ws = nullptr;
   if (tab_bytes + img_bytes > 0) {
@@ -151,12 +149,13 @@ extern "C" jt_status jt_simulate_image(jt_ctx* ctx, const jt_grid* grid, const j
     JT_TRY(ctx_workspace(ctx, stream, tab_bytes + img_bytes, &p));
     ws = (char*)p;
   }
-  const SubRec* tab = nullptr;
+  const void* tab = nullptr;
   int nloop = 0;
-  JT_TRY(resolve_subhalos(ctx, lens, pack ? (SubRec*)ws : nullptr, stream, &tab, &nloop));
+  bool tnfw = false;
+  JT_TRY(resolve_subhalos(ctx, lens, tab_bytes ? ws : nullptr, stream, &tab, &nloop, &tnfw));
   float* img = psf ? (float*)(ws + tab_bytes) : out;
   JT_TRY(timed_launch(ctx, JT_K_SIM, stream,
-                      [&] { return launch_simulate(g, mc, tab, nloop, s, l, img, stream); }, "simulate"));
+                      [&] { return launch_simulate(g, mc, tnfw, tab, nloop, s, l, img, stream); }, "simulate"));
   if (!psf) return JT_OK;
   return convolve_on(ctx, img, g.nx, g.ny, psf, k, 0, out, stream);
 }

@@ -161,20 +161,51 @@ jt_status pack_subhalos_host(int n, const float* x, const float* y, const float*
   return JT_OK;
 }
 
-jt_status resolve_subhalos(jt_ctx* ctx, const jt_lens* lens, SubRec* scratch, hipStream_t st,
-                           const SubRec** table, int* nloop) {
+jt_status pack_tnfw_host(int n, const float* x, const float* y, const float* rs, const float* ars, const float* rt,
+                         std::vector<TRec>& out) {
+  out.assign(subhalo_table_records(n), TRec{1e18f, 1e18f, 1.0f, 0.0f, 1.0f, 1.0f, 0.0f, 2.0f});
+  for (int i = 0; i < n; ++i) {
+    if (!std::isfinite(x[i]) || !std::isfinite(y[i]) || !std::isfinite(ars[i]))
+      return fail(JT_EINVAL, "subhalo %d: non-finite parameter", i);
+    if (!(rs[i] > 0.0f) || !std::isfinite(rs[i])) return fail(JT_EINVAL, "subhalo %d: Rs = %g", i, (double)rs[i]);
+    if (!(rt[i] > 0.0f) || !std::isfinite(rt[i]))
+      return fail(JT_EINVAL, "subhalo %d: r_trunc = %g", i, (double)rt[i]);
+    const double r = rs[i], tau = (double)rt[i] / r, t2 = tau * tau;
+    out[i] = TRec{x[i], y[i], (float)(1.0 / (r * r)),
+                  (float)((double)ars[i] / ((1.0 - kLn2d) * r) * t2 / ((t2 + 1.0) * (t2 + 1.0))), (float)tau,
+                  (float)t2, (float)(t2 - 1.0), (float)(t2 + 1.0)};
+  }
+  return JT_OK;
+}
+
+size_t subhalo_scratch_bytes(const jt_lens* lens) {
+  if (lens->subhalo_handle || lens->nfw.n <= 0) return 0;
+  const size_t rec = lens->nfw.r_trunc ? sizeof(TRec) : sizeof(SubRec);
+  return (rec * (size_t)subhalo_table_records(lens->nfw.n) + 255) & ~size_t(255);
+}
+
+jt_status resolve_subhalos(jt_ctx* ctx, const jt_lens* lens, void* scratch, hipStream_t st, const void** table,
+                           int* nloop, bool* tnfw) {
+  *tnfw = false;
   if (lens->subhalo_handle) {
     int n = 0;
-    JT_TRY(ctx_subhalo_handle(ctx, lens->subhalo_handle, table, &n));
+    JT_TRY(ctx_subhalo_handle(ctx, lens->subhalo_handle, table, &n, tnfw));
     *nloop = subhalo_loop_count(n);
     return JT_OK;
   }
   const jt_nfw& s = lens->nfw;
   if (s.n > 0) {
     if (!scratch) return fail(JT_EINVAL, "internal: no scratch for the subhalo table");
-    JT_TRY(timed_launch(ctx, JT_K_PREP, st,
-                        [&] { return launch_prep_subhalos(s.n, s.x, s.y, s.Rs, s.alpha_Rs, scratch, st); },
-                        "prep_subhalos"));
+    if (s.r_trunc) {
+      JT_TRY(timed_launch(ctx, JT_K_PREP, st,
+                          [&] { return launch_prep_tnfw(s.n, s.x, s.y, s.Rs, s.alpha_Rs, s.r_trunc, (TRec*)scratch, st); },
+                          "prep_tnfw"));
+      *tnfw = true;
+    } else {
+      JT_TRY(timed_launch(ctx, JT_K_PREP, st,
+                          [&] { return launch_prep_subhalos(s.n, s.x, s.y, s.Rs, s.alpha_Rs, (SubRec*)scratch, st); },
+                          "prep_subhalos"));
+    }
     *table = scratch;
     *nloop = subhalo_loop_count(s.n);
     return JT_OK;

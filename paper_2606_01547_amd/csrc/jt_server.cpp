@@ -756,7 +756,13 @@ extern "C" jt_status jt_server_submit(jt_server* srv, const jt_request* req, uin
   if (!req->out) return fail(JT_EINVAL, "server submit: null output");
   r->out = req->out;
   if (srv->ctx) {
-    if (req->subhalo_handle) JT_TRY(ctx_subhalo_handle(srv->ctx, req->subhalo_handle, &r->table, &r->nsub));
+    if (req->subhalo_handle) {
+      const void* tab = nullptr;
+      bool tnfw = false;
+      JT_TRY(ctx_subhalo_handle(srv->ctx, req->subhalo_handle, &tab, &r->nsub, &tnfw));
+      if (tnfw) return fail(JT_EUNSUPPORTED, "server submit: truncated (TNFW) subhalo tables are not batched");
+      r->table = (const SubRec*)tab;
+    }
     if (req->psf_handle) JT_TRY(jt_psf_pointer(srv->ctx, req->psf_handle, &r->psf, &r->k));
   } else {
     r->nsub = (int)req->subhalo_handle;

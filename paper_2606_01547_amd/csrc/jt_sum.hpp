@@ -41,23 +41,51 @@ __host__ __device__ __forceinline__ int part_bound(int n, int parts, int q) {
   return min(q * step, n);
 }
 
+// The pair kernels of the subhalo profiles: the record type, how a record is
+// read from the table, and the contribution of four records at one point.
+struct NfwPairs {
+  using Rec = SubRec;
+  static __device__ __forceinline__ Rec load(SubTable t, int k) { return load_rec(t, k); }
+  static __device__ __forceinline__ void run4(float tx, float ty, const Rec& a, const Rec& b, const Rec& c,
+                                              const Rec& d, float& px, float& py) {
+    nfw_pairs4(tx, ty, a, b, c, d, px, py);
+  }
+};
+
+struct TnfwPairs {
+  using Rec = TRec;
+  static __device__ __forceinline__ Rec load(SubTable t, int k) {
+    const SubTable p = t + 8 * k;
+    return TRec{p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7]};
+  }
+  static __device__ __forceinline__ void run4(float tx, float ty, const Rec& a, const Rec& b, const Rec& c,
+                                              const Rec& d, float& px, float& py) {
+    tnfw_pair(tx, ty, a, px, py);
+    tnfw_pair(tx, ty, b, px, py);
+    tnfw_pair(tx, ty, c, px, py);
+    tnfw_pair(tx, ty, d, px, py);
+  }
+};
+
 // Sum of the pair terms over records [kb, ke) as (hi, lo) per component.  The
 // table holds 4 readable records past every range end (the next range, or
 // the padding at the end), so the next group is always prefetched.
-__device__ __forceinline__ float4 subhalo_range_sum(float tx, float ty, const SubRec* table, int kb, int ke) {
+template <class P>
+__device__ __forceinline__ float4 subhalo_range_sum(float tx, float ty, const void* table, int kb, int ke) {
+  using Rec = typename P::Rec;
   const SubTable sub = (SubTable)(const float*)table;
   float hx = 0.f, lx = 0.f, hy = 0.f, ly = 0.f;
-  SubRec n0 = load_rec(sub, kb), n1 = load_rec(sub, kb + 1), n2 = load_rec(sub, kb + 2), n3 = load_rec(sub, kb + 3);
+  Rec n0 = P::load(sub, kb), n1 = P::load(sub, kb + 1), n2 = P::load(sub, kb + 2), n3 = P::load(sub, kb + 3);
   for (int k0 = kb; k0 < ke; k0 += kSubTile) {
     const int kend = min(k0 + kSubTile, ke);
     float px = 0.f, py = 0.f;
     for (int k = k0; k < kend; k += 4) {
-      const SubRec s0 = n0, s1 = n1, s2 = n2, s3 = n3;
-      n0 = load_rec(sub, k + 4);
-      n1 = load_rec(sub, k + 5);
-      n2 = load_rec(sub, k + 6);
-      n3 = load_rec(sub, k + 7);
-      nfw_pairs4(tx, ty, s0, s1, s2, s3, px, py);
+      const Rec s0 = n0, s1 = n1, s2 = n2, s3 = n3;
+      n0 = P::load(sub, k + 4);
+      n1 = P::load(sub, k + 5);
+      n2 = P::load(sub, k + 6);
+      n3 = P::load(sub, k + 7);
+      P::run4(tx, ty, s0, s1, s2, s3, px, py);
     }
     two_sum_acc(hx, lx, px);
     two_sum_acc(hy, ly, py);
@@ -76,14 +104,14 @@ struct RangeScratch {
 // The ranges of wave-group g for the sub-pixel (tx, ty).  With one group they
 // are added to (sx, sy) in FP64 as they are computed; otherwise each group
 // stores its ranges for group 0, which adds them after the block's barrier.
-template <int kSplit>
-__device__ __forceinline__ void subhalo_ranges(float tx, float ty, const SubRec* __restrict__ sub, int nloop, int g,
+template <int kSplit, class P = NfwPairs>
+__device__ __forceinline__ void subhalo_ranges(float tx, float ty, const void* __restrict__ sub, int nloop, int g,
                                                int slot, RangeScratch<kSplit>& scratch, double& sx, double& sy) {
   constexpr int kOwn = kRanges / kSplit;
 #pragma unroll 1
   for (int i = 0; i < kOwn; ++i) {
     const int e = g * kOwn + i;
-    const float4 v = subhalo_range_sum(tx, ty, sub, range_bound(nloop, e), range_bound(nloop, e + 1));
+    const float4 v = subhalo_range_sum<P>(tx, ty, sub, range_bound(nloop, e), range_bound(nloop, e + 1));
     if (kSplit == 1) {
       sx += (double)v.x + (double)v.y;
       sy += (double)v.z + (double)v.w;

@@ -1,6 +1,7 @@
 // HIP kernels of the lensed-image simulation for gfx950.
 //
 //  k_prep_subhalos  device SoA (x, y, Rs, alpha_Rs) -> packed SubRec table
+//  k_prep_tnfw      device SoA (x, y, Rs, alpha_Rs, r_trunc) -> packed TRec table
 //  k_ray_shoot      step 1 at explicit points: beta = theta - alpha (or alpha)
 //  k_source_sb      step 2 at explicit points
 //  k_simulate       steps 1-2 plus the supersample average, fused
@@ -39,13 +40,28 @@ __global__ __launch_bounds__(256) void k_prep_subhalos(int n, int padded, const 
   out[i] = s;
 }
 
+__global__ __launch_bounds__(256) void k_prep_tnfw(int n, int padded, const float* __restrict__ x,
+                                                  const float* __restrict__ y, const float* __restrict__ rs,
+                                                  const float* __restrict__ ars, const float* __restrict__ rt,
+                                                  TRec* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) {
+    if (i < padded) out[i] = TRec{1e18f, 1e18f, 1.0f, 0.0f, 1.0f, 1.0f, 0.0f, 2.0f};
+    return;
+  }
+  const double r = rs[i], tau = (double)rt[i] / r, t2 = tau * tau;
+  out[i] = TRec{x[i], y[i], (float)(1.0 / (r * r)),
+                (float)((double)ars[i] / ((1.0 - kLn2d) * r) * t2 / ((t2 + 1.0) * (t2 + 1.0))), (float)tau, (float)t2,
+                (float)(t2 - 1.0), (float)(t2 + 1.0)};
+}
+
 // ---------------------------------------------------------------------------
 // Step 1 at explicit points.  Block = kSplit wave-groups x split_lanes(kSplit)
 // points; all groups see the same points.
-template <bool kAlpha, int kSplit>
+template <bool kAlpha, int kSplit, class P>
 __global__ __launch_bounds__(split_threads(kSplit)) void k_ray_shoot(int n, const float* __restrict__ x,
                                                                     const float* __restrict__ y, MacroC mc,
-                                                                    const SubRec* __restrict__ sub, int nloop,
+                                                                    const void* __restrict__ sub, int nloop,
                                                                     float* __restrict__ ox, float* __restrict__ oy) {
   __shared__ RangeScratch<kSplit> scratch;
   constexpr int kW = split_lanes(kSplit);
@@ -58,7 +74,7 @@ __global__ __launch_bounds__(split_threads(kSplit)) void k_ray_shoot(int n, cons
   const float tx = valid ? x[i] : 0.f;
   const float ty = valid ? y[i] : 0.f;
   double sx = 0.0, sy = 0.0;
-  subhalo_ranges<kSplit>(tx, ty, sub, nloop, g, slot, scratch, sx, sy);
+  subhalo_ranges<kSplit, P>(tx, ty, sub, nloop, g, slot, scratch, sx, sy);
   __syncthreads();
   if (g == 0 && valid) {
     double ax, ay;
@@ -112,8 +128,8 @@ __device__ __forceinline__ SubPixel subpixel_of(const GridC& g, int block, int t
 // image.  The kSplit wave-groups share the subhalo quarters of the same
 // slots; group 0 combines them, evaluates the light, and the pixel values are
 // reduced through LDS in a fixed order.
-template <int kSplit>
-__device__ __forceinline__ void simulate_block(const GridC& g, const MacroC& mc, const SubRec* __restrict__ sub,
+template <int kSplit, class P = NfwPairs>
+__device__ __forceinline__ void simulate_block(const GridC& g, const MacroC& mc, const void* __restrict__ sub,
                                                int nloop, const LightC& src, const LightC& ll,
                                                float* __restrict__ img, int block,
                                                RangeScratch<kSplit>& scratch, float* red) {
@@ -122,7 +138,7 @@ __device__ __forceinline__ void simulate_block(const GridC& g, const MacroC& mc,
   const int t = threadIdx.x - grp * kW;
   const SubPixel sp = subpixel_of(g, block, t);
   double sx = 0.0, sy = 0.0;
-  subhalo_ranges<kSplit>(sp.tx, sp.ty, sub, nloop, grp, t, scratch, sx, sy);
+  subhalo_ranges<kSplit, P>(sp.tx, sp.ty, sub, nloop, grp, t, scratch, sx, sy);
   __syncthreads();
   if (grp == 0) {
     double ax, ay;
@@ -143,13 +159,13 @@ __device__ __forceinline__ void simulate_block(const GridC& g, const MacroC& mc,
   }
 }
 
-template <int kSplit>
-__global__ __launch_bounds__(split_threads(kSplit)) void k_simulate(GridC g, MacroC mc, const SubRec* __restrict__ sub,
+template <int kSplit, class P>
+__global__ __launch_bounds__(split_threads(kSplit)) void k_simulate(GridC g, MacroC mc, const void* __restrict__ sub,
                                                                    int nloop, LightC src, LightC ll,
                                                                    float* __restrict__ img) {
   __shared__ RangeScratch<kSplit> scratch;
   __shared__ float red[split_lanes(kSplit)];
-  simulate_block<kSplit>(g, mc, sub, nloop, src, ll, img, blockIdx.x, scratch, red);
+  simulate_block<kSplit, P>(g, mc, sub, nloop, src, ll, img, blockIdx.x, scratch, red);
 }
 
 // Batched images: block b works on image descs[b / blocks_per_image] when
@@ -315,14 +331,19 @@ hipError_t launch_prep_subhalos(int n, const float* x, const float* y, const flo
   return hipGetLastError();
 }
 
-hipError_t launch_ray_shoot(bool alpha, int n, const float* x, const float* y, const MacroC& mc,
-                            const SubRec* sub, int nloop, float* ox, float* oy, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  const int split = pick_split(n, 1, nloop);
-  const int w = split_lanes(split);
-  const dim3 grid((n + w - 1) / w);
-#define JT_RAY(A, S) hipLaunchKernelGGL((k_ray_shoot<A, S>), grid, dim3(split_threads(S)), 0, st, n, x, y, mc, sub, \
-                                        nloop, ox, oy)
+hipError_t launch_prep_tnfw(int n, const float* x, const float* y, const float* rs, const float* ars,
+                            const float* rt, TRec* out, hipStream_t st) {
+  const int padded = subhalo_table_records(n);
+  hipLaunchKernelGGL(k_prep_tnfw, dim3((padded + 255) / 256), dim3(256), 0, st, n, padded, x, y, rs, ars, rt, out);
+  return hipGetLastError();
+}
+
+namespace {
+template <class P>
+void ray_shoot_on(bool alpha, int split, dim3 grid, int n, const float* x, const float* y, const MacroC& mc,
+                  const void* sub, int nloop, float* ox, float* oy, hipStream_t st) {
+#define JT_RAY(A, S) hipLaunchKernelGGL((k_ray_shoot<A, S, P>), grid, dim3(split_threads(S)), 0, st, n, x, y, mc, \
+                                        sub, nloop, ox, oy)
   if (alpha) {
     if (split == 1) JT_RAY(true, 1); else if (split == 2) JT_RAY(true, 2); else if (split == 4) JT_RAY(true, 4);
     else JT_RAY(true, 8);
@@ -331,6 +352,28 @@ hipError_t launch_ray_shoot(bool alpha, int n, const float* x, const float* y, c
     else JT_RAY(false, 8);
   }
 #undef JT_RAY
+}
+
+template <class P>
+void simulate_on(int split, unsigned blocks, const GridC& g, const MacroC& mc, const void* sub, int nloop,
+                 const LightC& src, const LightC& ll, float* img, hipStream_t st) {
+#define JT_SIM(S) hipLaunchKernelGGL((k_simulate<S, P>), dim3(blocks), dim3(split_threads(S)), 0, st, g, mc, sub, \
+                                     nloop, src, ll, img)
+  if (split == 1) JT_SIM(1); else if (split == 2) JT_SIM(2); else if (split == 4) JT_SIM(4); else JT_SIM(8);
+#undef JT_SIM
+}
+}  // namespace
+
+hipError_t launch_ray_shoot(bool alpha, bool tnfw, int n, const float* x, const float* y, const MacroC& mc,
+                            const void* sub, int nloop, float* ox, float* oy, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int split = pick_split(n, 1, nloop);
+  const int w = split_lanes(split);
+  const dim3 grid((n + w - 1) / w);
+  if (tnfw)
+    ray_shoot_on<TnfwPairs>(alpha, split, grid, n, x, y, mc, sub, nloop, ox, oy, st);
+  else
+    ray_shoot_on<NfwPairs>(alpha, split, grid, n, x, y, mc, sub, nloop, ox, oy, st);
   return hipGetLastError();
 }
 
@@ -341,16 +384,16 @@ hipError_t launch_source_sb(int n, const float* x, const float* y, const float* 
   return hipGetLastError();
 }
 
-hipError_t launch_simulate(GridC g, const MacroC& mc, const SubRec* sub, int nloop, const LightC& src,
+hipError_t launch_simulate(GridC g, const MacroC& mc, bool tnfw, const void* sub, int nloop, const LightC& src,
                            const LightC& ll, float* img, hipStream_t st) {
   const long npix = (long)g.nx * g.ny;
   const int split = pick_split(npix * g.s2, g.s2, nloop);
   g.ppb = split_lanes(split) / g.s2;
   const long blocks = (npix + g.ppb - 1) / g.ppb;
-#define JT_SIM(S) hipLaunchKernelGGL((k_simulate<S>), dim3((unsigned)blocks), dim3(split_threads(S)), 0, st, g, mc, \
-                                     sub, nloop, src, ll, img)
-  if (split == 1) JT_SIM(1); else if (split == 2) JT_SIM(2); else if (split == 4) JT_SIM(4); else JT_SIM(8);
-#undef JT_SIM
+  if (tnfw)
+    simulate_on<TnfwPairs>(split, (unsigned)blocks, g, mc, sub, nloop, src, ll, img, st);
+  else
+    simulate_on<NfwPairs>(split, (unsigned)blocks, g, mc, sub, nloop, src, ll, img, st);
   return hipGetLastError();
 }
 

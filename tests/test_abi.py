@@ -59,7 +59,7 @@ LAYOUT_C = r"""
 int main(void) {
   P(jt_grid); O(jt_grid, pixel_scale); O(jt_grid, y0);
   P(jt_sie); P(jt_shear);
-  P(jt_nfw); O(jt_nfw, x); O(jt_nfw, alpha_Rs);
+  P(jt_nfw); O(jt_nfw, x); O(jt_nfw, alpha_Rs); O(jt_nfw, r_trunc);
   P(jt_point_masses); O(jt_point_masses, theta_E);
   P(jt_epl); O(jt_epl, gamma); O(jt_epl, cy);
   P(jt_lens); O(jt_lens, sie); O(jt_lens, shear); O(jt_lens, nfw); O(jt_lens, subhalo_handle); O(jt_lens, pm);

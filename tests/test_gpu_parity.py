@@ -211,6 +211,88 @@ def test_resident_table_matches_device_soa_bitwise(ctx):
     ctx.release(h)
 
 
+# ---------------------------------------------------------------- TNFW subhalos
+@pytest.mark.parametrize("tau", [0.4, 1.0, 3.0, 25.0, 300.0])
+def test_single_tnfw_every_branch(ctx, tau):
+    """One truncated subhalo, points at r = X Rs across the log1p form, the
+    series near x = 1, the arctangent form and the far field: per-point
+    relative error of the deflection."""
+    Rs, aRs, cx, cy = 0.1, 2e-3, 0.3, -0.2
+    X = np.array([1e-3, 0.01, 0.05, 0.2, 0.5, 0.85, 0.89, 0.9, 0.95, 0.999, 1.0, 1.001, 1.05, 1.09, 1.1, 1.2,
+                  1.5, 2.0, 5.0, 50.0, 500.0, 3000.0])
+    ang = np.linspace(0.1, 6.0, X.size)
+    x = _f32(cx + X * Rs * np.cos(ang))
+    y = _f32(cy + X * Rs * np.sin(ang))
+    nfw = W.NFWTable(_f32([cx]), _f32([cy]), _f32([Rs]), _f32([aRs]), r_trunc=_f32([tau * Rs]))
+    lens = W.Lens(nfw=nfw)
+    ax, ay = ctx.deflection(x, y, lens)
+    ex, ey = O.total_deflection(x, y, lens)
+    rel = np.hypot(_np(ax) - ex, _np(ay) - ey) / np.hypot(ex, ey)
+    assert rel.max() <= 1e-5, dict(zip(X.tolist(), rel.tolist()))
+    a0 = ctx.deflection(_f32([cx]), _f32([cy]), lens)
+    assert _np(a0[0])[0] == 0.0 and _np(a0[1])[0] == 0.0
+
+
+def test_deflection_truncated_subhalos_full_lens(ctx):
+    sc = W.tnfw_scene()
+    rng = np.random.default_rng(6)
+    x1, y1 = W.random_points(1500, 5.0, seed=22)
+    x2, y2 = _near_points(sc.lens.nfw, rng, 700)
+    x, y = np.concatenate([x1, x2]), np.concatenate([y1, y2])
+    ax, ay = ctx.deflection(x, y, sc.lens)
+    ex, ey = O.total_deflection(x, y, sc.lens)
+    assert deflection_error(_np(ax), _np(ay), ex, ey) <= DEFLECTION_TOL
+    alone = W.Lens(nfw=sc.lens.nfw)
+    ax, ay = ctx.deflection(x, y, alone)
+    ex, ey = O.total_deflection(x, y, alone)
+    assert deflection_error(_np(ax), _np(ay), ex, ey) <= DEFLECTION_TOL
+
+
+@pytest.mark.parametrize("nsub", [1, 3, 5, 64, 65])
+def test_truncated_subhalos_ragged_counts(ctx, nsub):
+    sc = W.tnfw_scene(n_sub=nsub, npix=20)
+    x, y = W.random_points(257, 3.0, seed=nsub)
+    ax, ay = ctx.deflection(x, y, sc.lens)
+    ex, ey = O.total_deflection(x, y, sc.lens)
+    assert deflection_error(_np(ax), _np(ay), ex, ey) <= DEFLECTION_TOL
+
+
+def test_weakly_truncated_subhalos_match_the_nfw_kernel(ctx):
+    # tau = 1e6: the truncation changes these deflections by ~4e-9 (1e4 would
+    # already give ~2e-5), so the two kernels must agree to the bar
+    sc = W.config2_scene(n_sub=1000)
+    nfw = sc.lens.nfw
+    t = W.NFWTable(nfw.x, nfw.y, nfw.Rs, nfw.alpha_Rs, r_trunc=_f32(1e6 * nfw.Rs))
+    x, y = W.random_points(3000, 4.0, seed=3)
+    a = ctx.deflection(x, y, W.Lens(nfw=t))
+    b = ctx.deflection(x, y, W.Lens(nfw=nfw))
+    assert deflection_error(_np(a[0]), _np(a[1]), _np(b[0]), _np(b[1])) <= DEFLECTION_TOL
+
+
+def test_truncated_resident_table_matches_device_soa_bitwise(ctx):
+    sc = W.tnfw_scene(n_sub=777)
+    x, y = W.random_points(5000, 4.0, seed=1)
+    a1 = ctx.ray_shoot(x, y, sc.lens)
+    h = ctx.upload_subhalos(sc.lens.nfw)
+    lens_h = W.Lens(sie=sc.lens.sie, shear=sc.lens.shear)
+    lens_h.subhalo_handle = h
+    a2 = ctx.ray_shoot(x, y, lens_h)
+    np.testing.assert_array_equal(_np(a1[0]), _np(a2[0]))
+    np.testing.assert_array_equal(_np(a1[1]), _np(a2[1]))
+    ctx.release(h)
+
+
+def test_truncated_upload_rejects_bad_radii(ctx):
+    from paper_2606_01547_amd import JtError
+    sc = W.tnfw_scene(n_sub=10, npix=20)
+    for bad in (0.0, -1.0, float("nan")):
+        nfw = sc.lens.nfw
+        rt = nfw.r_trunc.copy()
+        rt[3] = bad
+        with pytest.raises(JtError):
+            ctx.upload_subhalos(W.NFWTable(nfw.x, nfw.y, nfw.Rs, nfw.alpha_Rs, r_trunc=rt))
+
+
 def test_ray_shoot_is_theta_minus_alpha(ctx):
     sc = W.config2_scene(n_sub=500)
     x, y = W.random_points(3333, 4.0, seed=2)
@@ -349,6 +431,13 @@ def test_simulate_headline_physics_reduced_grid(ctx):
 def test_simulate_epl_scene_reduced_grid(ctx):
     sc = W.epl_scene(npix=40, n_sub=3000)
     sc.grid = W.Grid(nx=40, ny=33, pixel_scale=0.05, x0=-0.06, y0=0.09, supersample=3)
+    got = _np(ctx.simulate_scene(sc))
+    assert image_error(got, O.simulate_image(sc)) <= IMAGE_TOL
+
+
+def test_simulate_truncated_subhalo_scene_reduced_grid(ctx):
+    sc = W.tnfw_scene(npix=40, n_sub=3000)
+    sc.grid = W.Grid(nx=40, ny=35, pixel_scale=0.05, x0=0.07, y0=-0.04, supersample=3)
     got = _np(ctx.simulate_scene(sc))
     assert image_error(got, O.simulate_image(sc)) <= IMAGE_TOL
 

@@ -128,6 +128,21 @@ def test_epl_requests_equal_single_requests(ctx):
     assert image_error(_np(outs[2]), O.simulate_image(epl[0])) <= IMAGE_TOL
 
 
+def test_server_refuses_truncated_subhalo_tables(ctx):
+    from paper_2606_01547_amd import JtError, Server
+    sc = W.tnfw_scene(n_sub=50, npix=20)
+    h = ctx.upload_subhalos(sc.lens.nfw)
+    srv = Server(ctx, hbm_budget_bytes=64 << 20, max_batch_images=4, max_batch_pairs=1e8, max_inflight_batches=2,
+                 n_streams=2)
+    try:
+        o = torch.empty((sc.grid.ny, sc.grid.nx), dtype=torch.float32, device="cuda")
+        with pytest.raises(JtError):
+            srv.submit(sc.grid, sc.lens, sc.source, sc.lens_light, out=o, subhalo_handle=h)
+    finally:
+        srv.close()
+        ctx.release(h)
+
+
 def test_tight_arena_serialises_but_completes(ctx):
     scenes = _requests(10, seed=11)
     outs, lat, st = _serve(ctx, scenes, None, hbm_budget_bytes=1 << 20, max_batch_images=4,
