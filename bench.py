@@ -298,6 +298,78 @@ def large_image_bench(ctx, reps):
             "simulate_frac_fp32_peak": round(achieved / PEAK_FP32_TFLOPS, 4)}
 
 
+def _kernel_ms(ctx, fn, kernels, reps):
+    """Average library-event time per launch of `kernels` over `reps` calls of
+    fn, and the wall time per call."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    base = {k: ctx.profile_read(k) for k in kernels}
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    per = {}
+    for k in kernels:
+        ms, n = ctx.profile_read(k)
+        per[k] = (ms - base[k][0]) / max(n - base[k][1], 1)
+    ctx.profile_enable(False)
+    return per, wall
+
+
+def profiles_bench(ctx, reps=20):
+    """The profile-dispatch rows: (a) each main-deflector profile alone on a
+    180x180 grid (the paper's deflection table), kernel time per call; (b) the
+    headline image with an elliptical power-law main deflector, and with
+    truncated subhalos, as images/s and (sub-pixel, subhalo) pairs/s."""
+    import numpy as np
+    import torch
+    import workloads as W
+    g = np.arange(180, dtype=np.float64) * 0.05 - 0.05 * 89.5
+    gx, gy = np.meshgrid(g, g)
+    x = torch.from_numpy(gx.astype(np.float32).ravel()).cuda()
+    y = torch.from_numpy(gy.astype(np.float32).ravel()).cuda()
+    ox, oy = torch.empty_like(x), torch.empty_like(y)
+    rng = np.random.default_rng(2024)
+    one = lambda **kw: W.NFWTable(*[torch.from_numpy(np.asarray(v, np.float32)).cuda()
+                                    for v in ([0.3], [-0.2], [0.25], [0.02])], **kw)
+    cases = {
+        "SIE": W.Lens(sie=W.SIE(1.2, 0.7, 0.4, 0.0, 0.0)),
+        "EPL": W.Lens(epl=W.EPL(1.2, 2.1, 0.7, 0.4, 0.0, 0.0)),
+        "SHEAR": W.Lens(shear=W.Shear(0.03, -0.02)),
+        "NFW": W.Lens(nfw=one()),
+        "TNFW": W.Lens(nfw=one(r_trunc=torch.tensor([2.5], device="cuda"))),
+    }
+    table = {}
+    for name, lens in cases.items():
+        per, _ = _kernel_ms(ctx, lambda: ctx.deflection(x, y, lens, out=(ox, oy)), ("ray",), reps)
+        table[name] = round(1e3 * per["ray"], 2)
+    images = {}
+    for name, sc in (("EPL main deflector", W.epl_scene()), ("TNFW subhalos", W.tnfw_scene())):
+        gr = sc.grid
+        nfw = sc.lens.nfw
+        cols = [nfw.x, nfw.y, nfw.Rs, nfw.alpha_Rs]
+        dev = [torch.from_numpy(np.asarray(a)).cuda() for a in cols]
+        rt = torch.from_numpy(np.asarray(nfw.r_trunc)).cuda() if nfw.r_trunc is not None else None
+        lens = W.Lens(sie=sc.lens.sie, epl=sc.lens.epl, shear=sc.lens.shear, nfw=W.NFWTable(*dev, r_trunc=rt))
+        psf = torch.from_numpy(sc.psf).cuda()
+        out = torch.empty((gr.ny, gr.nx), dtype=torch.float32, device="cuda")
+        per, wall = _kernel_ms(ctx, lambda: ctx.simulate_image(gr, lens, sc.source, sc.lens_light, psf, sc.bn_exact,
+                                                               out=out), ("sim", "conv", "prep"), reps)
+        pairs = gr.nx * gr.ny * gr.supersample ** 2 * nfw.n
+        images[name] = {"images_per_s": round(1.0 / wall, 2), "simulate_ms": round(per["sim"], 4),
+                        "convolve_ms": round(per["conv"], 4), "prep_ms": round(per["prep"], 4),
+                        "pairs_per_s": round(pairs / (1e-3 * per["sim"]), 1)}
+    return {"deflection_180x180_us": table,
+            "deflection_workload": "32,400 points of a 180x180 grid at 0.05\"/px; one deflector of each profile",
+            "images": images,
+            "images_workload": ("200x200 px, s = 3, shear + 10,000 subhalos, 1 lens-light + 2 source Sersic, "
+                                "41x41 PSF: EPL (gamma in [1.8, 2.2]) + NFW (seed 1006); SIE + TNFW with "
+                                "tau = r_trunc/Rs log-uniform in [3, 30] (seed 1007)")}
+
+
 def adjoint_bench(ctx, draws, reps):
     """Gradient of the chi^2 log-likelihood for a batch of parameter draws
     (100x100 px, 1000 NFW, 21x21 PSF) against the forward alone and the plain
@@ -355,6 +427,7 @@ def main():
     ap.add_argument("--adjoint-draws", type=int, default=256, help="parameter draws per gradient (0 = skip)")
     ap.add_argument("--large-reps", type=int, default=3, help="timed 1000^2-px images (0 = skip)")
     ap.add_argument("--conv-sweep", type=int, default=1, help="direct/FFT convolution sweep (0 = skip)")
+    ap.add_argument("--profiles", type=int, default=1, help="EPL / TNFW profile rows (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (3 times), to calibrate "
                          "the FETCH_SIZE / WRITE_SIZE counters")
@@ -453,6 +526,8 @@ def main():
         result["conv_sweep"] = conv_sweep(ctx)
     if args.large_reps > 0:
         result["large_image"] = large_image_bench(ctx, args.large_reps)
+    if args.profiles:
+        result["profiles"] = profiles_bench(ctx)
     if args.adjoint_draws > 0:
         result["adjoint"] = adjoint_bench(ctx, args.adjoint_draws, reps=10)
     if args.serve_requests > 0:
