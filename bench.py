@@ -33,7 +33,8 @@ PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector, published
 # FLOP per pair, reported beside it as executed_frac.
 FLOP_PER_PAIR = 33
 KERNEL_SOURCES = ["paper_2606_01547_amd/csrc/kernels.hip", "paper_2606_01547_amd/csrc/jt_device.hpp",
-                  "paper_2606_01547_amd/csrc/nfw_poly.inc", "paper_2606_01547_amd/csrc/jt_sum.hpp"]
+                  "paper_2606_01547_amd/csrc/nfw_poly.inc", "paper_2606_01547_amd/csrc/jt_sum.hpp",
+                  "paper_2606_01547_amd/csrc/atan_poly.inc"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_simulate_headline_traffic.json")
 
 

@@ -18,6 +18,7 @@ constexpr float kLn2 = 0.69314718055994530942f;
 constexpr double kLn2d = 0.69314718055994530942;
 
 #include "nfw_poly.inc"
+#include "atan_poly.inc"
 
 // Mean relative errors of gfx950's log2 and rsq instructions (measured over 4M
 // arguments in [1e-6, 1e6]: log2 sits 0.466 ulp low).  Their products with a
@@ -101,9 +102,9 @@ struct __align__(16) SubRec {
 
 // Truncated NFW record (Baltz, Marshall & Oguri 2009, truncation exponent 1):
 // centre, c1 = 1/Rs^2, c2 = alpha_Rs/((1 - ln 2) Rs) * tau^2/(tau^2 + 1)^2 and
-// tau = r_trunc/Rs with tau^2, tau^2 - 1, tau^2 + 1, each rounded once from FP64.
+// tau = r_trunc/Rs with tau^2, tau^2 - 1, 1/tau, each rounded once from FP64.
 struct __align__(16) TRec {
-  float x, y, c1, c2, tau, t2, t2m1, t2p1;
+  float x, y, c1, c2, tau, t2, t2m1, itau;
 };
 
 struct ImageDesc {
@@ -332,10 +333,29 @@ __device__ __forceinline__ void nfw_pairs4(float tx, float ty, const SubRec& s0,
 // ---------------------------------------------------------------------------
 // TNFW pair term
 // ---------------------------------------------------------------------------
+// log(1 + z) from the hardware log2, accurate for small z as well:
+// z ln(1+z) / ((1+z) - 1) (exact z when 1 + z rounds to 1).
+__device__ __forceinline__ float log1p_fast(float z) {
+  const float w = 1.0f + z;
+  const float d = w - 1.0f;
+  return d == 0.0f ? z : __builtin_amdgcn_logf(w) * kLn2 * z * __builtin_amdgcn_rcpf(d);
+}
+
+// atan(z) for z >= 0: z A(z^2) on [0, 1], pi/2 - atan(1/z) above.
+__device__ __forceinline__ float atan_pos(float z, float iz) {
+  const float m = fminf(z, iz);
+  const float t = m * m;
+  float p = kAtanP[0];
+#pragma unroll
+  for (int k = 1; k <= JT_ATAN_POLY_DEGREE; ++k) p = fmaf(p, t, kAtanP[k]);
+  p *= m;
+  return z > 1.0f ? 1.57079632679489661923f - p : p;
+}
+
 // With x^2 = X2, s = sqrt(tau^2 + x^2), sp = s + tau, the projected mass of
 // the truncated profile regrouped so that no step cancels catastrophically:
 //   G/x^2 = A [ (tau^2 - 1) P1 + P2 ],  A = tau^2/(tau^2 + 1)^2 (in c2),
-//   P1 = (g - ln((sp)/(2 tau))) / x^2 + L / (tau sp),
+//   P1 = (g - ln(sp/(2 tau))) / x^2 + L / (tau sp),
 //   P2 = 2F - pi/sp,
 // g = ln(x/2) + F the NFW function, L = ln(x/sp) = -log1p((tau + tau^2/(s+x))/x)
 // and ln(sp/(2 tau)) = log1p(x^2/(2 tau sp)).  F and g by branch:
@@ -344,23 +364,28 @@ __device__ __forceinline__ void nfw_pairs4(float tx, float ty, const SubRec& s0,
 //   otherwise:  u = sqrt(x^2 - 1), a = atan(1/u), F = (pi/2 - a)/u, and
 //               P2 = pi (tau + (tau^2+1)/(s+u)) / (u sp) - 2a/u, which avoids
 //               the cancellation of 2F against pi/sp far from the centre.
-// 0 at the centre (X2 = 0).
+// Hardware rsq, sqrt, rcp and log2 (about one ulp each, none of them in a
+// cancelling difference) and the polynomial arctangent.  0 at the centre
+// (X2 below 1e-30, where the term is below 1e-28 of alpha_Rs).
 __device__ __forceinline__ void tnfw_pair(float tx, float ty, const TRec& r, float& sx, float& sy) {
   constexpr float kPi = 3.14159265358979323846f;
   constexpr float kHalfPi = 1.57079632679489661923f;
   const float dx = tx - r.x, dy = ty - r.y;
   const float X2 = fmaf(dy, dy, dx * dx) * r.c1;
-  if (!(X2 > 0.0f)) return;
-  const float x = sqrtf(X2);
-  const float s = sqrtf(r.t2 + X2);
+  if (!(X2 > 1e-30f)) return;
+  const float ix = __builtin_amdgcn_rsqf(X2);
+  const float x = X2 * ix;
+  const float s = __builtin_amdgcn_sqrtf(r.t2 + X2);
   const float sp = s + r.tau;
-  const float Lh = 0.5f * logf(X2) - kLn2;   // ln(x/2)
+  const float isp = __builtin_amdgcn_rcpf(sp);
+  const float Lh = fmaf(__builtin_amdgcn_logf(X2), 0.5f * kLn2, -kLn2);   // ln(x/2)
   float F, g, P2;
   if (X2 < 0.8f) {
-    const float w = sqrtf(1.0f - X2);
-    g = (-Lh * X2 / (1.0f + w) + log1pf(-X2 / (2.0f * (1.0f + w)))) / w;
+    const float w = __builtin_amdgcn_sqrtf(1.0f - X2);
+    const float i1w = __builtin_amdgcn_rcpf(1.0f + w);
+    g = (-Lh * X2 * i1w + log1p_fast(-0.5f * X2 * i1w)) * __builtin_amdgcn_rcpf(w);
     F = g - Lh;
-    P2 = 2.0f * F - kPi / sp;
+    P2 = fmaf(2.0f, F, -kPi * isp);
   } else if (X2 < 1.2f) {
     const float v = -(X2 - 1.0f);
     F = 1.0f / 21.0f;
@@ -375,16 +400,17 @@ __device__ __forceinline__ void tnfw_pair(float tx, float ty, const TRec& r, flo
     F = fmaf(F, v, 1.0f / 3.0f);
     F = fmaf(F, v, 1.0f);
     g = Lh + F;
-    P2 = 2.0f * F - kPi / sp;
+    P2 = fmaf(2.0f, F, -kPi * isp);
   } else {
-    const float u = sqrtf(X2 - 1.0f);
-    const float a = atanf(1.0f / u);
-    F = (kHalfPi - a) / u;
+    const float u = __builtin_amdgcn_sqrtf(X2 - 1.0f);
+    const float iu = __builtin_amdgcn_rcpf(u);
+    const float a = atan_pos(iu, u);
+    F = (kHalfPi - a) * iu;
     g = Lh + F;
-    P2 = kPi * (r.tau + r.t2p1 / (s + u)) / (u * sp) - 2.0f * a / u;
+    P2 = (kPi * fmaf(r.t2 + 1.0f, __builtin_amdgcn_rcpf(s + u), r.tau) * isp - 2.0f * a) * iu;
   }
-  const float L = -log1pf((r.tau + r.t2 / (s + x)) / x);
-  const float P1 = (g - log1pf(X2 / (2.0f * r.tau * sp))) / X2 + L / (r.tau * sp);
+  const float L = -log1p_fast(fmaf(r.t2, __builtin_amdgcn_rcpf(s + x), r.tau) * ix);
+  const float P1 = (g - log1p_fast(0.5f * X2 * r.itau * isp)) * (ix * ix) + L * r.itau * isp;
   const float h = r.c2 * fmaf(r.t2m1, P1, P2);
   sx = fmaf(h, dx, sx);
   sy = fmaf(h, dy, sy);
