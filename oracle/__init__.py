@@ -18,21 +18,25 @@ tests/test_oracle_*.py.  The input generators are only used as data sources;
 the unpinned pieces are listed in `PARITY_UNPINNED`.
 """
 from .grid import subpixel_coords, supersample_reduce
-from .lens import (sie_deflection, sie_kappa, epl_deflection, epl_kappa, tnfw_G, tnfw_deflection, shear_deflection, nfw_g, nfw_deflection,
-                   nfw_kappa, point_mass_deflection, total_deflection, ray_shoot)
+from .lens import (sie_deflection, sie_kappa, epl_deflection, epl_kappa, tnfw_G, tnfw_deflection,
+                   shear_deflection, nfw_g, nfw_deflection, nfw_kappa, point_mass_deflection, total_deflection,
+                   ray_shoot)
 from .light import sersic_bn, sersic, surface_brightness
 from .conv import convolve_at, convolve_same
 from .simulate import simulate_image, simulate_unconvolved
 from .likelihood import log_likelihood, noise_variance
 from .grad import chi2_gradient, macro_vector, macro_names
+from .linear import basis_images, linear_amplitudes
 
 # Functions whose result no independent pin fixes (see the test modules).
 PARITY_UNPINNED = ()
 
 __all__ = [
-    "subpixel_coords", "supersample_reduce", "sie_deflection", "sie_kappa", "epl_deflection", "epl_kappa", "tnfw_G", "tnfw_deflection",
+    "subpixel_coords", "supersample_reduce", "sie_deflection", "sie_kappa", "epl_deflection", "epl_kappa",
+    "tnfw_G", "tnfw_deflection",
     "shear_deflection", "nfw_g", "nfw_deflection", "nfw_kappa", "point_mass_deflection",
     "total_deflection", "ray_shoot", "sersic_bn", "sersic", "surface_brightness",
     "convolve_at", "convolve_same", "simulate_image", "simulate_unconvolved", "log_likelihood",
-    "noise_variance", "chi2_gradient", "macro_vector", "macro_names", "PARITY_UNPINNED",
+    "noise_variance", "chi2_gradient", "macro_vector", "macro_names", "basis_images", "linear_amplitudes",
+    "PARITY_UNPINNED",
 ]
