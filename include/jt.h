@@ -234,6 +234,29 @@ jt_status jt_chi2_grad(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, 
                        float* g_sub, hipStream_t stream);
 
 /* ----------------------------------------------------------------------
+ * Linear amplitude solver
+ * -------------------------------------------------------------------- */
+/* The image is linear in each Sersic component's amplitude (the paper keeps
+ * lenstronomy's linear amplitude solver, section "Why JAXtronomy?").  With
+ * basis images B_j = PSF * (image of component j alone at unit amplitude),
+ * components ordered as src then lens_light (their amp fields are ignored),
+ * this solves
+ *     a = argmin_a sum_i w_i (d_i - sum_j a_j B_j,i)^2
+ * by the normal equations summed in FP64 in a fixed order and a Cholesky
+ * factorisation on the device (scaled to unit diagonal).  1 <= n_src + n_ll
+ * <= 8.  data d and inv_var w: device float32 [ny][nx].  Outputs (device,
+ * written on `stream`): amps double[n_src + n_ll]; model float32 [ny][nx]
+ * (may be NULL) = sum_j a_j B_j rounded once; logL double[1] (may be NULL)
+ * = -1/2 sum_i w_i (d_i - model_i)^2.  A normal matrix that is not positive
+ * definite (a component that adds nothing to the image, or two that
+ * coincide) gives NaN amplitudes (and a NaN model and logL).  Grid, lens and
+ * psf/k as in jt_simulate_image. */
+jt_status jt_linear_amplitudes(jt_ctx* ctx, const jt_grid* grid, const jt_lens* lens, const jt_light* src,
+                               const jt_light* lens_light, const float* psf, int k, const float* data,
+                               const float* inv_var, double* amps, float* model, double* logL,
+                               hipStream_t stream);
+
+/* ----------------------------------------------------------------------
  * Resident tables
  * -------------------------------------------------------------------- */
 /* Copy n subhalos (host float32 SoA) into a device-resident, pre-derived

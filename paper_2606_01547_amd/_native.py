@@ -123,6 +123,8 @@ _SIGS = {
     "jt_simulate_image": (c_int, [c_void_p, POINTER(JtGrid), POINTER(JtLens), POINTER(JtLight), POINTER(JtLight),
                                   c_void_p, c_int, c_void_p, c_void_p]),
     "jt_upload_subhalos": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_uint64)]),
+    "jt_linear_amplitudes": (c_int, [c_void_p, POINTER(JtGrid), POINTER(JtLens), POINTER(JtLight), POINTER(JtLight),
+                                     c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "jt_upload_tnfw": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                POINTER(c_uint64)]),
     "jt_upload_psf": (c_int, [c_void_p, c_void_p, c_int, POINTER(c_uint64)]),
@@ -353,6 +355,42 @@ class Context:
         """simulate_image for a workloads.Scene-like object."""
         return self.simulate_image(scene.grid, scene.lens, scene.source, scene.lens_light,
                                    scene.psf if psf else None, getattr(scene, "bn_exact", False), **kw)
+
+    # ---- linear amplitude solver
+    def linear_amplitudes(self, grid, lens, source, lens_light, data, inv_var, psf=None, bn_exact=False,
+                          model=True, stream=None):
+        """Weighted least-squares amplitudes of the light components (sources,
+        then lens light; their amp fields are ignored) for the image `data`
+        with weights `inv_var`.  Returns (amps float64 [n], model float32
+        [ny, nx] or None, logL float64 [1]) as device tensors."""
+        torch = _torch()
+        keep = []
+        G = JtGrid(int(grid.nx), int(grid.ny), int(grid.supersample), float(grid.pixel_scale),
+                   float(grid.x0), float(grid.y0))
+        L = self._lens(lens, keep)
+        S = self._light(source, bn_exact, keep)
+        LL = self._light(lens_light, bn_exact, keep)
+        shape = (int(grid.ny), int(grid.nx))
+        dt = _dev_f32(data, self.device, keep)
+        wt = _dev_f32(inv_var, self.device, keep)
+        if tuple(dt.shape) != shape or tuple(wt.shape) != shape:
+            raise ValueError("data and inv_var must be [ny, nx]")
+        if psf is None:
+            pp, k = c_void_p(), 0
+        else:
+            pt = _dev_f32(psf, self.device, keep)
+            pp, k = c_void_p(pt.data_ptr()), int(pt.shape[0])
+        n = len(source) + len(lens_light)
+        amps = torch.empty(max(n, 1), dtype=torch.float64, device=self.device)
+        mo = torch.empty(shape, dtype=torch.float32, device=self.device) if model else None
+        logL = torch.empty(1, dtype=torch.float64, device=self.device)
+        _check(self._lib.jt_linear_amplitudes(self._ptr, byref(G), byref(L), byref(S), byref(LL), pp, k,
+                                              c_void_p(dt.data_ptr()), c_void_p(wt.data_ptr()),
+                                              c_void_p(amps.data_ptr()),
+                                              c_void_p(mo.data_ptr() if mo is not None else None),
+                                              c_void_p(logL.data_ptr()), _stream_handle(stream)))
+        self._retain(keep, stream)
+        return amps[:n], mo, logL
 
     # ---- batches of parameter draws
     def _draws(self, batch, keep):

@@ -13,6 +13,7 @@
 namespace jt {
 
 constexpr int kMaxSersic = 8;
+constexpr int kMaxBasis = 8;     // light components of the linear amplitude solver
 constexpr int kMaxPointMass = 16;
 constexpr float kLn2 = 0.69314718055994530942f;
 constexpr double kLn2d = 0.69314718055994530942;
@@ -428,17 +429,19 @@ __device__ __forceinline__ void two_sum_acc(float& hi, float& lo, float v) {
 // ---------------------------------------------------------------------------
 // Sersic light
 // ---------------------------------------------------------------------------
+// One Sersic component at unit amplitude.
+__device__ __forceinline__ float sersic_unit(const SersicC& c, float x, float y) {
+  const float dx = x - c.cx, dy = y - c.cy;
+  const float xp = fmaf(c.cphi, dx, c.sphi * dy);
+  const float yp = fmaf(c.cphi, dy, -c.sphi * dx);
+  const float R2 = fmaf(c.q, xp * xp, c.inv_q * (yp * yp));
+  const float t = __builtin_amdgcn_exp2f(c.e * __builtin_amdgcn_logf(R2 * c.inv_r2));
+  return __builtin_amdgcn_exp2f(fmaf(-c.kb, t, c.kb));
+}
+
 __device__ __forceinline__ float sersic_sum(const LightC& L, float x, float y) {
   float acc = 0.f;
-  for (int k = 0; k < L.n; ++k) {
-    const SersicC& c = L.c[k];
-    const float dx = x - c.cx, dy = y - c.cy;
-    const float xp = fmaf(c.cphi, dx, c.sphi * dy);
-    const float yp = fmaf(c.cphi, dy, -c.sphi * dx);
-    const float R2 = fmaf(c.q, xp * xp, c.inv_q * (yp * yp));
-    const float t = __builtin_amdgcn_exp2f(c.e * __builtin_amdgcn_logf(R2 * c.inv_r2));
-    acc = fmaf(c.amp, __builtin_amdgcn_exp2f(fmaf(-c.kb, t, c.kb)), acc);
-  }
+  for (int k = 0; k < L.n; ++k) acc = fmaf(L.c[k].amp, sersic_unit(L.c[k], x, y), acc);
   return acc;
 }
 

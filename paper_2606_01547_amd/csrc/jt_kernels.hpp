@@ -27,6 +27,18 @@ hipError_t launch_source_sb(int n, const float* x, const float* y, const float* 
 // g.ppb is set by the launcher from the chosen split.
 hipError_t launch_simulate(GridC g, const MacroC& mc, bool tnfw, const void* sub, int nloop, const LightC& src,
                            const LightC& ll, float* img, hipStream_t st);
+// Unit-amplitude image of every light component (sources, then lens light)
+// into basis [src.n + ll.n][ny][nx]; src.n + ll.n <= kMaxBasis.
+hipError_t launch_simulate_basis(GridC g, const MacroC& mc, bool tnfw, const void* sub, int nloop,
+                                 const LightC& src, const LightC& ll, float* basis, hipStream_t st);
+// Linear amplitude solver over n <= kMaxBasis basis images of npix pixels:
+// FP64 normal-equation partials of kLinBlocks blocks (kLinTerms each), the
+// Cholesky solve on the device (NaN amplitudes when the matrix is not
+// positive definite), then the model and the log-likelihood.
+constexpr int kLinTerms = kMaxBasis * (kMaxBasis + 1) / 2 + kMaxBasis;
+constexpr int kLinBlocks = 256;
+hipError_t launch_linear_solve(int npix, int n, const float* basis, const float* data, const float* w,
+                               double* part, double* amps, float* model, double* logL, hipStream_t st);
 // Wave-groups per block for `points` sub-pixels in whole units of `unit`.
 int pick_split(long points, int unit, int nloop);
 size_t conv_direct_lds_bytes(int k);

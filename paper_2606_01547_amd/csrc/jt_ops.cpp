@@ -159,3 +159,56 @@ extern "C" jt_status jt_simulate_image(jt_ctx* ctx, const jt_grid* grid, const j
   if (!psf) return JT_OK;
   return convolve_on(ctx, img, g.nx, g.ny, psf, k, 0, out, stream);
 }
+
+extern "C" jt_status jt_linear_amplitudes(jt_ctx* ctx, const jt_grid* grid, const jt_lens* lens,
+                                          const jt_light* src, const jt_light* lens_light, const float* psf, int k,
+                                          const float* data, const float* inv_var, double* amps, float* model,
+                                          double* logL, hipStream_t stream) {
+  JT_TRY(ctx_enter(ctx));
+  GridC g;
+  MacroC mc;
+  LightC s, l;
+  JT_TRY(make_grid(grid, g));
+  JT_TRY(make_macro(lens, mc));
+  JT_TRY(make_light(src, s, "source"));
+  JT_TRY(make_light(lens_light, l, "lens light"));
+  const int n = s.n + l.n;
+  if (n < 1) return fail(JT_EINVAL, "linear amplitudes: no light component");
+  if (n > kMaxBasis) return fail(JT_EUNSUPPORTED, "linear amplitudes: %d components (max %d)", n, kMaxBasis);
+  if (!data || !inv_var || !amps) return fail(JT_EINVAL, "linear amplitudes: null data, weights or amplitudes");
+  if ((psf == nullptr) != (k == 0)) return fail(JT_EINVAL, "linear amplitudes: psf and k must be given together");
+  if (psf && (k < 1 || k % 2 == 0)) return fail(JT_EINVAL, "linear amplitudes: PSF side %d must be odd", k);
+  const long npix = (long)g.nx * g.ny;
+  if ((double)npix * n > 2147483647.0) return fail(JT_EUNSUPPORTED, "linear amplitudes: basis too large");
+  // workspace: [subhalo table][basis n x npix][convolved basis][solver partials]
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t tab_bytes = subhalo_scratch_bytes(lens);
+  const size_t basis_bytes = al(sizeof(float) * (size_t)n * npix);
+  const size_t conv_bytes = psf ? basis_bytes : 0;
+  const size_t part_bytes = al(sizeof(double) * (size_t)kLinBlocks * (kLinTerms + 1));
+  void* p = nullptr;
+  JT_TRY(ctx_workspace(ctx, stream, tab_bytes + basis_bytes + conv_bytes + part_bytes, &p));
+  char* ws = (char*)p;
+  float* basis = (float*)(ws + tab_bytes);
+  float* conv = psf ? (float*)(ws + tab_bytes + basis_bytes) : basis;
+  double* part = (double*)(ws + tab_bytes + basis_bytes + conv_bytes);
+  const void* tab = nullptr;
+  int nloop = 0;
+  bool tnfw = false;
+  JT_TRY(resolve_subhalos(ctx, lens, tab_bytes ? ws : nullptr, stream, &tab, &nloop, &tnfw));
+  JT_TRY(timed_launch(ctx, JT_K_SIM, stream,
+                      [&] { return launch_simulate_basis(g, mc, tnfw, tab, nloop, s, l, basis, stream); },
+                      "simulate_basis"));
+  if (psf) {
+    if (!conv_prefers_fft(g.nx, g.ny, k) && k <= JT_MAX_PSF) {
+      JT_TRY(timed_launch(ctx, JT_K_CONV, stream, [&] {
+        return launch_conv_direct_batched(false, n, basis, npix, g.nx, g.ny, psf, k, conv, npix, stream);
+      }, "conv_basis"));
+    } else {
+      for (int j = 0; j < n; ++j)
+        JT_TRY(convolve_on(ctx, basis + (size_t)j * npix, g.nx, g.ny, psf, k, 2, conv + (size_t)j * npix, stream));
+    }
+  }
+  return check_hip(launch_linear_solve((int)npix, n, conv, data, inv_var, part, amps, model, logL, stream),
+                   "linear_solve");
+}

@@ -168,6 +168,47 @@ __global__ __launch_bounds__(split_threads(kSplit)) void k_simulate(GridC g, Mac
   simulate_block<kSplit, P>(g, mc, sub, nloop, src, ll, img, blockIdx.x, scratch, red);
 }
 
+// Basis images of the linear amplitude solver: the deflection of each
+// sub-pixel once, then every light component at unit amplitude (sources at
+// beta, lens light at theta, sources first), each averaged over its pixel in
+// the same order as k_simulate.  basis: [src.n + ll.n][ny][nx].
+template <int kSplit, class P>
+__global__ __launch_bounds__(split_threads(kSplit)) void k_simulate_basis(GridC g, MacroC mc,
+                                                                         const void* __restrict__ sub, int nloop,
+                                                                         LightC src, LightC ll,
+                                                                         float* __restrict__ basis) {
+  __shared__ RangeScratch<kSplit> scratch;
+  __shared__ float red[kMaxBasis][split_lanes(kSplit)];
+  constexpr int kW = split_lanes(kSplit);
+  const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / kW);
+  const int t = threadIdx.x - grp * kW;
+  const SubPixel sp = subpixel_of(g, blockIdx.x, t);
+  double sx = 0.0, sy = 0.0;
+  subhalo_ranges<kSplit, P>(sp.tx, sp.ty, sub, nloop, grp, t, scratch, sx, sy);
+  __syncthreads();
+  if (grp == 0) {
+    double ax, ay;
+    total_deflection64<kSplit>(mc, sp.dx, sp.dy, scratch, t, sx, sy, ax, ay);
+    const float bx = (float)(sp.dx - ax), by = (float)(sp.dy - ay);
+    for (int j = 0; j < src.n; ++j) red[j][t] = sersic_unit(src.c[j], bx, by);
+    for (int j = 0; j < ll.n; ++j) red[src.n + j][t] = sersic_unit(ll.c[j], sp.tx, sp.ty);
+  }
+  __syncthreads();
+  const int n = src.n + ll.n;
+  const long npix = (long)g.nx * g.ny;
+  for (int idx = threadIdx.x; idx < g.ppb * n; idx += blockDim.x) {
+    const int j = idx / g.ppb;
+    const int lp = idx - j * g.ppb;
+    const long q = (long)blockIdx.x * g.ppb + lp;
+    if (q < npix) {
+      float acc = 0.f;
+      const float* r = red[j] + lp * g.s2;
+      for (int k = 0; k < g.s2; ++k) acc += r[k];
+      basis[j * npix + q] = acc * g.area_over_s2;
+    }
+  }
+}
+
 // Batched images: block b works on image descs[b / blocks_per_image] when
 // every image has the same grid (tiles == nullptr), otherwise on the
 // (image, pixel block) pair tiles[b].
@@ -397,6 +438,30 @@ hipError_t launch_simulate(GridC g, const MacroC& mc, bool tnfw, const void* sub
   return hipGetLastError();
 }
 
+
+namespace {
+template <class P>
+void basis_on(int split, unsigned blocks, const GridC& g, const MacroC& mc, const void* sub, int nloop,
+              const LightC& src, const LightC& ll, float* basis, hipStream_t st) {
+#define JT_BAS(S) hipLaunchKernelGGL((k_simulate_basis<S, P>), dim3(blocks), dim3(split_threads(S)), 0, st, g, mc, \
+                                     sub, nloop, src, ll, basis)
+  if (split == 1) JT_BAS(1); else if (split == 2) JT_BAS(2); else if (split == 4) JT_BAS(4); else JT_BAS(8);
+#undef JT_BAS
+}
+}  // namespace
+
+hipError_t launch_simulate_basis(GridC g, const MacroC& mc, bool tnfw, const void* sub, int nloop,
+                                 const LightC& src, const LightC& ll, float* basis, hipStream_t st) {
+  const long npix = (long)g.nx * g.ny;
+  const int split = pick_split(npix * g.s2, g.s2, nloop);
+  g.ppb = split_lanes(split) / g.s2;
+  const long blocks = (npix + g.ppb - 1) / g.ppb;
+  if (tnfw)
+    basis_on<TnfwPairs>(split, (unsigned)blocks, g, mc, sub, nloop, src, ll, basis, st);
+  else
+    basis_on<NfwPairs>(split, (unsigned)blocks, g, mc, sub, nloop, src, ll, basis, st);
+  return hipGetLastError();
+}
 
 hipError_t launch_conv_direct(const float* img, int nx, int ny, const float* psf, int k, float* out,
                               hipStream_t st) {

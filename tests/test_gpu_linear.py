@@ -1,0 +1,113 @@
+"""GPU parity of the linear amplitude solver (jt_linear_amplitudes) against
+the oracle's weighted least squares on the same seeded inputs."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from parity import IMAGE_TOL, image_error
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2606_01547_amd import Context
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.float64)
+
+
+def _scene(n_sub=2000, npix=40, s=3, k=21, seed=1002):
+    sc = W.config2_scene(seed=seed, n_sub=n_sub, npix=npix, supersample=s, psf_size=k)
+    sc.grid = W.Grid(nx=npix, ny=npix - 3, pixel_scale=0.05, x0=0.03, y0=-0.02, supersample=s)
+    sc.source.append(W.Sersic(amp=3.0, R_sersic=0.25, n_sersic=1.2, q=0.8, phi=1.1, cx=-0.15, cy=0.1))
+    return sc
+
+
+def _data(sc, seed):
+    d = W.noisy_image(O.simulate_image(sc), seed=seed)
+    w = (1.0 / O.noise_variance(d, 0.01, 1000.0)).astype(np.float32)
+    return d, w
+
+
+def _solve(ctx, sc, d, w, **kw):
+    return ctx.linear_amplitudes(sc.grid, sc.lens, sc.source, sc.lens_light, d, w, psf=sc.psf, **kw)
+
+
+def _check_against_oracle(ctx, sc, seed):
+    d, w = _data(sc, seed)
+    amps, model, logL = _solve(ctx, sc, d, w)
+    ea, em, el = O.linear_amplitudes(sc, d.astype(np.float64), w.astype(np.float64))
+    ga = _np(amps)
+    np.testing.assert_allclose(ga, ea, rtol=1e-4, atol=1e-4 * np.abs(ea).max())
+    assert image_error(_np(model), em) <= IMAGE_TOL
+    assert abs(_np(logL)[0] - el) <= 1e-4 * abs(el) + 1e-3
+
+
+def test_linear_amplitudes_headline_physics(ctx):
+    _check_against_oracle(ctx, _scene(), seed=1)
+
+
+def test_linear_amplitudes_without_psf_and_without_subhalos(ctx):
+    sc = _scene(n_sub=1, s=1)
+    sc.lens.nfw = None
+    sc.psf = None
+    _check_against_oracle(ctx, sc, seed=2)
+
+
+def test_linear_amplitudes_fft_path_and_truncated_subhalos(ctx):
+    sc = W.tnfw_scene(n_sub=500, npix=48, supersample=2, psf_size=101)
+    sc.grid = W.Grid(nx=48, ny=44, pixel_scale=0.05, supersample=2)
+    from paper_2606_01547_amd import convolve_auto_method
+    assert convolve_auto_method(48, 44, 101) == 2
+    _check_against_oracle(ctx, sc, seed=3)
+
+
+def test_noise_free_image_returns_the_amplitudes(ctx):
+    sc = _scene()
+    img = ctx.simulate_scene(sc)
+    w = torch.ones_like(img)
+    amps, model, logL = _solve(ctx, sc, img, w)
+    truth = np.array([c.amp for c in sc.source] + [c.amp for c in sc.lens_light])
+    np.testing.assert_allclose(_np(amps), truth, rtol=1e-5)
+    assert image_error(_np(model), _np(img)) <= 1e-5
+
+
+def test_coinciding_components_give_nan(ctx):
+    sc = _scene(n_sub=10, npix=24, s=1)
+    sc.source.append(sc.source[0])
+    d, w = _data(sc, seed=5)
+    amps, model, logL = _solve(ctx, sc, d, w)
+    assert np.all(np.isnan(_np(amps))) and np.isnan(_np(logL)[0])
+
+
+def test_repeated_calls_are_bitwise_equal(ctx):
+    sc = _scene(n_sub=300)
+    d, w = _data(sc, seed=6)
+    a1, m1, l1 = _solve(ctx, sc, d, w)
+    a2, m2, l2 = _solve(ctx, sc, d, w)
+    np.testing.assert_array_equal(_np(a1), _np(a2))
+    np.testing.assert_array_equal(_np(m1), _np(m2))
+    assert _np(l1)[0] == _np(l2)[0]
+
+
+def test_invalid_arguments_raise(ctx):
+    from paper_2606_01547_amd import JtError
+    sc = _scene(n_sub=10, npix=24, s=1)
+    d, w = _data(sc, seed=7)
+    with pytest.raises(JtError):
+        ctx.linear_amplitudes(sc.grid, sc.lens, [], [], d, w, psf=sc.psf)
+    many = [sc.source[0]] * 9
+    with pytest.raises(JtError):
+        ctx.linear_amplitudes(sc.grid, sc.lens, many, [], d, w, psf=sc.psf)
+    with pytest.raises(ValueError):
+        ctx.linear_amplitudes(sc.grid, sc.lens, sc.source, sc.lens_light, d[:-1], w[:-1], psf=sc.psf)
