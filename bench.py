@@ -371,6 +371,40 @@ def profiles_bench(ctx, reps=20):
                                 "tau = r_trunc/Rs log-uniform in [3, 30] (seed 1007)")}
 
 
+def linear_bench(ctx, reps=20):
+    """The linear amplitude solver on the headline image (four components:
+    the two sources, a third added source and the lens light) against
+    seeded noisy data: wall time per call, and the basis, convolution and
+    plain-image kernel times."""
+    import numpy as np
+    import torch
+    import workloads as W
+    sc = W.config2_scene()
+    sc.source.append(W.Sersic(amp=3.0, R_sersic=0.25, n_sersic=1.2, q=0.8, phi=1.1, cx=-0.15, cy=0.1))
+    g = sc.grid
+    nfw = sc.lens.nfw
+    dev = W.NFWTable(*[torch.from_numpy(np.asarray(a)).cuda() for a in (nfw.x, nfw.y, nfw.Rs, nfw.alpha_Rs)])
+    lens = W.Lens(sie=sc.lens.sie, shear=sc.lens.shear, nfw=dev)
+    psf = torch.from_numpy(sc.psf).cuda()
+    img = ctx.simulate_image(g, lens, sc.source, sc.lens_light, psf, sc.bn_exact)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(11)
+    m = img.cpu().numpy().astype(np.float64)
+    d = rng.poisson(1000.0 * np.maximum(m, 0.0)) / 1000.0 + rng.normal(0.0, 0.01, m.shape)
+    data = torch.from_numpy(d.astype(np.float32)).cuda()
+    w = 1.0 / (0.01 ** 2 + torch.clamp(data, min=0.0) / 1000.0)
+    model = torch.empty_like(data)
+    fn = lambda: ctx.linear_amplitudes(g, lens, sc.source, sc.lens_light, data, w, psf=psf, bn_exact=sc.bn_exact)
+    per, wall = _kernel_ms(ctx, fn, ("sim", "conv", "prep"), reps)
+    amps, _, logL = fn()
+    torch.cuda.synchronize()
+    return {"workload": "headline image with 4 light components (3 sources + lens light), seeded noisy data",
+            "ms_per_solve": round(1e3 * wall, 4), "basis_kernel_ms": round(per["sim"], 4),
+            "convolution_ms": round(per["conv"], 4), "amplitudes": [round(float(a), 6) for a in amps.cpu()],
+            "true_amplitudes": [c.amp for c in sc.source] + [c.amp for c in sc.lens_light],
+            "logL": float(logL.cpu()[0])}
+
+
 def adjoint_bench(ctx, draws, reps):
     """Gradient of the chi^2 log-likelihood for a batch of parameter draws
     (100x100 px, 1000 NFW, 21x21 PSF) against the forward alone and the plain
@@ -429,6 +463,7 @@ def main():
     ap.add_argument("--large-reps", type=int, default=3, help="timed 1000^2-px images (0 = skip)")
     ap.add_argument("--conv-sweep", type=int, default=1, help="direct/FFT convolution sweep (0 = skip)")
     ap.add_argument("--profiles", type=int, default=1, help="EPL / TNFW profile rows (0 = skip)")
+    ap.add_argument("--linear", type=int, default=1, help="linear amplitude solver row (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (3 times), to calibrate "
                          "the FETCH_SIZE / WRITE_SIZE counters")
@@ -529,6 +564,8 @@ def main():
         result["large_image"] = large_image_bench(ctx, args.large_reps)
     if args.profiles:
         result["profiles"] = profiles_bench(ctx)
+    if args.linear:
+        result["linear_amplitudes"] = linear_bench(ctx)
     if args.adjoint_draws > 0:
         result["adjoint"] = adjoint_bench(ctx, args.adjoint_draws, reps=10)
     if args.serve_requests > 0:
