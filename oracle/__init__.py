@@ -27,6 +27,7 @@ from .simulate import simulate_image, simulate_unconvolved
 from .likelihood import log_likelihood, noise_variance
 from .grad import chi2_gradient, macro_vector, macro_names
 from .linear import basis_images, linear_amplitudes
+from .fit import splitmix64, uniform, pso, pso_start, pso_move, pso_bests, lbfgs
 
 # Functions whose result no independent pin fixes (see the test modules).
 PARITY_UNPINNED = ()
@@ -38,5 +39,6 @@ __all__ = [
     "total_deflection", "ray_shoot", "sersic_bn", "sersic", "surface_brightness",
     "convolve_at", "convolve_same", "simulate_image", "simulate_unconvolved", "log_likelihood",
     "noise_variance", "chi2_gradient", "macro_vector", "macro_names", "basis_images", "linear_amplitudes",
+    "splitmix64", "uniform", "pso", "pso_start", "pso_move", "pso_bests", "lbfgs",
     "PARITY_UNPINNED",
 ]
