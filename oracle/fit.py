@@ -18,14 +18,16 @@ PSO (Kennedy & Eberhart 1995, with the inertia weight of Shi & Eberhart
          v <- w v + c1 r_0 (pbest - x) + c2 r_1 (gbest - x);  x <- x + v;
          a coordinate outside the box is set to the bound and its velocity to
          zero; then f at every particle; a personal best moves when its new
-         value is strictly larger; the swarm best is the first particle with
-         the largest personal best.
+         value is strictly larger (NaN counts as -inf); the swarm best is the
+         first particle with the largest personal best.
 
 L-BFGS (Nocedal 1980; Liu & Nocedal 1989), minimising F = -f from x0 in the
-box: the direction is -H g by the two-loop recursion over the last m pairs
-(s, y) with H0 = (s.y / y.y) I from the newest pair (the steepest-descent
-direction scaled to unit length when there is none, or when the direction
-does not descend, which also clears the pairs); the step starts at 1 and is
+box: a coordinate on a bound whose gradient points out of the box is held
+(also every coordinate with equal bounds); on the free coordinates the
+direction is -H g by the two-loop recursion over the last m pairs (s, y)
+with H0 = (s.y / y.y) I from the newest pair (the steepest-descent direction
+scaled to unit length when there is none, or when the direction does not
+descend, which also clears the pairs); the step starts at 1 and is
 halved until the projected trial point x_t = clamp(x + a d) satisfies
 F(x_t) <= F(x) + 1e-4 g.(x_t - x) (at most 40 halvings, else the run
 stops); a pair is kept when s.y > 1e-12 |s| |y|; the run stops after
@@ -85,6 +87,7 @@ def pso_bests(x, f, pbest, pbest_f):
     """Personal bests after the values f at x; the swarm best."""
     pbest = pbest.copy()
     pbest_f = pbest_f.copy()
+    f = np.where(np.isnan(f), -np.inf, f)          # an undefined value never wins
     better = f > pbest_f
     pbest[better] = x[better]
     pbest_f[better] = f[better]
@@ -119,26 +122,31 @@ def lbfgs(F, x0, lo, hi, m=10, max_iter=200, ftol=1e-12, gtol=1e-10):
     S, Y = [], []
     it = 0
     while it < max_iter:
-        pg = np.where((x <= lo) & (g > 0) | (x >= hi) & (g < 0), 0.0, g)
-        if np.max(np.abs(pg)) <= gtol:
+        # coordinates on a bound whose gradient points out of the box stay
+        # put; the recursion runs on the free ones
+        free = ~(((x <= lo) & (g > 0)) | ((x >= hi) & (g < 0)))
+        gf = np.where(free, g, 0.0)
+        if np.max(np.abs(gf)) <= gtol:
             break
-        q = g.copy()
+        Sf = [np.where(free, s, 0.0) for s in S]
+        Yf = [np.where(free, y, 0.0) for y in Y]
+        q = gf.copy()
         alphas = []
-        for s, y in zip(reversed(S), reversed(Y)):
+        for s, y in zip(reversed(Sf), reversed(Yf)):
             a = (s @ q) / (y @ s)
             q = q - a * y
             alphas.append(a)
-        if S:
-            q = q * ((S[-1] @ Y[-1]) / (Y[-1] @ Y[-1]))
+        if Sf:
+            q = q * ((Sf[-1] @ Yf[-1]) / (Yf[-1] @ Yf[-1]))
         else:
-            q = q / np.linalg.norm(g)
-        for (s, y), a in zip(zip(S, Y), reversed(alphas)):
+            q = q / np.linalg.norm(gf)
+        for (s, y), a in zip(zip(Sf, Yf), reversed(alphas)):
             b = (y @ q) / (y @ s)
             q = q + s * (a - b)
         d = -q
-        if g @ d >= 0.0:
+        if not (g @ d < 0.0):
             S, Y = [], []
-            d = -g / np.linalg.norm(g)
+            d = -gf / np.linalg.norm(gf)
         step = 1.0
         for _ in range(41):
             xt = np.clip(x + step * d, lo, hi)

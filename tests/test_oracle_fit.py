@@ -73,3 +73,20 @@ def test_lbfgs_active_bound():
     F = lambda x: ((x[0] - 2.0) ** 2 + (x[1] + 0.5) ** 2, np.array([2 * (x[0] - 2.0), 2 * (x[1] + 0.5)]))
     x, fx, _ = O.lbfgs(F, [0.2, 0.3], [0.0, -1.0], [1.0, 1.0])
     np.testing.assert_allclose(x, [1.0, -0.5], atol=1e-9)
+
+
+def test_lbfgs_holds_fixed_coordinates():
+    # a coupled quadratic with coordinate 2 fixed (equal bounds): the free
+    # coordinates solve the reduced system
+    rng = np.random.default_rng(4)
+    M = rng.normal(size=(5, 5))
+    A = M @ M.T + 5 * np.eye(5)
+    b = rng.normal(size=5)
+    F = lambda x: (0.5 * x @ A @ x - b @ x, A @ x - b)
+    lo, hi = np.full(5, -1e3), np.full(5, 1e3)
+    lo[2] = hi[2] = 0.7
+    x, _, _ = O.lbfgs(F, np.zeros(5), lo, hi, ftol=0.0, gtol=1e-10)
+    keep = [0, 1, 3, 4]
+    expect = np.linalg.solve(A[np.ix_(keep, keep)], b[keep] - A[keep, 2] * 0.7)
+    assert x[2] == 0.7
+    np.testing.assert_allclose(x[keep], expect, rtol=1e-7, atol=1e-7)
