@@ -257,6 +257,67 @@ jt_status jt_linear_amplitudes(jt_ctx* ctx, const jt_grid* grid, const jt_lens* 
                                hipStream_t stream);
 
 /* ----------------------------------------------------------------------
+ * Fitting loops (section "Improvements over lenstronomy in lens modelling":
+ * the particle swarm kept from lenstronomy, and L-BFGS on gradients)
+ * -------------------------------------------------------------------- */
+/* The parameter vector is a jt_draws macro row: (theta_E, q, phi, cx, cy) of
+ * the SIE, (gamma1, gamma2), then (amp, R_sersic, n_sersic, q, phi, cx, cy)
+ * per source and per lens-light component; P = 7 + 7 (n_src + n_ll).  Every
+ * evaluation shares the fixed subhalos, the PSF and the data. */
+typedef struct {
+  int n_src, n_ll;                  /* n_src + n_ll >= 1 (<= 3 for jt_lbfgs) */
+  const double *lower, *upper;      /* host [P]: the search box, inside each parameter's domain */
+  int n_sub;                        /* fixed NFW subhalos, device float32 [n_sub] each */
+  const float *sub_x, *sub_y, *sub_Rs, *sub_alpha_Rs;
+  const float* psf;                 /* device [k][k] (odd k), or NULL with k = 0 */
+  int k;
+  const float *data, *inv_var;      /* device float32 [ny][nx] */
+} jt_fit_problem;
+
+/* Particle swarm (Kennedy & Eberhart 1995, inertia weight of Shi & Eberhart
+ * 1998) maximising log L: starts uniform in the box (v = 0), then
+ * v <- w v + c1 r0 (pbest - x) + c2 r1 (gbest - x), x <- x + v, a coordinate
+ * leaving the box is set on it with zero velocity.  Random numbers r are
+ * jt_uniform(seed, i) at fixed counters (jt_pso_move), so a run is
+ * reproducible.  Each step's N particles are one batched jt_chi2 launch. */
+typedef struct {
+  int n_particles, n_iterations;    /* >= 1, >= 0 */
+  double inertia, c_cognitive, c_social;   /* w, c1, c2 (e.g. 0.7298, 1.49618, 1.49618) */
+  uint64_t seed;
+} jt_pso_cfg;
+/* Host outputs: best [P], best_logL, history [n_iterations] (swarm best after
+ * each step; may be NULL).  Synchronises `stream` once per step. */
+jt_status jt_pso(jt_ctx* ctx, const jt_grid* grid, const jt_fit_problem* prob, const jt_pso_cfg* cfg,
+                 double* best, double* best_logL, double* history, hipStream_t stream);
+/* The update jt_pso applies at step t >= 1 to the host arrays x, v [N][P]
+ * (pbest [N][P], gbest [P]), with r0, r1 = jt_uniform(seed, 2 ((t N + p) P + d) + 0, 1). */
+jt_status jt_pso_move(int N, int P, int t, uint64_t seed, double w, double c1, double c2, const double* lower,
+                      const double* upper, double* x, double* v, const double* pbest, const double* gbest);
+/* Counter-based uniform in [0, 1): the (i+1)-th output of SplitMix64 (Steele,
+ * Lea & Flood 2014) seeded with `seed`, shifted right by 11, times 2^-53. */
+double jt_uniform(uint64_t seed, uint64_t i);
+
+/* L-BFGS (Nocedal 1980; Liu & Nocedal 1989) minimising -log L from `starts`
+ * points at once.  A coordinate on a bound whose gradient points out of the
+ * box (so every coordinate with lower = upper) is held; on the free ones the
+ * direction is the two-loop recursion over the last `memory` pairs with
+ * H0 = (s.y / y.y) I (unit steepest descent without pairs or when the
+ * direction does not descend); steps from 1, halved until the box-projected
+ * trial satisfies the Armijo condition with constant 1e-4 (41 trials, then
+ * the chain stops); stops after max_iter accepted steps, a relative change
+ * of -log L at most ftol, or a projected gradient at most gtol.  The trial
+ * points of all running chains are one batched jt_chi2_grad launch per round.
+ * x0, x: host [starts][P]; logL host [starts]; iterations host [starts] (may
+ * be NULL).  The gradient is the FP32 adjoint's, so chains stop once its
+ * round-off hides further descent. */
+typedef struct {
+  int starts, memory, max_iter;     /* >= 1, >= 1, >= 0 */
+  double ftol, gtol;
+} jt_lbfgs_cfg;
+jt_status jt_lbfgs(jt_ctx* ctx, const jt_grid* grid, const jt_fit_problem* prob, const jt_lbfgs_cfg* cfg,
+                   const double* x0, double* x, double* logL, int* iterations, hipStream_t stream);
+
+/* ----------------------------------------------------------------------
  * Resident tables
  * -------------------------------------------------------------------- */
 /* Copy n subhalos (host float32 SoA) into a device-resident, pre-derived

@@ -6,8 +6,8 @@ exposes the same calls as the ABI (ray_shoot, deflection, source_sb,
 convolve, simulate_image, upload_subhalos, upload_psf, ...) on torch CUDA
 tensors and torch's current HIP stream.
 """
-from ._native import (Context, JtError, LIB_PATH, Server, convolve_auto_method, load_library, sersic_bn,
-                      STATUS_NAMES)
+from ._native import (Context, JtError, LIB_PATH, Server, convolve_auto_method, load_library, pso_move,
+                      sersic_bn, uniform, STATUS_NAMES)
 
-__all__ = ["Context", "JtError", "LIB_PATH", "Server", "convolve_auto_method", "load_library", "sersic_bn",
-           "STATUS_NAMES"]
+__all__ = ["Context", "JtError", "LIB_PATH", "Server", "convolve_auto_method", "load_library", "pso_move",
+           "sersic_bn", "uniform", "STATUS_NAMES"]

@@ -84,6 +84,21 @@ class JtDraws(ctypes.Structure):
                 ("n_src", c_int), ("n_ll", c_int), ("src", POINTER(JtSersic)), ("ll", POINTER(JtSersic))]
 
 
+class JtFitProblem(ctypes.Structure):
+    _fields_ = [("n_src", c_int), ("n_ll", c_int), ("lower", POINTER(c_double)), ("upper", POINTER(c_double)),
+                ("n_sub", c_int), ("sub_x", c_void_p), ("sub_y", c_void_p), ("sub_Rs", c_void_p),
+                ("sub_alpha_Rs", c_void_p), ("psf", c_void_p), ("k", c_int), ("data", c_void_p), ("inv_var", c_void_p)]
+
+
+class JtPsoCfg(ctypes.Structure):
+    _fields_ = [("n_particles", c_int), ("n_iterations", c_int), ("inertia", c_double), ("c_cognitive", c_double),
+                ("c_social", c_double), ("seed", c_uint64)]
+
+
+class JtLbfgsCfg(ctypes.Structure):
+    _fields_ = [("starts", c_int), ("memory", c_int), ("max_iter", c_int), ("ftol", c_double), ("gtol", c_double)]
+
+
 class JtServerCfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_batch_images", c_int), ("max_batch_pairs", c_double),
                 ("max_inflight_batches", c_int), ("n_streams", c_int)]
@@ -125,6 +140,14 @@ _SIGS = {
     "jt_upload_subhalos": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_uint64)]),
     "jt_linear_amplitudes": (c_int, [c_void_p, POINTER(JtGrid), POINTER(JtLens), POINTER(JtLight), POINTER(JtLight),
                                      c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "jt_pso": (c_int, [c_void_p, POINTER(JtGrid), POINTER(JtFitProblem), POINTER(JtPsoCfg), POINTER(c_double),
+                       POINTER(c_double), POINTER(c_double), c_void_p]),
+    "jt_pso_move": (c_int, [c_int, c_int, c_int, c_uint64, c_double, c_double, c_double, POINTER(c_double),
+                            POINTER(c_double), POINTER(c_double), POINTER(c_double), POINTER(c_double),
+                            POINTER(c_double)]),
+    "jt_uniform": (c_double, [c_uint64, c_uint64]),
+    "jt_lbfgs": (c_int, [c_void_p, POINTER(JtGrid), POINTER(JtFitProblem), POINTER(JtLbfgsCfg), POINTER(c_double),
+                         POINTER(c_double), POINTER(c_double), POINTER(c_int), c_void_p]),
     "jt_upload_tnfw": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                POINTER(c_uint64)]),
     "jt_upload_psf": (c_int, [c_void_p, c_void_p, c_int, POINTER(c_uint64)]),
@@ -178,6 +201,26 @@ def sersic_bn(n: float, exact: bool = False) -> float:
 def convolve_auto_method(nx: int, ny: int, k: int) -> int:
     """The convolution path method 0 takes: 1 direct, 2 FFT, 0 none."""
     return int(load_library().jt_convolve_auto_method(int(nx), int(ny), int(k)))
+
+
+def uniform(seed: int, i: int) -> float:
+    """The library's counter-based uniform (SplitMix64 output i of `seed`)."""
+    return float(load_library().jt_uniform(int(seed), int(i)))
+
+
+def _dptr(a):
+    return a.ctypes.data_as(POINTER(c_double))
+
+
+def pso_move(t, seed, w, c1, c2, lower, upper, x, v, pbest, gbest):
+    """The library's swarm update at step t on host arrays (x, v updated in place)."""
+    N, P = x.shape
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (lower, upper, pbest, gbest)]
+    if x.dtype != np.float64 or v.dtype != np.float64 or not x.flags.c_contiguous or not v.flags.c_contiguous:
+        raise ValueError("x and v must be C-contiguous float64")
+    _check(load_library().jt_pso_move(int(N), int(P), int(t), int(seed), float(w), float(c1), float(c2),
+                                      _dptr(arrs[0]), _dptr(arrs[1]), _dptr(x), _dptr(v), _dptr(arrs[2]),
+                                      _dptr(arrs[3])))
 
 
 # ---------------------------------------------------------------- helpers
@@ -391,6 +434,62 @@ class Context:
                                               c_void_p(logL.data_ptr()), _stream_handle(stream)))
         self._retain(keep, stream)
         return amps[:n], mo, logL
+
+    # ---- fitting loops
+    def _fit_problem(self, n_src, n_ll, lower, upper, data, inv_var, psf, nfw, keep):
+        lo = np.ascontiguousarray(np.asarray(lower, dtype=np.float64))
+        hi = np.ascontiguousarray(np.asarray(upper, dtype=np.float64))
+        keep.extend([lo, hi])
+        Pr = JtFitProblem()
+        Pr.n_src, Pr.n_ll = int(n_src), int(n_ll)
+        Pr.lower, Pr.upper = _dptr(lo), _dptr(hi)
+        if nfw is not None and len(nfw.x) > 0:
+            arrs = [_dev_f32(a, self.device, keep) for a in (nfw.x, nfw.y, nfw.Rs, nfw.alpha_Rs)]
+            Pr.n_sub = int(arrs[0].numel())
+            Pr.sub_x, Pr.sub_y, Pr.sub_Rs, Pr.sub_alpha_Rs = [c_void_p(a.data_ptr()) for a in arrs]
+        if psf is not None:
+            pt = _dev_f32(psf, self.device, keep)
+            Pr.psf, Pr.k = c_void_p(pt.data_ptr()), int(pt.shape[0])
+        Pr.data = c_void_p(_dev_f32(data, self.device, keep).data_ptr())
+        Pr.inv_var = c_void_p(_dev_f32(inv_var, self.device, keep).data_ptr())
+        return Pr, lo.size
+
+    def pso(self, grid, n_src, n_ll, lower, upper, data, inv_var, psf=None, nfw=None, n_particles=64,
+            n_iterations=100, inertia=0.7298, c_cognitive=1.49618, c_social=1.49618, seed=0, stream=None):
+        """Particle swarm maximising log L over the box; returns (best [P],
+        best log L, history [n_iterations]) on the host."""
+        keep = []
+        G = JtGrid(int(grid.nx), int(grid.ny), int(grid.supersample), float(grid.pixel_scale),
+                   float(grid.x0), float(grid.y0))
+        Pr, P = self._fit_problem(n_src, n_ll, lower, upper, data, inv_var, psf, nfw, keep)
+        cfg = JtPsoCfg(int(n_particles), int(n_iterations), float(inertia), float(c_cognitive), float(c_social),
+                       int(seed))
+        best = np.empty(P)
+        hist = np.empty(max(int(n_iterations), 1))
+        bl = c_double()
+        _check(self._lib.jt_pso(self._ptr, byref(G), byref(Pr), byref(cfg), _dptr(best), byref(bl), _dptr(hist),
+                                _stream_handle(stream)))
+        return best, bl.value, hist[:int(n_iterations)]
+
+    def lbfgs(self, grid, n_src, n_ll, lower, upper, data, inv_var, x0, psf=None, nfw=None, memory=10,
+              max_iter=200, ftol=1e-12, gtol=1e-10, stream=None):
+        """L-BFGS chains minimising -log L from the rows of x0 [starts, P];
+        returns (x [starts, P], log L [starts], iterations [starts])."""
+        keep = []
+        G = JtGrid(int(grid.nx), int(grid.ny), int(grid.supersample), float(grid.pixel_scale),
+                   float(grid.x0), float(grid.y0))
+        Pr, P = self._fit_problem(n_src, n_ll, lower, upper, data, inv_var, psf, nfw, keep)
+        x0 = np.ascontiguousarray(np.atleast_2d(np.asarray(x0, dtype=np.float64)))
+        if x0.shape[1] != P:
+            raise ValueError(f"x0 rows must hold {P} values")
+        C = x0.shape[0]
+        cfg = JtLbfgsCfg(C, int(memory), int(max_iter), float(ftol), float(gtol))
+        x = np.empty_like(x0)
+        ll = np.empty(C)
+        its = np.empty(C, dtype=np.int32)
+        _check(self._lib.jt_lbfgs(self._ptr, byref(G), byref(Pr), byref(cfg), _dptr(x0), _dptr(x), _dptr(ll),
+                                  its.ctypes.data_as(POINTER(c_int)), _stream_handle(stream)))
+        return x, ll, its
 
     # ---- batches of parameter draws
     def _draws(self, batch, keep):

@@ -69,6 +69,9 @@ int main(void) {
   P(jt_sersic); P(jt_light); O(jt_light, c); O(jt_light, bn_exact);
   P(jt_draws); O(jt_draws, sie); O(jt_draws, n_sub); O(jt_draws, sub_alpha_Rs); O(jt_draws, n_ll); O(jt_draws, ll);
   P(jt_server_stats); O(jt_server_stats, device_seconds); O(jt_server_stats, max_wait_seconds);
+  P(jt_fit_problem); O(jt_fit_problem, lower); O(jt_fit_problem, n_sub); O(jt_fit_problem, sub_alpha_Rs);
+  O(jt_fit_problem, psf); O(jt_fit_problem, k); O(jt_fit_problem, inv_var);
+  P(jt_pso_cfg); O(jt_pso_cfg, inertia); O(jt_pso_cfg, seed); P(jt_lbfgs_cfg); O(jt_lbfgs_cfg, ftol);
   return 0;
 }
 """
@@ -86,7 +89,8 @@ def test_ctypes_structs_match_c_layout(tmp_path):
     m = {"jt_grid": nat.JtGrid, "jt_sie": nat.JtSie, "jt_shear": nat.JtShear, "jt_nfw": nat.JtNfw,
          "jt_point_masses": nat.JtPointMasses, "jt_lens": nat.JtLens, "jt_sersic": nat.JtSersic,
          "jt_light": nat.JtLight, "jt_draws": nat.JtDraws, "jt_server_stats": nat.JtServerStats,
-         "jt_epl": nat.JtEpl, "jt_request": nat.JtRequest}
+         "jt_epl": nat.JtEpl, "jt_request": nat.JtRequest, "jt_fit_problem": nat.JtFitProblem,
+         "jt_pso_cfg": nat.JtPsoCfg, "jt_lbfgs_cfg": nat.JtLbfgsCfg}
     for key, val in got.items():
         if "." in key:
             t, f = key.split(".")
@@ -126,3 +130,31 @@ def test_convolve_auto_method_host_rule():
     assert nat.convolve_auto_method(2000, 2000, 101) == 1    # FFT size over 2048: direct
     assert nat.convolve_auto_method(10, 10, 4) == 0          # even kernel
     assert nat.convolve_auto_method(0, 10, 3) == 0
+
+
+def test_counter_uniforms_match_the_oracle_generator():
+    import oracle as O
+    _, nat = _lib()
+    for seed in (0, 1, 1234567, 2 ** 63 + 5):
+        for i in (0, 1, 2, 1000, 2 ** 40 + 3):
+            assert nat.uniform(seed, i) == O.uniform(seed, i)
+
+
+def test_swarm_update_matches_the_oracle_step():
+    import oracle as O
+    _, nat = _lib()
+    rng = np.random.default_rng(2)
+    N, P = 7, 5
+    lo, hi = -np.ones(P), 2.0 * np.ones(P)
+    x = rng.uniform(-1, 2, (N, P))
+    v = rng.normal(0, 0.8, (N, P))
+    pbest = rng.uniform(-1, 2, (N, P))
+    gbest = rng.uniform(-1, 2, P)
+    for t in (1, 2, 9):
+        ex, ev = O.pso_move(t, x, v, pbest, gbest, lo, hi, 11, 0.7298, 1.49618, 1.49618)
+        gx, gv = x.copy(), v.copy()
+        nat.pso_move(t, 11, 0.7298, 1.49618, 1.49618, lo, hi, gx, gv, pbest, gbest)
+        np.testing.assert_allclose(gx, ex, rtol=1e-15, atol=1e-15)
+        np.testing.assert_allclose(gv, ev, rtol=1e-15, atol=1e-15)
+        assert np.all(gx >= lo) and np.all(gx <= hi)
+        x, v = gx, gv
