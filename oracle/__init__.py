@@ -21,7 +21,8 @@ from .grid import subpixel_coords, supersample_reduce
 from .lens import (sie_deflection, sie_kappa, epl_deflection, epl_kappa, tnfw_G, tnfw_deflection,
                    shear_deflection, nfw_g, nfw_deflection, nfw_kappa, point_mass_deflection, total_deflection,
                    ray_shoot)
-from .light import sersic_bn, sersic, surface_brightness
+from .light import (sersic_bn, sersic, surface_brightness, gaussian, core_sersic, shapelets, shapelet_phi,
+                    shapelet_index, component)
 from .conv import convolve_at, convolve_same
 from .simulate import simulate_image, simulate_unconvolved
 from .likelihood import log_likelihood, noise_variance
@@ -37,6 +38,7 @@ __all__ = [
     "tnfw_G", "tnfw_deflection",
     "shear_deflection", "nfw_g", "nfw_deflection", "nfw_kappa", "point_mass_deflection",
     "total_deflection", "ray_shoot", "sersic_bn", "sersic", "surface_brightness",
+    "gaussian", "core_sersic", "shapelets", "shapelet_phi", "shapelet_index", "component",
     "convolve_at", "convolve_same", "simulate_image", "simulate_unconvolved", "log_likelihood",
     "noise_variance", "chi2_gradient", "macro_vector", "macro_names", "basis_images", "linear_amplitudes",
     "splitmix64", "uniform", "pso", "pso_start", "pso_move", "pso_bests", "lbfgs",

@@ -129,6 +129,44 @@ class Sersic:
 
 
 @dataclass
+class Gaussian:
+    """Elliptical Gaussian light of total flux amp, width sigma (arcsec)."""
+    amp: float
+    sigma: float
+    q: float
+    phi: float
+    cx: float
+    cy: float
+
+
+@dataclass
+class CoreSersic:
+    """Core-Sersic light: Sersic outside the break radius R_b, inner power
+    law of slope gamma, transition sharpness alpha."""
+    amp: float
+    R_sersic: float
+    R_b: float
+    n_sersic: float
+    gamma: float
+    alpha: float
+    q: float
+    phi: float
+    cx: float
+    cy: float
+
+
+@dataclass
+class Shapelets:
+    """Cartesian shapelets up to order n_max, scale beta, centre (cx, cy);
+    (n_max + 1)(n_max + 2)/2 coefficients ordered by n = n1 + n2, then n2."""
+    n_max: int
+    beta: float
+    cx: float
+    cy: float
+    coeff: np.ndarray
+
+
+@dataclass
 class Lens:
     sie: Optional[SIE] = None
     epl: Optional[EPL] = None
