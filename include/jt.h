@@ -128,10 +128,38 @@ typedef struct {
  * q in (0, 1]. */
 typedef struct { double amp, R_sersic, n_sersic, q, phi, cx, cy; } jt_sersic;
 
-/* A list of Sersic components (host array c[n], n <= JT_MAX_SERSIC).
+/* Elliptical Gaussian light (the paper's flux table: GAUSSIAN, GAUSSIAN_ELLIPSE,
+ * MULTI_GAUSSIAN as several of them): I = amp/(2 pi sigma^2) exp(-R^2/(2 sigma^2)),
+ * R^2 = q x'^2 + y'^2/q, so amp is the total flux.  sigma > 0, q in (0, 1]. */
+typedef struct { double amp, sigma, q, phi, cx, cy; } jt_gaussian;
+
+/* Core-Sersic light (CORE_SERSIC; Graham et al. 2003, Trujillo et al. 2004):
+ * I = amp (1 + (R_b/R)^alpha)^(gamma/alpha)
+ *         exp(-b_n [((R^alpha + R_b^alpha)/R_sersic^alpha)^(1/(n alpha)) - 1]),
+ * R as the Sersic's, floored at 1e-6 R_b; R_b -> 0 gives the Sersic.
+ * R_sersic, R_b > 0, n in [0.2, 10], gamma in [0, 2), alpha in (0, 20]. */
+typedef struct { double amp, R_sersic, R_b, n_sersic, gamma, alpha, q, phi, cx, cy; } jt_core_sersic;
+
+/* Cartesian shapelets (SHAPELETS; Refregier 2003): I = sum over
+ * n1 + n2 <= n_max of coeff c_{n1 n2} beta^-1 phi_n1((x-cx)/beta) phi_n2((y-cy)/beta),
+ * phi_n(u) = (2^n sqrt(pi) n!)^(-1/2) H_n(u) exp(-u^2/2).  coeff: host double
+ * [(n_max+1)(n_max+2)/2], ordered by n = n1 + n2, then n2 = 0..n.
+ * n_max in [0, 10], beta > 0. */
+typedef struct { int n_max; double beta, cx, cy; const double* coeff; } jt_shapelets;
+
+/* A light list: Sersic components (host array c[n], n <= JT_MAX_SERSIC) and
+ * optionally up to 8 Gaussians, 2 core-Sersic components and one shapelet
+ * set (host arrays, read during the call).
  * bn_exact = 0: b_n = 1.9992 n - 0.3271 (Capaccioli 1989);
- * bn_exact = 1: b_n solves P(2n, b_n) = 1/2 (R_sersic is the half-light radius). */
-typedef struct { int n; const jt_sersic* c; int bn_exact; } jt_light;
+ * bn_exact = 1: b_n solves P(2n, b_n) = 1/2 (R_sersic is the half-light radius).
+ * The batched draws, the adjoint and the linear amplitude solver take Sersic
+ * components only. */
+typedef struct {
+  int n; const jt_sersic* c; int bn_exact;
+  int n_gauss; const jt_gaussian* gauss;
+  int n_core; const jt_core_sersic* core;
+  const jt_shapelets* shapelets;     /* NULL: none */
+} jt_light;
 
 /* b_n of the Sersic profile as the library uses it (host FP64): the
  * Capaccioli fit 1.9992 n - 0.3271, or (exact != 0) the root of

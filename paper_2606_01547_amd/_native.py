@@ -74,8 +74,26 @@ class JtSersic(ctypes.Structure):
                 ("phi", c_double), ("cx", c_double), ("cy", c_double)]
 
 
+class JtGaussian(ctypes.Structure):
+    _fields_ = [("amp", c_double), ("sigma", c_double), ("q", c_double), ("phi", c_double), ("cx", c_double),
+                ("cy", c_double)]
+
+
+class JtCoreSersic(ctypes.Structure):
+    _fields_ = [("amp", c_double), ("R_sersic", c_double), ("R_b", c_double), ("n_sersic", c_double),
+                ("gamma", c_double), ("alpha", c_double), ("q", c_double), ("phi", c_double), ("cx", c_double),
+                ("cy", c_double)]
+
+
+class JtShapelets(ctypes.Structure):
+    _fields_ = [("n_max", c_int), ("beta", c_double), ("cx", c_double), ("cy", c_double),
+                ("coeff", POINTER(c_double))]
+
+
 class JtLight(ctypes.Structure):
-    _fields_ = [("n", c_int), ("c", POINTER(JtSersic)), ("bn_exact", c_int)]
+    _fields_ = [("n", c_int), ("c", POINTER(JtSersic)), ("bn_exact", c_int), ("n_gauss", c_int),
+                ("gauss", POINTER(JtGaussian)), ("n_core", c_int), ("core", POINTER(JtCoreSersic)),
+                ("shapelets", POINTER(JtShapelets))]
 
 
 class JtDraws(ctypes.Structure):
@@ -316,12 +334,38 @@ class Context:
 
     @staticmethod
     def _light(comps, bn_exact, keep):
+        """A jt_light from a list of components, sorted by profile: Sersic
+        (amp, R_sersic, n_sersic, ...), Gaussian (sigma), core-Sersic (R_b)
+        and at most one shapelet set (coeff)."""
         comps = list(comps or [])
-        arr = (JtSersic * max(1, len(comps)))()
-        for i, c in enumerate(comps):
+        sh = [c for c in comps if hasattr(c, "coeff")]
+        ga = [c for c in comps if hasattr(c, "sigma")]
+        co = [c for c in comps if hasattr(c, "R_b")]
+        se = [c for c in comps if not (hasattr(c, "coeff") or hasattr(c, "sigma") or hasattr(c, "R_b"))]
+        if len(sh) > 1:
+            raise ValueError("at most one shapelet set per light list")
+        arr = (JtSersic * max(1, len(se)))()
+        for i, c in enumerate(se):
             arr[i] = JtSersic(c.amp, c.R_sersic, c.n_sersic, c.q, c.phi, c.cx, c.cy)
-        keep.append(arr)
-        return JtLight(len(comps), ctypes.cast(arr, POINTER(JtSersic)), int(bool(bn_exact)))
+        garr = (JtGaussian * max(1, len(ga)))()
+        for i, c in enumerate(ga):
+            garr[i] = JtGaussian(c.amp, c.sigma, c.q, c.phi, c.cx, c.cy)
+        carr = (JtCoreSersic * max(1, len(co)))()
+        for i, c in enumerate(co):
+            carr[i] = JtCoreSersic(c.amp, c.R_sersic, c.R_b, c.n_sersic, c.gamma, c.alpha, c.q, c.phi, c.cx, c.cy)
+        keep.extend([arr, garr, carr])
+        L = JtLight(len(se), ctypes.cast(arr, POINTER(JtSersic)), int(bool(bn_exact)), len(ga),
+                    ctypes.cast(garr, POINTER(JtGaussian)), len(co), ctypes.cast(carr, POINTER(JtCoreSersic)), None)
+        if sh:
+            s0 = sh[0]
+            coeff = np.ascontiguousarray(np.asarray(s0.coeff, dtype=np.float64))
+            if coeff.size != (s0.n_max + 1) * (s0.n_max + 2) // 2:
+                raise ValueError("shapelet coefficients must number (n_max + 1)(n_max + 2)/2")
+            S = JtShapelets(int(s0.n_max), float(s0.beta), float(s0.cx), float(s0.cy),
+                            coeff.ctypes.data_as(POINTER(c_double)))
+            keep.extend([coeff, S])
+            L.shapelets = ctypes.pointer(S)
+        return L
 
     # ---- step 1
     def _ray(self, fn, x, y, lens, out, stream):

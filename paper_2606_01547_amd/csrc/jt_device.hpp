@@ -71,9 +71,38 @@ struct SersicC {
   float R, n, b;         // R_sersic, n, b_n (used by the adjoint)
 };
 
+// Elliptical Gaussian: I = norm exp2(-k R^2), norm = amp/(2 pi sigma^2),
+// k = log2(e)/(2 sigma^2), R^2 as the Sersic's.
+struct GaussC {
+  float cx, cy, cphi, sphi, q, inv_q, k, norm;
+};
+
+// Core-Sersic in base-2 logarithms: lRb = alpha log2 R_b, lRe = alpha log2 R_e,
+// half_alpha = alpha/2, g_over_a = gamma/alpha, e = 1/(n alpha),
+// kb = b_n log2(e); R^2 floored at R2_floor = (1e-6 R_b)^2.
+struct CoreC {
+  float cx, cy, cphi, sphi, q, inv_q;
+  float half_alpha, lRb, lRe, g_over_a, e, kb, amp, R2_floor;
+};
+
+// Cartesian shapelets up to order kShapeletMaxN: coefficients by n = n1 + n2,
+// then n2 (zero beyond the set's n_max); scale = pi^(-1/2)/beta.
+constexpr int kShapeletMaxN = 10;
+constexpr int kShapeletCoeffs = (kShapeletMaxN + 1) * (kShapeletMaxN + 2) / 2;
+struct ShapeC {
+  float cx, cy, inv_beta, scale;
+  float coeff[kShapeletCoeffs];
+};
+constexpr int kMaxGauss = 8;
+constexpr int kMaxCore = 2;
+
 struct LightC {
   int n;
   SersicC c[kMaxSersic];
+  int ng, ncs, nsh;      // Gaussians, core-Sersic components, shapelet sets (0 or 1)
+  GaussC g[kMaxGauss];
+  CoreC cs[kMaxCore];
+  ShapeC sh;
 };
 
 // Implicit sub-pixel grid: theta = origin + step * (m + 1/2) along each axis,
@@ -442,6 +471,73 @@ __device__ __forceinline__ float sersic_unit(const SersicC& c, float x, float y)
 __device__ __forceinline__ float sersic_sum(const LightC& L, float x, float y) {
   float acc = 0.f;
   for (int k = 0; k < L.n; ++k) acc = fmaf(L.c[k].amp, sersic_unit(L.c[k], x, y), acc);
+  return acc;
+}
+
+__device__ __forceinline__ float shapelet_sum(const ShapeC& s, float x, float y) {
+  constexpr float kHalfLog2e = 0.72134752044448170368f;   // log2(e)/2
+  const float u = (x - s.cx) * s.inv_beta, v = (y - s.cy) * s.inv_beta;
+  // phi_n(v) / pi^(-1/4) by the normalised Hermite recurrence
+  float pv[kShapeletMaxN + 1];
+  pv[0] = __builtin_amdgcn_exp2f(-kHalfLog2e * v * v);
+  pv[1] = 1.41421356237309504880f * v * pv[0];
+#pragma unroll
+  for (int n = 1; n < kShapeletMaxN; ++n)
+    pv[n + 1] = fmaf((float)__builtin_sqrt(2.0 / (n + 1)) * v, pv[n], -(float)__builtin_sqrt((double)n / (n + 1)) * pv[n - 1]);
+  float pu_prev = 0.f, pu = __builtin_amdgcn_exp2f(-kHalfLog2e * u * u);
+  float acc = 0.f;
+#pragma unroll
+  for (int n1 = 0; n1 <= kShapeletMaxN; ++n1) {
+    float row = 0.f;
+#pragma unroll
+    for (int n2 = 0; n1 + n2 <= kShapeletMaxN; ++n2) {
+      const int n = n1 + n2;
+      row = fmaf(s.coeff[n * (n + 1) / 2 + n2], pv[n2], row);
+    }
+    acc = fmaf(pu, row, acc);
+    const float next = n1 == 0 ? 1.41421356237309504880f * u * pu
+                               : fmaf((float)__builtin_sqrt(2.0 / (n1 + 1)) * u, pu,
+                                      -(float)__builtin_sqrt((double)n1 / (n1 + 1)) * pu_prev);
+    pu_prev = pu;
+    pu = next;
+  }
+  return acc * s.scale;
+}
+
+// The profiles beyond the Sersic: Gaussians, core-Sersic components and a
+// shapelet set.
+__device__ __forceinline__ float light_extra(const LightC& L, float x, float y) {
+  float acc = 0.f;
+  for (int k = 0; k < L.ng; ++k) {
+    const GaussC& c = L.g[k];
+    const float dx = x - c.cx, dy = y - c.cy;
+    const float xp = fmaf(c.cphi, dx, c.sphi * dy);
+    const float yp = fmaf(c.cphi, dy, -c.sphi * dx);
+    const float R2 = fmaf(c.q, xp * xp, c.inv_q * (yp * yp));
+    acc = fmaf(c.norm, __builtin_amdgcn_exp2f(-c.k * R2), acc);
+  }
+  for (int k = 0; k < L.ncs; ++k) {
+    const CoreC& c = L.cs[k];
+    const float dx = x - c.cx, dy = y - c.cy;
+    const float xp = fmaf(c.cphi, dx, c.sphi * dy);
+    const float yp = fmaf(c.cphi, dy, -c.sphi * dx);
+    const float R2 = fmaxf(fmaf(c.q, xp * xp, c.inv_q * (yp * yp)), c.R2_floor);
+    const float lRa = c.half_alpha * __builtin_amdgcn_logf(R2);                    // log2 R^alpha
+    const float lsum = fmaxf(lRa, c.lRb) + __builtin_amdgcn_logf(1.0f + __builtin_amdgcn_exp2f(-fabsf(lRa - c.lRb)));
+    const float inner = __builtin_amdgcn_exp2f(c.g_over_a * (lsum - lRa));
+    const float t = __builtin_amdgcn_exp2f(c.e * (lsum - c.lRe));
+    acc = fmaf(c.amp * inner, __builtin_amdgcn_exp2f(fmaf(-c.kb, t, c.kb)), acc);
+  }
+  if (L.nsh) acc += shapelet_sum(L.sh, x, y);
+  return acc;
+}
+
+__host__ __device__ __forceinline__ bool light_any(const LightC& L) { return (L.n | L.ng | L.ncs | L.nsh) != 0; }
+
+// Every light component of a list at (x, y).
+__device__ __forceinline__ float light_sum(const LightC& L, float x, float y) {
+  float acc = sersic_sum(L, x, y);
+  if (L.ng | L.ncs | L.nsh) acc += light_extra(L, x, y);
   return acc;
 }
 

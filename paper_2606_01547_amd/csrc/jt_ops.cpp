@@ -104,8 +104,8 @@ extern "C" jt_status jt_source_sb(jt_ctx* ctx, int n, const float* x, const floa
   JT_TRY(make_light(lens_light, l, "lens light"));
   if (n == 0) return JT_OK;
   if (!sb) return fail(JT_EINVAL, "source_sb: null output");
-  if (s.n > 0 && (!bx || !by)) return fail(JT_EINVAL, "source_sb: null traced coordinates");
-  if (l.n > 0 && (!x || !y)) return fail(JT_EINVAL, "source_sb: null image-plane coordinates");
+  if (light_any(s) && (!bx || !by)) return fail(JT_EINVAL, "source_sb: null traced coordinates");
+  if (light_any(l) && (!x || !y)) return fail(JT_EINVAL, "source_sb: null image-plane coordinates");
   const float* zx = bx ? bx : x;  // unused when the matching list is empty
   const float* zy = by ? by : y;
   return timed_launch(ctx, JT_K_SB, stream,
@@ -173,6 +173,8 @@ extern "C" jt_status jt_linear_amplitudes(jt_ctx* ctx, const jt_grid* grid, cons
   JT_TRY(make_light(src, s, "source"));
   JT_TRY(make_light(lens_light, l, "lens light"));
   const int n = s.n + l.n;
+  if (s.ng | s.ncs | s.nsh | l.ng | l.ncs | l.nsh)
+    return fail(JT_EUNSUPPORTED, "linear amplitudes: Sersic components only");
   if (n < 1) return fail(JT_EINVAL, "linear amplitudes: no light component");
   if (n > kMaxBasis) return fail(JT_EUNSUPPORTED, "linear amplitudes: %d components (max %d)", n, kMaxBasis);
   if (!data || !inv_var || !amps) return fail(JT_EINVAL, "linear amplitudes: null data, weights or amplitudes");

@@ -218,12 +218,25 @@ jt_status resolve_subhalos(jt_ctx* ctx, const jt_lens* lens, void* scratch, hipS
 // ---------------------------------------------------------------------------
 // light
 // ---------------------------------------------------------------------------
+namespace {
+void set_frame(double phi, double q, double cx, double cy, float& fcx, float& fcy, float& cphi, float& sphi, float& fq,
+               float& inv_q) {
+  fcx = (float)cx;
+  fcy = (float)cy;
+  cphi = (float)std::cos(phi);
+  sphi = (float)std::sin(phi);
+  fq = (float)q;
+  inv_q = (float)(1.0 / q);
+}
+}  // namespace
+
 jt_status make_light(const jt_light* light, LightC& out, const char* which) {
   std::memset(&out, 0, sizeof(out));
-  if (!light || light->n == 0) return JT_OK;
-  if (light->n < 0) return fail(JT_EINVAL, "%s: n = %d", which, light->n);
+  if (!light) return JT_OK;
+  if (light->n < 0 || light->n_gauss < 0 || light->n_core < 0)
+    return fail(JT_EINVAL, "%s: negative component count", which);
   if (light->n > JT_MAX_SERSIC) return fail(JT_EUNSUPPORTED, "%s: %d components (max %d)", which, light->n, JT_MAX_SERSIC);
-  if (!light->c) return fail(JT_EINVAL, "%s: null component array", which);
+  if (light->n > 0 && !light->c) return fail(JT_EINVAL, "%s: null component array", which);
   for (int k = 0; k < light->n; ++k) {
     const jt_sersic& c = light->c[k];
     if (!finite(c.amp) || !finite(c.R_sersic) || !finite(c.n_sersic) || !finite(c.q) || !finite(c.phi) ||
@@ -234,12 +247,7 @@ jt_status make_light(const jt_light* light, LightC& out, const char* which) {
     if (!(c.q > 0.0 && c.q <= 1.0)) return fail(JT_EINVAL, "%s[%d]: q = %g not in (0, 1]", which, k, c.q);
     const double b = light->bn_exact ? sersic_bn_exact(c.n_sersic) : 1.9992 * c.n_sersic - 0.3271;
     SersicC& o = out.c[k];
-    o.cx = (float)c.cx;
-    o.cy = (float)c.cy;
-    o.cphi = (float)std::cos(c.phi);
-    o.sphi = (float)std::sin(c.phi);
-    o.q = (float)c.q;
-    o.inv_q = (float)(1.0 / c.q);
+    set_frame(c.phi, c.q, c.cx, c.cy, o.cx, o.cy, o.cphi, o.sphi, o.q, o.inv_q);
     o.inv_r2 = (float)(1.0 / (c.R_sersic * c.R_sersic));
     o.e = (float)(0.5 / c.n_sersic);
     o.kb = (float)(b / kLn2d);
@@ -249,6 +257,68 @@ jt_status make_light(const jt_light* light, LightC& out, const char* which) {
     o.b = (float)b;
   }
   out.n = light->n;
+  // Gaussians
+  if (light->n_gauss > kMaxGauss)
+    return fail(JT_EUNSUPPORTED, "%s: %d Gaussians (max %d)", which, light->n_gauss, kMaxGauss);
+  if (light->n_gauss > 0 && !light->gauss) return fail(JT_EINVAL, "%s: null Gaussian array", which);
+  for (int k = 0; k < light->n_gauss; ++k) {
+    const jt_gaussian& c = light->gauss[k];
+    if (!finite(c.amp) || !finite(c.sigma) || !finite(c.q) || !finite(c.phi) || !finite(c.cx) || !finite(c.cy))
+      return fail(JT_EINVAL, "%s Gaussian %d: non-finite parameter", which, k);
+    if (!(c.sigma > 0.0)) return fail(JT_EINVAL, "%s Gaussian %d: sigma = %g", which, k, c.sigma);
+    if (!(c.q > 0.0 && c.q <= 1.0)) return fail(JT_EINVAL, "%s Gaussian %d: q = %g not in (0, 1]", which, k, c.q);
+    GaussC& o = out.g[k];
+    set_frame(c.phi, c.q, c.cx, c.cy, o.cx, o.cy, o.cphi, o.sphi, o.q, o.inv_q);
+    o.k = (float)(1.0 / (kLn2d * 2.0 * c.sigma * c.sigma));
+    o.norm = (float)(c.amp / (2.0 * M_PI * c.sigma * c.sigma));
+  }
+  out.ng = light->n_gauss;
+  // core-Sersic components
+  if (light->n_core > kMaxCore)
+    return fail(JT_EUNSUPPORTED, "%s: %d core-Sersic components (max %d)", which, light->n_core, kMaxCore);
+  if (light->n_core > 0 && !light->core) return fail(JT_EINVAL, "%s: null core-Sersic array", which);
+  for (int k = 0; k < light->n_core; ++k) {
+    const jt_core_sersic& c = light->core[k];
+    if (!finite(c.amp) || !finite(c.R_sersic) || !finite(c.R_b) || !finite(c.n_sersic) || !finite(c.gamma) ||
+        !finite(c.alpha) || !finite(c.q) || !finite(c.phi) || !finite(c.cx) || !finite(c.cy))
+      return fail(JT_EINVAL, "%s core-Sersic %d: non-finite parameter", which, k);
+    if (!(c.R_sersic > 0.0) || !(c.R_b > 0.0)) return fail(JT_EINVAL, "%s core-Sersic %d: radii must be > 0", which, k);
+    if (!(c.n_sersic >= 0.2 && c.n_sersic <= 10.0)) return fail(JT_EINVAL, "%s core-Sersic %d: n_sersic = %g", which, k, c.n_sersic);
+    if (!(c.gamma >= 0.0 && c.gamma < 2.0)) return fail(JT_EINVAL, "%s core-Sersic %d: gamma = %g not in [0, 2)", which, k, c.gamma);
+    if (!(c.alpha > 0.0 && c.alpha <= 20.0)) return fail(JT_EINVAL, "%s core-Sersic %d: alpha = %g not in (0, 20]", which, k, c.alpha);
+    if (!(c.q > 0.0 && c.q <= 1.0)) return fail(JT_EINVAL, "%s core-Sersic %d: q = %g not in (0, 1]", which, k, c.q);
+    const double b = light->bn_exact ? sersic_bn_exact(c.n_sersic) : 1.9992 * c.n_sersic - 0.3271;
+    CoreC& o = out.cs[k];
+    set_frame(c.phi, c.q, c.cx, c.cy, o.cx, o.cy, o.cphi, o.sphi, o.q, o.inv_q);
+    o.half_alpha = (float)(0.5 * c.alpha);
+    o.lRb = (float)(c.alpha * std::log2(c.R_b));
+    o.lRe = (float)(c.alpha * std::log2(c.R_sersic));
+    o.g_over_a = (float)(c.gamma / c.alpha);
+    o.e = (float)(1.0 / (c.n_sersic * c.alpha));
+    o.kb = (float)(b / kLn2d);
+    o.amp = (float)c.amp;
+    o.R2_floor = (float)(1e-12 * c.R_b * c.R_b);
+  }
+  out.ncs = light->n_core;
+  // shapelets
+  if (light->shapelets) {
+    const jt_shapelets& c = *light->shapelets;
+    if (c.n_max < 0 || c.n_max > kShapeletMaxN)
+      return fail(JT_EUNSUPPORTED, "%s shapelets: n_max = %d not in [0, %d]", which, c.n_max, kShapeletMaxN);
+    if (!(c.beta > 0.0) || !finite(c.beta) || !finite(c.cx) || !finite(c.cy))
+      return fail(JT_EINVAL, "%s shapelets: bad beta or centre", which);
+    if (!c.coeff) return fail(JT_EINVAL, "%s shapelets: null coefficients", which);
+    const int m = (c.n_max + 1) * (c.n_max + 2) / 2;
+    for (int i = 0; i < m; ++i)
+      if (!finite(c.coeff[i])) return fail(JT_EINVAL, "%s shapelets: non-finite coefficient %d", which, i);
+    ShapeC& o = out.sh;
+    o.cx = (float)c.cx;
+    o.cy = (float)c.cy;
+    o.inv_beta = (float)(1.0 / c.beta);
+    o.scale = (float)(1.0 / (std::sqrt(M_PI) * c.beta));
+    for (int i = 0; i < m; ++i) o.coeff[i] = (float)c.coeff[i];
+    out.nsh = 1;
+  }
   return JT_OK;
 }
 

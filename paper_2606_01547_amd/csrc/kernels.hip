@@ -91,8 +91,8 @@ __global__ __launch_bounds__(256) void k_source_sb(int n, const float* __restric
                                                   LightC ll, float* __restrict__ sb) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  float v = sersic_sum(src, bx[i], by[i]);
-  if (ll.n > 0) v += sersic_sum(ll, x[i], y[i]);
+  float v = light_sum(src, bx[i], by[i]);
+  if (light_any(ll)) v += light_sum(ll, x[i], y[i]);
   sb[i] = v;
 }
 
@@ -143,8 +143,8 @@ __device__ __forceinline__ void simulate_block(const GridC& g, const MacroC& mc,
   if (grp == 0) {
     double ax, ay;
     total_deflection64<kSplit>(mc, sp.dx, sp.dy, scratch, t, sx, sy, ax, ay);
-    float v = sersic_sum(src, (float)(sp.dx - ax), (float)(sp.dy - ay));
-    if (ll.n > 0) v += sersic_sum(ll, sp.tx, sp.ty);
+    float v = light_sum(src, (float)(sp.dx - ax), (float)(sp.dy - ay));
+    if (light_any(ll)) v += light_sum(ll, sp.tx, sp.ty);
     red[t] = v;
   }
   __syncthreads();

@@ -66,7 +66,10 @@ int main(void) {
   O(jt_lens, has_epl); O(jt_lens, epl);
   P(jt_request); O(jt_request, sie); O(jt_request, subhalo_handle); O(jt_request, src); O(jt_request, lens_light);
   O(jt_request, psf_handle); O(jt_request, out); O(jt_request, has_epl); O(jt_request, epl);
-  P(jt_sersic); P(jt_light); O(jt_light, c); O(jt_light, bn_exact);
+  P(jt_sersic); P(jt_light); O(jt_light, c); O(jt_light, bn_exact); O(jt_light, n_gauss); O(jt_light, gauss);
+  O(jt_light, n_core); O(jt_light, core); O(jt_light, shapelets);
+  P(jt_gaussian); P(jt_core_sersic); O(jt_core_sersic, alpha); P(jt_shapelets); O(jt_shapelets, beta);
+  O(jt_shapelets, coeff);
   P(jt_draws); O(jt_draws, sie); O(jt_draws, n_sub); O(jt_draws, sub_alpha_Rs); O(jt_draws, n_ll); O(jt_draws, ll);
   P(jt_server_stats); O(jt_server_stats, device_seconds); O(jt_server_stats, max_wait_seconds);
   P(jt_fit_problem); O(jt_fit_problem, lower); O(jt_fit_problem, n_sub); O(jt_fit_problem, sub_alpha_Rs);
@@ -90,7 +93,8 @@ def test_ctypes_structs_match_c_layout(tmp_path):
          "jt_point_masses": nat.JtPointMasses, "jt_lens": nat.JtLens, "jt_sersic": nat.JtSersic,
          "jt_light": nat.JtLight, "jt_draws": nat.JtDraws, "jt_server_stats": nat.JtServerStats,
          "jt_epl": nat.JtEpl, "jt_request": nat.JtRequest, "jt_fit_problem": nat.JtFitProblem,
-         "jt_pso_cfg": nat.JtPsoCfg, "jt_lbfgs_cfg": nat.JtLbfgsCfg}
+         "jt_pso_cfg": nat.JtPsoCfg, "jt_lbfgs_cfg": nat.JtLbfgsCfg, "jt_gaussian": nat.JtGaussian,
+         "jt_core_sersic": nat.JtCoreSersic, "jt_shapelets": nat.JtShapelets}
     for key, val in got.items():
         if "." in key:
             t, f = key.split(".")
