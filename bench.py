@@ -347,6 +347,21 @@ def profiles_bench(ctx, reps=20):
     for name, lens in cases.items():
         per, _ = _kernel_ms(ctx, lambda: ctx.deflection(x, y, lens, out=(ox, oy)), ("ray",), reps)
         table[name] = round(1e3 * per["ray"], 2)
+    gs = [W.Gaussian(1.0 + k, 0.1 + 0.05 * k, 1.0, 0.0, 0.0, 0.0) for k in range(5)]
+    ge = [W.Gaussian(1.0 + k, 0.1 + 0.05 * k, 0.7, 0.4, 0.0, 0.0) for k in range(5)]
+    coef = lambda n: rng.normal(0, 1, (n + 1) * (n + 2) // 2)
+    lights = {
+        "GAUSSIAN": [gs[0]], "GAUSSIAN_ELLIPSE": [ge[0]], "MULTI_GAUSSIAN (5)": gs, "MULTI_GAUSSIAN_ELLIPSE (5)": ge,
+        "SERSIC": [W.Sersic(1.0, 0.5, 3.0, 1.0, 0.0, 0.0, 0.0)], "SERSIC_ELLIPSE": [W.Sersic(1.0, 0.5, 3.0, 0.7, 0.4, 0.0, 0.0)],
+        "CORE_SERSIC": [W.CoreSersic(1.0, 0.5, 0.05, 3.0, 0.3, 3.0, 0.7, 0.4, 0.0, 0.0)],
+        "SHAPELETS (n_max=6)": [W.Shapelets(6, 0.2, 0.0, 0.0, coef(6))],
+        "SHAPELETS (n_max=10)": [W.Shapelets(10, 0.2, 0.0, 0.0, coef(10))],
+    }
+    sb = torch.empty_like(x)
+    light = {}
+    for name, comps in lights.items():
+        per, _ = _kernel_ms(ctx, lambda: ctx.source_sb(x, y, x, y, comps, [], out=sb), ("sb",), reps)
+        light[name] = round(1e3 * per["sb"], 2)
     images = {}
     for name, sc in (("EPL main deflector", W.epl_scene()), ("TNFW subhalos", W.tnfw_scene())):
         gr = sc.grid
@@ -363,7 +378,7 @@ def profiles_bench(ctx, reps=20):
         images[name] = {"images_per_s": round(1.0 / wall, 2), "simulate_ms": round(per["sim"], 4),
                         "convolve_ms": round(per["conv"], 4), "prep_ms": round(per["prep"], 4),
                         "pairs_per_s": round(pairs / (1e-3 * per["sim"]), 1)}
-    return {"deflection_180x180_us": table,
+    return {"deflection_180x180_us": table, "light_180x180_us": light,
             "deflection_workload": "32,400 points of a 180x180 grid at 0.05\"/px; one deflector of each profile",
             "images": images,
             "images_workload": ("200x200 px, s = 3, shear + 10,000 subhalos, 1 lens-light + 2 source Sersic, "
