@@ -533,11 +533,15 @@ __device__ __forceinline__ float light_extra(const LightC& L, float x, float y) 
 }
 
 __host__ __device__ __forceinline__ bool light_any(const LightC& L) { return (L.n | L.ng | L.ncs | L.nsh) != 0; }
+__host__ __device__ __forceinline__ bool light_has_extra(const LightC& L) { return (L.ng | L.ncs | L.nsh) != 0; }
 
-// Every light component of a list at (x, y).
+// Every light component of a list at (x, y).  Kernels instantiated with
+// kExtra = false see Sersic components only: the extra profiles' code (and
+// the scalar registers its constants take) stays out of them.
+template <bool kExtra = true>
 __device__ __forceinline__ float light_sum(const LightC& L, float x, float y) {
   float acc = sersic_sum(L, x, y);
-  if (L.ng | L.ncs | L.nsh) acc += light_extra(L, x, y);
+  if (kExtra && light_has_extra(L)) acc += light_extra(L, x, y);
   return acc;
 }
 

@@ -237,9 +237,11 @@ jt_status jt_server::launch_hip(Batch& b) {
   size_t img_total = 0;
   for (Req* r : order) img_total += r->k ? a256(4 * (size_t)r->g.nx * r->g.ny) : 0;
   size_t ntiles = 0, nctiles = 0, ncon = 0;
+  bool extra = false;
   for (Req* r : order) {
     const int ppb = split_lanes(split) / r->g.s2;
     ntiles += ((long)r->g.nx * r->g.ny + ppb - 1) / ppb;
+    extra = extra || light_has_extra(r->src) || light_has_extra(r->ll);
     if (r->k) {
       nctiles += (size_t)conv_tiles_x(r->g.nx) * conv_tiles_y(r->g.ny);
       ++ncon;
@@ -283,7 +285,7 @@ jt_status jt_server::launch_hip(Batch& b) {
   if (nctiles) std::memcpy(host.data() + o_ct, ctiles.data(), sizeof(int4) * nctiles);
   JT_TRY(upload(b, host.data(), o_img, base, s));
   JT_TRY(timed_launch(ctx, JT_K_SIM, s, [&] {
-    return launch_simulate_desc(split, (const ImageDesc*)base, (const int2*)(base + o_t), (int)ntiles, 0, s);
+    return launch_simulate_desc(split, extra, (const ImageDesc*)base, (const int2*)(base + o_t), (int)ntiles, 0, s);
   }, "server simulate"));
   if (ncon)
     JT_TRY(timed_launch(ctx, JT_K_CONV, s, [&] {
@@ -315,7 +317,8 @@ jt_status jt_server::launch_chunk_hip(Batch& b) {
   for (int i = 0; i < nt; ++i) tl[i] = make_int2(0, b.blk0 + i);
   JT_TRY(upload(b, host.data(), end, base, s));
   JT_TRY(timed_launch(ctx, JT_K_SIM, s, [&] {
-    return launch_simulate_desc(r->split, (const ImageDesc*)base, (const int2*)(base + o_t), nt, 0, s);
+    return launch_simulate_desc(r->split, light_has_extra(r->src) || light_has_extra(r->ll), (const ImageDesc*)base,
+                                (const int2*)(base + o_t), nt, 0, s);
   }, "server simulate chunk"));
   return check_hip(hipEventRecord(b.ev, s), "hipEventRecord(batch)");
 }

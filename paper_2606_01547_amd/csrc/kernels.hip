@@ -128,7 +128,7 @@ __device__ __forceinline__ SubPixel subpixel_of(const GridC& g, int block, int t
 // image.  The kSplit wave-groups share the subhalo quarters of the same
 // slots; group 0 combines them, evaluates the light, and the pixel values are
 // reduced through LDS in a fixed order.
-template <int kSplit, class P = NfwPairs>
+template <int kSplit, class P = NfwPairs, bool kExtra = false>
 __device__ __forceinline__ void simulate_block(const GridC& g, const MacroC& mc, const void* __restrict__ sub,
                                                int nloop, const LightC& src, const LightC& ll,
                                                float* __restrict__ img, int block,
@@ -143,8 +143,8 @@ __device__ __forceinline__ void simulate_block(const GridC& g, const MacroC& mc,
   if (grp == 0) {
     double ax, ay;
     total_deflection64<kSplit>(mc, sp.dx, sp.dy, scratch, t, sx, sy, ax, ay);
-    float v = light_sum(src, (float)(sp.dx - ax), (float)(sp.dy - ay));
-    if (light_any(ll)) v += light_sum(ll, sp.tx, sp.ty);
+    float v = light_sum<kExtra>(src, (float)(sp.dx - ax), (float)(sp.dy - ay));
+    if (light_any(ll)) v += light_sum<kExtra>(ll, sp.tx, sp.ty);
     red[t] = v;
   }
   __syncthreads();
@@ -159,13 +159,13 @@ __device__ __forceinline__ void simulate_block(const GridC& g, const MacroC& mc,
   }
 }
 
-template <int kSplit, class P>
+template <int kSplit, class P, bool kExtra>
 __global__ __launch_bounds__(split_threads(kSplit)) void k_simulate(GridC g, MacroC mc, const void* __restrict__ sub,
                                                                    int nloop, LightC src, LightC ll,
                                                                    float* __restrict__ img) {
   __shared__ RangeScratch<kSplit> scratch;
   __shared__ float red[split_lanes(kSplit)];
-  simulate_block<kSplit, P>(g, mc, sub, nloop, src, ll, img, blockIdx.x, scratch, red);
+  simulate_block<kSplit, P, kExtra>(g, mc, sub, nloop, src, ll, img, blockIdx.x, scratch, red);
 }
 
 // Basis images of the linear amplitude solver: the deflection of each
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(split_threads(kSplit)) void k_simulate_basis(GridC 
 // Batched images: block b works on image descs[b / blocks_per_image] when
 // every image has the same grid (tiles == nullptr), otherwise on the
 // (image, pixel block) pair tiles[b].
-template <int kSplit>
+template <int kSplit, bool kExtra>
 __global__ __launch_bounds__(split_threads(kSplit)) void k_simulate_desc(const ImageDesc* __restrict__ descs,
                                                                         const int2* __restrict__ tiles,
                                                                         int blocks_per_image) {
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(split_threads(kSplit)) void k_simulate_desc(const I
     blk = blockIdx.x - di * blocks_per_image;
   }
   const ImageDesc& d = descs[di];
-  simulate_block<kSplit>(d.g, d.mc, d.sub, d.nloop, d.src, d.ll, d.img, blk, scratch, red);
+  simulate_block<kSplit, NfwPairs, kExtra>(d.g, d.mc, d.sub, d.nloop, d.src, d.ll, d.img, blk, scratch, red);
 }
 
 // Direct convolution tiles: 64 x 4 outputs per block of kW waves.  Thread
@@ -395,11 +395,11 @@ void ray_shoot_on(bool alpha, int split, dim3 grid, int n, const float* x, const
 #undef JT_RAY
 }
 
-template <class P>
+template <class P, bool kExtra>
 void simulate_on(int split, unsigned blocks, const GridC& g, const MacroC& mc, const void* sub, int nloop,
                  const LightC& src, const LightC& ll, float* img, hipStream_t st) {
-#define JT_SIM(S) hipLaunchKernelGGL((k_simulate<S, P>), dim3(blocks), dim3(split_threads(S)), 0, st, g, mc, sub, \
-                                     nloop, src, ll, img)
+#define JT_SIM(S) hipLaunchKernelGGL((k_simulate<S, P, kExtra>), dim3(blocks), dim3(split_threads(S)), 0, st, g, mc, \
+                                     sub, nloop, src, ll, img)
   if (split == 1) JT_SIM(1); else if (split == 2) JT_SIM(2); else if (split == 4) JT_SIM(4); else JT_SIM(8);
 #undef JT_SIM
 }
@@ -431,10 +431,15 @@ hipError_t launch_simulate(GridC g, const MacroC& mc, bool tnfw, const void* sub
   const int split = pick_split(npix * g.s2, g.s2, nloop);
   g.ppb = split_lanes(split) / g.s2;
   const long blocks = (npix + g.ppb - 1) / g.ppb;
-  if (tnfw)
-    simulate_on<TnfwPairs>(split, (unsigned)blocks, g, mc, sub, nloop, src, ll, img, st);
+  const bool extra = light_has_extra(src) || light_has_extra(ll);
+  if (tnfw && extra)
+    simulate_on<TnfwPairs, true>(split, (unsigned)blocks, g, mc, sub, nloop, src, ll, img, st);
+  else if (tnfw)
+    simulate_on<TnfwPairs, false>(split, (unsigned)blocks, g, mc, sub, nloop, src, ll, img, st);
+  else if (extra)
+    simulate_on<NfwPairs, true>(split, (unsigned)blocks, g, mc, sub, nloop, src, ll, img, st);
   else
-    simulate_on<NfwPairs>(split, (unsigned)blocks, g, mc, sub, nloop, src, ll, img, st);
+    simulate_on<NfwPairs, false>(split, (unsigned)blocks, g, mc, sub, nloop, src, ll, img, st);
   return hipGetLastError();
 }
 
@@ -499,12 +504,18 @@ hipError_t launch_conv_desc(const ConvDesc* descs, const int4* tiles, int ntiles
 int conv_tiles_x(int nx) { return (nx + kConvTX - 1) / kConvTX; }
 int conv_tiles_y(int ny) { return (ny + kConvTY - 1) / kConvTY; }
 
-hipError_t launch_simulate_desc(int split, const ImageDesc* descs, const int2* tiles, int nblocks,
+hipError_t launch_simulate_desc(int split, bool extra, const ImageDesc* descs, const int2* tiles, int nblocks,
                                 int blocks_per_image, hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
-#define JT_SIMD(S) hipLaunchKernelGGL((k_simulate_desc<S>), dim3((unsigned)nblocks), dim3(split_threads(S)), 0, st, \
-                                      descs, tiles, blocks_per_image)
-  if (split == 1) JT_SIMD(1); else if (split == 2) JT_SIMD(2); else if (split == 4) JT_SIMD(4); else JT_SIMD(8);
+#define JT_SIMD(S, E) hipLaunchKernelGGL((k_simulate_desc<S, E>), dim3((unsigned)nblocks), dim3(split_threads(S)), 0, \
+                                         st, descs, tiles, blocks_per_image)
+  if (extra) {
+    if (split == 1) JT_SIMD(1, true); else if (split == 2) JT_SIMD(2, true); else if (split == 4) JT_SIMD(4, true);
+    else JT_SIMD(8, true);
+  } else {
+    if (split == 1) JT_SIMD(1, false); else if (split == 2) JT_SIMD(2, false); else if (split == 4) JT_SIMD(4, false);
+    else JT_SIMD(8, false);
+  }
 #undef JT_SIMD
   return hipGetLastError();
 }
