@@ -472,6 +472,24 @@ def test_simulate_headline_full_size_sampled(ctx):
     assert image_error(full, O.convolve_same(un, sc.psf)) <= 2e-5
 
 
+@pytest.mark.parametrize("make", [W.epl_scene, W.tnfw_scene], ids=["epl", "tnfw"])
+def test_profile_scenes_full_size_sampled(ctx, make):
+    """The bench's EPL and truncated-subhalo images (200x200 px, s = 3, 10,000
+    subhalos, 41x41 PSF) in the bench's launch, on sampled pixels."""
+    sc = make()
+    un = _np(ctx.simulate_scene(sc, psf=False))
+    rng = np.random.default_rng(3)
+    rows = rng.integers(0, 200, 160)
+    cols = rng.integers(0, 200, 160)
+    flat = np.argsort(un.reshape(-1))[-30:]
+    rows = np.concatenate([rows, flat // 200])
+    cols = np.concatenate([cols, flat % 200])
+    ref = _oracle_pixels(sc, rows, cols)
+    floor = 1e-3 * np.abs(un).max()
+    err = np.max(np.abs(un[rows, cols] - ref) / np.maximum(np.abs(ref), floor))
+    assert err <= IMAGE_TOL
+
+
 def _oracle_pixels_direct(sc, rows, cols):
     """Sampled pixels of a large grid without forming its whole sub-pixel
     array: pixel (i, j) is the 1 x 1 grid centred on that pixel."""
