@@ -313,18 +313,15 @@ __device__ __forceinline__ void nfw_h_dh_near(float X2, float& h, float& dh) {
   }
 }
 
-__device__ __forceinline__ void nfw_h_dh(float X2, float& h, float& dh) {
+// Far field (X2 >= 1.2) from l2 = log2(X2), y2 = 1/X2, the fitted
+// polynomial p = P(y) (psi = (ln2/2)(1 - kLog2Bias) P, F = psi + ln 2) and
+// inv = 1/(X2 - 1): h = (l2 + p) y2, dh/d(X2) = ((1 - F)/(2 (X2 - 1)) - h) y2.
+__device__ __forceinline__ void nfw_h_dh_far(float l2, float y2, float p, float inv, float& h, float& dh) {
   constexpr float kA1 = (float)(0.5 * kLn2d * (1.0 - kLog2Bias));   // psi = kA1 * P
   constexpr float kInv2U = (float)(0.5 / kNfwRecScale);
-  const float y = __builtin_amdgcn_rsqf(X2);
-  const float l2 = __builtin_amdgcn_logf(X2);
-  float p = kNfwP[0];
-#pragma unroll
-  for (int i = 1; i <= JT_NFW_POLY_DEGREE; ++i) p = fmaf(p, y, kNfwP[i]);
-  const float y2 = y * y;
   h = (l2 + p) * y2;
   const float oneF = fmaf(-kA1, p, (float)(1.0 - kLn2d));           // 1 - F
-  dh = fmaf(oneF * kInv2U, __builtin_amdgcn_rcpf(X2 - 1.0f), -h) * y2;
+  dh = fmaf(oneF * kInv2U, inv, -h) * y2;
 }
 
 // grid (ceil(n / 64), B, kRecParts); lane = subhalo.  Writes the part
@@ -338,6 +335,7 @@ __global__ __launch_bounds__(64) void k_grad_subhalo(const ImageDesc* __restrict
   const SubRec s = descs[b].sub[valid ? k : 0];
   // alpha / alpha_Rs = c2n * h * d  (h in units of ln2/2)
   const float c2n = sqrtf(s.c1) * (float)(kNfwRecScale / (1.0 - kLn2d));
+  const float c1x2 = 2.0f * s.c1;
   const float4* __restrict__ r = rec + (size_t)b * rec_stride;
   const int kb = part_bound(nrec_loop, kRecParts, q), ke = part_bound(nrec_loop, kRecParts, q + 1);
   float hx = 0.f, lx = 0.f, hy = 0.f, ly = 0.f, ha = 0.f, la = 0.f;
@@ -351,26 +349,41 @@ __global__ __launch_bounds__(64) void k_grad_subhalo(const ImageDesc* __restrict
       n1 = r[j + 5];
       n2 = r[j + 6];
       n3 = r[j + 7];
-      float dx[4], dy[4], X[4], h[4], dh[4];
+      float dx[4], dy[4], X[4], y[4], l2[4], y2[4], p[4], inv[4], h[4], dh[4];
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         dx[m] = rr[m].x - s.x;
         dy[m] = rr[m].y - s.y;
         X[m] = fmaf(dy[m], dy[m], dx[m] * dx[m]) * s.c1;
-        nfw_h_dh(X[m], h[m], dh[m]);
+        y[m] = __builtin_amdgcn_rsqf(X[m]);
+        l2[m] = __builtin_amdgcn_logf(X[m]);
+        y2[m] = y[m] * y[m];
       }
+      // lanes are different subhalos, so a wave seldom agrees on the short
+      // far-field form: one polynomial for every pair keeps the wave coherent
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        float q = kNfwP[0];
+#pragma unroll
+        for (int i = 1; i <= JT_NFW_POLY_DEGREE; ++i) q = fmaf(q, y[m], kNfwP[i]);
+        p[m] = q;
+        inv[m] = __builtin_amdgcn_rcpf(X[m] - 1.0f);
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) nfw_h_dh_far(l2[m], y2[m], p[m], inv[m], h[m], dh[m]);
       if (__builtin_expect(fminf(fminf(X[0], X[1]), fminf(X[2], X[3])) < 1.2f, 0)) {
 #pragma unroll
         for (int m = 0; m < 4; ++m)
           if (X[m] < 1.2f) nfw_h_dh_near(X[m], h[m], dh[m]);
       }
+      // c2, -c2n and the 2 c1 of e are applied once per subhalo below
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const float GD = fmaf(rr[m].z, dx[m], rr[m].w * dy[m]);
-        const float e = 2.0f * s.c1 * dh[m] * GD;
-        px = fmaf(s.c2, fmaf(h[m], rr[m].z, e * dx[m]), px);
-        py = fmaf(s.c2, fmaf(h[m], rr[m].w, e * dy[m]), py);
-        pa = fmaf(-c2n, h[m] * GD, pa);
+        const float e = c1x2 * dh[m] * GD;
+        px = fmaf(e, dx[m], fmaf(h[m], rr[m].z, px));
+        py = fmaf(e, dy[m], fmaf(h[m], rr[m].w, py));
+        pa = fmaf(h[m], GD, pa);
       }
     }
     two_sum_acc(hx, lx, px);
@@ -379,9 +392,9 @@ __global__ __launch_bounds__(64) void k_grad_subhalo(const ImageDesc* __restrict
   }
   if (valid) {
     float* o = gpart + (((size_t)q * B + b) * n + k) * 3;
-    o[0] = hx + lx;
-    o[1] = hy + ly;
-    o[2] = ha + la;
+    o[0] = s.c2 * (hx + lx);
+    o[1] = s.c2 * (hy + ly);
+    o[2] = -c2n * (ha + la);
   }
 }
 
