@@ -6,9 +6,10 @@
 // Reverse pass, per parameter draw:
 //   r = -w (m - d)                         k_residual (+ log L block partials)
 //   lambda_U = K correlated with r         k_conv_direct<flip>
-//   lambda   = lambda_U * d^2 / s^2 per sub-pixel; beta is recomputed (never
-//   stored by the forward), G = lambda * dI/dbeta; Sersic, SIE and shear
-//   parameter partials are reduced per block          k_grad_pixel
+//   lambda   = lambda_U * d^2 / s^2 per sub-pixel; beta is the forward
+//   launch's own traced position (kept, 8 bytes per sub-pixel), G = lambda *
+//   dI/dbeta; Sersic, SIE and shear parameter partials are reduced per
+//   block                                             k_grad_pixel
 //   subhalo (x, y, alpha_Rs) gradients: a subhalo-major pass over the
 //   sub-pixel records (theta, G)                      k_grad_subhalo
 //   fixed-order sums of the partials                  k_grad_finalize
@@ -168,7 +169,6 @@ __global__ __launch_bounds__(split_threads(kSplit)) void k_grad_pixel(const Imag
                                                                      const float* __restrict__ lamU,
                                                                      float4* __restrict__ rec, int rec_stride,
                                                                      float* __restrict__ part, int P) {
-  __shared__ RangeScratch<kSplit> scratch;
   __shared__ float wsum[4][kGradMaxP];
   constexpr int kW = split_lanes(kSplit);
   const int di = blockIdx.x / bpi;
@@ -188,16 +188,13 @@ __global__ __launch_bounds__(split_threads(kSplit)) void k_grad_pixel(const Imag
   const double tx64 = g.ox + g.step * ((double)(col * g.s + b) + 0.5);
   const double ty64 = g.oy + g.step * ((double)(row * g.s + a) + 0.5);
   const float tx = (float)tx64, ty = (float)ty64;
-  double sx = 0.0, sy = 0.0;
-  subhalo_ranges<kSplit>(tx, ty, d.sub, d.nloop, grp, t, scratch, sx, sy);
-  __syncthreads();
   float c[kGradMaxP];
 #pragma unroll
   for (int i = 0; i < kGradMaxP; ++i) c[i] = 0.f;
   if (grp == 0) {
-    double ax, ay;
-    total_deflection64<kSplit>(d.mc, tx64, ty64, scratch, t, sx, sy, ax, ay);
-    const float bx = (float)(tx64 - ax), by = (float)(ty64 - ay);
+    // the traced position the forward launch kept for this sub-pixel
+    const float2 bb = d.beta[(size_t)pp * g.s2 + si];
+    const float bx = bb.x, by = bb.y;
     const float lam = valid ? lamU[(size_t)di * npix + pp] * g.area_over_s2 : 0.f;
     float Gx = 0.f, Gy = 0.f, dd[7], gx, gy;
     const int ns = d.src.n, nl = d.ll.n;

@@ -144,6 +144,7 @@ struct ImageDesc {
   const SubRec* sub;     // subhalo_table_records(n) records
   int nloop;             // loop count (multiple of 4)
   float* img;            // unconvolved image [ny][nx]
+  float2* beta;          // traced sub-pixel positions [ny * nx][s^2] kept for the adjoint, or null
 };
 
 // One convolution of a heterogeneous batch: out = psf * img ([ny][nx], odd k).

@@ -86,10 +86,11 @@ jt_status make_batch(const jt_grid* grid, const jt_draws* d, bool for_grad, Batc
 // device pointers of the descriptors from the carved workspace and uploads
 // them.  model_u / model: [B][npix].
 jt_status run_forward(jt_ctx* ctx, Batch& bt, const jt_draws* d, const float* psf, int k, SubRec* tables,
-                      ImageDesc* ddescs, float* model_u, float* model, hipStream_t st) {
+                      ImageDesc* ddescs, float* model_u, float* model, hipStream_t st, float2* beta = nullptr) {
   for (int b = 0; b < bt.B; ++b) {
     bt.descs[b].sub = bt.n > 0 ? tables + (size_t)b * bt.records : ctx_empty_table(ctx);
     bt.descs[b].img = model_u + (size_t)b * bt.npix;
+    bt.descs[b].beta = beta ? beta + (size_t)b * bt.nsubpix : nullptr;
   }
   JT_TRY(ctx_upload(ctx, st, ddescs, bt.descs.data(), sizeof(ImageDesc) * bt.B));
   if (bt.n > 0)
@@ -97,7 +98,7 @@ jt_status run_forward(jt_ctx* ctx, Batch& bt, const jt_draws* d, const float* ps
       return launch_prep_subhalos_batched(bt.B, bt.n, d->sub_x, d->sub_y, d->sub_Rs, d->sub_alpha_Rs, tables, st);
     }, "prep_subhalos_batched"));
   JT_TRY(timed_launch(ctx, JT_K_SIM, st, [&] {
-    return launch_simulate_desc(bt.split, false, ddescs, nullptr, bt.B * bt.bpi, bt.bpi, st);
+    return launch_simulate_desc(bt.split, false, beta != nullptr, ddescs, nullptr, bt.B * bt.bpi, bt.bpi, st);
   }, "simulate_batch"));
   if (psf && model != model_u)
     JT_TRY(timed_launch(ctx, JT_K_CONV, st, [&] {
@@ -155,7 +156,8 @@ jt_status chi2_common(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, c
   if (grad)
     bytes += align256(sizeof(float) * BN) + align256(sizeof(float4) * (size_t)bt.B * rec_stride) +
              align256(sizeof(float) * (size_t)bt.B * bt.bpi * bt.P) +
-             align256(sizeof(float) * (size_t)kRecPartsHost * bt.B * bt.n * 3);
+             align256(sizeof(float) * (size_t)kRecPartsHost * bt.B * bt.n * 3) +
+             align256(sizeof(float2) * (size_t)bt.B * bt.nsubpix);
   void* ws = nullptr;
   JT_TRY(ctx_workspace(ctx, st, bytes, &ws));
   Carve cv{(char*)ws};
@@ -165,7 +167,9 @@ jt_status chi2_common(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, c
   float* model = psf ? cv.take<float>(BN) : mu;
   float* resid = cv.take<float>(BN);
   float* lpart = cv.take<float>((size_t)bt.B * nres);
-  JT_TRY(run_forward(ctx, bt, draws, psf, k, tables, dd, mu, model, st));
+  // the gradient keeps the forward's traced positions instead of recomputing them
+  float2* beta = grad ? cv.take<float2>((size_t)bt.B * bt.nsubpix) : nullptr;
+  JT_TRY(run_forward(ctx, bt, draws, psf, k, tables, dd, mu, model, st, beta));
   int nb = 0;
   JT_TRY(timed_launch(ctx, JT_K_GRAD, st, [&] {
     return launch_residual(bt.B, bt.npix, model, data, inv_var, resid, lpart, &nb, st);

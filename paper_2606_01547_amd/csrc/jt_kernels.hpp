@@ -52,7 +52,8 @@ hipError_t launch_conv_desc(const ConvDesc* descs, const int4* tiles, int ntiles
 int conv_tiles_x(int nx);
 int conv_tiles_y(int ny);
 // Batched fused simulation over image descriptors (see k_simulate_desc).
-hipError_t launch_simulate_desc(int split, bool extra, const ImageDesc* descs, const int2* tiles, int nblocks,
+hipError_t launch_simulate_desc(int split, bool extra, bool keep_beta, const ImageDesc* descs, const int2* tiles,
+                                int nblocks,
                                 int blocks_per_image, hipStream_t st);
 // Per-draw subhalo tables from [B][n] SoA into B tables of
 // subhalo_table_records(n) records.

@@ -285,7 +285,8 @@ jt_status jt_server::launch_hip(Batch& b) {
   if (nctiles) std::memcpy(host.data() + o_ct, ctiles.data(), sizeof(int4) * nctiles);
   JT_TRY(upload(b, host.data(), o_img, base, s));
   JT_TRY(timed_launch(ctx, JT_K_SIM, s, [&] {
-    return launch_simulate_desc(split, extra, (const ImageDesc*)base, (const int2*)(base + o_t), (int)ntiles, 0, s);
+    return launch_simulate_desc(split, extra, false, (const ImageDesc*)base, (const int2*)(base + o_t), (int)ntiles,
+                                0, s);
   }, "server simulate"));
   if (ncon)
     JT_TRY(timed_launch(ctx, JT_K_CONV, s, [&] {
@@ -317,7 +318,7 @@ jt_status jt_server::launch_chunk_hip(Batch& b) {
   for (int i = 0; i < nt; ++i) tl[i] = make_int2(0, b.blk0 + i);
   JT_TRY(upload(b, host.data(), end, base, s));
   JT_TRY(timed_launch(ctx, JT_K_SIM, s, [&] {
-    return launch_simulate_desc(r->split, light_has_extra(r->src) || light_has_extra(r->ll), (const ImageDesc*)base,
+    return launch_simulate_desc(r->split, light_has_extra(r->src) || light_has_extra(r->ll), false, (const ImageDesc*)base,
                                 (const int2*)(base + o_t), nt, 0, s);
   }, "server simulate chunk"));
   return check_hip(hipEventRecord(b.ev, s), "hipEventRecord(batch)");

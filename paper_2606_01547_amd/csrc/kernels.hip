@@ -100,6 +100,7 @@ __global__ __launch_bounds__(256) void k_source_sb(int n, const float* __restric
 // sub-pixel (t mod s^2) of local pixel (t / s^2) of the block's g.ppb pixels.
 struct SubPixel {
   int pixel;             // global pixel index (0 when invalid)
+  int sub;               // sub-pixel index in the pixel, a * s + b
   bool valid;
   double dx, dy;         // sub-pixel centre (FP64)
   float tx, ty;          // its correctly rounded FP32 value (pair loop, lens light)
@@ -113,6 +114,7 @@ __device__ __forceinline__ SubPixel subpixel_of(const GridC& g, int block, int t
   const int p = block * g.ppb + lp;
   sp.valid = (lp < g.ppb) && (p < npix);
   sp.pixel = sp.valid ? p : 0;
+  sp.sub = si;
   const int row = sp.pixel / g.nx;
   const int col = sp.pixel - row * g.nx;
   const int a = si / g.s;
@@ -128,11 +130,12 @@ __device__ __forceinline__ SubPixel subpixel_of(const GridC& g, int block, int t
 // image.  The kSplit wave-groups share the subhalo quarters of the same
 // slots; group 0 combines them, evaluates the light, and the pixel values are
 // reduced through LDS in a fixed order.
-template <int kSplit, class P = NfwPairs, bool kExtra = false>
+template <int kSplit, class P = NfwPairs, bool kExtra = false, bool kKeepBeta = false>
 __device__ __forceinline__ void simulate_block(const GridC& g, const MacroC& mc, const void* __restrict__ sub,
                                                int nloop, const LightC& src, const LightC& ll,
                                                float* __restrict__ img, int block,
-                                               RangeScratch<kSplit>& scratch, float* red) {
+                                               RangeScratch<kSplit>& scratch, float* red,
+                                               float2* __restrict__ beta = nullptr) {
   constexpr int kW = split_lanes(kSplit);
   const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / kW);  // wave-uniform (kW % 64 == 0)
   const int t = threadIdx.x - grp * kW;
@@ -143,7 +146,10 @@ __device__ __forceinline__ void simulate_block(const GridC& g, const MacroC& mc,
   if (grp == 0) {
     double ax, ay;
     total_deflection64<kSplit>(mc, sp.dx, sp.dy, scratch, t, sx, sy, ax, ay);
-    float v = light_sum<kExtra>(src, (float)(sp.dx - ax), (float)(sp.dy - ay));
+    const float bx = (float)(sp.dx - ax), by = (float)(sp.dy - ay);
+    // the traced position, kept for the adjoint: [pixel][sub-pixel]
+    if (kKeepBeta && sp.valid) beta[(long)sp.pixel * g.s2 + sp.sub] = make_float2(bx, by);
+    float v = light_sum<kExtra>(src, bx, by);
     if (light_any(ll)) v += light_sum<kExtra>(ll, sp.tx, sp.ty);
     red[t] = v;
   }
@@ -212,7 +218,7 @@ __global__ __launch_bounds__(split_threads(kSplit)) void k_simulate_basis(GridC 
 // Batched images: block b works on image descs[b / blocks_per_image] when
 // every image has the same grid (tiles == nullptr), otherwise on the
 // (image, pixel block) pair tiles[b].
-template <int kSplit, bool kExtra>
+template <int kSplit, bool kExtra, bool kKeepBeta>
 __global__ __launch_bounds__(split_threads(kSplit)) void k_simulate_desc(const ImageDesc* __restrict__ descs,
                                                                         const int2* __restrict__ tiles,
                                                                         int blocks_per_image) {
@@ -228,7 +234,8 @@ __global__ __launch_bounds__(split_threads(kSplit)) void k_simulate_desc(const I
     blk = blockIdx.x - di * blocks_per_image;
   }
   const ImageDesc& d = descs[di];
-  simulate_block<kSplit, NfwPairs, kExtra>(d.g, d.mc, d.sub, d.nloop, d.src, d.ll, d.img, blk, scratch, red);
+  simulate_block<kSplit, NfwPairs, kExtra, kKeepBeta>(d.g, d.mc, d.sub, d.nloop, d.src, d.ll, d.img, blk, scratch,
+                                                      red, d.beta);
 }
 
 // Direct convolution tiles: 64 x 4 outputs per block of kW waves.  Thread
@@ -504,18 +511,22 @@ hipError_t launch_conv_desc(const ConvDesc* descs, const int4* tiles, int ntiles
 int conv_tiles_x(int nx) { return (nx + kConvTX - 1) / kConvTX; }
 int conv_tiles_y(int ny) { return (ny + kConvTY - 1) / kConvTY; }
 
-hipError_t launch_simulate_desc(int split, bool extra, const ImageDesc* descs, const int2* tiles, int nblocks,
-                                int blocks_per_image, hipStream_t st) {
+hipError_t launch_simulate_desc(int split, bool extra, bool keep_beta, const ImageDesc* descs, const int2* tiles,
+                                int nblocks, int blocks_per_image, hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
-#define JT_SIMD(S, E) hipLaunchKernelGGL((k_simulate_desc<S, E>), dim3((unsigned)nblocks), dim3(split_threads(S)), 0, \
-                                         st, descs, tiles, blocks_per_image)
-  if (extra) {
-    if (split == 1) JT_SIMD(1, true); else if (split == 2) JT_SIMD(2, true); else if (split == 4) JT_SIMD(4, true);
-    else JT_SIMD(8, true);
+#define JT_SIMD(S, E, K) hipLaunchKernelGGL((k_simulate_desc<S, E, K>), dim3((unsigned)nblocks), \
+                                            dim3(split_threads(S)), 0, st, descs, tiles, blocks_per_image)
+#define JT_SIMD_S(E, K) \
+  if (split == 1) JT_SIMD(1, E, K); else if (split == 2) JT_SIMD(2, E, K); else if (split == 4) JT_SIMD(4, E, K); \
+  else JT_SIMD(8, E, K)
+  if (keep_beta) {
+    JT_SIMD_S(false, true);
+  } else if (extra) {
+    JT_SIMD_S(true, false);
   } else {
-    if (split == 1) JT_SIMD(1, false); else if (split == 2) JT_SIMD(2, false); else if (split == 4) JT_SIMD(4, false);
-    else JT_SIMD(8, false);
+    JT_SIMD_S(false, false);
   }
+#undef JT_SIMD_S
 #undef JT_SIMD
   return hipGetLastError();
 }
