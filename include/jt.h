@@ -248,7 +248,8 @@ jt_status jt_chi2(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, const
                   const float* data, const float* inv_var, double* logL, hipStream_t stream);
 
 /* log L and its gradient for every draw, by a hand-written adjoint that
- * recomputes the traced positions instead of storing them.
+ * reads back the traced positions the forward launch kept (8 bytes per sub-pixel
+ * of workspace) instead of recomputing them.
  * g_macro: device float32 [B][P], P = 7 + 7 (n_src + n_ll), in the order
  *   (theta_E, q, phi, cx, cy) of the SIE, (gamma1, gamma2), then
  *   (amp, R_sersic, n_sersic, q, phi, cx, cy) per source, then per lens-light
