@@ -7,8 +7,9 @@
 // A request whose work exceeds the per-batch cap and that has more than two
 // minimum chunks of pixel blocks runs in chunks instead (a smaller one over
 // the cap forms a batch of its own): each chunk is a launch of at least
-// kChunkMinBlocks blocks
-// (two rounds of wave slots) and otherwise about the cap, all on one stream
+// kChunkMinBlocks blocks (about what the chip holds at once in 256-thread
+// blocks, so a chunk is dispatched almost as soon as it is queued and the
+// batches of other streams get in between) and otherwise about the cap, all on one stream
 // with two chunks queued at a time, and the convolution follows as a launch of
 // its own once every chunk has completed.  The hardware dispatches every
 // workgroup of a queued kernel before it turns to another queue, but switches
@@ -41,7 +42,7 @@ size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Smallest chunk of a chunked request: 4096 blocks of 4 waves, two full rounds
 // of wave slots on 256 CUs at 8 waves per SIMD.
-constexpr int kChunkMinBlocks = 4096;
+constexpr int kChunkMinBlocks = 2048;
 
 // Pinned host memory for the batches' descriptor uploads.  Each batch keeps its
 // own slice until it completes, so forming a batch never waits for a copy

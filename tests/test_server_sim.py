@@ -41,9 +41,9 @@ def test_all_requests_complete_in_fifo_order():
 
 
 def test_batches_pack_waiting_requests_up_to_the_caps():
-    srv = _srv(max_batch_images=8, max_inflight_batches=1)
+    srv = _srv(max_batch_images=8, max_inflight_batches=1, simulated_pairs_per_s=1e9)
     sc = _sc()
-    first = _submit(srv, sc, nsub=20000)          # occupies the device
+    first = _submit(srv, sc, nsub=20000)          # occupies the device for ~80 ms
     rest = [_submit(srv, sc, nsub=10) for _ in range(16)]
     srv.wait(first)
     for t in rest:
@@ -56,7 +56,7 @@ def test_batches_pack_waiting_requests_up_to_the_caps():
 
 def test_large_request_runs_in_chunks_beside_small_ones():
     # 2.6e10 pairs over a 1e7 cap: 51 429 blocks of 28 pixels in chunks of
-    # 4096 blocks (13 chunks) and a convolution launch; the small requests
+    # 2048 blocks (26 chunks) and a convolution launch; the small requests
     # queued behind it are batched while its chunks run (this simulated device
     # runs batches one after another, so they wait for at most the chunks
     # already queued), long before it ends
@@ -67,7 +67,7 @@ def test_large_request_runs_in_chunks_beside_small_ones():
     lat_big = srv.wait(t_big)
     st = srv.stats()
     assert st["completed"] == 6 and st["arena_in_use"] == 0
-    assert st["batches"] >= 13 + 1 + 1
+    assert st["batches"] >= 26 + 1 + 1
     assert max(lat_small) < 0.3 * lat_big
     srv.close()
 
@@ -99,10 +99,10 @@ def test_several_chunked_requests_run_together():
 
 
 def test_request_over_the_cap_with_few_blocks_runs_alone():
-    # 200^2, s = 3: 5715 blocks, too few to chunk; over the cap it forms a
+    # 120^2, s = 3: 2058 blocks, too few to chunk; over the cap it forms a
     # batch of its own instead of joining the small ones
     srv = _srv(max_batch_pairs=1e7, max_inflight_batches=1, max_batch_images=16)
-    ts = [_submit(srv, _sc(200, 3), nsub=2000) for _ in range(3)]
+    ts = [_submit(srv, _sc(120, 3), nsub=2000) for _ in range(3)]
     for t in ts:
         srv.wait(t)
     assert srv.stats()["batches"] == 3
