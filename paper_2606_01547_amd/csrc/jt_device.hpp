@@ -396,7 +396,8 @@ __device__ __forceinline__ float atan_pos(float z, float iz) {
 //               P2 = pi (tau + (tau^2+1)/(s+u)) / (u sp) - 2a/u, which avoids
 //               the cancellation of 2F against pi/sp far from the centre.
 // Hardware rsq, sqrt, rcp and log2 (about one ulp each, none of them in a
-// cancelling difference) and the polynomial arctangent.  0 at the centre
+// cancelling difference; nine per distant pair, reciprocals shared where two
+// are needed) and the polynomial arctangent.  0 at the centre
 // (X2 below 1e-30, where the term is below 1e-28 of alpha_Rs).
 __device__ __forceinline__ void tnfw_pair(float tx, float ty, const TRec& r, float& sx, float& sy) {
   constexpr float kPi = 3.14159265358979323846f;
@@ -410,13 +411,15 @@ __device__ __forceinline__ void tnfw_pair(float tx, float ty, const TRec& r, flo
   const float sp = s + r.tau;
   const float isp = __builtin_amdgcn_rcpf(sp);
   const float Lh = fmaf(__builtin_amdgcn_logf(X2), 0.5f * kLn2, -kLn2);   // ln(x/2)
-  float F, g, P2;
+  const float spx = s + x;
+  float F, g, P2, isx;   // isx = 1/(s + x)
   if (X2 < 0.8f) {
     const float w = __builtin_amdgcn_sqrtf(1.0f - X2);
     const float i1w = __builtin_amdgcn_rcpf(1.0f + w);
     g = (-Lh * X2 * i1w + log1p_fast(-0.5f * X2 * i1w)) * __builtin_amdgcn_rcpf(w);
     F = g - Lh;
     P2 = fmaf(2.0f, F, -kPi * isp);
+    isx = __builtin_amdgcn_rcpf(spx);
   } else if (X2 < 1.2f) {
     const float v = -(X2 - 1.0f);
     F = 1.0f / 21.0f;
@@ -432,16 +435,31 @@ __device__ __forceinline__ void tnfw_pair(float tx, float ty, const TRec& r, flo
     F = fmaf(F, v, 1.0f);
     g = Lh + F;
     P2 = fmaf(2.0f, F, -kPi * isp);
+    isx = __builtin_amdgcn_rcpf(spx);
   } else {
-    const float u = __builtin_amdgcn_sqrtf(X2 - 1.0f);
-    const float iu = __builtin_amdgcn_rcpf(u);
+    const float v1 = X2 - 1.0f;
+    const float iu = __builtin_amdgcn_rsqf(v1);
+    const float u = v1 * iu;
     const float a = atan_pos(iu, u);
     F = (kHalfPi - a) * iu;
     g = Lh + F;
-    P2 = (kPi * fmaf(r.t2 + 1.0f, __builtin_amdgcn_rcpf(s + u), r.tau) * isp - 2.0f * a) * iu;
+    const float spu = s + u;
+    const float r2 = __builtin_amdgcn_rcpf(spu * spx);    // 1/(s+u) and 1/(s+x) from one reciprocal
+    isx = r2 * spu;
+    P2 = (kPi * fmaf(r.t2 + 1.0f, r2 * spx, r.tau) * isp - 2.0f * a) * iu;
   }
-  const float L = -log1p_fast(fmaf(r.t2, __builtin_amdgcn_rcpf(s + x), r.tau) * ix);
-  const float P1 = (g - log1p_fast(0.5f * X2 * r.itau * isp)) * (ix * ix) + L * r.itau * isp;
+  // L = -log1p(z1) and the log1p(z2) of P1, both as z ln(1+z)/((1+z) - 1)
+  // with one reciprocal for the two quotients (an exact z where 1 + z rounds
+  // to 1)
+  const float z1 = fmaf(r.t2, isx, r.tau) * ix;
+  const float z2 = 0.5f * X2 * r.itau * isp;
+  const float w1 = 1.0f + z1, w2 = 1.0f + z2;
+  const float d1 = w1 - 1.0f, d2 = w2 - 1.0f;
+  const float e1 = d1 == 0.0f ? 1.0f : d1, e2 = d2 == 0.0f ? 1.0f : d2;
+  const float rd = __builtin_amdgcn_rcpf(e1 * e2);
+  const float lp1 = d1 == 0.0f ? z1 : __builtin_amdgcn_logf(w1) * kLn2 * z1 * (rd * e2);
+  const float lp2 = d2 == 0.0f ? z2 : __builtin_amdgcn_logf(w2) * kLn2 * z2 * (rd * e1);
+  const float P1 = (g - lp2) * (ix * ix) - lp1 * r.itau * isp;
   const float h = r.c2 * fmaf(r.t2m1, P1, P2);
   sx = fmaf(h, dx, sx);
   sy = fmaf(h, dy, sy);
