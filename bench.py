@@ -504,6 +504,7 @@ def adjoint_bench(ctx, draws, reps):
         return (time.perf_counter() - t0) / reps
 
     t_grad = timeit(lambda: ctx.chi2_grad(truth.grid, batch, dt, wt, psf))
+    t_kept = timeit(lambda: ctx.chi2_grad(truth.grid, batch, dt, wt, psf, keep_positions=True))
     t_fwd = timeit(lambda: ctx.chi2(truth.grid, batch, dt, wt, psf))
     out = torch.empty((truth.grid.ny, truth.grid.nx), dtype=torch.float32, device="cuda")
 
@@ -515,6 +516,8 @@ def adjoint_bench(ctx, draws, reps):
             "gradient_ms_per_batch": round(1e3 * t_grad, 3), "forward_ms_per_batch": round(1e3 * t_fwd, 3),
             "per_image_forward_ms_per_batch": round(1e3 * t_pi, 3),
             "gradients_per_s": round(draws / t_grad, 1), "adjoint_over_forward": round(t_grad / t_fwd, 3),
+            "kept_positions_gradient_ms_per_batch": round(1e3 * t_kept, 3),
+            "kept_positions_over_forward": round(t_kept / t_fwd, 3),
             "params_per_draw": int(macro.shape[1] + 3 * scenes[0].lens.nfw.n)}
 
 

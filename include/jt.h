@@ -247,9 +247,10 @@ jt_status jt_simulate_batch(jt_ctx* ctx, const jt_grid* grid, const jt_draws* dr
 jt_status jt_chi2(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, const float* psf, int k,
                   const float* data, const float* inv_var, double* logL, hipStream_t stream);
 
-/* log L and its gradient for every draw, by a hand-written adjoint that
- * reads back the traced positions the forward launch kept (8 bytes per sub-pixel
- * of workspace) instead of recomputing them.
+/* log L and its gradient for every draw, by a hand-written adjoint.  The backward
+ * pass recomputes each sub-pixel's traced position from the lens parameters
+ * instead of storing it in the forward launch, so its workspace does not
+ * grow with the supersampled grid.
  * g_macro: device float32 [B][P], P = 7 + 7 (n_src + n_ll), in the order
  *   (theta_E, q, phi, cx, cy) of the SIE, (gamma1, gamma2), then
  *   (amp, R_sersic, n_sersic, q, phi, cx, cy) per source, then per lens-light
@@ -261,6 +262,15 @@ jt_status jt_chi2(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, const
 jt_status jt_chi2_grad(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, const float* psf, int k,
                        const float* data, const float* inv_var, double* logL, float* g_macro,
                        float* g_sub, hipStream_t stream);
+
+/* Same results as jt_chi2_grad, bit for bit, but the forward launch keeps
+ * every sub-pixel's traced position (8 bytes per sub-pixel per draw of extra
+ * workspace, allocated from the context) and the backward pass reads it back
+ * instead of summing the subhalos a second time: faster when the subhalo sum
+ * dominates and the workspace fits.  Same arguments and errors. */
+jt_status jt_chi2_grad_kept(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, const float* psf, int k,
+                            const float* data, const float* inv_var, double* logL, float* g_macro,
+                            float* g_sub, hipStream_t stream);
 
 /* ----------------------------------------------------------------------
  * Linear amplitude solver

@@ -179,6 +179,8 @@ _SIGS = {
                         c_void_p]),
     "jt_chi2_grad": (c_int, [c_void_p, POINTER(JtGrid), POINTER(JtDraws), c_void_p, c_int, c_void_p, c_void_p,
                              c_void_p, c_void_p, c_void_p, c_void_p]),
+    "jt_chi2_grad_kept": (c_int, [c_void_p, POINTER(JtGrid), POINTER(JtDraws), c_void_p, c_int, c_void_p, c_void_p,
+                                  c_void_p, c_void_p, c_void_p, c_void_p]),
     "jt_server_create": (c_int, [c_void_p, POINTER(JtServerCfg), POINTER(c_void_p)]),
     "jt_server_create_simulated": (c_int, [POINTER(JtServerCfg), c_double, POINTER(c_void_p)]),
     "jt_server_submit": (c_int, [c_void_p, POINTER(JtRequest), POINTER(c_uint64)]),
@@ -604,8 +606,12 @@ class Context:
         self._retain(keep, stream)
         return logL
 
-    def chi2_grad(self, grid, batch, data, inv_var, psf=None, stream=None):
-        """(log L [B] float64, d log L / d macro [B, P], d log L / d (x, y, alpha_Rs) [B, n, 3])."""
+    def chi2_grad(self, grid, batch, data, inv_var, psf=None, stream=None, keep_positions=False):
+        """(log L [B] float64, d log L / d macro [B, P], d log L / d (x, y, alpha_Rs) [B, n, 3]).
+
+        The backward pass recomputes the traced positions; with
+        `keep_positions` the forward keeps them (8 bytes per sub-pixel per
+        draw) and the backward reads them back, with identical results."""
         torch = _torch()
         keep = []
         D, B, n, P = self._draws(batch, keep)
@@ -616,9 +622,10 @@ class Context:
         logL = torch.empty(B, dtype=torch.float64, device=self.device)
         gm = torch.empty((B, P), dtype=torch.float32, device=self.device)
         gs = torch.empty((B, n, 3), dtype=torch.float32, device=self.device)
-        _check(self._lib.jt_chi2_grad(self._ptr, byref(G), byref(D), pp, k, c_void_p(dt.data_ptr()),
-                                      c_void_p(wt.data_ptr()), c_void_p(logL.data_ptr()), c_void_p(gm.data_ptr()),
-                                      c_void_p(gs.data_ptr() if n else None), _stream_handle(stream)))
+        fn = self._lib.jt_chi2_grad_kept if keep_positions else self._lib.jt_chi2_grad
+        _check(fn(self._ptr, byref(G), byref(D), pp, k, c_void_p(dt.data_ptr()), c_void_p(wt.data_ptr()),
+                  c_void_p(logL.data_ptr()), c_void_p(gm.data_ptr()), c_void_p(gs.data_ptr() if n else None),
+                  _stream_handle(stream)))
         self._retain(keep, stream)
         return logL, gm, gs
 

@@ -6,8 +6,9 @@
 // Reverse pass, per parameter draw:
 //   r = -w (m - d)                         k_residual (+ log L block partials)
 //   lambda_U = K correlated with r         k_conv_direct<flip>
-//   lambda   = lambda_U * d^2 / s^2 per sub-pixel; beta is the forward
-//   launch's own traced position (kept, 8 bytes per sub-pixel), G = lambda *
+//   lambda   = lambda_U * d^2 / s^2 per sub-pixel; beta recomputed by the
+//   forward's canonical subhalo sum (or, in the kept variant, the forward
+//   launch's own traced position, 8 bytes per sub-pixel), G = lambda *
 //   dI/dbeta; Sersic, SIE and shear parameter partials are reduced per
 //   block                                             k_grad_pixel
 //   subhalo (x, y, alpha_Rs) gradients: a subhalo-major pass over the
@@ -164,11 +165,12 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-template <int kSplit>
+template <int kSplit, bool kKept>
 __global__ __launch_bounds__(split_threads(kSplit)) void k_grad_pixel(const ImageDesc* __restrict__ descs, int bpi,
                                                                      const float* __restrict__ lamU,
                                                                      float4* __restrict__ rec, int rec_stride,
                                                                      float* __restrict__ part, int P) {
+  __shared__ RangeScratch<kSplit> scratch;   // the recomputed subhalo sum
   __shared__ float wsum[4][kGradMaxP];
   constexpr int kW = split_lanes(kSplit);
   const int di = blockIdx.x / bpi;
@@ -188,13 +190,28 @@ __global__ __launch_bounds__(split_threads(kSplit)) void k_grad_pixel(const Imag
   const double tx64 = g.ox + g.step * ((double)(col * g.s + b) + 0.5);
   const double ty64 = g.oy + g.step * ((double)(row * g.s + a) + 0.5);
   const float tx = (float)tx64, ty = (float)ty64;
+  double sx = 0.0, sy = 0.0;
+  if (!kKept) {
+    subhalo_ranges<kSplit>(tx, ty, d.sub, d.nloop, grp, t, scratch, sx, sy);
+    __syncthreads();
+  }
   float c[kGradMaxP];
 #pragma unroll
   for (int i = 0; i < kGradMaxP; ++i) c[i] = 0.f;
   if (grp == 0) {
-    // the traced position the forward launch kept for this sub-pixel
-    const float2 bb = d.beta[(size_t)pp * g.s2 + si];
-    const float bx = bb.x, by = bb.y;
+    float bx, by;
+    if (kKept) {
+      // the traced position the forward launch kept for this sub-pixel
+      const float2 bb = d.beta[(size_t)pp * g.s2 + si];
+      bx = bb.x;
+      by = bb.y;
+    } else {
+      // recomputed: the same canonical sum as the forward, so the same bits
+      double ax, ay;
+      total_deflection64<kSplit>(d.mc, tx64, ty64, scratch, t, sx, sy, ax, ay);
+      bx = (float)(tx64 - ax);
+      by = (float)(ty64 - ay);
+    }
     const float lam = valid ? lamU[(size_t)di * npix + pp] * g.area_over_s2 : 0.f;
     float Gx = 0.f, Gy = 0.f, dd[7], gx, gy;
     const int ns = d.src.n, nl = d.ll.n;
@@ -433,12 +450,18 @@ hipError_t launch_residual(int B, int npix, const float* model, const float* dat
   return hipGetLastError();
 }
 
-hipError_t launch_grad_pixel(int split, int B, int bpi, const ImageDesc* descs, const float* lamU, float4* rec,
-                             int rec_stride, float* part, int P, hipStream_t st) {
+hipError_t launch_grad_pixel(int split, bool kept, int B, int bpi, const ImageDesc* descs, const float* lamU,
+                             float4* rec, int rec_stride, float* part, int P, hipStream_t st) {
   const dim3 grid((unsigned)((long)B * bpi));
-#define JT_GP(S) hipLaunchKernelGGL((k_grad_pixel<S>), grid, dim3(split_threads(S)), 0, st, descs, bpi, lamU, rec, \
-                                    rec_stride, part, P)
-  if (split == 1) JT_GP(1); else if (split == 2) JT_GP(2); else if (split == 4) JT_GP(4); else JT_GP(8);
+#define JT_GP(S, K) hipLaunchKernelGGL((k_grad_pixel<S, K>), grid, dim3(split_threads(S)), 0, st, descs, bpi, lamU, \
+                                       rec, rec_stride, part, P)
+  if (kept) {
+    if (split == 1) JT_GP(1, true); else if (split == 2) JT_GP(2, true); else if (split == 4) JT_GP(4, true);
+    else JT_GP(8, true);
+  } else {
+    if (split == 1) JT_GP(1, false); else if (split == 2) JT_GP(2, false); else if (split == 4) JT_GP(4, false);
+    else JT_GP(8, false);
+  }
 #undef JT_GP
   return hipGetLastError();
 }

@@ -138,7 +138,7 @@ namespace {
 
 jt_status chi2_common(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, const float* psf, int k,
                       const float* data, const float* inv_var, double* logL, float* g_macro, float* g_sub,
-                      bool grad, hipStream_t st) {
+                      bool grad, hipStream_t st, bool keep = false) {
   JT_TRY(ctx_enter(ctx));
   Batch bt;
   JT_TRY(make_batch(grid, draws, grad, bt));
@@ -157,7 +157,7 @@ jt_status chi2_common(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, c
     bytes += align256(sizeof(float) * BN) + align256(sizeof(float4) * (size_t)bt.B * rec_stride) +
              align256(sizeof(float) * (size_t)bt.B * bt.bpi * bt.P) +
              align256(sizeof(float) * (size_t)kRecPartsHost * bt.B * bt.n * 3) +
-             align256(sizeof(float2) * (size_t)bt.B * bt.nsubpix);
+             (keep ? align256(sizeof(float2) * (size_t)bt.B * bt.nsubpix) : 0);
   void* ws = nullptr;
   JT_TRY(ctx_workspace(ctx, st, bytes, &ws));
   Carve cv{(char*)ws};
@@ -167,8 +167,9 @@ jt_status chi2_common(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, c
   float* model = psf ? cv.take<float>(BN) : mu;
   float* resid = cv.take<float>(BN);
   float* lpart = cv.take<float>((size_t)bt.B * nres);
-  // the gradient keeps the forward's traced positions instead of recomputing them
-  float2* beta = grad ? cv.take<float2>((size_t)bt.B * bt.nsubpix) : nullptr;
+  // the kept variant of the gradient reads the forward's traced positions back
+  // instead of recomputing them
+  float2* beta = keep ? cv.take<float2>((size_t)bt.B * bt.nsubpix) : nullptr;
   JT_TRY(run_forward(ctx, bt, draws, psf, k, tables, dd, mu, model, st, beta));
   int nb = 0;
   JT_TRY(timed_launch(ctx, JT_K_GRAD, st, [&] {
@@ -187,7 +188,7 @@ jt_status chi2_common(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, c
       return launch_conv_direct_batched(true, bt.B, resid, bt.npix, bt.g.nx, bt.g.ny, psf, k, lamU, bt.npix, st);
     }, "conv_adjoint"));
   JT_TRY(timed_launch(ctx, JT_K_GRAD, st, [&] {
-    return launch_grad_pixel(bt.split, bt.B, bt.bpi, dd, lamU, rec, rec_stride, part, bt.P, st);
+    return launch_grad_pixel(bt.split, keep, bt.B, bt.bpi, dd, lamU, rec, rec_stride, part, bt.P, st);
   }, "grad_pixel"));
   JT_TRY(timed_launch(ctx, JT_K_GRAD, st, [&] {
     return launch_grad_subhalo(bt.B, bt.n, dd, rec, rec_stride, nrec_loop, gpart, st);
@@ -209,4 +210,10 @@ extern "C" jt_status jt_chi2_grad(jt_ctx* ctx, const jt_grid* grid, const jt_dra
                                   int k, const float* data, const float* inv_var, double* logL, float* g_macro,
                                   float* g_sub, hipStream_t stream) {
   return chi2_common(ctx, grid, draws, psf, k, data, inv_var, logL, g_macro, g_sub, true, stream);
+}
+
+extern "C" jt_status jt_chi2_grad_kept(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, const float* psf,
+                                       int k, const float* data, const float* inv_var, double* logL, float* g_macro,
+                                       float* g_sub, hipStream_t stream) {
+  return chi2_common(ctx, grid, draws, psf, k, data, inv_var, logL, g_macro, g_sub, true, stream, true);
 }

@@ -85,8 +85,8 @@ hipError_t launch_fft_convolve(const float* img, int nx, int ny, const float* ps
 constexpr int kRecPartsHost = 4;  // parts of the adjoint's subhalo-major pass
 hipError_t launch_residual(int B, int npix, const float* model, const float* data, const float* w, float* resid,
                            float* part, int* nblocks, hipStream_t st);
-hipError_t launch_grad_pixel(int split, int B, int bpi, const ImageDesc* descs, const float* lamU, float4* rec,
-                             int rec_stride, float* part, int P, hipStream_t st);
+hipError_t launch_grad_pixel(int split, bool kept, int B, int bpi, const ImageDesc* descs, const float* lamU,
+                             float4* rec, int rec_stride, float* part, int P, hipStream_t st);
 hipError_t launch_grad_subhalo(int B, int n, const ImageDesc* descs, const float4* rec, int rec_stride,
                                int nrec_loop, float* gpart, hipStream_t st);
 hipError_t launch_grad_finalize(int B, int P, int bpi, const float* part, float* g_macro, int nres,

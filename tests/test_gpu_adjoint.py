@@ -140,6 +140,20 @@ def test_gradient_deterministic_and_batch_independent(ctx):
     np.testing.assert_array_equal(_np(a[2])[3], _np(c[2])[0])
 
 
+@pytest.mark.parametrize("n_sub,s,lens_light", [(400, 1, False), (150, 3, True), (0, 2, False)])
+def test_kept_positions_give_the_recomputed_gradient_bit_for_bit(ctx, n_sub, s, lens_light):
+    grid = W.Grid(nx=52, ny=47, pixel_scale=0.08, supersample=s)
+    truth, draws = W.config4_draws(B=5, n_sub=max(n_sub, 1), grid=grid, lens_light=lens_light)
+    if n_sub == 0:
+        for sc in [truth] + draws:
+            sc.lens.nfw = None
+    d, w = _data(truth, seed=6)
+    a = ctx.chi2_grad(truth.grid, _batch(draws), d, w, truth.psf)
+    b = ctx.chi2_grad(truth.grid, _batch(draws), d, w, truth.psf, keep_positions=True)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(_np(x), _np(y))
+
+
 def test_autograd_function_backward_is_the_adjoint(ctx):
     from paper_2606_01547_amd.grad import chi2_loglike
     truth, draws = W.config4_draws(B=3, n_sub=120)
