@@ -347,9 +347,11 @@ __global__ __launch_bounds__(64) void k_grad_subhalo(const ImageDesc* __restrict
   const int k = blockIdx.x * 64 + threadIdx.x;
   const bool valid = k < n;
   const SubRec s = descs[b].sub[valid ? k : 0];
+  // the record holds c1/4 and c2/4 (exact quarters)
+  const float c1 = 4.0f * s.c1, c2 = 4.0f * s.c2;
   // alpha / alpha_Rs = c2n * h * d  (h in units of ln2/2)
-  const float c2n = sqrtf(s.c1) * (float)(kNfwRecScale / (1.0 - kLn2d));
-  const float c1x2 = 2.0f * s.c1;
+  const float c2n = sqrtf(c1) * (float)(kNfwRecScale / (1.0 - kLn2d));
+  const float c1x2 = 2.0f * c1;
   const float4* __restrict__ r = rec + (size_t)b * rec_stride;
   const int kb = part_bound(nrec_loop, kRecParts, q), ke = part_bound(nrec_loop, kRecParts, q + 1);
   float hx = 0.f, lx = 0.f, hy = 0.f, ly = 0.f, ha = 0.f, la = 0.f;
@@ -368,7 +370,7 @@ __global__ __launch_bounds__(64) void k_grad_subhalo(const ImageDesc* __restrict
       for (int m = 0; m < 4; ++m) {
         dx[m] = rr[m].x - s.x;
         dy[m] = rr[m].y - s.y;
-        X[m] = fmaf(dy[m], dy[m], dx[m] * dx[m]) * s.c1;
+        X[m] = fmaf(dy[m], dy[m], dx[m] * dx[m]) * c1;
         y[m] = __builtin_amdgcn_rsqf(X[m]);
         l2[m] = __builtin_amdgcn_logf(X[m]);
         y2[m] = y[m] * y[m];
@@ -406,8 +408,8 @@ __global__ __launch_bounds__(64) void k_grad_subhalo(const ImageDesc* __restrict
   }
   if (valid) {
     float* o = gpart + (((size_t)q * B + b) * n + k) * 3;
-    o[0] = s.c2 * (hx + lx);
-    o[1] = s.c2 * (hy + ly);
+    o[0] = c2 * (hx + lx);
+    o[1] = c2 * (hy + ly);
     o[2] = -c2n * (ha + la);
   }
 }

@@ -176,7 +176,7 @@ extern "C" jt_status jt_create(int device, jt_ctx** out) {
   jt_ctx* ctx = new jt_ctx();
   ctx->device = device;
   const int rec = subhalo_table_records(0);
-  std::vector<SubRec> pad(rec, SubRec{1e18f, 1e18f, 1.0f, 0.0f});
+  std::vector<SubRec> pad(rec, kSubRecPad);
   jt_status st = check_hip(hipMalloc(&ctx->empty_table, rec * sizeof(SubRec)), "hipMalloc(empty table)");
   if (st == JT_OK)
     st = check_hip(hipMemcpy(ctx->empty_table, pad.data(), rec * sizeof(SubRec), hipMemcpyHostToDevice),

@@ -121,14 +121,24 @@ struct GridC {
 struct ImageDesc;
 
 // Packed subhalo record: centre and the two derived constants of the pair term
-// alpha = c2 * g'(x) / x^2 * (dx, dy), x^2 = r^2 c1, c1 = 1/Rs^2, with g in
-// units of ln2/2 (g' = g / (ln2/2)) and the factor carried by
-// c2 = kNfwRecScale alpha_Rs / ((1 - ln 2) Rs).  Folding the constant into c2
+// alpha = c2 * g'(x) / Xq * (dx, dy), Xq = x^2/4 = r^2 c1, c1 = 1/(4 Rs^2),
+// with g in units of ln2/2 (g' = g / (ln2/2)) and the factor carried by
+// c2 = kNfwRecScale alpha_Rs / (4 (1 - ln 2) Rs).  Folding the constant into c2
 // (one FP64 product rounded per subhalo) keeps its FP32 rounding from biasing
-// every term the same way.
+// every term the same way.  The quarters are exact (powers of two), so
+// 4 c1 = 1/Rs^2 and 4 c2 are the unscaled constants rounded once.
 struct __align__(16) SubRec {
   float x, y, c1, c2;
 };
+
+// The record of one subhalo (host and device use the same roundings).
+__host__ __device__ inline SubRec make_subrec(float x, float y, float rs, float ars) {
+  const double r = rs;
+  return SubRec{x, y, (float)(0.25 * (1.0 / (r * r))),
+                (float)(0.25 * (kNfwRecScale * (double)ars / ((1.0 - kLn2d) * r)))};
+}
+// Padding record: far away, zero amplitude.
+constexpr SubRec kSubRecPad{1e18f, 1e18f, 0.25f, 0.0f};
 
 // Truncated NFW record (Baltz, Marshall & Oguri 2009, truncation exponent 1):
 // centre, c1 = 1/Rs^2, c2 = alpha_Rs/((1 - ln 2) Rs) * tau^2/(tau^2 + 1)^2 and
@@ -245,18 +255,22 @@ __device__ __forceinline__ void macro_deflection64(const MacroC& m, double tx, d
 // ---------------------------------------------------------------------------
 // NFW pair term
 // ---------------------------------------------------------------------------
-// g'(x)/x^2 = g(x)/((ln2/2) x^2) for x^2 = X2 < 1 (rare near-field pairs), from
-// l2 = log2(X2), with hardware transcendentals and forms that avoid
-// cancellation.  In these units ln(x/2) = (ln2/2)(l2 - 2) exactly:
-//   X2 >= 0.81: F = sum_k (-u)^k/(2k+1), u = X2 - 1 in [-0.19, 0), and
-//               g' = (l2 - 2) + F / (ln2/2);
-//   X2 <  0.81: g = [-L X2/(1+w) + log1p(-X2/(2(1+w)))]/w, L = ln(x/2),
-//               w = sqrt(1 - X2), with log1p(t) = t ln(1+t)/((1+t) - 1)
-//               (exact t when 1 + t rounds to 1);
-// 0 at X2 = 0.
-__device__ __forceinline__ float nfw_near_g_over_x2(float X2, float l2) {
+// The pair kernel works with the quarter squared radius Xq = x^2/4 (the
+// record carries c1/4), lq = log2(Xq) and yq = rsq(Xq) = 2/x, and returns
+// hq = g'(x)/Xq = 4 g'(x)/x^2 (the record carries c2/4), g' = g/(ln2/2).
+//
+// Near field, x^2 = 4 Xq < 1 (rare pairs), with hardware transcendentals and
+// forms that avoid cancellation.  In these units ln(x/2) = (ln2/2) lq exactly:
+//   x^2 >= 0.81: F = sum_k (-u)^k/(2k+1), u = x^2 - 1 in [-0.19, 0), and
+//                g' = lq + F / (ln2/2);
+//   x^2 <  0.81: g = [-L x^2/(1+w) + log1p(-x^2/(2(1+w)))]/w, L = ln(x/2),
+//                w = sqrt(1 - x^2), with log1p(t) = t ln(1+t)/((1+t) - 1)
+//                (exact t when 1 + t rounds to 1);
+// 0 at x = 0.
+__device__ __forceinline__ float nfw_near_hq(float Xq, float lq) {
   constexpr float kInvA = (float)(2.0 / kLn2d);   // 1 / (ln2/2)
-  const float Lp = l2 - 2.0f;                      // ln(x/2) / (ln2/2)
+  const float X2 = 4.0f * Xq;
+  const float Lp = lq;                             // ln(x/2) / (ln2/2)
   float g;
   if (X2 >= 0.81f) {
     const float u = X2 - 1.0f;
@@ -282,35 +296,32 @@ __device__ __forceinline__ float nfw_near_g_over_x2(float X2, float l2) {
     const float lp = (u == 1.0f) ? t * kInvA : 2.0f * __builtin_amdgcn_logf(u) * t * __builtin_amdgcn_rcpf(u - 1.0f);
     g = fmaf(-Lp * X2, ropw, lp) * __builtin_amdgcn_rcpf(w);
   }
-  return X2 > 0.f ? g * kNfwNearScale * __builtin_amdgcn_rcpf(X2) : 0.f;
+  return Xq > 0.f ? g * kNfwNearScale * __builtin_amdgcn_rcpf(Xq) : 0.f;
 }
 
-// Far-field g'(x)/x^2 for x^2 = X2 >= 1, l2 = log2(X2) and y = rsq(X2):
-// g' = l2 + P(y), P ~ psi/(ln2/2) the fitted polynomial (P(0) ~ -2), and
-// g'/x^2 = g' y^2.  The short form uses the polynomial fitted on
-// [0, kNfwFastY] only.
-__device__ __forceinline__ float nfw_far_h(float l2, float y) {
-  float p = kNfwP[0];
+// Far field, x >= 1: g' = lq + yq R(yq) with R the fitted polynomial in the
+// shifted form (the constant -2 of g' is what log2(x^2/4) = log2(x^2) - 2
+// absorbs), and hq = g' yq^2.  The short form uses the fit on
+// [0, kNfwFastY] in y = 1/x only.
+__device__ __forceinline__ float nfw_far_hq(float lq, float yq) {
+  float p = kNfwR[0];
 #pragma unroll
-  for (int i = 1; i <= JT_NFW_POLY_DEGREE; ++i) p = fmaf(p, y, kNfwP[i]);
-  return (l2 + p) * (y * y);
+  for (int i = 1; i < JT_NFW_POLY_DEGREE; ++i) p = fmaf(p, yq, kNfwR[i]);
+  return fmaf(p, yq, lq) * (yq * yq);
 }
 
-__device__ __forceinline__ float nfw_far_h_short(float l2, float y) {
-  float p = kNfwPFast[0];
+__device__ __forceinline__ float nfw_far_hq_short(float lq, float yq) {
+  float p = kNfwRFast[0];
 #pragma unroll
-  for (int i = 1; i <= JT_NFW_FAST_DEGREE; ++i) p = fmaf(p, y, kNfwPFast[i]);
-  return (l2 + p) * (y * y);
+  for (int i = 1; i < JT_NFW_FAST_DEGREE; ++i) p = fmaf(p, yq, kNfwRFast[i]);
+  return fmaf(p, yq, lq) * (yq * yq);
 }
 
-__device__ __forceinline__ float nfw_far_g_over_x2(float X2, float l2) {
-  return nfw_far_h(l2, __builtin_amdgcn_rsqf(X2));
-}
-
-// Four (sub-pixel, subhalo) pairs: adds alpha_k, k = 0..3, to (sx, sy).
-// When y = Rs/r < kNfwFastY for all four (distant subhalos: nearly every
+// Four (sub-pixel, subhalo) pairs: adds alpha_k, k = 0..3, to (sx, sy), with
+// X = Xq, l = lq and y = yq of the quarter-radius form above.  When
+// y = 2 Rs/r < kNfwFastYq for all four (distant subhalos: nearly every
 // group) the short polynomial is used; otherwise the full one, and a second
-// branch recomputes the rare near-field (X2 < 1) terms.  The choice is made
+// branch recomputes the rare near-field (x < 1) terms.  The choice is made
 // per lane from its own four pairs, so a sub-pixel's result does not depend
 // on which sub-pixels share its wave; in practice the lanes of a wave agree
 // and the branches are uniform.
@@ -334,21 +345,21 @@ __device__ __forceinline__ void nfw_pairs4(float tx, float ty, const SubRec& s0,
   const float y2 = __builtin_amdgcn_rsqf(X2);
   const float y3 = __builtin_amdgcn_rsqf(X3);
   float h0, h1, h2, h3;
-  if (fmaxf(fmaxf(y0, y1), fmaxf(y2, y3)) < kNfwFastY) {
-    h0 = nfw_far_h_short(l0, y0);
-    h1 = nfw_far_h_short(l1, y1);
-    h2 = nfw_far_h_short(l2, y2);
-    h3 = nfw_far_h_short(l3, y3);
+  if (fmaxf(fmaxf(y0, y1), fmaxf(y2, y3)) < kNfwFastYq) {
+    h0 = nfw_far_hq_short(l0, y0);
+    h1 = nfw_far_hq_short(l1, y1);
+    h2 = nfw_far_hq_short(l2, y2);
+    h3 = nfw_far_hq_short(l3, y3);
   } else {
-    h0 = nfw_far_h(l0, y0);
-    h1 = nfw_far_h(l1, y1);
-    h2 = nfw_far_h(l2, y2);
-    h3 = nfw_far_h(l3, y3);
-    if (fminf(fminf(X0, X1), fminf(X2, X3)) < 1.0f) {
-      if (X0 < 1.0f) h0 = nfw_near_g_over_x2(X0, l0);
-      if (X1 < 1.0f) h1 = nfw_near_g_over_x2(X1, l1);
-      if (X2 < 1.0f) h2 = nfw_near_g_over_x2(X2, l2);
-      if (X3 < 1.0f) h3 = nfw_near_g_over_x2(X3, l3);
+    h0 = nfw_far_hq(l0, y0);
+    h1 = nfw_far_hq(l1, y1);
+    h2 = nfw_far_hq(l2, y2);
+    h3 = nfw_far_hq(l3, y3);
+    if (fminf(fminf(X0, X1), fminf(X2, X3)) < 0.25f) {
+      if (X0 < 0.25f) h0 = nfw_near_hq(X0, l0);
+      if (X1 < 0.25f) h1 = nfw_near_hq(X1, l1);
+      if (X2 < 0.25f) h2 = nfw_near_hq(X2, l2);
+      if (X3 < 0.25f) h3 = nfw_near_hq(X3, l3);
     }
   }
   sx = fmaf(h0 * s0.c2, dx0, sx);

@@ -150,13 +150,12 @@ jt_status make_macro(const jt_lens* lens, MacroC& m) {
 
 jt_status pack_subhalos_host(int n, const float* x, const float* y, const float* rs, const float* ars,
                              std::vector<SubRec>& out) {
-  out.assign(subhalo_table_records(n), SubRec{1e18f, 1e18f, 1.0f, 0.0f});
+  out.assign(subhalo_table_records(n), kSubRecPad);
   for (int i = 0; i < n; ++i) {
     if (!std::isfinite(x[i]) || !std::isfinite(y[i]) || !std::isfinite(ars[i]))
       return fail(JT_EINVAL, "subhalo %d: non-finite parameter", i);
     if (!(rs[i] > 0.0f) || !std::isfinite(rs[i])) return fail(JT_EINVAL, "subhalo %d: Rs = %g", i, (double)rs[i]);
-    const double r = rs[i];
-    out[i] = SubRec{x[i], y[i], (float)(1.0 / (r * r)), (float)(kNfwRecScale * (double)ars[i] / ((1.0 - kLn2d) * r))};
+    out[i] = make_subrec(x[i], y[i], rs[i], ars[i]);
   }
   return JT_OK;
 }

@@ -28,16 +28,10 @@ __global__ __launch_bounds__(256) void k_prep_subhalos(int n, int padded, const 
                                                       SubRec* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) {
-    if (i < padded) out[i] = SubRec{1e18f, 1e18f, 1.0f, 0.0f};
+    if (i < padded) out[i] = kSubRecPad;
     return;
   }
-  const double r = rs[i];
-  SubRec s;
-  s.x = x[i];
-  s.y = y[i];
-  s.c1 = (float)(1.0 / (r * r));
-  s.c2 = (float)(kNfwRecScale * (double)ars[i] / ((1.0 - kLn2d) * r));
-  out[i] = s;
+  out[i] = make_subrec(x[i], y[i], rs[i], ars[i]);
 }
 
 __global__ __launch_bounds__(256) void k_prep_tnfw(int n, int padded, const float* __restrict__ x,
@@ -542,12 +536,11 @@ __global__ __launch_bounds__(256) void k_prep_subhalos_batched(int n, int record
   if (i >= records) return;
   SubRec* o = out + (size_t)b * records;
   if (i >= n) {
-    o[i] = SubRec{1e18f, 1e18f, 1.0f, 0.0f};
+    o[i] = kSubRecPad;
     return;
   }
   const size_t j = (size_t)b * n + i;
-  const double r = rs[j];
-  o[i] = SubRec{x[j], y[j], (float)(1.0 / (r * r)), (float)(kNfwRecScale * (double)ars[j] / ((1.0 - kLn2d) * r))};
+  o[i] = make_subrec(x[j], y[j], rs[j], ars[j]);
 }
 
 hipError_t launch_prep_subhalos_batched(int B, int n, const float* x, const float* y, const float* rs,
