@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "simulated images/s + p50/p99 latency (200² px, 10k NFW, 41² PSF); % FP32 peak"
 PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector, published
+PEAK_HBM_BYTES = 8.0e12           # MI355X HBM3E, published
 # Algorithmic FP32 work of one (sub-pixel, subhalo) NFW pair with the general
 # (degree-8) far-field polynomial (FMA = 2, transcendental = 1): dx, dy 2;
 # r^2 3; x^2 1; rsq + log2 2; polynomial 16; g 1; y^2, g y^2 2; * c2 1;
@@ -386,6 +387,64 @@ def profiles_bench(ctx, reps=20):
                                 "tau = r_trunc/Rs log-uniform in [3, 30] (seed 1007)")}
 
 
+def stages_bench(ctx, reps=10):
+    """The three steps as separate calls, with their algorithmic bytes or
+    pairs: step 1 (jt_ray_shoot) and step 2 (jt_source_sb) streaming over the
+    1000x1000 px, s = 5 image's 25 million sub-pixels (macro lens only for
+    step 1, the image's four Sersic components for step 2), and step 1 with
+    the headline's 10,000 NFW at its 360,000 sub-pixels.  Kernel time from
+    the library's HIP events."""
+    import numpy as np
+    import torch
+    import workloads as W
+    out = {}
+    sc = W.config5_scene()
+    g = sc.grid
+    n1 = g.nx * g.supersample
+    d = g.pixel_scale / g.supersample
+    ax = (torch.arange(n1, device="cuda", dtype=torch.float64) - 0.5 * (n1 - 1)) * d
+    yy, xx = torch.meshgrid(ax, ax, indexing="ij")
+    x, y = xx.float().contiguous().view(-1), yy.float().contiguous().view(-1)
+    del xx, yy
+    n = x.numel()
+    bx, by = torch.empty_like(x), torch.empty_like(y)
+    macro = W.Lens(sie=sc.lens.sie, shear=sc.lens.shear)
+    per, _ = _kernel_ms(ctx, lambda: ctx.ray_shoot(x, y, macro, out=(bx, by)), ("ray",), reps)
+    t = 1e-3 * per["ray"]
+    out["ray_shoot_macro"] = {"points": n, "us": round(1e6 * t, 1), "bytes_per_point": 16,
+                              "GB_per_s": round(16 * n / t / 1e9, 1),
+                              "frac_hbm_peak": round(16 * n / t / PEAK_HBM_BYTES, 4),
+                              "note": "SIE + shear in FP64 per point (atan/atanh): FP64 VALU work beside 16 B of HBM"}
+    sb = torch.empty_like(x)
+    per, _ = _kernel_ms(ctx, lambda: ctx.source_sb(x, y, bx, by, sc.source, sc.lens_light, sc.bn_exact, out=sb),
+                        ("sb",), reps)
+    t = 1e-3 * per["sb"]
+    out["source_sb"] = {"points": n, "components": len(sc.source) + len(sc.lens_light), "us": round(1e6 * t, 1),
+                        "bytes_per_point": 20, "GB_per_s": round(20 * n / t / 1e9, 1),
+                        "frac_hbm_peak": round(20 * n / t / PEAK_HBM_BYTES, 4)}
+    del x, y, bx, by, sb
+    sc2 = W.config2_scene()
+    g2 = sc2.grid
+    m = g2.nx * g2.supersample
+    d2 = g2.pixel_scale / g2.supersample
+    ax2 = (torch.arange(m, device="cuda", dtype=torch.float64) - 0.5 * (m - 1)) * d2
+    yy, xx = torch.meshgrid(ax2, ax2, indexing="ij")
+    x, y = xx.float().contiguous().view(-1), yy.float().contiguous().view(-1)
+    bx, by = torch.empty_like(x), torch.empty_like(y)
+    nfw = sc2.lens.nfw
+    dev = W.NFWTable(*[torch.from_numpy(np.asarray(a)).cuda() for a in (nfw.x, nfw.y, nfw.Rs, nfw.alpha_Rs)])
+    lens = W.Lens(sie=sc2.lens.sie, shear=sc2.lens.shear, nfw=dev)
+    per, _ = _kernel_ms(ctx, lambda: ctx.ray_shoot(x, y, lens, out=(bx, by)), ("ray", "prep"), reps)
+    t = 1e-3 * per["ray"]
+    pairs = x.numel() * nfw.n
+    out["ray_shoot_subhalos"] = {"points": x.numel(), "subhalos": nfw.n, "us": round(1e6 * t, 1),
+                                 "pairs_per_s": round(pairs / t, 1),
+                                 "frac_fp32_peak": round(FLOP_PER_PAIR * pairs / t / 1e12 / PEAK_FP32_TFLOPS, 4)}
+    out["workload"] = ("steps 1 and 2 alone on the 1000x1000 px, s = 5 image's 5000x5000 sub-pixel grid "
+                       "(seed 1005); step 1 with the headline's 10,000 NFW on its 600x600 sub-pixels (seed 1002)")
+    return out
+
+
 def linear_bench(ctx, reps=20):
     """The linear amplitude solver on the headline image (four components:
     the two sources, a third added source and the lens light) against
@@ -537,6 +596,7 @@ def main():
     ap.add_argument("--conv-sweep", type=int, default=1, help="direct/FFT convolution sweep (0 = skip)")
     ap.add_argument("--profiles", type=int, default=1, help="EPL / TNFW profile rows (0 = skip)")
     ap.add_argument("--linear", type=int, default=1, help="linear amplitude solver row (0 = skip)")
+    ap.add_argument("--stages", type=int, default=1, help="steps 1 and 2 as separate calls (0 = skip)")
     ap.add_argument("--fitting", type=int, default=1, help="swarm and L-BFGS fitting row (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (3 times), to calibrate "
@@ -638,6 +698,8 @@ def main():
         result["large_image"] = large_image_bench(ctx, args.large_reps)
     if args.profiles:
         result["profiles"] = profiles_bench(ctx)
+    if args.stages:
+        result["stages"] = stages_bench(ctx)
     if args.linear:
         result["linear_amplitudes"] = linear_bench(ctx)
     if args.fitting:

@@ -78,16 +78,53 @@ __global__ __launch_bounds__(split_threads(kSplit)) void k_ray_shoot(int n, cons
   }
 }
 
+// Step 2 at explicit points: sb = sources at beta + lens light at theta.  A
+// list without components reads none of its coordinates.  With kVec every
+// thread below n/4 takes four consecutive points through 16-byte loads and
+// stores (all arrays 16-byte aligned), and the last n mod 4 points take one
+// thread each; otherwise one point per thread.
+template <bool kExtra>
+__device__ __forceinline__ float sb_at(const LightC& src, const LightC& ll, bool hs, bool hl, const float* x,
+                                       const float* y, const float* bx, const float* by, int i) {
+  float v = hs ? light_sum<kExtra>(src, bx[i], by[i]) : 0.f;
+  if (hl) v += light_sum<kExtra>(ll, x[i], y[i]);
+  return v;
+}
+
+template <bool kExtra, bool kVec>
 __global__ __launch_bounds__(256) void k_source_sb(int n, const float* __restrict__ x,
                                                   const float* __restrict__ y,
                                                   const float* __restrict__ bx,
                                                   const float* __restrict__ by, LightC src,
                                                   LightC ll, float* __restrict__ sb) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float v = light_sum(src, bx[i], by[i]);
-  if (light_any(ll)) v += light_sum(ll, x[i], y[i]);
-  sb[i] = v;
+  const bool hs = light_any(src), hl = light_any(ll);
+  if (!kVec) {
+    if (i < n) sb[i] = sb_at<kExtra>(src, ll, hs, hl, x, y, bx, by, i);
+    return;
+  }
+  const int n4 = n >> 2;
+  if (i >= n4) {
+    const int j = 4 * n4 + (i - n4);
+    if (j < n) sb[j] = sb_at<kExtra>(src, ll, hs, hl, x, y, bx, by, j);
+    return;
+  }
+  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (hs) {
+    const float4 u = reinterpret_cast<const float4*>(bx)[i], w = reinterpret_cast<const float4*>(by)[i];
+    v.x = light_sum<kExtra>(src, u.x, w.x);
+    v.y = light_sum<kExtra>(src, u.y, w.y);
+    v.z = light_sum<kExtra>(src, u.z, w.z);
+    v.w = light_sum<kExtra>(src, u.w, w.w);
+  }
+  if (hl) {
+    const float4 u = reinterpret_cast<const float4*>(x)[i], w = reinterpret_cast<const float4*>(y)[i];
+    v.x += light_sum<kExtra>(ll, u.x, w.x);
+    v.y += light_sum<kExtra>(ll, u.y, w.y);
+    v.z += light_sum<kExtra>(ll, u.z, w.z);
+    v.w += light_sum<kExtra>(ll, u.w, w.w);
+  }
+  reinterpret_cast<float4*>(sb)[i] = v;
 }
 
 // Sub-pixel slot of a simulate block: slot t of wave-group 0..kSplit-1 holds
@@ -422,7 +459,20 @@ hipError_t launch_ray_shoot(bool alpha, bool tnfw, int n, const float* x, const 
 hipError_t launch_source_sb(int n, const float* x, const float* y, const float* bx, const float* by,
                             const LightC& src, const LightC& ll, float* sb, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_source_sb, dim3((n + 255) / 256), dim3(256), 0, st, n, x, y, bx, by, src, ll, sb);
+  const bool hs = light_any(src), hl = light_any(ll);
+  const auto a16 = [](const float* p) { return ((uintptr_t)p & 15) == 0; };
+  const bool vec = a16(sb) && (!hs || (a16(bx) && a16(by))) && (!hl || (a16(x) && a16(y)));
+  const bool extra = light_has_extra(src) || light_has_extra(ll);
+  const int threads = vec ? (n >> 2) + (n & 3) : n;
+  const dim3 grid((threads + 255) / 256), block(256);
+  if (vec && extra)
+    hipLaunchKernelGGL((k_source_sb<true, true>), grid, block, 0, st, n, x, y, bx, by, src, ll, sb);
+  else if (vec)
+    hipLaunchKernelGGL((k_source_sb<false, true>), grid, block, 0, st, n, x, y, bx, by, src, ll, sb);
+  else if (extra)
+    hipLaunchKernelGGL((k_source_sb<true, false>), grid, block, 0, st, n, x, y, bx, by, src, ll, sb);
+  else
+    hipLaunchKernelGGL((k_source_sb<false, false>), grid, block, 0, st, n, x, y, bx, by, src, ll, sb);
   return hipGetLastError();
 }
 

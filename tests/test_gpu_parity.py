@@ -335,6 +335,48 @@ def test_source_sb_at_gpu_traced_points(ctx):
     assert image_error(_np(sb), ref) <= 2e-5
 
 
+@pytest.mark.parametrize("n", [1, 3, 4, 5, 257, 1030])
+def test_source_sb_ragged_and_unaligned_points(ctx, n):
+    # 16-byte aligned arrays take four points per thread (and one per thread
+    # for the last n mod 4); views starting one element in take one per
+    # thread: the two give the same bits, and both match the oracle
+    sc = W.config2_scene(n_sub=10)
+    x, y = W.random_points(n + 1, 3.0, seed=11)
+    bx, by = W.random_points(n + 1, 1.0, seed=12)
+    dev = [torch.from_numpy(np.asarray(a, np.float32)).cuda() for a in (x, y, bx, by)]
+    vec = ctx.source_sb(*[t[:n] for t in dev], sc.source, sc.lens_light)
+    one = ctx.source_sb(*[t[1:] for t in dev], sc.source, sc.lens_light)
+    ref = O.surface_brightness(x[:n], y[:n], bx[:n], by[:n], sc.source, sc.lens_light, False)
+    assert image_error(_np(vec), ref) <= 2e-5
+    ref1 = O.surface_brightness(x[1:], y[1:], bx[1:], by[1:], sc.source, sc.lens_light, False)
+    assert image_error(_np(one), ref1) <= 2e-5
+    if n > 1:
+        np.testing.assert_array_equal(_np(vec)[1:], _np(
+            ctx.source_sb(*[t[1:n] for t in dev], sc.source, sc.lens_light)))
+
+
+def test_source_sb_reads_no_coordinates_of_an_empty_list(ctx):
+    # through the C ABI: the traced coordinates may be NULL without sources,
+    # and all four when both lists are empty
+    from ctypes import byref, c_void_p
+    from paper_2606_01547_amd._native import _stream_handle
+    sc = W.config2_scene(n_sub=10)
+    x, y = W.random_points(1001, 3.0, seed=13)
+    xt = torch.from_numpy(np.asarray(x, np.float32)).cuda()
+    yt = torch.from_numpy(np.asarray(y, np.float32)).cuda()
+    keep = []
+    none, ll = ctx._light([], False, keep), ctx._light(sc.lens_light, False, keep)
+    sb = torch.full((1001,), 7.0, dtype=torch.float32, device="cuda")
+    lib, st = ctx._lib, _stream_handle(None)
+    assert lib.jt_source_sb(ctx._ptr, 1001, c_void_p(xt.data_ptr()), c_void_p(yt.data_ptr()), None, None,
+                            byref(none), byref(ll), c_void_p(sb.data_ptr()), st) == 0
+    ref = O.surface_brightness(x, y, x, y, [], sc.lens_light, False)
+    assert image_error(_np(sb), ref) <= 2e-5
+    assert lib.jt_source_sb(ctx._ptr, 1001, None, None, None, None, byref(none), byref(none),
+                            c_void_p(sb.data_ptr()), st) == 0
+    assert np.all(_np(sb) == 0.0)
+
+
 # ---------------------------------------------------------------- convolution
 @pytest.mark.parametrize("shape,k", [((53, 77), 1), ((53, 77), 3), ((53, 77), 11), ((200, 200), 41),
                                      ((64, 64), 101), ((300, 33), 129), ((9, 300), 255), ((1, 1), 5)])
