@@ -364,8 +364,9 @@ jt_status jt_lbfgs(jt_ctx* ctx, const jt_grid* grid, const jt_fit_problem* prob,
 jt_status jt_upload_subhalos(jt_ctx* ctx, int n, const float* x, const float* y,
                              const float* Rs, const float* alpha_Rs, uint64_t* handle);
 /* The same for truncated subhalos (r_trunc, host float32[n], each > 0; see
- * jt_nfw).  The continuous-batching server does not take such tables
- * (JT_EUNSUPPORTED at submit); the single-image calls do. */
+ * jt_nfw).  Every call that takes a subhalo handle takes such tables too;
+ * the continuous-batching server keeps each launch to one profile (a TNFW
+ * request and an NFW one never share a batch). */
 jt_status jt_upload_tnfw(jt_ctx* ctx, int n, const float* x, const float* y, const float* Rs,
                          const float* alpha_Rs, const float* r_trunc, uint64_t* handle);
 /* Copy a host float32 [k][k] PSF (odd k) into device memory owned by ctx. */
@@ -390,7 +391,8 @@ typedef struct jt_server jt_server;
 typedef struct {
   size_t hbm_budget_bytes;   /* device arena for in-flight request buffers (> 0) */
   int max_batch_images;      /* requests per batch (>= 1) */
-  double max_batch_pairs;    /* work cap per batch in (sub-pixel, subhalo) pairs (> 0);
+  double max_batch_pairs;    /* work cap per batch in (sub-pixel, subhalo) pairs (> 0;
+                                a truncated-NFW pair counts as 5.3, its measured cost);
                                 a larger request runs in chunks of its pixel blocks of
                                 at most this much work, one such request at a time,
                                 while later requests are batched beside it */
@@ -405,7 +407,7 @@ typedef struct {
   int has_sie, has_shear;
   jt_sie sie;
   jt_shear shear;
-  uint64_t subhalo_handle;   /* from jt_upload_subhalos; 0 = no subhalos */
+  uint64_t subhalo_handle;   /* from jt_upload_subhalos or jt_upload_tnfw; 0 = none */
   jt_light src, lens_light;  /* host arrays, read during jt_server_submit */
   uint64_t psf_handle;       /* from jt_upload_psf; 0 = no convolution */
   float* out;                /* device float32 [ny][nx], written when the ticket completes */

@@ -346,7 +346,7 @@ __global__ __launch_bounds__(64) void k_grad_subhalo(const ImageDesc* __restrict
   const int b = blockIdx.y, q = blockIdx.z, B = gridDim.y;
   const int k = blockIdx.x * 64 + threadIdx.x;
   const bool valid = k < n;
-  const SubRec s = descs[b].sub[valid ? k : 0];
+  const SubRec s = static_cast<const SubRec*>(descs[b].sub)[valid ? k : 0];
   // the record holds c1/4 and c2/4 (exact quarters)
   const float c1 = 4.0f * s.c1, c2 = 4.0f * s.c2;
   // alpha / alpha_Rs = c2n * h * d  (h in units of ln2/2)

@@ -151,7 +151,7 @@ struct ImageDesc {
   GridC g;               // g.ppb matches the launch's wave split
   MacroC mc;
   LightC src, ll;
-  const SubRec* sub;     // subhalo_table_records(n) records
+  const void* sub;       // subhalo_table_records(n) records: SubRec, or TRec in a TNFW launch
   int nloop;             // loop count (multiple of 4)
   float* img;            // unconvolved image [ny][nx]
   float2* beta;          // traced sub-pixel positions [ny * nx][s^2] kept for the adjoint, or null

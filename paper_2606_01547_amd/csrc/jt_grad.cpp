@@ -98,7 +98,7 @@ jt_status run_forward(jt_ctx* ctx, Batch& bt, const jt_draws* d, const float* ps
       return launch_prep_subhalos_batched(bt.B, bt.n, d->sub_x, d->sub_y, d->sub_Rs, d->sub_alpha_Rs, tables, st);
     }, "prep_subhalos_batched"));
   JT_TRY(timed_launch(ctx, JT_K_SIM, st, [&] {
-    return launch_simulate_desc(bt.split, false, beta != nullptr, ddescs, nullptr, bt.B * bt.bpi, bt.bpi, st);
+    return launch_simulate_desc(bt.split, false, false, beta != nullptr, ddescs, nullptr, bt.B * bt.bpi, bt.bpi, st);
   }, "simulate_batch"));
   if (psf && model != model_u)
     JT_TRY(timed_launch(ctx, JT_K_CONV, st, [&] {

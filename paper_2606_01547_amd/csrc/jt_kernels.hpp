@@ -52,9 +52,9 @@ hipError_t launch_conv_desc(const ConvDesc* descs, const int4* tiles, int ntiles
 int conv_tiles_x(int nx);
 int conv_tiles_y(int ny);
 // Batched fused simulation over image descriptors (see k_simulate_desc).
-hipError_t launch_simulate_desc(int split, bool extra, bool keep_beta, const ImageDesc* descs, const int2* tiles,
-                                int nblocks,
-                                int blocks_per_image, hipStream_t st);
+// tnfw: every descriptor's table holds TRec records (not with keep_beta).
+hipError_t launch_simulate_desc(int split, bool tnfw, bool extra, bool keep_beta, const ImageDesc* descs,
+                                const int2* tiles, int nblocks, int blocks_per_image, hipStream_t st);
 // Per-draw subhalo tables from [B][n] SoA into B tables of
 // subhalo_table_records(n) records.
 hipError_t launch_prep_subhalos_batched(int B, int n, const float* x, const float* y, const float* rs,

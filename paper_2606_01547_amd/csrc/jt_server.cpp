@@ -40,9 +40,13 @@ namespace {
 
 size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 
-// Smallest chunk of a chunked request: 4096 blocks of 4 waves, two full rounds
+// Smallest chunk of a chunked request: 2048 blocks of 4 waves, one full round
 // of wave slots on 256 CUs at 8 waves per SIMD.
 constexpr int kChunkMinBlocks = 2048;
+
+// A truncated-NFW pair costs about 5.3 NFW pairs of GPU time (headline image:
+// 7.01 ms against 1.333 ms); the work caps count it so.
+constexpr double kTnfwPairCost = 5.3;
 
 // Pinned host memory for the batches' descriptor uploads.  Each batch keeps its
 // own slice until it completes, so forming a batch never waits for a copy
@@ -94,7 +98,8 @@ struct Req {
   GridC g;
   MacroC mc;
   LightC src, ll;
-  const SubRec* table = nullptr;
+  const void* table = nullptr;     // SubRec records, or TRec when tnfw
+  bool tnfw = false;
   int nsub = 0, nloop = 0;
   const float* psf = nullptr;
   int k = 0;
@@ -286,7 +291,7 @@ jt_status jt_server::launch_hip(Batch& b) {
   if (nctiles) std::memcpy(host.data() + o_ct, ctiles.data(), sizeof(int4) * nctiles);
   JT_TRY(upload(b, host.data(), o_img, base, s));
   JT_TRY(timed_launch(ctx, JT_K_SIM, s, [&] {
-    return launch_simulate_desc(split, extra, false, (const ImageDesc*)base, (const int2*)(base + o_t), (int)ntiles,
+    return launch_simulate_desc(split, order[0]->tnfw, extra, false, (const ImageDesc*)base, (const int2*)(base + o_t), (int)ntiles,
                                 0, s);
   }, "server simulate"));
   if (ncon)
@@ -319,7 +324,7 @@ jt_status jt_server::launch_chunk_hip(Batch& b) {
   for (int i = 0; i < nt; ++i) tl[i] = make_int2(0, b.blk0 + i);
   JT_TRY(upload(b, host.data(), end, base, s));
   JT_TRY(timed_launch(ctx, JT_K_SIM, s, [&] {
-    return launch_simulate_desc(r->split, light_has_extra(r->src) || light_has_extra(r->ll), false, (const ImageDesc*)base,
+    return launch_simulate_desc(r->split, r->tnfw, light_has_extra(r->src) || light_has_extra(r->ll), false, (const ImageDesc*)base,
                                 (const int2*)(base + o_t), nt, 0, s);
   }, "server simulate chunk"));
   return check_hip(hipEventRecord(b.ev, s), "hipEventRecord(batch)");
@@ -627,6 +632,7 @@ void jt_server::launch_ready() {
       if ((int)pick.size() >= cfg.max_batch_images) break;
       if (r->chunked) break;  // it waits at its place
       if (!pick.empty() && pairs + r->pairs > cfg.max_batch_pairs) break;
+      if (!pick.empty() && r->tnfw != pick[0]->tnfw) break;  // one subhalo profile per launch
       pick.push_back(r);
       pairs += r->pairs;
       bytes += r->footprint;
@@ -763,10 +769,8 @@ extern "C" jt_status jt_server_submit(jt_server* srv, const jt_request* req, uin
   if (srv->ctx) {
     if (req->subhalo_handle) {
       const void* tab = nullptr;
-      bool tnfw = false;
-      JT_TRY(ctx_subhalo_handle(srv->ctx, req->subhalo_handle, &tab, &r->nsub, &tnfw));
-      if (tnfw) return fail(JT_EUNSUPPORTED, "server submit: truncated (TNFW) subhalo tables are not batched");
-      r->table = (const SubRec*)tab;
+      JT_TRY(ctx_subhalo_handle(srv->ctx, req->subhalo_handle, &tab, &r->nsub, &r->tnfw));
+      r->table = tab;
     }
     if (req->psf_handle) JT_TRY(jt_psf_pointer(srv->ctx, req->psf_handle, &r->psf, &r->k));
   } else {
@@ -776,7 +780,7 @@ extern "C" jt_status jt_server_submit(jt_server* srv, const jt_request* req, uin
   }
   if (r->k > JT_MAX_PSF) return fail(JT_EUNSUPPORTED, "server submit: PSF side %d > %d", r->k, JT_MAX_PSF);
   r->nloop = subhalo_loop_count(r->nsub);
-  r->pairs = request_pairs(r->g, r->nloop);
+  r->pairs = request_pairs(r->g, r->nloop) * (r->tnfw ? kTnfwPairCost : 1.0);
   // block shape as the request would run alone; chunked when over the work
   // cap and large enough for more than two minimum chunks, otherwise a
   // request over the cap runs as a batch of its own

@@ -249,7 +249,7 @@ __global__ __launch_bounds__(split_threads(kSplit)) void k_simulate_basis(GridC 
 // Batched images: block b works on image descs[b / blocks_per_image] when
 // every image has the same grid (tiles == nullptr), otherwise on the
 // (image, pixel block) pair tiles[b].
-template <int kSplit, bool kExtra, bool kKeepBeta>
+template <int kSplit, class P, bool kExtra, bool kKeepBeta>
 __global__ __launch_bounds__(split_threads(kSplit)) void k_simulate_desc(const ImageDesc* __restrict__ descs,
                                                                         const int2* __restrict__ tiles,
                                                                         int blocks_per_image) {
@@ -265,8 +265,8 @@ __global__ __launch_bounds__(split_threads(kSplit)) void k_simulate_desc(const I
     blk = blockIdx.x - di * blocks_per_image;
   }
   const ImageDesc& d = descs[di];
-  simulate_block<kSplit, NfwPairs, kExtra, kKeepBeta>(d.g, d.mc, d.sub, d.nloop, d.src, d.ll, d.img, blk, scratch,
-                                                      red, d.beta);
+  simulate_block<kSplit, P, kExtra, kKeepBeta>(d.g, d.mc, d.sub, d.nloop, d.src, d.ll, d.img, blk, scratch, red,
+                                               d.beta);
 }
 
 // Direct convolution tiles: 64 x 4 outputs per block of kW waves.  Thread
@@ -555,20 +555,25 @@ hipError_t launch_conv_desc(const ConvDesc* descs, const int4* tiles, int ntiles
 int conv_tiles_x(int nx) { return (nx + kConvTX - 1) / kConvTX; }
 int conv_tiles_y(int ny) { return (ny + kConvTY - 1) / kConvTY; }
 
-hipError_t launch_simulate_desc(int split, bool extra, bool keep_beta, const ImageDesc* descs, const int2* tiles,
-                                int nblocks, int blocks_per_image, hipStream_t st) {
+hipError_t launch_simulate_desc(int split, bool tnfw, bool extra, bool keep_beta, const ImageDesc* descs,
+                                const int2* tiles, int nblocks, int blocks_per_image, hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
-#define JT_SIMD(S, E, K) hipLaunchKernelGGL((k_simulate_desc<S, E, K>), dim3((unsigned)nblocks), \
-                                            dim3(split_threads(S)), 0, st, descs, tiles, blocks_per_image)
-#define JT_SIMD_S(E, K) \
-  if (split == 1) JT_SIMD(1, E, K); else if (split == 2) JT_SIMD(2, E, K); else if (split == 4) JT_SIMD(4, E, K); \
-  else JT_SIMD(8, E, K)
+  if (tnfw && keep_beta) return hipErrorInvalidValue;
+#define JT_SIMD(S, P, E, K) hipLaunchKernelGGL((k_simulate_desc<S, P, E, K>), dim3((unsigned)nblocks), \
+                                               dim3(split_threads(S)), 0, st, descs, tiles, blocks_per_image)
+#define JT_SIMD_S(P, E, K) \
+  if (split == 1) JT_SIMD(1, P, E, K); else if (split == 2) JT_SIMD(2, P, E, K); \
+  else if (split == 4) JT_SIMD(4, P, E, K); else JT_SIMD(8, P, E, K)
   if (keep_beta) {
-    JT_SIMD_S(false, true);
+    JT_SIMD_S(NfwPairs, false, true);
+  } else if (tnfw && extra) {
+    JT_SIMD_S(TnfwPairs, true, false);
+  } else if (tnfw) {
+    JT_SIMD_S(TnfwPairs, false, false);
   } else if (extra) {
-    JT_SIMD_S(true, false);
+    JT_SIMD_S(NfwPairs, true, false);
   } else {
-    JT_SIMD_S(false, false);
+    JT_SIMD_S(NfwPairs, false, false);
   }
 #undef JT_SIMD_S
 #undef JT_SIMD
