@@ -338,17 +338,22 @@ __device__ __forceinline__ void nfw_h_dh_far(float l2, float y2, float p, float 
   dh = fmaf(oneF * kInv2U, inv, -h) * y2;
 }
 
-// grid (ceil(n / 64), B, kRecParts); lane = subhalo.  Writes the part
-// partial (x, y, alpha_Rs) gradients to gpart[q][b][k][3].
-__global__ __launch_bounds__(64) void k_grad_subhalo(const ImageDesc* __restrict__ descs,
+// grid (ceil(n / 64), B, kRecParts); lane = subhalo k of draw b, read from
+// the draws' SoA [B][n] (x, y, Rs, alpha_Rs).  Writes the part partial
+// (x, y, alpha_Rs) gradients to gpart[q][b][k][3].
+__global__ __launch_bounds__(64) void k_grad_subhalo(const float* __restrict__ sub_x, const float* __restrict__ sub_y,
+                                                    const float* __restrict__ sub_rs, const float* __restrict__ sub_ars,
                                                     const float4* __restrict__ rec, int rec_stride,
                                                     int nrec_loop, int n, float* __restrict__ gpart) {
   const int b = blockIdx.y, q = blockIdx.z, B = gridDim.y;
   const int k = blockIdx.x * 64 + threadIdx.x;
   const bool valid = k < n;
-  const SubRec s = static_cast<const SubRec*>(descs[b].sub)[valid ? k : 0];
-  // the record holds c1/4 and c2/4 (exact quarters)
-  const float c1 = 4.0f * s.c1, c2 = 4.0f * s.c2;
+  const size_t j = (size_t)b * n + (valid ? k : 0);
+  const float x0 = sub_x[j], y0 = sub_y[j];
+  // c1 = 1/Rs^2 and c2 = kNfwRecScale alpha_Rs / ((1 - ln 2) Rs), each rounded once
+  const double rs = sub_rs[j];
+  const float c1 = (float)(1.0 / (rs * rs));
+  const float c2 = (float)(kNfwRecScale * (double)sub_ars[j] / ((1.0 - kLn2d) * rs));
   // alpha / alpha_Rs = c2n * h * d  (h in units of ln2/2)
   const float c2n = sqrtf(c1) * (float)(kNfwRecScale / (1.0 - kLn2d));
   const float c1x2 = 2.0f * c1;
@@ -368,8 +373,8 @@ __global__ __launch_bounds__(64) void k_grad_subhalo(const ImageDesc* __restrict
       float dx[4], dy[4], X[4], y[4], l2[4], y2[4], p[4], inv[4], h[4], dh[4];
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        dx[m] = rr[m].x - s.x;
-        dy[m] = rr[m].y - s.y;
+        dx[m] = rr[m].x - x0;
+        dy[m] = rr[m].y - y0;
         X[m] = fmaf(dy[m], dy[m], dx[m] * dx[m]) * c1;
         y[m] = __builtin_amdgcn_rsqf(X[m]);
         l2[m] = __builtin_amdgcn_logf(X[m]);
@@ -468,11 +473,11 @@ hipError_t launch_grad_pixel(int split, bool kept, int B, int bpi, const ImageDe
   return hipGetLastError();
 }
 
-hipError_t launch_grad_subhalo(int B, int n, const ImageDesc* descs, const float4* rec, int rec_stride,
-                               int nrec_loop, float* gpart, hipStream_t st) {
+hipError_t launch_grad_subhalo(int B, int n, const float* x, const float* y, const float* rs, const float* ars,
+                               const float4* rec, int rec_stride, int nrec_loop, float* gpart, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_grad_subhalo, dim3((n + 63) / 64, B, kRecParts), dim3(64), 0, st, descs, rec, rec_stride,
-                     nrec_loop, n, gpart);
+  hipLaunchKernelGGL(k_grad_subhalo, dim3((n + 63) / 64, B, kRecParts), dim3(64), 0, st, x, y, rs, ars, rec,
+                     rec_stride, nrec_loop, n, gpart);
   return hipGetLastError();
 }
 

@@ -191,7 +191,8 @@ jt_status chi2_common(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, c
     return launch_grad_pixel(bt.split, keep, bt.B, bt.bpi, dd, lamU, rec, rec_stride, part, bt.P, st);
   }, "grad_pixel"));
   JT_TRY(timed_launch(ctx, JT_K_GRAD, st, [&] {
-    return launch_grad_subhalo(bt.B, bt.n, dd, rec, rec_stride, nrec_loop, gpart, st);
+    return launch_grad_subhalo(bt.B, bt.n, draws->sub_x, draws->sub_y, draws->sub_Rs, draws->sub_alpha_Rs, rec,
+                               rec_stride, nrec_loop, gpart, st);
   }, "grad_subhalo"));
   return timed_launch(ctx, JT_K_GRAD, st, [&] {
     return launch_grad_finalize(bt.B, bt.P, bt.bpi, part, g_macro, nres, lpart, logL, bt.n, gpart,

@@ -87,8 +87,9 @@ hipError_t launch_residual(int B, int npix, const float* model, const float* dat
                            float* part, int* nblocks, hipStream_t st);
 hipError_t launch_grad_pixel(int split, bool kept, int B, int bpi, const ImageDesc* descs, const float* lamU,
                              float4* rec, int rec_stride, float* part, int P, hipStream_t st);
-hipError_t launch_grad_subhalo(int B, int n, const ImageDesc* descs, const float4* rec, int rec_stride,
-                               int nrec_loop, float* gpart, hipStream_t st);
+// draws' subhalo SoA x, y, rs, ars: device [B][n]
+hipError_t launch_grad_subhalo(int B, int n, const float* x, const float* y, const float* rs, const float* ars,
+                               const float4* rec, int rec_stride, int nrec_loop, float* gpart, hipStream_t st);
 hipError_t launch_grad_finalize(int B, int P, int bpi, const float* part, float* g_macro, int nres,
                                 const float* lpart, double* logL, int n, const float* gpart, float* g_sub,
                                 hipStream_t st);
