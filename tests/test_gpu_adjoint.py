@@ -97,6 +97,29 @@ def test_chi2_grad_differentiation_case(ctx):
     _check_grad(ctx, truth, draws, d, w)
 
 
+def test_chi2_grad_full_batch_sampled(ctx):
+    """The benchmark's launch: 256 draws of the differentiation case in one
+    call.  The last draw against the oracle; the first against the same draw
+    computed alone, which runs with another wave split (8 instead of 1) and so
+    groups its sub-pixels into other reduction blocks: equal to FP32 rounding."""
+    truth, draws = W.config4_draws(B=256)
+    d, w = _data(truth, seed=1)
+    logL, gm, gs = ctx.chi2_grad(truth.grid, _batch(draws), d, w, truth.psf)
+    gm, gs, logL = _np(gm), _np(gs), _np(logL)
+    lo, em, es = O.chi2_gradient(draws[255], d.astype(np.float64), w.astype(np.float64))
+    assert _group_err(gm[255], em) <= GRAD_TOL
+    for col in range(3):
+        assert _group_err(gs[255, :, col], es[:, col]) <= GRAD_TOL
+    assert float(logL[255]) == pytest.approx(lo, rel=1e-3)
+    # each entry sums 10^4 sub-pixel terms of both signs in FP32; another
+    # grouping moves it by up to ~1e-5 of the group's largest (measured 1.2e-5)
+    one = ctx.chi2_grad(truth.grid, _batch(draws[:1]), d, w, truth.psf)
+    assert _group_err(gm[0], _np(one[1])[0]) <= 1e-4
+    for col in range(3):
+        assert _group_err(gs[0, :, col], _np(one[2])[0, :, col]) <= 1e-4
+    assert np.all(np.isfinite(gm)) and np.all(np.isfinite(gs))
+
+
 def test_chi2_grad_supersampled_with_lens_light(ctx):
     grid = W.Grid(nx=37, ny=29, pixel_scale=0.09, x0=0.04, y0=-0.03, supersample=2)
     truth, draws = W.config4_draws(B=3, n_sub=150, grid=grid, lens_light=True, psf_size=7)
