@@ -93,6 +93,31 @@ __device__ __forceinline__ float4 subhalo_range_sum(float tx, float ty, const vo
   return make_float4(hx, lx, hy, ly);
 }
 
+// The truncated profile's 32-byte records, two at a time with two
+// prefetched (four at a time would hold 64 scalar registers of records and
+// cost a wave per SIMD): the same pairs in the same order, so the same sums.
+template <>
+__device__ __forceinline__ float4 subhalo_range_sum<TnfwPairs>(float tx, float ty, const void* table, int kb,
+                                                               int ke) {
+  const SubTable sub = (SubTable)(const float*)table;
+  float hx = 0.f, lx = 0.f, hy = 0.f, ly = 0.f;
+  TRec n0 = TnfwPairs::load(sub, kb), n1 = TnfwPairs::load(sub, kb + 1);
+  for (int k0 = kb; k0 < ke; k0 += kSubTile) {
+    const int kend = min(k0 + kSubTile, ke);
+    float px = 0.f, py = 0.f;
+    for (int k = k0; k < kend; k += 2) {
+      const TRec s0 = n0, s1 = n1;
+      n0 = TnfwPairs::load(sub, k + 2);
+      n1 = TnfwPairs::load(sub, k + 3);
+      tnfw_pair(tx, ty, s0, px, py);
+      tnfw_pair(tx, ty, s1, px, py);
+    }
+    two_sum_acc(hx, lx, px);
+    two_sum_acc(hy, ly, py);
+  }
+  return make_float4(hx, lx, hy, ly);
+}
+
 // Range partials of a block's sub-pixels, [range][slot], slot <
 // split_lanes(kSplit).  With one group the ranges are added as they are
 // computed and nothing is stored.
