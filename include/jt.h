@@ -172,7 +172,8 @@ double jt_sersic_bn(double n, int exact);
  * -------------------------------------------------------------------- */
 /* beta = theta - sum of the deflections of `lens` at the n points
  * (x[i], y[i]) (device float32).  Outputs bx, by: device float32[n],
- * may not alias the inputs.  n = 0 is a no-op. */
+ * overlapping neither the inputs nor each other (JT_EINVAL).  n = 0 is a
+ * no-op. */
 jt_status jt_ray_shoot(jt_ctx* ctx, int n, const float* x, const float* y,
                        const jt_lens* lens, float* bx, float* by, hipStream_t stream);
 
@@ -185,7 +186,9 @@ jt_status jt_deflection(jt_ctx* ctx, int n, const float* x, const float* y,
  * -------------------------------------------------------------------- */
 /* sb[i] = sum_src I(bx[i], by[i]) + sum_lens_light I(x[i], y[i]).
  * Device float32 arrays of length n.  `src` or `lens_light` may be NULL
- * (no component); x, y may be NULL when lens_light is empty. */
+ * (no component); x, y may be NULL when lens_light is empty, bx, by when src
+ * is.  sb may be one of the inputs itself (in place) but must not otherwise
+ * overlap them (JT_EINVAL). */
 jt_status jt_source_sb(jt_ctx* ctx, int n, const float* x, const float* y,
                        const float* bx, const float* by, const jt_light* src,
                        const jt_light* lens_light, float* sb, hipStream_t stream);
@@ -195,7 +198,8 @@ jt_status jt_source_sb(jt_ctx* ctx, int n, const float* x, const float* y,
  * -------------------------------------------------------------------- */
 /* out[i][j] = sum_{a,b} psf[a][b] img[i - a + c][j - b + c], c = (k-1)/2,
  * zero outside the image, same size (a true convolution).  img, out: device
- * float32 [ny][nx] (must not alias); psf: device float32 [k][k], k odd.
+ * float32 [ny][nx], out overlapping neither img nor psf (JT_EINVAL); psf:
+ * device float32 [k][k], k odd.
  * method: 0 = auto (direct below the measured crossover), 1 = direct
  * (LDS-tiled, k <= JT_MAX_PSF), 2 = FFT (FP64 transform). */
 jt_status jt_convolve(jt_ctx* ctx, const float* img, int nx, int ny, const float* psf,

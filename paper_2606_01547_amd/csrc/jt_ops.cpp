@@ -3,6 +3,7 @@
 // launch on error) and enqueues kernels on the caller's stream.
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 
 #include "jt_host.hpp"
 #include "jt_kernels.hpp"
@@ -10,6 +11,13 @@
 using namespace jt;
 
 namespace {
+
+// [a, a + n) and [b, b + m) share an element (null pointers share none).
+bool overlap(const float* a, size_t n, const float* b, size_t m) {
+  if (!a || !b || n == 0 || m == 0) return false;
+  const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+  return pa < pb + sizeof(float) * m && pb < pa + sizeof(float) * n;
+}
 
 jt_status ray_common(bool alpha, jt_ctx* ctx, int n, const float* x, const float* y, const jt_lens* lens,
                      float* ox, float* oy, hipStream_t st) {
@@ -19,7 +27,10 @@ jt_status ray_common(bool alpha, jt_ctx* ctx, int n, const float* x, const float
   JT_TRY(make_macro(lens, mc));
   if (n == 0) return JT_OK;
   if (!x || !y || !ox || !oy) return fail(JT_EINVAL, "ray_shoot: null array");
-  if (ox == x || ox == y || oy == x || oy == y || ox == oy) return fail(JT_EINVAL, "ray_shoot: outputs alias inputs");
+  const size_t N = (size_t)n;
+  if (overlap(ox, N, x, N) || overlap(ox, N, y, N) || overlap(oy, N, x, N) || overlap(oy, N, y, N) ||
+      overlap(ox, N, oy, N))
+    return fail(JT_EINVAL, "ray_shoot: outputs overlap the inputs or each other");
   void* scratch = nullptr;
   const size_t tab_bytes = subhalo_scratch_bytes(lens);
   if (tab_bytes) JT_TRY(ctx_workspace(ctx, st, tab_bytes, &scratch));
@@ -36,7 +47,9 @@ jt_status check_conv_args(const float* img, int nx, int ny, const float* psf, in
   if (!img || !out || !psf) return fail(JT_EINVAL, "convolve: null pointer");
   if (nx < 1 || ny < 1) return fail(JT_EINVAL, "convolve: %d x %d image", nx, ny);
   if (k < 1 || k % 2 == 0) return fail(JT_EINVAL, "convolve: PSF side %d must be odd", k);
-  if (img == out) return fail(JT_EINVAL, "convolve: output aliases input");
+  const size_t npix = (size_t)std::max(nx, 0) * (size_t)std::max(ny, 0);
+  if (overlap(out, npix, img, npix) || overlap(out, npix, psf, (size_t)k * k))
+    return fail(JT_EINVAL, "convolve: output overlaps the image or the PSF");
   if ((double)nx * ny > 2147483647.0) return fail(JT_EUNSUPPORTED, "convolve: image too large");
   return JT_OK;
 }
@@ -106,6 +119,11 @@ extern "C" jt_status jt_source_sb(jt_ctx* ctx, int n, const float* x, const floa
   if (!sb) return fail(JT_EINVAL, "source_sb: null output");
   if (light_any(s) && (!bx || !by)) return fail(JT_EINVAL, "source_sb: null traced coordinates");
   if (light_any(l) && (!x || !y)) return fail(JT_EINVAL, "source_sb: null image-plane coordinates");
+  // in place is fine (each element is read before its own output is written)
+  for (const float* p : {light_any(s) ? bx : nullptr, light_any(s) ? by : nullptr, light_any(l) ? x : nullptr,
+                         light_any(l) ? y : nullptr})
+    if (p != sb && overlap(sb, (size_t)n, p, (size_t)n))
+      return fail(JT_EINVAL, "source_sb: output overlaps an input without being it");
   const float* zx = bx ? bx : x;  // unused when the matching list is empty
   const float* zy = by ? by : y;
   return timed_launch(ctx, JT_K_SB, stream,

@@ -594,6 +594,33 @@ def test_simulate_without_light_or_lens(ctx):
 
 
 # ---------------------------------------------------------------- argument errors
+def test_overlapping_outputs_are_rejected_and_in_place_sb_is_exact(ctx):
+    from paper_2606_01547_amd import JtError
+    from paper_2606_01547_amd._native import JT_EINVAL
+    sc = W.config2_scene(n_sub=10)
+    buf = torch.from_numpy(np.concatenate(W.random_points(1500, 2.0, seed=21))).cuda()   # 3000 floats
+    x, y = buf[:1000], buf[1000:2000]
+    for out in ((buf[500:1500], buf[2000:3000]), (buf[2000:3000], buf[1999:2999]), (buf[1000:2000], buf[2000:3000])):
+        with pytest.raises(JtError) as e:
+            ctx.ray_shoot(x, y, sc.lens, out=out)
+        assert e.value.status == JT_EINVAL
+    img = torch.zeros(2 * 64 * 64, device="cuda")
+    psf = torch.full((5, 5), 1.0 / 25, device="cuda")
+    with pytest.raises(JtError) as e:
+        ctx.convolve(img[:4096].view(64, 64), psf, out=img[100:4196].view(64, 64))
+    assert e.value.status == JT_EINVAL
+    bx = torch.empty(1001, device="cuda")
+    bx[:1000] = buf[2000:3000]
+    by = buf[:1000] * 0.5
+    ref = _np(ctx.source_sb(x, y, bx[:1000], by, sc.source, sc.lens_light))
+    with pytest.raises(JtError) as e:
+        ctx.source_sb(x, y, bx[:1000], by, sc.source, sc.lens_light, out=bx[1:1001])
+    assert e.value.status == JT_EINVAL
+    inplace = bx[:1000].clone()
+    ctx.source_sb(x, y, inplace, by, sc.source, sc.lens_light, out=inplace)
+    np.testing.assert_array_equal(_np(inplace), ref)
+
+
 def test_invalid_arguments_raise_without_launch(ctx):
     from paper_2606_01547_amd import JtError
     from paper_2606_01547_amd._native import JT_EINVAL, JT_EUNSUPPORTED
