@@ -213,9 +213,9 @@ int jt_convolve_auto_method(int nx, int ny, int k);
  * Fused simulation: steps 1-2 and the supersample average in one kernel,
  * then step 3.
  * -------------------------------------------------------------------- */
-/* out: device float32 [ny][nx].  psf: device float32 [k][k] (odd k), or
- * NULL with k = 0 to return the unconvolved image.  Uses ctx workspace for
- * the unconvolved image when a PSF is given. */
+/* out: device float32 [ny][nx], not overlapping psf (JT_EINVAL).  psf: device
+ * float32 [k][k] (odd k), or NULL with k = 0 to return the unconvolved image.
+ * Uses ctx workspace for the unconvolved image when a PSF is given. */
 jt_status jt_simulate_image(jt_ctx* ctx, const jt_grid* grid, const jt_lens* lens,
                             const jt_light* src, const jt_light* lens_light,
                             const float* psf, int k, float* out, hipStream_t stream);

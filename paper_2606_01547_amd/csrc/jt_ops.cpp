@@ -158,6 +158,8 @@ extern "C" jt_status jt_simulate_image(jt_ctx* ctx, const jt_grid* grid, const j
   if (!out) return fail(JT_EINVAL, "simulate: null output");
   if ((psf == nullptr) != (k == 0)) return fail(JT_EINVAL, "simulate: psf and k must be given together");
   if (psf && (k < 1 || k % 2 == 0)) return fail(JT_EINVAL, "simulate: PSF side %d must be odd", k);
+  if (psf && overlap(out, (size_t)g.nx * g.ny, psf, (size_t)k * k))
+    return fail(JT_EINVAL, "simulate: output overlaps the PSF");
   // workspace: [subhalo table][unconvolved image]
   const size_t tab_bytes = subhalo_scratch_bytes(lens);
   const size_t img_bytes = psf ? sizeof(float) * (size_t)g.nx * g.ny : 0;
