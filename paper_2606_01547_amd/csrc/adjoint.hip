@@ -23,6 +23,9 @@ namespace jt {
 
 // Parts of the subhalo-major pass over sub-pixel records (summed in order).
 constexpr int kRecParts = kRecPartsHost;
+// Subhalos per block of that pass: its waves read the same records, so a
+// block of several waves shares them through its CU's scalar cache.
+constexpr int kSubhaloBlock = 256;
 
 constexpr float kCapaccioliSlope = 1.9992f;   // d b_n / d n of the Capaccioli fit
 
@@ -338,15 +341,15 @@ __device__ __forceinline__ void nfw_h_dh_far(float l2, float y2, float p, float 
   dh = fmaf(oneF * kInv2U, inv, -h) * y2;
 }
 
-// grid (ceil(n / 64), B, kRecParts); lane = subhalo k of draw b, read from
+// grid (ceil(n / kSubhaloBlock), B, kRecParts); lane = subhalo k of draw b, read from
 // the draws' SoA [B][n] (x, y, Rs, alpha_Rs).  Writes the part partial
 // (x, y, alpha_Rs) gradients to gpart[q][b][k][3].
-__global__ __launch_bounds__(64) void k_grad_subhalo(const float* __restrict__ sub_x, const float* __restrict__ sub_y,
+__global__ __launch_bounds__(kSubhaloBlock) void k_grad_subhalo(const float* __restrict__ sub_x, const float* __restrict__ sub_y,
                                                     const float* __restrict__ sub_rs, const float* __restrict__ sub_ars,
                                                     const float4* __restrict__ rec, int rec_stride,
                                                     int nrec_loop, int n, float* __restrict__ gpart) {
   const int b = blockIdx.y, q = blockIdx.z, B = gridDim.y;
-  const int k = blockIdx.x * 64 + threadIdx.x;
+  const int k = blockIdx.x * kSubhaloBlock + threadIdx.x;
   const bool valid = k < n;
   const size_t j = (size_t)b * n + (valid ? k : 0);
   const float x0 = sub_x[j], y0 = sub_y[j];
@@ -476,7 +479,8 @@ hipError_t launch_grad_pixel(int split, bool kept, int B, int bpi, const ImageDe
 hipError_t launch_grad_subhalo(int B, int n, const float* x, const float* y, const float* rs, const float* ars,
                                const float4* rec, int rec_stride, int nrec_loop, float* gpart, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_grad_subhalo, dim3((n + 63) / 64, B, kRecParts), dim3(64), 0, st, x, y, rs, ars, rec,
+  hipLaunchKernelGGL(k_grad_subhalo, dim3((n + kSubhaloBlock - 1) / kSubhaloBlock, B, kRecParts), dim3(kSubhaloBlock),
+                     0, st, x, y, rs, ars, rec,
                      rec_stride, nrec_loop, n, gpart);
   return hipGetLastError();
 }
