@@ -82,11 +82,12 @@ def test_simulate_with_extra_profiles(ctx):
     assert image_error(got, O.simulate_image(sc)) <= IMAGE_TOL
 
 
-def test_server_serves_extra_profiles(ctx):
+@pytest.mark.parametrize("make", [W.config2_scene, W.tnfw_scene], ids=["nfw", "tnfw"])
+def test_server_serves_extra_profiles(ctx, make):
     from paper_2606_01547_amd import Server
     scenes = []
     for i in range(4):
-        sc = W.config2_scene(seed=40 + i, n_sub=200, npix=32, supersample=1 + 2 * (i % 2), psf_size=11)
+        sc = make(seed=40 + i, n_sub=200, npix=32, supersample=1 + 2 * (i % 2), psf_size=11)
         sc.source.append(_shapelets(3 + i, 20 + i, beta=0.12))
         sc.lens_light = _gaussians(2, True, 30 + i)
         scenes.append(sc)
