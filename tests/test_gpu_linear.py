@@ -72,6 +72,12 @@ def test_linear_amplitudes_fft_path_and_truncated_subhalos(ctx):
     _check_against_oracle(ctx, sc, seed=3)
 
 
+def test_linear_amplitudes_with_an_epl_main_deflector(ctx):
+    sc = W.epl_scene(n_sub=300, npix=40, supersample=3, psf_size=21)
+    sc.grid = W.Grid(nx=40, ny=37, pixel_scale=0.05, x0=-0.01, y0=0.02, supersample=3)
+    _check_against_oracle(ctx, sc, seed=4)
+
+
 def test_noise_free_image_returns_the_amplitudes(ctx):
     sc = _scene()
     img = ctx.simulate_scene(sc)
