@@ -82,6 +82,19 @@ def test_simulate_with_extra_profiles(ctx):
     assert image_error(got, O.simulate_image(sc)) <= IMAGE_TOL
 
 
+def test_every_profile_at_once(ctx):
+    """EPL main deflector, shear, truncated subhalos, Sersic, core-Sersic,
+    Gaussian and shapelet light in one image, against the oracle."""
+    sc = W.epl_scene(seed=77, n_sub=800, npix=36, supersample=3, psf_size=15)
+    sc.grid = W.Grid(nx=36, ny=31, pixel_scale=0.06, x0=0.01, y0=-0.02, supersample=3)
+    rng = np.random.default_rng(78)
+    sc.lens.nfw.r_trunc = (10.0 ** rng.uniform(0.5, 1.5, sc.lens.nfw.n) * sc.lens.nfw.Rs).astype(np.float32)
+    sc.source = [sc.source[0], _shapelets(5, 79, beta=0.1)] + _gaussians(2, True, 80)
+    sc.lens_light = [CORE] + _gaussians(1, False, 81)
+    got = _np(ctx.simulate_scene(sc))
+    assert image_error(got, O.simulate_image(sc)) <= IMAGE_TOL
+
+
 @pytest.mark.parametrize("make", [W.config2_scene, W.tnfw_scene], ids=["nfw", "tnfw"])
 def test_server_serves_extra_profiles(ctx, make):
     from paper_2606_01547_amd import Server
