@@ -261,7 +261,10 @@ jt_status jt_chi2(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, const
  *   component.
  * g_sub: device float32 [B][n_sub][3] = d log L / d(x, y, alpha_Rs) per
  *   subhalo (may be NULL when n_sub = 0).
- * logL: device double [B] (may be NULL).  Deterministic: fixed summation order.
+ * logL: device double [B] (may be NULL).  Deterministic: fixed summation order,
+ * so a call repeated gives the same bits.  A draw's gradient depends on the
+ * rest of the batch only through the wave split picked from the batch's total
+ * sub-pixel count, which regroups the sums (FP32 rounding, ~1e-6 relative).
  * JT_EUNSUPPORTED when n_src + n_ll > 3. */
 jt_status jt_chi2_grad(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, const float* psf, int k,
                        const float* data, const float* inv_var, double* logL, float* g_macro,
