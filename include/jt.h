@@ -241,8 +241,9 @@ typedef struct {
   const jt_sersic* ll;              /* host [B][n_ll] (NULL when n_ll = 0) */
 } jt_draws;
 
-/* Forward images of every draw: out device float32 [B][ny][nx].  psf device
- * [k][k] (odd k) or NULL with k = 0 (no convolution). */
+/* Forward images of every draw: out device float32 [B][ny][nx], not
+ * overlapping psf (JT_EINVAL).  psf device [k][k] (odd k) or NULL with k = 0
+ * (no convolution). */
 jt_status jt_simulate_batch(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws,
                             const float* psf, int k, float* out, hipStream_t stream);
 

@@ -1,6 +1,7 @@
 // Batches of parameter draws: batched forward images, the chi^2
 // log-likelihood and its hand-written adjoint (host side).
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <vector>
 
@@ -123,6 +124,11 @@ extern "C" jt_status jt_simulate_batch(jt_ctx* ctx, const jt_grid* grid, const j
   JT_TRY(make_batch(grid, draws, false, bt));
   JT_TRY(check_psf(psf, k));
   if (!out) return fail(JT_EINVAL, "simulate_batch: null output");
+  if (psf) {   // the convolution reads the PSF while it writes out
+    const uintptr_t po = (uintptr_t)out, pp = (uintptr_t)psf;
+    const size_t no = sizeof(float) * (size_t)bt.B * bt.npix, np = sizeof(float) * (size_t)k * k;
+    if (po < pp + np && pp < po + no) return fail(JT_EINVAL, "simulate_batch: output overlaps the PSF");
+  }
   const size_t bytes = align256(sizeof(ImageDesc) * bt.B) + align256(sizeof(SubRec) * (size_t)bt.B * bt.records) +
                        align256(sizeof(float) * (size_t)bt.B * bt.npix);
   void* ws = nullptr;

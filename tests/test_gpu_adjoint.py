@@ -231,6 +231,19 @@ def test_autograd_function_backward_is_the_adjoint(ctx):
     np.testing.assert_allclose(_np(sa.grad), gs[..., 2] * s[:, None], rtol=1e-6)
 
 
+def test_batch_output_overlapping_the_psf_is_rejected(ctx):
+    from paper_2606_01547_amd import JtError
+    from paper_2606_01547_amd._native import JT_EINVAL
+    grid = W.Grid(nx=16, ny=16, pixel_scale=0.1)
+    truth, draws = W.config4_draws(B=2, n_sub=10, grid=grid, psf_size=5)
+    buf = torch.zeros(2 * 256 + 25, device="cuda")
+    buf[2 * 256 - 10:2 * 256 + 15] = torch.from_numpy(truth.psf.ravel().astype(np.float32)).cuda()
+    with pytest.raises(JtError) as e:
+        ctx.simulate_batch(grid, _batch(draws), buf[2 * 256 - 10:2 * 256 + 15].view(5, 5),
+                           out=buf[:512].view(2, 16, 16))
+    assert e.value.status == JT_EINVAL
+
+
 def test_gradient_argument_errors(ctx):
     from paper_2606_01547_amd import JtError
     from paper_2606_01547_amd._native import JT_EUNSUPPORTED
