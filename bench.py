@@ -140,8 +140,8 @@ def serving_bench(ctx, n_requests, large_every, seed=1003, loads=(0.5, 0.8, 1.0)
     """The request stream served by the continuous-batching server: a
     saturated calibration pass (everything submitted at once), then Poisson
     arrivals at each of `loads` times the saturated rate, each schedule also
-    served by one jt_simulate_image call per request (FIFO, one stream) for
-    comparison."""
+    served by one jt_simulate_image call per request (FIFO, one stream, the
+    same resident subhalo tables and device PSFs) for comparison."""
     import numpy as np
     import torch
     import workloads as W
@@ -151,12 +151,16 @@ def serving_bench(ctx, n_requests, large_every, seed=1003, loads=(0.5, 0.8, 1.0)
     if large_every:
         for i in range(large_every - 1, n_requests, large_every):
             scenes[i] = W.config5_scene(seed=1005 + i)
-    handles, outs, pairs = [], [], 0.0
+    import types
+    handles, outs, pairs, direct = [], [], 0.0, []
     for sc in scenes:
         hs = ctx.upload_subhalos(sc.lens.nfw) if sc.lens.nfw.n > 0 else 0
         hp = ctx.upload_psf(sc.psf)
         handles.append((hs, hp))
         outs.append(torch.empty((sc.grid.ny, sc.grid.nx), dtype=torch.float32, device="cuda"))
+        # the per-image path gets the same resident subhalo table and a device PSF
+        direct.append((types.SimpleNamespace(sie=sc.lens.sie, shear=sc.lens.shear, subhalo_handle=hs),
+                       torch.from_numpy(np.ascontiguousarray(sc.psf, dtype=np.float32)).cuda()))
         pairs += sc.grid.nx * sc.grid.ny * sc.grid.supersample ** 2 * sc.lens.nfw.n
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t_gen
@@ -185,13 +189,13 @@ def serving_bench(ctx, n_requests, large_every, seed=1003, loads=(0.5, 0.8, 1.0)
         # one jt_simulate_image per request, FIFO, waiting for each
         lat = []
         t0 = time.perf_counter()
-        for sc, o, ta in zip(scenes, outs, arrivals):
+        for sc, (lens, psf), o, ta in zip(scenes, direct, outs, arrivals):
             while True:
                 dt = t0 + ta - time.perf_counter()
                 if dt <= 0:
                     break
                 time.sleep(min(dt, 2e-3))
-            ctx.simulate_scene(sc, out=o)
+            ctx.simulate_image(sc.grid, lens, sc.source, sc.lens_light, psf, getattr(sc, "bn_exact", False), out=o)
             torch.cuda.synchronize()
             lat.append(time.perf_counter() - (t0 + ta))
         return np.array(lat), time.perf_counter() - t0
