@@ -53,7 +53,9 @@ def _sie(t, x, y, te, q, phi, cx, cy):
     dx, dy = x - cx, y - cy
     xp, yp = c * dx + s * dy, -s * dx + c * dy
     f = t.sqrt((1 - q) * (1 + q))
-    psi = t.sqrt(q * q * xp * xp + yp * yp)
+    psi2 = q * q * xp * xp + yp * yp
+    pos = psi2 > 0                        # alpha = 0 at the centre (psi = 0)
+    psi = t.sqrt(t.where(pos, psi2, t.ones_like(psi2)))
     pref = te * t.sqrt(q)
     if float(f.detach()) < 1e-3:
         zx, zy = f * xp / psi, f * yp / psi
@@ -62,6 +64,8 @@ def _sie(t, x, y, te, q, phi, cx, cy):
     else:
         axp = pref / f * t.atan(f * xp / psi)
         ayp = pref / f * t.atanh(f * yp / psi)
+    axp = t.where(pos, axp, t.zeros_like(axp))
+    ayp = t.where(pos, ayp, t.zeros_like(ayp))
     return c * axp - s * ayp, s * axp + c * ayp
 
 

@@ -137,3 +137,23 @@ def test_shear_gradient_closed_form_without_subhalos():
         vm[k] -= h
         fd = (_logL(_set_macro(sc, vp), d, w) - _logL(_set_macro(sc, vm), d, w)) / (2 * h)
         assert fd == pytest.approx(gm[k], rel=1e-6)
+
+
+def test_torch_sie_is_zero_at_its_centre_like_the_numpy_oracle():
+    # the deflection of the SIE is set to zero where psi = 0 (its centre); the
+    # torch restatement must agree there, for q < 1 and in the q -> 1 series,
+    # and keep finite gradients at the other points
+    import torch
+    from oracle import grad as G
+    for q in (0.7, 1.0 - 1e-8):
+        cx, cy = 0.125, -0.0625
+        x = torch.tensor([cx, cx + 0.3, cx - 0.2], dtype=torch.float64)
+        y = torch.tensor([cy, cy - 0.1, cy + 0.4], dtype=torch.float64)
+        par = torch.tensor([1.2, q, 0.4, cx, cy], dtype=torch.float64, requires_grad=True)
+        ax, ay = G._sie(torch, x, y, *par)
+        ex, ey = O.sie_deflection(x.numpy(), y.numpy(), 1.2, q, 0.4, cx, cy)
+        assert float(ax[0].detach()) == 0.0 and float(ay[0].detach()) == 0.0 and ex[0] == 0.0 and ey[0] == 0.0
+        np.testing.assert_allclose(ax.detach().numpy(), ex, rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(ay.detach().numpy(), ey, rtol=1e-12, atol=1e-15)
+        (ax[1:].sum() + ay[1:].sum()).backward()
+        assert bool(torch.isfinite(par.grad).all())
