@@ -544,7 +544,6 @@ def adjoint_bench(ctx, draws, reps):
     per-image path."""
     import numpy as np
     import torch
-    import oracle as O
     import workloads as W
     from paper_2606_01547_amd.grad import DrawBatch, macro_row
     truth, scenes = W.config4_draws(B=draws)
