@@ -442,8 +442,15 @@ jt_status jt_server_create(jt_ctx* ctx, const jt_server_cfg* cfg, jt_server** ou
  * subhalo_handle as the subhalo count and psf_handle as the PSF side; `out` is
  * never touched.  For tests of the scheduler. */
 jt_status jt_server_create_simulated(const jt_server_cfg* cfg, double pairs_per_second, jt_server** out);
+/* Simulated server only (JT_EINVAL otherwise): the batch launched as number
+ * `batch` (1-based count of launches; 0 = none) fails when it completes, as
+ * a device error would.  For tests of the failure path. */
+jt_status jt_server_simulate_failure(jt_server* srv, uint64_t batch);
 /* Queue a request: JT_EINVAL (bad request), JT_ENOMEM (can never fit the
- * arena), JT_OK (*ticket set). */
+ * arena), JT_EDEVICE (the server has seen a device failure), JT_OK (*ticket
+ * set).  A batch that fails on the device fails every ticket in flight and
+ * queued (JT_TICKET_FAILED), and the server refuses all later submissions:
+ * create a new one (on a fresh context if the device itself failed). */
 jt_status jt_server_submit(jt_server* srv, const jt_request* req, uint64_t* ticket);
 /* Current state (jt_ticket_state) of a ticket. */
 jt_status jt_server_poll(jt_server* srv, uint64_t ticket, int* state);
@@ -455,7 +462,12 @@ jt_status jt_server_wait(jt_server* srv, uint64_t ticket, double timeout_s, doub
 /* Cancel a queued ticket (JT_EBUSY once it runs). */
 jt_status jt_server_cancel(jt_server* srv, uint64_t ticket);
 jt_status jt_server_get_stats(jt_server* srv, jt_server_stats* stats);
-/* Stop scheduling, cancel queued tickets, wait for running batches, free. */
+/* Stop scheduling, cancel queued tickets, wait for running batches, free.
+ * A chunked request in progress launches no further chunk and ends
+ * CANCELLED once its launched chunks have finished (a request whose
+ * convolution is already running completes normally).  Threads already in
+ * jt_server_wait return (every ticket reaches a final state) before the
+ * server is freed; no call on the server may start once this has begun. */
 void jt_server_destroy(jt_server* srv);
 
 /* ----------------------------------------------------------------------

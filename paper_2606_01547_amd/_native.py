@@ -183,6 +183,7 @@ _SIGS = {
                                   c_void_p, c_void_p, c_void_p, c_void_p]),
     "jt_server_create": (c_int, [c_void_p, POINTER(JtServerCfg), POINTER(c_void_p)]),
     "jt_server_create_simulated": (c_int, [POINTER(JtServerCfg), c_double, POINTER(c_void_p)]),
+    "jt_server_simulate_failure": (c_int, [c_void_p, c_uint64]),
     "jt_server_submit": (c_int, [c_void_p, POINTER(JtRequest), POINTER(c_uint64)]),
     "jt_server_poll": (c_int, [c_void_p, c_uint64, POINTER(c_int)]),
     "jt_server_wait": (c_int, [c_void_p, c_uint64, c_double, POINTER(c_double)]),
@@ -752,6 +753,10 @@ class Server:
 
     def cancel(self, ticket):
         _check(self._lib.jt_server_cancel(self._ptr, c_uint64(ticket)))
+
+    def simulate_failure(self, batch):
+        """Simulated server: launch number `batch` (1-based) fails on completion."""
+        _check(self._lib.jt_server_simulate_failure(self._ptr, c_uint64(int(batch))))
 
     def stats(self):
         s = JtServerStats()

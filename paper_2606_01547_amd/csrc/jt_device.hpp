@@ -162,7 +162,8 @@ struct ConvDesc {
   const float* img;
   float* out;
   const float* psf;
-  int nx, ny, k, pad;
+  int nx, ny, k;
+  int rb;                // kernel rows per staged chunk: conv_rows_per_chunk(k)
 };
 
 // ---------------------------------------------------------------------------

@@ -42,13 +42,22 @@ hipError_t launch_linear_solve(int npix, int n, const float* basis, const float*
 // Wave-groups per block for `points` sub-pixels in whole units of `unit`.
 int pick_split(long points, int unit, int nloop);
 size_t conv_direct_lds_bytes(int k);
+// Kernel rows per LDS-staged chunk, and whether the direct convolution of
+// `tiles` output tiles with a k x k kernel takes 16-wave blocks (else 4).
+// Both fix the order of the sums, so a batch that convolves an image with
+// the values the image alone would get gives the same bits.
+int conv_rows_per_chunk(int k);
+bool conv_wide_blocks(long tiles, int k);
 // `batch` images at img + z * in_stride -> out + z * out_stride; flip = the
 // adjoint (correlation with the kernel).
 hipError_t launch_conv_direct_batched(bool flip, int batch, const float* img, long in_stride, int nx, int ny,
                                       const float* psf, int k, float* out, long out_stride, hipStream_t st);
 // Heterogeneous convolutions: tiles (desc, tile_x, tile_y, -) over 64 x 4
-// output tiles; kmax = largest kernel side in the batch.
-hipError_t launch_conv_desc(const ConvDesc* descs, const int4* tiles, int ntiles, int kmax, hipStream_t st);
+// output tiles, in 16-wave blocks when `wide`, else 4-wave blocks; each
+// descriptor carries its own row chunk, and `lds` bytes cover the largest
+// conv_direct_lds_bytes(k) of the launch's descriptors.
+hipError_t launch_conv_desc(bool wide, const ConvDesc* descs, const int4* tiles, int ntiles, size_t lds,
+                            hipStream_t st);
 int conv_tiles_x(int nx);
 int conv_tiles_y(int ny);
 // Batched fused simulation over image descriptors (see k_simulate_desc).

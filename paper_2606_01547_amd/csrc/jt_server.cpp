@@ -16,6 +16,14 @@
 // at kernel boundaries of one queue: batches of the requests behind a large
 // one therefore start at the next chunk boundary instead of after the whole
 // image.
+//
+// A batch that fails on the device (its completion event reports an error,
+// or its launch fails) puts the server in a failed state: a device fault can
+// leave any memory the device touched untrustworthy, so every request in
+// flight or queued then fails (JT_EDEVICE), chunked requests stop launching
+// chunks, and new submissions are refused.  Destroying the server cancels the
+// queue and the chunked requests in progress (their chunks on the device are
+// waited for, then their tickets read CANCELLED).
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -26,6 +34,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -195,6 +204,10 @@ struct jt_server {
   jt_server_stats st{};
   Clock::time_point sim_last;       // simulated device: last advance
   bool stop = false;
+  int waiters = 0;                  // threads inside jt_server_wait
+  bool broken = false;              // a batch failed on the device: no more work
+  std::string broken_why;
+  uint64_t sim_fail_batch = 0;      // simulated device: launch index (1-based) that fails
   std::thread thread;
 
   void run();
@@ -203,6 +216,9 @@ struct jt_server {
   void launch_ready();
   void complete_finished();
   void finish_request(Req* r, bool failed, Clock::time_point t);
+  void cancel_request(Req* r, Clock::time_point t);
+  void fail_all(const char* why);
+  void retire_stopped_chunked(Clock::time_point t);
   bool launch_batch(std::unique_ptr<Batch> bp);
   jt_status launch_hip(Batch& b);
   jt_status launch_chunk_hip(Batch& b);
@@ -223,12 +239,11 @@ jt_status jt_server::launch_hip(Batch& b) {
   hipStream_t s = streams[b.stream];
   // one split for the whole tile list
   long subpix = 0;
-  int max_nloop = 0, max_s2 = 1, kmax = 0;
+  int max_nloop = 0, max_s2 = 1;
   for (Req* r : b.reqs) {
     subpix += (long)r->g.nx * r->g.ny * r->g.s2;
     max_nloop = std::max(max_nloop, r->nloop);
     max_s2 = std::max(max_s2, r->g.s2);
-    kmax = std::max(kmax, r->k);
   }
   const int split = pick_split(subpix, max_s2, max_nloop);
   // longest tiles first
@@ -238,7 +253,10 @@ jt_status jt_server::launch_hip(Batch& b) {
   std::vector<ImageDesc> descs(n);
   std::vector<ConvDesc> cdescs;
   std::vector<int2> tiles;
-  std::vector<int4> ctiles;
+  // convolution tiles of the requests that alone would take 4-wave blocks
+  // (first) and 16-wave blocks (second), and the LDS each launch needs
+  std::vector<int4> ctiles[2];
+  size_t clds[2] = {0, 0};
   // block layout: descs | conv descs | tiles | conv tiles | images
   size_t img_total = 0;
   for (Req* r : order) img_total += r->k ? a256(4 * (size_t)r->g.nx * r->g.ny) : 0;
@@ -277,9 +295,14 @@ jt_status jt_server::launch_hip(Batch& b) {
       D.img = (float*)(base + img_off);
       img_off += a256(4 * (size_t)r->g.nx * r->g.ny);
       const int ci = (int)cdescs.size();
-      cdescs.push_back(ConvDesc{D.img, r->out, r->psf, r->g.nx, r->g.ny, r->k, 0});
+      // the row chunk and block width the request alone would get, so its
+      // image does not depend on what else the batch holds
+      cdescs.push_back(ConvDesc{D.img, r->out, r->psf, r->g.nx, r->g.ny, r->k, conv_rows_per_chunk(r->k)});
+      const long nct = (long)conv_tiles_x(r->g.nx) * conv_tiles_y(r->g.ny);
+      const int wide = conv_wide_blocks(nct, r->k) ? 1 : 0;
+      clds[wide] = std::max(clds[wide], conv_direct_lds_bytes(r->k));
       for (int ty = 0; ty < conv_tiles_y(r->g.ny); ++ty)
-        for (int tx = 0; tx < conv_tiles_x(r->g.nx); ++tx) ctiles.push_back(make_int4(ci, tx, ty, 0));
+        for (int tx = 0; tx < conv_tiles_x(r->g.nx); ++tx) ctiles[wide].push_back(make_int4(ci, tx, ty, 0));
     } else {
       D.img = r->out;
     }
@@ -288,16 +311,21 @@ jt_status jt_server::launch_hip(Batch& b) {
   std::memcpy(host.data(), descs.data(), sizeof(ImageDesc) * n);
   if (ncon) std::memcpy(host.data() + o_cd, cdescs.data(), sizeof(ConvDesc) * ncon);
   std::memcpy(host.data() + o_t, tiles.data(), sizeof(int2) * ntiles);
-  if (nctiles) std::memcpy(host.data() + o_ct, ctiles.data(), sizeof(int4) * nctiles);
+  const size_t nct0 = ctiles[0].size();
+  if (nct0) std::memcpy(host.data() + o_ct, ctiles[0].data(), sizeof(int4) * nct0);
+  if (ctiles[1].size()) std::memcpy(host.data() + o_ct + sizeof(int4) * nct0, ctiles[1].data(), sizeof(int4) * ctiles[1].size());
   JT_TRY(upload(b, host.data(), o_img, base, s));
   JT_TRY(timed_launch(ctx, JT_K_SIM, s, [&] {
     return launch_simulate_desc(split, order[0]->tnfw, extra, false, (const ImageDesc*)base, (const int2*)(base + o_t), (int)ntiles,
                                 0, s);
   }, "server simulate"));
-  if (ncon)
+  for (int wide = 0; wide < 2; ++wide) {
+    if (ctiles[wide].empty()) continue;
+    const int4* tl = (const int4*)(base + o_ct) + (wide ? nct0 : 0);
     JT_TRY(timed_launch(ctx, JT_K_CONV, s, [&] {
-      return launch_conv_desc((const ConvDesc*)(base + o_cd), (const int4*)(base + o_ct), (int)nctiles, kmax, s);
+      return launch_conv_desc(wide == 1, (const ConvDesc*)(base + o_cd), tl, (int)ctiles[wide].size(), clds[wide], s);
     }, "server convolve"));
+  }
   return check_hip(hipEventRecord(b.ev, s), "hipEventRecord(batch)");
 }
 
@@ -340,14 +368,16 @@ jt_status jt_server::launch_conv_hip(Batch& b) {
   if (end > b.bytes) return fail(JT_EDEVICE, "server: convolution block too small (internal)");
   char* base = arena_dev + b.off;
   std::vector<char> host(end, 0);
-  *(ConvDesc*)host.data() = ConvDesc{(const float*)(arena_dev + r->img_off), r->out, r->psf, r->g.nx, r->g.ny, r->k, 0};
+  *(ConvDesc*)host.data() = ConvDesc{(const float*)(arena_dev + r->img_off), r->out, r->psf, r->g.nx, r->g.ny, r->k,
+                                     conv_rows_per_chunk(r->k)};
   int4* ct = (int4*)(host.data() + o_ct);
   long j = 0;
   for (int ty = 0; ty < conv_tiles_y(r->g.ny); ++ty)
     for (int tx = 0; tx < conv_tiles_x(r->g.nx); ++tx) ct[j++] = make_int4(0, tx, ty, 0);
   JT_TRY(upload(b, host.data(), end, base, s));
   JT_TRY(timed_launch(ctx, JT_K_CONV, s, [&] {
-    return launch_conv_desc((const ConvDesc*)base, (const int4*)(base + o_ct), (int)nct, r->k, s);
+    return launch_conv_desc(conv_wide_blocks(nct, r->k), (const ConvDesc*)base, (const int4*)(base + o_ct), (int)nct,
+                            conv_direct_lds_bytes(r->k), s);
   }, "server convolve"));
   return check_hip(hipEventRecord(b.ev, s), "hipEventRecord(batch)");
 }
@@ -418,6 +448,47 @@ void jt_server::finish_request(Req* r, bool failed, Clock::time_point t) {
   st.run_seconds += std::chrono::duration<double>(t - r->t_launch).count();
 }
 
+// Called with mu held: a request ends without running to completion.
+void jt_server::cancel_request(Req* r, Clock::time_point t) {
+  r->state = JT_TICKET_CANCELLED;
+  r->t_done = t;
+  ++st.cancelled;
+}
+
+// Called with mu held, on the first failed batch: the queue fails at once,
+// chunked requests stop launching chunks (they fail once nothing of theirs
+// runs), and every batch still in flight will report failure.
+void jt_server::fail_all(const char* why) {
+  if (broken) return;
+  broken = true;
+  broken_why = why;
+  const auto now = Clock::now();
+  for (Req* r : queue) {
+    r->t_launch = now;
+    finish_request(r, true, now);
+  }
+  queue.clear();
+  for (Req* r : active) r->failed = true;
+  done_cv.notify_all();
+}
+
+// Called with mu held once stopping: chunked requests with nothing on the
+// device end as cancelled (a request whose convolution was launched finishes
+// normally when it completes).
+void jt_server::retire_stopped_chunked(Clock::time_point t) {
+  for (auto it = active.begin(); it != active.end();) {
+    Req* r = *it;
+    if (r->chunks_inflight == 0 && !r->conv_launched) {
+      if (r->failed) finish_request(r, true, t); else cancel_request(r, t);
+      if (r->img_bytes) arena.release(r->img_off, r->img_bytes);
+      it = active.erase(it);
+      done_cv.notify_all();
+    } else {
+      ++it;
+    }
+  }
+}
+
 // Called with mu held.
 void jt_server::complete_finished() {
   const auto now = Clock::now();
@@ -450,6 +521,8 @@ void jt_server::complete_finished() {
     }
     if (b.ev) events.push_back(b.ev);
     const auto t = ctx ? b.t_done : b.sim_done;
+    if (b.failed) fail_all("a batch failed on the device");
+    if (broken) b.failed = true;
     if (b.chunk || b.conv) {
       --chunk_batches;
       Req* r = b.reqs[0];
@@ -529,6 +602,8 @@ bool jt_server::launch_batch(std::unique_ptr<Batch> bp) {
     sim_advance(now);
     b.sim_left = dur;
     st.device_seconds += dur;
+    // an injected failure shows when the batch completes, as a device error would
+    if (sim_fail_batch && st.batches == sim_fail_batch) b.failed = true;
   }
   inflight.push_back(std::move(bp));
   return ok;
@@ -547,7 +622,7 @@ void jt_server::launch_ready() {
   const int n_streams = std::max(1, cfg.n_streams);
   const int max_active = std::max(1, n_streams - 1);
   const int max_chunk_batches = std::max(1, cfg.max_inflight_batches - 1);
-  while (!stop && (int)inflight.size() < cfg.max_inflight_batches) {
+  while (!stop && !broken && (int)inflight.size() < cfg.max_inflight_batches) {
     // next chunk of a chunked request, or its convolution once every chunk
     // has completed
     Req* r = nullptr;
@@ -674,6 +749,7 @@ void jt_server::run() {
   for (;;) {
     complete_finished();
     launch_ready();
+    if (stop || broken) retire_stopped_chunked(Clock::now());
     if (stop && inflight.empty()) break;
     if (inflight.empty()) {
       cv.wait(lk, [&] { return stop || !queue.empty(); });
@@ -804,6 +880,9 @@ extern "C" jt_status jt_server_submit(jt_server* srv, const jt_request* req, uin
     return fail(JT_ENOMEM, "server submit: request needs %zu bytes, arena holds %zu", r->footprint, srv->arena.size);
   std::lock_guard<std::mutex> lk(srv->mu);
   if (srv->stop) return fail(JT_ECANCELLED, "server submit: server is stopping");
+  if (srv->broken)
+    return fail(JT_EDEVICE, "server submit: refused after a device failure (%s); create a new server",
+                srv->broken_why.c_str());
   r->ticket = srv->next_ticket++;
   r->t_submit = Clock::now();
   *ticket = r->ticket;
@@ -830,11 +909,16 @@ extern "C" jt_status jt_server_wait(jt_server* srv, uint64_t ticket, double time
   if (it == srv->tickets.end()) return fail(JT_EINVAL, "server wait: unknown ticket %llu", (unsigned long long)ticket);
   Req* r = it->second.get();
   auto final_state = [&] { return r->state >= JT_TICKET_DONE; };
-  if (timeout_s < 0) {
+  // jt_server_destroy waits until no thread is in here
+  ++srv->waiters;
+  bool ended = true;
+  if (timeout_s < 0)
     srv->done_cv.wait(lk, final_state);
-  } else if (!srv->done_cv.wait_for(lk, std::chrono::duration<double>(timeout_s), final_state)) {
-    return fail(JT_EBUSY, "server wait: ticket %llu still pending", (unsigned long long)ticket);
-  }
+  else
+    ended = srv->done_cv.wait_for(lk, std::chrono::duration<double>(timeout_s), final_state);
+  --srv->waiters;
+  srv->done_cv.notify_all();
+  if (!ended) return fail(JT_EBUSY, "server wait: ticket %llu still pending", (unsigned long long)ticket);
   const int state = r->state;
   if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
   srv->tickets.erase(it);
@@ -857,6 +941,14 @@ extern "C" jt_status jt_server_cancel(jt_server* srv, uint64_t ticket) {
   ++srv->st.cancelled;
   srv->done_cv.notify_all();
   srv->cv.notify_all();
+  return JT_OK;
+}
+
+extern "C" jt_status jt_server_simulate_failure(jt_server* srv, uint64_t batch) {
+  if (!srv) return fail(JT_EINVAL, "server failure injection: null server");
+  if (srv->ctx) return fail(JT_EINVAL, "server failure injection: simulated servers only");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  srv->sim_fail_batch = batch;
   return JT_OK;
 }
 
@@ -884,6 +976,12 @@ extern "C" void jt_server_destroy(jt_server* srv) {
     srv->done_cv.notify_all();
   }
   if (srv->thread.joinable()) srv->thread.join();
+  {
+    // every ticket is final now; let threads still in jt_server_wait leave
+    std::unique_lock<std::mutex> lk(srv->mu);
+    srv->done_cv.notify_all();
+    srv->done_cv.wait(lk, [&] { return srv->waiters == 0; });
+  }
   if (srv->ctx) {
     (void)hipSetDevice(srv->ctx->device);
     for (auto s : srv->streams) {

@@ -375,11 +375,11 @@ __global__ __launch_bounds__(kW * 64) void k_conv_direct(const float* __restrict
 // image descs[tiles[b].x]; the dynamic LDS fits the batch's largest kernel.
 template <int kW>
 __global__ __launch_bounds__(kW * 64) void k_conv_desc(const ConvDesc* __restrict__ descs,
-                                                      const int4* __restrict__ tiles, int rb) {
+                                                      const int4* __restrict__ tiles) {
   extern __shared__ float tile[];
   const int4 tl = tiles[blockIdx.x];
   const ConvDesc& d = descs[tl.x];
-  conv_tile<false, kW>(d.img, d.nx, d.ny, d.psf, d.k, min(rb, d.k), d.out, tl.y, tl.z, tile);
+  conv_tile<false, kW>(d.img, d.nx, d.ny, d.psf, d.k, d.rb, d.out, tl.y, tl.z, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -461,13 +461,14 @@ hipError_t launch_source_sb(int n, const float* x, const float* y, const float* 
   if (n <= 0) return hipSuccess;
   const bool hs = light_any(src), hl = light_any(ll);
   const auto a16 = [](const float* p) { return ((uintptr_t)p & 15) == 0; };
-  const bool vec = a16(sb) && (!hs || (a16(bx) && a16(by))) && (!hl || (a16(x) && a16(y)));
   const bool extra = light_has_extra(src) || light_has_extra(ll);
+  // The extra profiles take one point per thread: four inlined copies of their
+  // code (shapelets above all) left the four-point variant with 97 VGPRs and
+  // 2 KB of per-lane scratch, four times slower than the plain Sersic list.
+  const bool vec = !extra && a16(sb) && (!hs || (a16(bx) && a16(by))) && (!hl || (a16(x) && a16(y)));
   const int threads = vec ? (n >> 2) + (n & 3) : n;
   const dim3 grid((threads + 255) / 256), block(256);
-  if (vec && extra)
-    hipLaunchKernelGGL((k_source_sb<true, true>), grid, block, 0, st, n, x, y, bx, by, src, ll, sb);
-  else if (vec)
+  if (vec)
     hipLaunchKernelGGL((k_source_sb<false, true>), grid, block, 0, st, n, x, y, bx, by, src, ll, sb);
   else if (extra)
     hipLaunchKernelGGL((k_source_sb<true, false>), grid, block, 0, st, n, x, y, bx, by, src, ll, sb);
@@ -541,14 +542,13 @@ hipError_t launch_conv_direct_batched(bool flip, int batch, const float* img, lo
   return hipGetLastError();
 }
 
-hipError_t launch_conv_desc(const ConvDesc* descs, const int4* tiles, int ntiles, int kmax, hipStream_t st) {
+hipError_t launch_conv_desc(bool wide, const ConvDesc* descs, const int4* tiles, int ntiles, size_t lds,
+                            hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-  const size_t lds = conv_direct_lds_bytes(kmax);
-  const int rb = conv_rows_per_chunk(kmax);
-  if (conv_wide_blocks(ntiles, kmax))
-    hipLaunchKernelGGL(k_conv_desc<16>, dim3((unsigned)ntiles), dim3(1024), lds, st, descs, tiles, rb);
+  if (wide)
+    hipLaunchKernelGGL(k_conv_desc<16>, dim3((unsigned)ntiles), dim3(1024), lds, st, descs, tiles);
   else
-    hipLaunchKernelGGL(k_conv_desc<4>, dim3((unsigned)ntiles), dim3(256), lds, st, descs, tiles, rb);
+    hipLaunchKernelGGL(k_conv_desc<4>, dim3((unsigned)ntiles), dim3(256), lds, st, descs, tiles);
   return hipGetLastError();
 }
 

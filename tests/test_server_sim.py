@@ -191,3 +191,95 @@ def test_destroy_with_pending_work_cancels_the_queue():
     t0 = time.time()
     srv.close()
     assert time.time() - t0 < 5.0
+
+
+def test_injected_device_failure_fails_in_flight_and_queued_and_refuses_submits():
+    """Batch 3 fails on the (simulated) device: tickets 1-2 completed before
+    it are done; 3, the batch in flight beside it and everything queued fail
+    (JT_EDEVICE); later submissions are refused; the arena drains."""
+    from paper_2606_01547_amd import JtError
+    from paper_2606_01547_amd._native import JT_EDEVICE
+    srv = _srv(max_inflight_batches=2, max_batch_images=1, n_streams=2, simulated_pairs_per_s=1e9)
+    srv.simulate_failure(3)
+    sc = _sc(100, 1)
+    tickets = [_submit(srv, sc, nsub=2000) for _ in range(10)]      # ~20 ms each, one per batch
+    ok, failed = [], []
+    for t in tickets:
+        try:
+            srv.wait(t, timeout=30.0)
+            ok.append(t)
+        except JtError as e:
+            assert e.status == JT_EDEVICE, e
+            failed.append(t)
+    assert ok == tickets[:2] and failed == tickets[2:]
+    with pytest.raises(JtError) as e:
+        _submit(srv, sc)
+    assert e.value.status == JT_EDEVICE and "device failure" in str(e.value)
+    st = srv.stats()
+    assert st["completed"] == 2 and st["failed"] == 8 and st["batches"] <= 4
+    assert st["arena_in_use"] == 0
+    srv.close()
+
+
+def test_injected_failure_inside_a_chunked_request():
+    """The second chunk of a large request fails: the request fails once its
+    launched chunks are done, without launching more chunks or its
+    convolution; small requests that ran beside it on another stream before
+    the failure completed, the rest fail, and later submissions are refused."""
+    from paper_2606_01547_amd import JtError
+    from paper_2606_01547_amd._native import JT_EDEVICE
+    srv = _srv(max_batch_pairs=1e7, max_inflight_batches=3, n_streams=2, simulated_pairs_per_s=1e10)
+    srv.simulate_failure(2)
+    big = _submit(srv, _sc(1200, 3), nsub=2000)                        # 26 chunks of ~0.1 s + a convolution
+    small = [_submit(srv, _sc(), nsub=10) for _ in range(3)]
+    with pytest.raises(JtError) as e:
+        srv.wait(big, timeout=30.0)
+    assert e.value.status == JT_EDEVICE
+    outcome = []
+    for t in small:
+        try:
+            srv.wait(t, timeout=30.0)
+            outcome.append("done")
+        except JtError as e:
+            assert e.status == JT_EDEVICE
+            outcome.append("failed")
+    with pytest.raises(JtError) as e:
+        _submit(srv, _sc(), nsub=10)
+    assert e.value.status == JT_EDEVICE
+    st = srv.stats()
+    assert st["failed"] == 1 + outcome.count("failed") and st["completed"] == outcome.count("done")
+    assert st["batches"] < 8                    # of the 27 launches the request needs, at most its first 3 ran
+    assert st["arena_in_use"] == 0
+    srv.close()
+
+
+def test_destroy_cancels_a_chunked_request_in_progress():
+    """Closing the server while a chunked request runs launches no further
+    chunk; a thread waiting on its ticket is released with JT_ECANCELLED
+    before the server is freed."""
+    from paper_2606_01547_amd import JtError
+    from paper_2606_01547_amd._native import JT_ECANCELLED, TICKET_RUNNING
+    srv = _srv(max_batch_pairs=1e7, max_inflight_batches=3, n_streams=2, simulated_pairs_per_s=1e9)
+    big = _submit(srv, _sc(1200, 3), nsub=2000)                        # ~26 s of simulated work
+    t0 = time.time()
+    while srv.poll(big) != TICKET_RUNNING:
+        assert time.time() - t0 < 5.0
+        time.sleep(1e-3)
+    seen = []
+
+    def waiter():
+        try:
+            srv.wait(big)
+            seen.append("done")
+        except JtError as e:
+            seen.append(e.status)
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    time.sleep(0.05)
+    t0 = time.time()
+    srv.close()
+    th.join(timeout=10.0)
+    assert not th.is_alive()
+    assert seen == [JT_ECANCELLED]
+    assert time.time() - t0 < 5.0               # two queued chunks of ~1 s at most, not the whole image
