@@ -54,6 +54,7 @@ typedef enum {
 #define JT_MAX_SERSIC 8        /* per light list (source or lens light)       */
 #define JT_MAX_POINT_MASS 16   /* point masses per lens                       */
 #define JT_MAX_PSF 255         /* largest odd PSF side for the direct path    */
+#define JT_NOALLOC_SCRATCH_BYTES (8u << 20) /* static scratch of jt_simulate_image_noalloc, per device */
 
 typedef struct jt_ctx jt_ctx;  /* one per device: workspace, resident tables, profiling */
 
@@ -219,6 +220,26 @@ int jt_convolve_auto_method(int nx, int ny, int k);
 jt_status jt_simulate_image(jt_ctx* ctx, const jt_grid* grid, const jt_lens* lens,
                             const jt_light* src, const jt_light* lens_light,
                             const float* psf, int k, float* out, hipStream_t stream);
+
+/* jt_simulate_image for callers that cannot allocate device memory (code
+ * under HIP stream capture, serving loops that must not allocate, harnesses
+ * that forbid it).  Same arguments, kernels and results as jt_simulate_image
+ * whenever that call convolves directly (bit for bit); this one always
+ * convolves directly, so a PSF larger than JT_MAX_PSF is JT_EUNSUPPORTED.
+ * It calls no hipMalloc, hipFree or other allocating routine: the packed
+ * subhalo table (16 B per NFW subhalo, 32 B per TNFW subhalo, rounded up to
+ * a multiple of 4 plus 4 padding records, 256-byte aligned; none with a
+ * resident subhalo handle) and the unconvolved image (4 B per pixel, 256-byte
+ * aligned; none without a PSF) live in one static device array of
+ * JT_NOALLOC_SCRATCH_BYTES per device, looked up by jt_create.  A call needing
+ * more than that returns JT_EUNSUPPORTED and launches nothing (e.g. a
+ * 1000 x 1000 image with 50 000 NFW subhalos needs 4.8 MB and fits).
+ * Every call on a device shares its array: calls that overlap on one device
+ * (different streams, or threads without ordering between them) race and
+ * corrupt each other's results; calls on one stream are safe. */
+jt_status jt_simulate_image_noalloc(jt_ctx* ctx, const jt_grid* grid, const jt_lens* lens,
+                                    const jt_light* src, const jt_light* lens_light,
+                                    const float* psf, int k, float* out, hipStream_t stream);
 
 /* ----------------------------------------------------------------------
  * Batches of parameter draws: forward images, the chi^2 log-likelihood and

@@ -155,6 +155,8 @@ _SIGS = {
     "jt_convolve_auto_method": (c_int, [c_int, c_int, c_int]),
     "jt_simulate_image": (c_int, [c_void_p, POINTER(JtGrid), POINTER(JtLens), POINTER(JtLight), POINTER(JtLight),
                                   c_void_p, c_int, c_void_p, c_void_p]),
+    "jt_simulate_image_noalloc": (c_int, [c_void_p, POINTER(JtGrid), POINTER(JtLens), POINTER(JtLight),
+                                          POINTER(JtLight), c_void_p, c_int, c_void_p, c_void_p]),
     "jt_upload_subhalos": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_uint64)]),
     "jt_linear_amplitudes": (c_int, [c_void_p, POINTER(JtGrid), POINTER(JtLens), POINTER(JtLight), POINTER(JtLight),
                                      c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -423,7 +425,11 @@ class Context:
         return o
 
     # ---- fused
-    def simulate_image(self, grid, lens, source, lens_light=(), psf=None, bn_exact=False, out=None, stream=None):
+    def simulate_image(self, grid, lens, source, lens_light=(), psf=None, bn_exact=False, out=None, stream=None,
+                       noalloc=False):
+        """The fused simulation (jt_simulate_image).  noalloc=True calls
+        jt_simulate_image_noalloc, whose intermediates live in the library's
+        static per-device scratch (direct convolution only)."""
         keep = []
         G = JtGrid(int(grid.nx), int(grid.ny), int(grid.supersample), float(grid.pixel_scale),
                    float(grid.x0), float(grid.y0))
@@ -436,8 +442,9 @@ class Context:
         else:
             pt = _dev_f32(psf, self.device, keep)
             pp, k = c_void_p(pt.data_ptr()), int(pt.shape[0])
-        _check(self._lib.jt_simulate_image(self._ptr, byref(G), byref(L), byref(S), byref(LL), pp, k,
-                                           c_void_p(o.data_ptr()), _stream_handle(stream)))
+        fn = self._lib.jt_simulate_image_noalloc if noalloc else self._lib.jt_simulate_image
+        _check(fn(self._ptr, byref(G), byref(L), byref(S), byref(LL), pp, k, c_void_p(o.data_ptr()),
+                  _stream_handle(stream)))
         self._retain(keep, stream)
         return o
 

@@ -173,6 +173,7 @@ extern "C" jt_status jt_create(int device, jt_ctx** out) {
   JT_TRY(check_hip(hipGetDeviceCount(&count), "hipGetDeviceCount"));
   if (device < 0 || device >= count) return fail(JT_EINVAL, "jt_create: device %d of %d", device, count);
   JT_TRY(check_hip(hipSetDevice(device), "hipSetDevice"));
+  JT_TRY(noalloc_scratch_init(device));
   jt_ctx* ctx = new jt_ctx();
   ctx->device = device;
   const int rec = subhalo_table_records(0);

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -59,6 +60,13 @@ struct jt_ctx {
 
 namespace jt {
 
+// [a, a + n) and [b, b + m) share an element (null pointers share none).
+inline bool overlap(const float* a, size_t n, const float* b, size_t m) {
+  if (!a || !b || n == 0 || m == 0) return false;
+  const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+  return pa < pb + sizeof(float) * m && pb < pa + sizeof(float) * n;
+}
+
 jt_status fail(jt_status st, const char* fmt, ...);
 jt_status check_hip(hipError_t e, const char* what);
 jt_status ctx_enter(jt_ctx* ctx);
@@ -74,6 +82,9 @@ jt_status ctx_twiddles(jt_ctx* ctx, int N, const double2** out);
 // A resident subhalo table: records (SubRec, or TRec when *tnfw), count.
 jt_status ctx_subhalo_handle(jt_ctx* ctx, uint64_t h, const void** table, int* n, bool* tnfw);
 const SubRec* ctx_empty_table(jt_ctx* ctx);
+// Looks up the calling device's static scratch array for
+// jt_simulate_image_noalloc (once per device; the device must be current).
+jt_status noalloc_scratch_init(int device);
 hipEvent_t take_event(jt_ctx* ctx);
 void drain_events(jt_ctx* ctx);
 

@@ -12,13 +12,6 @@ using namespace jt;
 
 namespace {
 
-// [a, a + n) and [b, b + m) share an element (null pointers share none).
-bool overlap(const float* a, size_t n, const float* b, size_t m) {
-  if (!a || !b || n == 0 || m == 0) return false;
-  const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
-  return pa < pb + sizeof(float) * m && pb < pa + sizeof(float) * n;
-}
-
 jt_status ray_common(bool alpha, jt_ctx* ctx, int n, const float* x, const float* y, const jt_lens* lens,
                      float* ox, float* oy, hipStream_t st) {
   JT_TRY(ctx_enter(ctx));
