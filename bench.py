@@ -26,13 +26,15 @@ sys.path.insert(0, ROOT)
 METRIC = "simulated images/s + p50/p99 latency (200² px, 10k NFW, 41² PSF); % FP32 peak"
 PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector, published
 PEAK_HBM_BYTES = 8.0e12           # MI355X HBM3E, published
-# Algorithmic FP32 work of one (sub-pixel, subhalo) NFW pair with the general
-# (degree-8) far-field polynomial (FMA = 2, transcendental = 1): dx, dy 2;
-# r^2 3; x^2 1; rsq + log2 2; polynomial 16; g 1; y^2, g y^2 2; * c2 1;
-# accumulate 4; plus the branch test 1.  Distant pairs take a degree-4 form,
-# so the device executes fewer: the committed counters give the executed
-# FLOP per pair, reported beside it as executed_frac.
-FLOP_PER_PAIR = 33
+# Algorithmic FP32 work of one (sub-pixel, subhalo) NFW pair in the form a
+# distant pair takes (y = Rs/r below 0.125 for its group of four subhalos: at
+# least 93% of the headline's pairs), FMA = 2: dx, dy 2; r^2 = dx dx + dy dy 3;
+# x^2/4 = r^2 c1/4 1; rsq + log2 2; degree-4 polynomial (3 FMA) 6;
+# g' = fma(R, y, log) 2; y^2 and g' y^2 2; * c2 1; two accumulating FMAs 4;
+# the group's branch test 1.  The remaining pairs take the degree-8 form
+# (33 FLOP), not counted, so `achieved` is a lower bound; the executed FLOP
+# from the committed counters is reported beside it as executed_frac.
+FLOP_PER_PAIR = 24
 KERNEL_SOURCES = ["paper_2606_01547_amd/csrc/kernels.hip", "paper_2606_01547_amd/csrc/jt_device.hpp",
                   "paper_2606_01547_amd/csrc/nfw_poly.inc", "paper_2606_01547_amd/csrc/jt_sum.hpp",
                   "paper_2606_01547_amd/csrc/atan_poly.inc"]
@@ -592,6 +594,39 @@ def adjoint_bench(ctx, draws, reps):
             "params_per_draw": int(macro.shape[1] + 3 * scenes[0].lens.nfw.n)}
 
 
+# Lane-operations per round of each calibration kind (jt_calibrate_valu) and
+# FLOP per lane-operation (FMA = 2).
+CALIB_KINDS = {0: ("fma", 8, 2.0), 1: ("rsq", 8, 1.0), 2: ("16 fma + 2 rsq", 18, 34.0 / 18.0),
+               3: ("mul", 16, 1.0), 4: ("fma with literal", 8, 2.0), 5: ("log + add", 16, 1.0),
+               6: ("fmac, sgpr operand", 8, 2.0), 7: ("fma, three vgprs", 8, 2.0)}
+CLOCK_HZ = 2.4e9   # MI355X peak engine clock (published)
+N_CU = 256
+
+
+def valu_calibration(iters):
+    """FP32 issue rates measured by the library's calibration kernels: for
+    each instruction class and 1, 2, 4, 8 waves per SIMD, lane-operations per
+    second, per CU per clock (at the published 2.4 GHz) and the implied SIMD
+    cycles per wave64 instruction."""
+    from paper_2606_01547_amd import Context
+    ctx = Context(0)
+    rows = []
+    for kind, (name, ops, flop_per_op) in CALIB_KINDS.items():
+        for waves in (1, 2, 4, 8):
+            blocks = N_CU * waves              # 4 waves per block, 4 SIMDs per CU
+            ms = ctx.calibrate_valu(kind, blocks, iters)
+            lane_ops = blocks * 256.0 * iters * ops
+            rate = lane_ops / (1e-3 * ms)
+            per_cu_clk = rate / (N_CU * CLOCK_HZ)
+            rows.append({"kind": kind, "class": name, "waves_per_simd": waves, "ms": round(ms, 4),
+                         "lane_ops_per_s": float(f"{rate:.4g}"), "lane_ops_per_cu_clock": round(per_cu_clk, 2),
+                         "simd_cycles_per_wave_instruction": round(4 * 64 / per_cu_clk, 3),
+                         "fp32_tflops": round(rate * flop_per_op / 1e12, 2)})
+    ctx.close()
+    return {"valu_calibration": rows, "iters": iters, "clock_hz": CLOCK_HZ, "cus": N_CU,
+            "note": "lane_ops_per_cu_clock assumes the published 2.4 GHz; rates are measured"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -613,7 +648,13 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (3 times), to calibrate "
                          "the FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--valu-calibration", type=int, default=0, metavar="ITERS",
+                    help="only run the FP32 issue-rate calibration kernels (ITERS rounds per lane) at 1, 2, 4 "
+                         "and 8 waves per SIMD and print their rates")
     args = ap.parse_args()
+    if args.valu_calibration:
+        print(json.dumps(valu_calibration(args.valu_calibration)), flush=True)
+        return
     if args.copy_calibration:
         import torch
         n = args.copy_calibration * (1 << 20) // 4
@@ -684,7 +725,8 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": cnt.get("bytes_per_launch"),
                 "kernel": "k_simulate", "avg_ms": round(1e3 * sim_avg_s, 4),
-                "flop_per_launch": FLOP_PER_PAIR * pairs, "pairs_per_s": round(pairs / sim_avg_s, 1)}
+                "flop_per_launch": FLOP_PER_PAIR * pairs, "flop_per_pair": FLOP_PER_PAIR,
+                "pairs_per_s": round(pairs / sim_avg_s, 1)}
     if cnt.get("executed_flop_per_pair"):
         ex = cnt["executed_flop_per_pair"] * pairs / sim_avg_s / 1e12
         roofline["executed_flop_per_pair"] = cnt["executed_flop_per_pair"]

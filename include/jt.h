@@ -503,6 +503,19 @@ typedef enum {
   JT_K_GRAD = 5,        /* adjoint: residual, per-sub-pixel and subhalo passes */
   JT_K_COUNT = 6
 } jt_kernel_id;
+/* Measurement: FP32 issue-rate calibration (not part of the simulation).
+ * Launches `blocks` blocks of 256 threads; every lane runs `iters` rounds over
+ * eight independent FP32 chains of one instruction class:
+ *   kind 0: 8 FMA per round (register operands)   kind 3: 16 multiplies
+ *   kind 1: 8 v_rsq_f32                           kind 4: 8 FMA with a literal
+ *   kind 2: 16 FMA + 2 v_rsq_f32                  kind 5: 8 v_log_f32 + 8 adds
+ *   kind 6: 8 accumulating FMA, SGPR operand       kind 7: 8 FMA on three VGPRs
+ * out: device float32[blocks * 256] (chain sums, written so nothing is
+ * optimised away).  Timing is the caller's (events on `stream`), so that the
+ * rates the roofline figures use are measured by committed code.
+ * JT_EINVAL for a kind outside 0..7 or non-positive sizes. */
+jt_status jt_calibrate_valu(int kind, int blocks, int iters, float* out, hipStream_t stream);
+
 /* Enable (1) or disable (0) event timing of every launch; resets the totals. */
 jt_status jt_profile_enable(jt_ctx* ctx, int on);
 /* Total milliseconds and launch count of kernel `id` since enabling (waits for

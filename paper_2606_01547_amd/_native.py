@@ -157,6 +157,7 @@ _SIGS = {
                                   c_void_p, c_int, c_void_p, c_void_p]),
     "jt_simulate_image_noalloc": (c_int, [c_void_p, POINTER(JtGrid), POINTER(JtLens), POINTER(JtLight),
                                           POINTER(JtLight), c_void_p, c_int, c_void_p, c_void_p]),
+    "jt_calibrate_valu": (c_int, [c_int, c_int, c_int, c_void_p, c_void_p]),
     "jt_upload_subhalos": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_uint64)]),
     "jt_linear_amplitudes": (c_int, [c_void_p, POINTER(JtGrid), POINTER(JtLens), POINTER(JtLight), POINTER(JtLight),
                                      c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -666,6 +667,26 @@ class Context:
     # ---- timing
     def profile_enable(self, on=True):
         _check(self._lib.jt_profile_enable(self._ptr, int(bool(on))))
+
+    def calibrate_valu(self, kind: int, blocks: int, iters: int, reps: int = 3, stream=None):
+        """Runs the FP32 issue-rate calibration kernel `kind` (jt_calibrate_valu)
+        reps times; returns the fastest launch in milliseconds (HIP events on
+        the launch stream)."""
+        torch = _torch()
+        out = torch.empty(int(blocks) * 256, dtype=torch.float32, device=self.device)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        best = float("inf")
+        for _ in range(int(reps) + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            _check(self._lib.jt_calibrate_valu(int(kind), int(blocks), int(iters), c_void_p(out.data_ptr()),
+                                               c_void_p(s.cuda_stream)))
+            b.record(s)
+            b.synchronize()
+            best = min(best, a.elapsed_time(b))
+        if not torch.isfinite(out).all():
+            raise RuntimeError("calibration chains did not stay finite")
+        return best
 
     def profile_read(self, kernel: str):
         ms, n = c_double(), c_int()
