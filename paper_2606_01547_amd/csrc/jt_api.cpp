@@ -253,12 +253,24 @@ extern "C" jt_status jt_upload_tnfw(jt_ctx* ctx, int n, const float* x, const fl
   if (!handle) return fail(JT_EINVAL, "jt_upload_tnfw: null handle pointer");
   if (n < 0) return fail(JT_EINVAL, "jt_upload_tnfw: n = %d", n);
   if (n > 0 && (!x || !y || !Rs || !alpha_Rs || !r_trunc)) return fail(JT_EINVAL, "jt_upload_tnfw: null array");
-  std::vector<TRec> tab;
-  JT_TRY(pack_tnfw_host(n, x, y, Rs, alpha_Rs, r_trunc, tab));
+  JT_TRY(validate_tnfw_host(n, x, y, Rs, alpha_Rs, r_trunc));
+  // the records (with their far-field fits) are derived on the device by the
+  // prep kernel, exactly as for a device SoA
   void* dev = nullptr;
-  JT_TRY(check_hip(hipMalloc(&dev, tab.size() * sizeof(TRec)), "hipMalloc(tnfw)"));
-  jt_status st = check_hip(hipMemcpy(dev, tab.data(), tab.size() * sizeof(TRec), hipMemcpyHostToDevice),
-                           "hipMemcpy(tnfw)");
+  float* soa = nullptr;
+  JT_TRY(check_hip(hipMalloc(&dev, (size_t)subhalo_table_records(n) * sizeof(TRec)), "hipMalloc(tnfw)"));
+  jt_status st = JT_OK;
+  if (n > 0) st = check_hip(hipMalloc((void**)&soa, 5 * sizeof(float) * (size_t)n), "hipMalloc(tnfw staging)");
+  const float* cols[5] = {x, y, Rs, alpha_Rs, r_trunc};
+  for (int c = 0; c < 5 && st == JT_OK && n > 0; ++c)
+    st = check_hip(hipMemcpy(soa + (size_t)c * n, cols[c], sizeof(float) * (size_t)n, hipMemcpyHostToDevice),
+                   "hipMemcpy(tnfw)");
+  if (st == JT_OK)
+    st = check_hip(launch_prep_tnfw(n, soa, soa + n, soa + 2 * (size_t)n, soa + 3 * (size_t)n,
+                                    soa + 4 * (size_t)n, (TRec*)dev, nullptr),
+                   "prep_tnfw");
+  if (st == JT_OK) st = check_hip(hipStreamSynchronize(nullptr), "prep_tnfw sync");
+  if (soa) (void)hipFree(soa);
   if (st != JT_OK) {
     (void)hipFree(dev);
     return st;

@@ -125,9 +125,11 @@ double gamma_p(double a, double x);
 // Packed subhalo table (with padding records) from host FP32 SoA; validates.
 jt_status pack_subhalos_host(int n, const float* x, const float* y, const float* rs, const float* ars,
                              std::vector<SubRec>& out);
-// The same for truncated subhalos (r_trunc > 0).
-jt_status pack_tnfw_host(int n, const float* x, const float* y, const float* rs, const float* ars, const float* rt,
-                         std::vector<TRec>& out);
+// Validates host FP32 SoA of truncated subhalos (r_trunc > 0); their table
+// is packed on the device by the same kernel as a device SoA's, so that both
+// give bit-identical records.
+jt_status validate_tnfw_host(int n, const float* x, const float* y, const float* rs, const float* ars,
+                             const float* rt);
 // Bytes of the packed table the device SoA of `lens` needs (0 with a handle or
 // no subhalos), 256-byte aligned.
 size_t subhalo_scratch_bytes(const jt_lens* lens);

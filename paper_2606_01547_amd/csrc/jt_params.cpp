@@ -160,19 +160,14 @@ jt_status pack_subhalos_host(int n, const float* x, const float* y, const float*
   return JT_OK;
 }
 
-jt_status pack_tnfw_host(int n, const float* x, const float* y, const float* rs, const float* ars, const float* rt,
-                         std::vector<TRec>& out) {
-  out.assign(subhalo_table_records(n), TRec{1e18f, 1e18f, 1.0f, 0.0f, 1.0f, 1.0f, 0.0f, 1.0f});
+jt_status validate_tnfw_host(int n, const float* x, const float* y, const float* rs, const float* ars,
+                             const float* rt) {
   for (int i = 0; i < n; ++i) {
     if (!std::isfinite(x[i]) || !std::isfinite(y[i]) || !std::isfinite(ars[i]))
       return fail(JT_EINVAL, "subhalo %d: non-finite parameter", i);
     if (!(rs[i] > 0.0f) || !std::isfinite(rs[i])) return fail(JT_EINVAL, "subhalo %d: Rs = %g", i, (double)rs[i]);
     if (!(rt[i] > 0.0f) || !std::isfinite(rt[i]))
       return fail(JT_EINVAL, "subhalo %d: r_trunc = %g", i, (double)rt[i]);
-    const double r = rs[i], tau = (double)rt[i] / r, t2 = tau * tau;
-    out[i] = TRec{x[i], y[i], (float)(1.0 / (r * r)),
-                  (float)((double)ars[i] / ((1.0 - kLn2d) * r) * t2 / ((t2 + 1.0) * (t2 + 1.0))), (float)tau,
-                  (float)t2, (float)(t2 - 1.0), (float)(1.0 / tau)};
   }
   return JT_OK;
 }

@@ -53,9 +53,9 @@ size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 // of wave slots on 256 CUs at 8 waves per SIMD.
 constexpr int kChunkMinBlocks = 2048;
 
-// A truncated-NFW pair costs about 5.3 NFW pairs of GPU time (headline image:
-// 7.01 ms against 1.333 ms); the work caps count it so.
-constexpr double kTnfwPairCost = 5.3;
+// A truncated-NFW pair costs about 2.2 NFW pairs of GPU time (headline image:
+// 2.92 ms against 1.33 ms); the work caps count it so.
+constexpr double kTnfwPairCost = 2.2;
 
 // Pinned host memory for the batches' descriptor uploads.  Each batch keeps its
 // own slice until it completes, so forming a batch never waits for a copy

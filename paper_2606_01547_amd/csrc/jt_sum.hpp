@@ -55,8 +55,22 @@ struct NfwPairs {
 struct TnfwPairs {
   using Rec = TRec;
   static __device__ __forceinline__ Rec load(SubTable t, int k) {
-    const SubTable p = t + 8 * k;
-    return TRec{p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7]};
+    const SubTable p = t + 20 * k;
+    TRec r;
+    r.x = p[0];
+    r.y = p[1];
+    r.c1 = p[2];
+    r.c2 = p[3];
+    r.tau = p[4];
+    r.t2 = p[5];
+    r.t2m1 = p[6];
+    r.itau = p[7];
+    r.Xf = p[8];
+    r.k1 = p[9];
+#pragma unroll
+    for (int i = 0; i <= kTnfwFarDeg; ++i) r.a[i] = p[10 + i];
+    r.pad = 0.0f;
+    return r;
   }
   static __device__ __forceinline__ void run4(float tx, float ty, const Rec& a, const Rec& b, const Rec& c,
                                               const Rec& d, float& px, float& py) {
@@ -93,24 +107,22 @@ __device__ __forceinline__ float4 subhalo_range_sum(float tx, float ty, const vo
   return make_float4(hx, lx, hy, ly);
 }
 
-// The truncated profile's 32-byte records, two at a time with two
-// prefetched (four at a time would hold 64 scalar registers of records and
-// cost a wave per SIMD): the same pairs in the same order, so the same sums.
+// The truncated profile's 80-byte records one at a time with one prefetched
+// (two at a time would hold 80 scalar registers of records): the same pairs in
+// the same order as the general loop, so the same sums.
 template <>
 __device__ __forceinline__ float4 subhalo_range_sum<TnfwPairs>(float tx, float ty, const void* table, int kb,
                                                                int ke) {
   const SubTable sub = (SubTable)(const float*)table;
   float hx = 0.f, lx = 0.f, hy = 0.f, ly = 0.f;
-  TRec n0 = TnfwPairs::load(sub, kb), n1 = TnfwPairs::load(sub, kb + 1);
+  TRec n0 = TnfwPairs::load(sub, kb);
   for (int k0 = kb; k0 < ke; k0 += kSubTile) {
     const int kend = min(k0 + kSubTile, ke);
     float px = 0.f, py = 0.f;
-    for (int k = k0; k < kend; k += 2) {
-      const TRec s0 = n0, s1 = n1;
-      n0 = TnfwPairs::load(sub, k + 2);
-      n1 = TnfwPairs::load(sub, k + 3);
+    for (int k = k0; k < kend; ++k) {
+      const TRec s0 = n0;
+      n0 = TnfwPairs::load(sub, k + 1);
       tnfw_pair(tx, ty, s0, px, py);
-      tnfw_pair(tx, ty, s1, px, py);
     }
     two_sum_acc(hx, lx, px);
     two_sum_acc(hy, ly, py);

@@ -40,13 +40,10 @@ __global__ __launch_bounds__(256) void k_prep_tnfw(int n, int padded, const floa
                                                   TRec* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) {
-    if (i < padded) out[i] = TRec{1e18f, 1e18f, 1.0f, 0.0f, 1.0f, 1.0f, 0.0f, 1.0f};
+    if (i < padded) out[i] = trec_pad();
     return;
   }
-  const double r = rs[i], tau = (double)rt[i] / r, t2 = tau * tau;
-  out[i] = TRec{x[i], y[i], (float)(1.0 / (r * r)),
-                (float)((double)ars[i] / ((1.0 - kLn2d) * r) * t2 / ((t2 + 1.0) * (t2 + 1.0))), (float)tau, (float)t2,
-                (float)(t2 - 1.0), (float)(1.0 / tau)};
+  out[i] = make_trec(x[i], y[i], rs[i], ars[i], rt[i]);
 }
 
 // ---------------------------------------------------------------------------

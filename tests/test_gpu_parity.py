@@ -236,6 +236,24 @@ def test_single_tnfw_every_branch(ctx, tau):
     assert _np(a0[0])[0] == 0.0 and _np(a0[1])[0] == 0.0
 
 
+@pytest.mark.parametrize("tau", [0.4, 2.0, 7.0, 40.0, 300.0, 1e4])
+def test_single_tnfw_far_field_boundary(ctx, tau):
+    """Points just inside and outside x_f = 1.5 max(tau, 1), where the pair
+    switches between the general form and the far-field polynomial, and far
+    beyond it: per-point relative error of the deflection."""
+    Rs, aRs, cx, cy = 0.1, 2e-3, 0.3, -0.2
+    xf = 1.5 * max(tau, 1.0)
+    X = xf * np.array([0.95, 0.99, 0.999, 1.0005, 1.001, 1.01, 1.1, 1.5, 3.0, 10.0, 100.0, 1000.0])
+    ang = np.linspace(0.2, 6.1, X.size)
+    x = _f32(cx + X * Rs * np.cos(ang))
+    y = _f32(cy + X * Rs * np.sin(ang))
+    lens = W.Lens(nfw=W.NFWTable(_f32([cx]), _f32([cy]), _f32([Rs]), _f32([aRs]), r_trunc=_f32([tau * Rs])))
+    ax, ay = ctx.deflection(x, y, lens)
+    ex, ey = O.total_deflection(x, y, lens)
+    rel = np.hypot(_np(ax) - ex, _np(ay) - ey) / np.hypot(ex, ey)
+    assert rel.max() <= 1e-5, dict(zip((X / xf).tolist(), rel.tolist()))
+
+
 def test_deflection_truncated_subhalos_full_lens(ctx):
     sc = W.tnfw_scene()
     rng = np.random.default_rng(6)
