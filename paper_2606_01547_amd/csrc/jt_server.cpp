@@ -15,7 +15,9 @@
 // workgroup of a queued kernel before it turns to another queue, but switches
 // at kernel boundaries of one queue: batches of the requests behind a large
 // one therefore start at the next chunk boundary instead of after the whole
-// image.
+// image.  While whole requests are queued or running, chunks shrink to half a
+// round of wave slots, one at a time (kChunkSharedBlocks), so the small
+// batches always find half the chip open.
 //
 // A batch that fails on the device (its completion event reports an error,
 // or its launch fails) puts the server in a failed state: a device fault can
@@ -52,6 +54,14 @@ size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 // Smallest chunk of a chunked request: 2048 blocks of 4 waves, one full round
 // of wave slots on 256 CUs at 8 waves per SIMD.
 constexpr int kChunkMinBlocks = 2048;
+// While whole requests wait in the queue or run, a chunked request takes
+// chunks of at most this many blocks (half a round of wave slots), one at a
+// time, so that at least half the chip stays open to the small batches: the
+// blocks of a large image each run for milliseconds, and the hardware hands a
+// freed slot to whichever queue's kernel is next, so a full-round chunk would
+// hold the whole chip for one block lifetime per chunk.  With nothing else to
+// run the request goes back to full chunks, two queued.
+constexpr int kChunkSharedBlocks = 1024;
 
 // A truncated-NFW pair costs about 2.2 NFW pairs of GPU time (headline image:
 // 2.92 ms against 1.33 ms); the work caps count it so.
@@ -627,11 +637,14 @@ void jt_server::launch_ready() {
     // has completed
     Req* r = nullptr;
     bool conv = false;
+    // whole requests queued or on the device: chunks share the chip
+    const bool shared = !queue.empty() || (int)inflight.size() > chunk_batches;
+    const int chunk_depth = shared ? 1 : 2;
     if (chunk_batches < max_chunk_batches) {
       for (size_t i = 0; i < active.size() && !r; ++i) {
         Req* a = active[(rr + i) % active.size()];
         if (a->failed) continue;
-        if (a->next_block < a->blocks && a->chunks_inflight < 2) {
+        if (a->next_block < a->blocks && a->chunks_inflight < chunk_depth) {
           r = a;
         } else if (a->k && !a->conv_launched && a->next_block == a->blocks && a->chunks_inflight == 0) {
           r = a;
@@ -641,7 +654,8 @@ void jt_server::launch_ready() {
       }
     }
     if (r) {
-      const int b0 = r->next_block, b1 = conv ? b0 : std::min(r->blocks, b0 + r->chunk_blocks);
+      const int cb = shared ? std::min(r->chunk_blocks, kChunkSharedBlocks) : r->chunk_blocks;
+      const int b0 = r->next_block, b1 = conv ? b0 : std::min(r->blocks, b0 + cb);
       const size_t bytes = conv ? conv_footprint(r->g) : chunk_footprint(b1 - b0);
       size_t off = 0, so = 0;
       if (!arena.alloc(bytes, &off)) return;
