@@ -2,18 +2,22 @@
 // transforms of zero-padded rows and columns, a pointwise product with the
 // kernel spectrum, the inverse transforms and a crop to the same-size output.
 //
-// Each row transform runs in LDS as a radix-2 Stockham autosort FFT
-// (Stockham; formulation of Govindaraju et al. 2008): log2 N stages, stage
-// with half-span L reads src[j] and src[j + N/2], multiplies the second by
-// exp(-+2 pi i (j mod L) / (2L)) and writes the sum and difference to
-// dst[2L floor(j/L) + (j mod L)] and that index + L.  Columns are transformed
-// as rows of a transposed array.
+// Each row transform runs in LDS as a mixed-radix Stockham autosort FFT
+// (radices 4, 2, 3 and 5; the radix-2 formulation of Govindaraju et al. 2008
+// generalised to radix p): a pass of radix p over sub-transforms of length Ns
+// takes, for j < N/p with k = j mod Ns, the p values src[j + t N/p],
+// multiplies value t by exp(-+2 pi i t k / (Ns p)), applies the p-point DFT and
+// writes its outputs to dst[(j - k) p + k + t Ns]; after the passes (radix 4
+// while N has a factor 4, then 2, 3, 5) the result is in natural order.
+// Columns are transformed as rows of a transposed array.
 //
-// Sizes: Nx >= max(nx + c, k) and Ny >= max(ny + c, k) (c = (k-1)/2), powers
-// of two up to kFftMaxN; with that padding the circular convolution equals the
-// linear one on every output of the "same" region (the wrapped indices of the
-// image land in zero padding, and the kernel itself is not wrapped).  FP64 keeps the round-off ~1e-15 of
-// the image maximum, far inside the per-pixel error bar of faint pixels.
+// Sizes: Nx >= max(nx + c, k) and Ny >= max(ny + c, k) (c = (k-1)/2), the
+// smallest such products 2^a 3^b 5^c up to kFftMaxN (a 1000-pixel side with a
+// 101-pixel kernel pads to 1080, not 2048); with that padding the circular
+// convolution equals the linear one on every output of the "same" region (the
+// wrapped indices of the image land in zero padding, and the kernel itself is
+// not wrapped).  FP64 keeps the round-off ~1e-15 of the image maximum, far
+// inside the per-pixel error bar of faint pixels.
 #include "jt_device.hpp"
 #include "jt_kernels.hpp"
 
@@ -21,30 +25,94 @@ namespace jt {
 
 constexpr int kFftThreads = 256;
 
-// In-LDS FFT of length N = 2^logN over buffers a (input) and b; returns the
-// buffer holding the result.  tw[t] = exp(-2 pi i t / N), t < N/2.
+// p-point DFT of v[0..p) in place: y_m = sum_n v_n exp(-+2 pi i m n / p).
+template <int P>
+__device__ __forceinline__ void dft_small(double2* v, bool inverse) {
+  const double sg = inverse ? -1.0 : 1.0;   // the sign of the sine terms
+  if (P == 2) {
+    const double2 a = v[0], b = v[1];
+    v[0] = make_double2(a.x + b.x, a.y + b.y);
+    v[1] = make_double2(a.x - b.x, a.y - b.y);
+  } else if (P == 4) {
+    // y1 = (a - c) - i (b - d), y3 = (a - c) + i (b - d) for the forward sign
+    const double2 a = v[0], b = v[1], c = v[2], d = v[3];
+    const double2 s0 = make_double2(a.x + c.x, a.y + c.y), d0 = make_double2(a.x - c.x, a.y - c.y);
+    const double2 s1 = make_double2(b.x + d.x, b.y + d.y), d1 = make_double2(b.x - d.x, b.y - d.y);
+    v[0] = make_double2(s0.x + s1.x, s0.y + s1.y);
+    v[2] = make_double2(s0.x - s1.x, s0.y - s1.y);
+    v[1] = make_double2(d0.x + sg * d1.y, d0.y - sg * d1.x);
+    v[3] = make_double2(d0.x - sg * d1.y, d0.y + sg * d1.x);
+  } else {
+    // direct sums with exp(-2 pi i q / P), q < P
+    constexpr double kC3[3] = {1.0, -0.5, -0.5};
+    constexpr double kS3[3] = {0.0, 0.86602540378443864676, -0.86602540378443864676};
+    constexpr double kC5[5] = {1.0, 0.30901699437494742410, -0.80901699437494742410, -0.80901699437494742410,
+                               0.30901699437494742410};
+    constexpr double kS5[5] = {0.0, 0.95105651629515357212, 0.58778525229247312917, -0.58778525229247312917,
+                               -0.95105651629515357212};
+    const double* C = P == 3 ? kC3 : kC5;
+    const double* S = P == 3 ? kS3 : kS5;
+    double2 x[P];
+#pragma unroll
+    for (int n = 0; n < P; ++n) x[n] = v[n];
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int n = 0; n < P; ++n) {
+        const int q = (m * n) % P;
+        const double c = C[q], sn = -sg * S[q];   // exp(-+i theta) = cos -+ i sin
+        re += x[n].x * c - x[n].y * sn;
+        im += x[n].x * sn + x[n].y * c;
+      }
+      v[m] = make_double2(re, im);
+    }
+  }
+}
+
+// One Stockham pass of radix P from src to dst (N points, sub-transforms of
+// length Ns so far); tw[t] = exp(-2 pi i t / N), t < N.
+template <int P>
+__device__ __forceinline__ void fft_pass(const double2* __restrict__ src, double2* __restrict__ dst, int N, int Ns,
+                                         const double2* __restrict__ tw, bool inverse) {
+  const int m = N / P;
+  const int step = N / (Ns * P);
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    const int k = j % Ns;
+    double2 v[P];
+#pragma unroll
+    for (int t = 0; t < P; ++t) v[t] = src[j + t * m];
+#pragma unroll
+    for (int t = 1; t < P; ++t) {
+      const double2 w = tw[t * k * step];
+      const double wi = inverse ? -w.y : w.y;
+      v[t] = make_double2(v[t].x * w.x - v[t].y * wi, v[t].x * wi + v[t].y * w.x);
+    }
+    dft_small<P>(v, inverse);
+    const int d = (j - k) * P + k;
+#pragma unroll
+    for (int t = 0; t < P; ++t) dst[d + t * Ns] = v[t];
+  }
+}
+
+// In-LDS FFT of length N (a product of 2, 3 and 5) over buffers a (input) and
+// b; returns the buffer holding the result.  tw[t] = exp(-2 pi i t / N), t < N.
 __device__ __forceinline__ double2* fft_lds(double2* a, double2* b, int N, const double2* __restrict__ tw, bool inverse) {
-  const int half = N >> 1;
   double2* src = a;
   double2* dst = b;
-  for (int L = 1; L < N; L <<= 1) {
-    const int stride = N / (2 * L);   // twiddle index step
-    for (int j = threadIdx.x; j < half; j += blockDim.x) {
-      const int k = j & (L - 1);
-      const double2 w0 = tw[k * stride];
-      const double wr = w0.x, wi = inverse ? -w0.y : w0.y;
-      const double2 u = src[j];
-      const double2 v = src[j + half];
-      const double vr = v.x * wr - v.y * wi;
-      const double vi = v.x * wi + v.y * wr;
-      const int d = 2 * (j - k) + k;
-      dst[d] = make_double2(u.x + vr, u.y + vi);
-      dst[d + L] = make_double2(u.x - vr, u.y - vi);
-    }
+  int Ns = 1, rem = N;
+  while (rem > 1) {
+    const int p = (rem & 3) == 0 ? 4 : (rem & 1) == 0 ? 2 : rem % 3 == 0 ? 3 : 5;
+    if (p == 4) fft_pass<4>(src, dst, N, Ns, tw, inverse);
+    else if (p == 2) fft_pass<2>(src, dst, N, Ns, tw, inverse);
+    else if (p == 3) fft_pass<3>(src, dst, N, Ns, tw, inverse);
+    else fft_pass<5>(src, dst, N, Ns, tw, inverse);
     __syncthreads();
     double2* t = src;
     src = dst;
     dst = t;
+    rem /= p;
+    Ns *= p;
   }
   return src;
 }
@@ -128,11 +196,16 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_crop(const double2* __
 }
 
 // ---------------------------------------------------------------------------
+// Smallest 2^a 3^b 5^c >= max(n + (k-1)/2, k, kFftMinN).
 int fft_size_for(int n, int k) {
-  const int need = n + (k - 1) / 2 > k ? n + (k - 1) / 2 : k;
-  int N = kFftMinN;
-  while (N < need) N <<= 1;
-  return N;
+  int N = n + (k - 1) / 2 > k ? n + (k - 1) / 2 : k;
+  if (N < kFftMinN) N = kFftMinN;
+  for (;; ++N) {
+    int r = N;
+    for (int p : {2, 3, 5})
+      while (r % p == 0) r /= p;
+    if (r == 1) return N;
+  }
 }
 
 size_t fft_workspace_bytes(int nx, int ny, int k) {

@@ -120,9 +120,9 @@ jt_status ctx_twiddles(jt_ctx* ctx, int N, const double2** out) {
   std::lock_guard<std::mutex> lk(ctx->mu);
   auto it = ctx->twiddles.find(N);
   if (it == ctx->twiddles.end()) {
-    std::vector<double2> tw(N / 2);
+    std::vector<double2> tw(N);
     const double two_pi = 6.283185307179586476925286766559;
-    for (int t = 0; t < N / 2; ++t) {
+    for (int t = 0; t < N; ++t) {
       const double a = two_pi * (double)t / (double)N;
       tw[t] = make_double2(std::cos(a), -std::sin(a));
     }

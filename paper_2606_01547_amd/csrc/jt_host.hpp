@@ -47,7 +47,7 @@ struct jt_ctx {
   std::map<hipStream_t, Buffer> ws;      // per-stream workspace
   std::map<hipStream_t, Buffer> ws_aux;  // per-stream second workspace (FFT buffers)
   std::map<hipStream_t, Staging> stage;  // per-stream pinned upload buffer
-  std::map<int, void*> twiddles;         // FFT length -> device exp(-2 pi i t / N), t < N/2
+  std::map<int, void*> twiddles;         // FFT length -> device exp(-2 pi i t / N), t < N
   std::map<uint64_t, Resident> handles;
   uint64_t next_handle = 1;
   jt::SubRec* empty_table = nullptr;  // padding records for lenses without subhalos

@@ -74,7 +74,7 @@ hipError_t launch_prep_subhalos_batched(int B, int n, const float* x, const floa
 // MI355X (images 100^2..1000^2, k = 3..255):
 //   direct: kConvDirectFixedS + nx ny k^2 / min(kConvDirectFmaPerS, tiles * kConvDirectFmaPerTileS)
 //           (small images have too few 64 x 4 tiles to fill the chip)
-//   FFT:    kConvFftFixedS + Nx Ny / kConvFftPointsPerS (padded power-of-two sizes)
+//   FFT:    kConvFftFixedS + Nx Ny / kConvFftPointsPerS (padded 2-3-5 sizes)
 constexpr double kConvDirectFixedS = 6e-6;
 constexpr double kConvDirectFmaPerS = 1.55e13;
 constexpr double kConvDirectFmaPerTileS = 5e10;
@@ -82,10 +82,11 @@ constexpr double kConvFftFixedS = 30e-6;
 constexpr double kConvFftPointsPerS = 1.45e10;
 bool conv_prefers_fft(int nx, int ny, int k);
 constexpr int kFftMinN = 16, kFftMaxN = 2048;
-// Padded power-of-two length for an image side n and kernel side k.
+// Padded FFT length (the smallest 2^a 3^b 5^c that avoids wrap-around) for an
+// image side n and kernel side k.
 int fft_size_for(int n, int k);
 size_t fft_workspace_bytes(int nx, int ny, int k);
-// tw_x, tw_y: tables exp(-2 pi i t / N), t < N/2, for N = fft_size_for(nx, k)
+// tw_x, tw_y: tables exp(-2 pi i t / N), t < N, for N = fft_size_for(nx, k)
 // and fft_size_for(ny, k); ws: fft_workspace_bytes.
 hipError_t launch_fft_convolve(const float* img, int nx, int ny, const float* psf, int k, float* out, void* ws,
                                const double2* tw_x, const double2* tw_y, hipStream_t st);
