@@ -157,3 +157,92 @@ def test_torch_sie_is_zero_at_its_centre_like_the_numpy_oracle():
         np.testing.assert_allclose(ay.detach().numpy(), ey, rtol=1e-12, atol=1e-15)
         (ax[1:].sum() + ay[1:].sum()).backward()
         assert bool(torch.isfinite(par.grad).all())
+
+
+# ---------------------------------------------------- EPL main deflector, TNFW
+def _epl_tnfw_scene(n_sub=25, s=2):
+    sc = W.epl_scene(n_sub=n_sub, npix=20, supersample=s, psf_size=5)
+    sc.grid = W.Grid(nx=22, ny=19, pixel_scale=0.12, x0=0.03, y0=-0.02, supersample=s)
+    nfw = sc.lens.nfw
+    rng = np.random.default_rng(77)
+    nfw.r_trunc = (10.0 ** rng.uniform(0.5, 1.5, nfw.n) * nfw.Rs).astype(np.float32)
+    return sc
+
+
+def _set_macro_epl(sc, vec):
+    sc = copy.deepcopy(sc)
+    sc.lens.epl = W.EPL(*vec[:6])
+    sc.lens.shear = W.Shear(*vec[6:8])
+    comps = list(sc.source) + list(sc.lens_light)
+    new = [W.Sersic(*vec[8 + 7 * k: 15 + 7 * k]) for k in range(len(comps))]
+    sc.source = new[:len(sc.source)]
+    sc.lens_light = new[len(sc.source):]
+    return sc
+
+
+def test_torch_forward_matches_numpy_oracle_epl_tnfw():
+    """The torch restatement's EPL (its hypergeometric series) and truncated
+    NFW against the NumPy oracle (SciPy's 2F1, the NumPy G)."""
+    import torch
+    from oracle import grad as G
+    sc = _epl_tnfw_scene()
+    assert G.main_kind(sc.lens) == "epl"
+    mac = torch.tensor(O.macro_vector(sc.lens, sc.source, sc.lens_light))
+    n = sc.lens.nfw
+    t = lambda a: torch.tensor(np.asarray(a, np.float64))
+    m = G.torch_forward(mac, t(n.x), t(n.y), t(n.alpha_Rs), t(n.Rs), sc.grid, len(sc.source),
+                        len(sc.lens_light), sc.psf, "epl", t(n.r_trunc)).numpy()
+    np.testing.assert_allclose(m, O.simulate_image(sc), rtol=1e-11, atol=1e-13 * np.abs(m).max())
+
+
+def test_gradient_matches_central_differences_epl_tnfw():
+    """Every macro parameter of an EPL + shear + Sersic scene (the slope gamma
+    included) and (x, y, alpha_Rs) of the four strongest truncated subhalos
+    against Richardson central differences of the NumPy oracle's log L."""
+    sc = _epl_tnfw_scene()
+    d, w = _data(sc, seed=2)
+    logL, gm, gs = O.chi2_gradient(sc, d, w)
+    assert logL == pytest.approx(_logL(sc, d, w), rel=1e-11)
+    vec = O.macro_vector(sc.lens, sc.source, sc.lens_light)
+    names = O.macro_names(len(sc.source), len(sc.lens_light), "epl")
+    assert len(names) == vec.size == gm.size
+    for k in range(vec.size):
+        def f(h, k=k):
+            v = vec.copy()
+            v[k] += h
+            return _logL(_set_macro_epl(sc, v), d, w)
+        fd = _richardson(f, 1e-4 * max(abs(vec[k]), 0.1))
+        assert abs(fd - gm[k]) <= 1e-6 * np.abs(gm).max(), (names[k], fd, gm[k])
+    nfw = sc.lens.nfw
+    for kk in np.argsort(-nfw.alpha_Rs)[:4]:
+        for col, arr in enumerate(("x", "y", "alpha_Rs")):
+            base = getattr(nfw, arr).astype(np.float64)
+
+            def f(h, kk=kk, arr=arr, base=base):
+                sc2 = copy.deepcopy(sc)
+                a = base.copy()
+                a[kk] += h
+                setattr(sc2.lens.nfw, arr, a)
+                return _logL(sc2, d, w)
+            h = 1e-4 * (max(abs(base[kk]), 0.1) if arr != "alpha_Rs" else base[kk])
+            fd = _richardson(f, h)
+            assert abs(fd - gs[kk, col]) <= 1e-6 * np.abs(gs[:, col]).max(), (kk, arr, fd, gs[kk, col])
+
+
+def test_epl_gradient_at_slope_two_is_the_sie_gradient():
+    """At gamma = 2 the EPL is the SIE (same theta_E normalisation): its
+    gradient in (theta_E, q, phi, cx, cy), the shear and the Sersic
+    parameters equals the SIE scene's, and the slope derivative is finite."""
+    sc = _epl_tnfw_scene(n_sub=0)
+    sc.lens.nfw = None
+    e = sc.lens.epl
+    sc.lens.epl = W.EPL(e.theta_E, 2.0, e.q, e.phi, e.cx, e.cy)
+    sie = copy.deepcopy(sc)
+    sie.lens.epl = None
+    sie.lens.sie = W.SIE(e.theta_E, e.q, e.phi, e.cx, e.cy)
+    d, w = _data(sie, seed=4)
+    _, g_epl, _ = O.chi2_gradient(sc, d, w)
+    _, g_sie, _ = O.chi2_gradient(sie, d, w)
+    keep = np.r_[0, 2:g_epl.size]
+    np.testing.assert_allclose(g_epl[keep], g_sie, rtol=1e-8, atol=1e-10 * np.abs(g_sie).max())
+    assert np.isfinite(g_epl[1])
