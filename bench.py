@@ -584,6 +584,15 @@ def adjoint_bench(ctx, draws, reps):
         for lens, src, ll in resident:
             ctx.simulate_image(truth.grid, lens, src, ll, psf, out=out)
     t_pi = timeit(per_image)
+    # the same case with an EPL main deflector and truncated subhalos
+    truth_p, scenes_p = W.config4_profile_draws(B=draws, n_sub=scenes[0].lens.nfw.n, grid=truth.grid, epl=True,
+                                                tnfw=True, psf_size=21)
+    macro_p = np.stack([macro_row(s.lens, s.source, s.lens_light) for s in scenes_p])
+    stp = lambda a: torch.from_numpy(np.stack([getattr(s.lens.nfw, a) for s in scenes_p])).cuda()
+    batch_p = DrawBatch(macro_p, 1, 0, stp("x"), stp("y"), stp("Rs"), stp("alpha_Rs"), main="epl",
+                        sub_r_trunc=stp("r_trunc"))
+    t_grad_p = timeit(lambda: ctx.chi2_grad(truth.grid, batch_p, dt, wt, psf))
+    t_fwd_p = timeit(lambda: ctx.chi2(truth.grid, batch_p, dt, wt, psf))
     return {"workload": f"{draws} draws of 100x100 px, s=1, SIE + shear + 1000 NFW, 1 source, 21x21 PSF",
             "gradient_ms_per_batch": round(1e3 * t_grad, 3), "forward_ms_per_batch": round(1e3 * t_fwd, 3),
             "per_image_forward_ms_per_batch": round(1e3 * t_pi, 3),
@@ -591,7 +600,12 @@ def adjoint_bench(ctx, draws, reps):
             "gradients_per_s": round(draws / t_grad, 1), "adjoint_over_forward": round(t_grad / t_fwd, 3),
             "kept_positions_gradient_ms_per_batch": round(1e3 * t_kept, 3),
             "kept_positions_over_forward": round(t_kept / t_fwd, 3),
-            "params_per_draw": int(macro.shape[1] + 3 * scenes[0].lens.nfw.n)}
+            "params_per_draw": int(macro.shape[1] + 3 * scenes[0].lens.nfw.n),
+            "epl_tnfw": {"workload": "the same draws with an EPL main deflector (slope 1.9 +- 1%) and truncated "
+                                     "subhalos (tau log-uniform in [3, 30])",
+                         "gradient_ms_per_batch": round(1e3 * t_grad_p, 3),
+                         "forward_ms_per_batch": round(1e3 * t_fwd_p, 3),
+                         "params_per_draw": int(macro_p.shape[1] + 3 * scenes_p[0].lens.nfw.n)}}
 
 
 # Lane-operations per round of each calibration kind (jt_calibrate_valu) and

@@ -247,19 +247,22 @@ jt_status jt_simulate_image_noalloc(jt_ctx* ctx, const jt_grid* grid, const jt_l
  * gradient-based fitting possible (section "Improvements over lenstronomy in
  * lens modelling", L-BFGS); here the gradient is a hand-written adjoint.
  * -------------------------------------------------------------------- */
-/* B draws on one grid, each with an SIE, an external shear, n_sub NFW
- * subhalos and n_src source + n_ll lens-light Sersic components (b_n from the
- * Capaccioli fit).  Host arrays are read during the call; the subhalo SoA is
- * device float32 [B][n_sub] (draw b at offset b * n_sub). */
+/* B draws on one grid, each with a main deflector (an SIE, or an EPL when
+ * `epl` is given), an external shear, n_sub NFW subhalos (truncated NFWs when
+ * `sub_r_trunc` is given) and n_src source + n_ll lens-light Sersic components
+ * (b_n from the Capaccioli fit).  Host arrays are read during the call; the
+ * subhalo SoA is device float32 [B][n_sub] (draw b at offset b * n_sub). */
 typedef struct {
   int B;
-  const jt_sie* sie;                /* host [B] */
+  const jt_sie* sie;                /* host [B] (ignored, may be NULL, when epl is given) */
   const jt_shear* shear;            /* host [B] */
   int n_sub;                        /* >= 0 */
   const float *sub_x, *sub_y, *sub_Rs, *sub_alpha_Rs;   /* device [B][n_sub] */
   int n_src, n_ll;                  /* n_src + n_ll <= 3 for jt_chi2_grad */
   const jt_sersic* src;             /* host [B][n_src] */
   const jt_sersic* ll;              /* host [B][n_ll] (NULL when n_ll = 0) */
+  const jt_epl* epl;                /* host [B], or NULL: the main deflector is the SIE */
+  const float* sub_r_trunc;         /* device [B][n_sub] (each > 0, not validated), or NULL */
 } jt_draws;
 
 /* Forward images of every draw: out device float32 [B][ny][nx], not
@@ -280,9 +283,13 @@ jt_status jt_chi2(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, const
  * g_macro: device float32 [B][P], P = 7 + 7 (n_src + n_ll), in the order
  *   (theta_E, q, phi, cx, cy) of the SIE, (gamma1, gamma2), then
  *   (amp, R_sersic, n_sersic, q, phi, cx, cy) per source, then per lens-light
- *   component.
+ *   component; with an EPL main deflector P = 8 + 7 (n_src + n_ll) and the
+ *   row starts (theta_E, gamma, q, phi, cx, cy) of the EPL (its partials by
+ *   forward-mode differentiation of the deflection's series; 0 when
+ *   theta_E = 0).
  * g_sub: device float32 [B][n_sub][3] = d log L / d(x, y, alpha_Rs) per
- *   subhalo (may be NULL when n_sub = 0).
+ *   subhalo, NFW or truncated (Rs and r_trunc held fixed; may be NULL when
+ *   n_sub = 0).
  * logL: device double [B] (may be NULL).  Deterministic: fixed summation order,
  * so a call repeated gives the same bits.  A draw's gradient depends on the
  * rest of the batch only through the wave split picked from the batch's total

@@ -99,7 +99,8 @@ class JtLight(ctypes.Structure):
 class JtDraws(ctypes.Structure):
     _fields_ = [("B", c_int), ("sie", POINTER(JtSie)), ("shear", POINTER(JtShear)), ("n_sub", c_int),
                 ("sub_x", c_void_p), ("sub_y", c_void_p), ("sub_Rs", c_void_p), ("sub_alpha_Rs", c_void_p),
-                ("n_src", c_int), ("n_ll", c_int), ("src", POINTER(JtSersic)), ("ll", POINTER(JtSersic))]
+                ("n_src", c_int), ("n_ll", c_int), ("src", POINTER(JtSersic)), ("ll", POINTER(JtSersic)),
+                ("epl", POINTER(JtEpl)), ("sub_r_trunc", c_void_p)]
 
 
 class JtFitProblem(ctypes.Structure):
@@ -548,21 +549,31 @@ class Context:
 
     # ---- batches of parameter draws
     def _draws(self, batch, keep):
-        """JtDraws from a DrawBatch (macro rows on the host, subhalo SoA on the device)."""
+        """JtDraws from a DrawBatch (macro rows on the host, subhalo SoA on the
+        device).  Macro row: SIE (5) or, with batch.main == "epl", EPL (6:
+        theta_E, gamma, q, phi, cx, cy), then shear (2), then 7 per Sersic."""
         mac = np.ascontiguousarray(np.asarray(batch.macro, dtype=np.float64))
         B, P = mac.shape
         ns, nl = int(batch.n_src), int(batch.n_ll)
-        if P != 7 + 7 * (ns + nl):
-            raise ValueError("macro rows must hold 7 + 7 (n_src + n_ll) values")
-        sie = (JtSie * B)(*[JtSie(*row[:5]) for row in mac])
-        sh = (JtShear * B)(*[JtShear(*row[5:7]) for row in mac])
-        src = (JtSersic * max(1, B * ns))(*[JtSersic(*row[7 + 7 * k:14 + 7 * k]) for row in mac for k in range(ns)])
-        ll = (JtSersic * max(1, B * nl))(*[JtSersic(*row[7 + 7 * (ns + k):14 + 7 * (ns + k)])
+        epl = getattr(batch, "main", "sie") == "epl"
+        m = 6 if epl else 5
+        if P != m + 2 + 7 * (ns + nl):
+            raise ValueError(f"macro rows must hold {m + 2} + 7 (n_src + n_ll) values")
+        o = m + 2
+        main = ((JtEpl * B)(*[JtEpl(*row[:6]) for row in mac]) if epl
+                else (JtSie * B)(*[JtSie(*row[:5]) for row in mac]))
+        sh = (JtShear * B)(*[JtShear(*row[m:m + 2]) for row in mac])
+        src = (JtSersic * max(1, B * ns))(*[JtSersic(*row[o + 7 * k:o + 7 + 7 * k]) for row in mac
+                                            for k in range(ns)])
+        ll = (JtSersic * max(1, B * nl))(*[JtSersic(*row[o + 7 * (ns + k):o + 7 + 7 * (ns + k)])
                                            for row in mac for k in range(nl)])
-        keep.extend([sie, sh, src, ll])
+        keep.extend([main, sh, src, ll])
         D = JtDraws()
         D.B = B
-        D.sie = ctypes.cast(sie, POINTER(JtSie))
+        if epl:
+            D.epl = ctypes.cast(main, POINTER(JtEpl))
+        else:
+            D.sie = ctypes.cast(main, POINTER(JtSie))
         D.shear = ctypes.cast(sh, POINTER(JtShear))
         D.n_src, D.n_ll = ns, nl
         D.src = ctypes.cast(src, POINTER(JtSersic))
@@ -575,6 +586,12 @@ class Context:
                 if tuple(a.shape) != (B, n):
                     raise ValueError("subhalo arrays must be [B, n_sub]")
             D.sub_x, D.sub_y, D.sub_Rs, D.sub_alpha_Rs = [c_void_p(a.data_ptr()) for a in arrs]
+            rt = getattr(batch, "sub_r_trunc", None)
+            if rt is not None:
+                t = _dev_f32(rt, self.device, keep)
+                if tuple(t.shape) != (B, n):
+                    raise ValueError("sub_r_trunc must be [B, n_sub]")
+                D.sub_r_trunc = c_void_p(t.data_ptr())
         return D, B, n, P
 
     @staticmethod

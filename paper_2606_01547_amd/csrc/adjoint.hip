@@ -133,6 +133,119 @@ __device__ __forceinline__ void sie_grad(const MacroC& m, float tx, float ty, fl
 }
 
 // ---------------------------------------------------------------------------
+// EPL partials by forward-mode differentiation in FP64: the forward's series
+// evaluated on numbers carrying their derivatives with respect to
+// (theta_E, gamma, q, phi, cx, cy).
+// ---------------------------------------------------------------------------
+struct Dual6 {
+  double v, d[6];
+};
+
+__device__ __forceinline__ Dual6 dnum(double v, int var) {
+  Dual6 r;
+  r.v = v;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) r.d[i] = i == var ? 1.0 : 0.0;
+  return r;
+}
+__device__ __forceinline__ Dual6 operator+(const Dual6& a, const Dual6& b) {
+  Dual6 r;
+  r.v = a.v + b.v;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) r.d[i] = a.d[i] + b.d[i];
+  return r;
+}
+__device__ __forceinline__ Dual6 operator-(const Dual6& a, const Dual6& b) {
+  Dual6 r;
+  r.v = a.v - b.v;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) r.d[i] = a.d[i] - b.d[i];
+  return r;
+}
+__device__ __forceinline__ Dual6 operator*(const Dual6& a, const Dual6& b) {
+  Dual6 r;
+  r.v = a.v * b.v;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i];
+  return r;
+}
+__device__ __forceinline__ Dual6 operator*(double s, const Dual6& a) {
+  Dual6 r;
+  r.v = s * a.v;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) r.d[i] = s * a.d[i];
+  return r;
+}
+__device__ __forceinline__ Dual6 operator+(double s, const Dual6& a) {
+  Dual6 r = a;
+  r.v += s;
+  return r;
+}
+__device__ __forceinline__ Dual6 inv(const Dual6& a) {   // 1/a
+  const double i = 1.0 / a.v, i2 = -i * i;
+  Dual6 r;
+  r.v = i;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) r.d[k] = i2 * a.d[k];
+  return r;
+}
+__device__ __forceinline__ Dual6 fn(const Dual6& a, double f, double df) {   // chain rule
+  Dual6 r;
+  r.v = f;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) r.d[k] = df * a.d[k];
+  return r;
+}
+__device__ __forceinline__ Dual6 dsqrt(const Dual6& a) {
+  const double s = sqrt(a.v);
+  return fn(a, s, 0.5 / s);
+}
+__device__ __forceinline__ Dual6 dlog(const Dual6& a) { return fn(a, log(a.v), 1.0 / a.v); }
+__device__ __forceinline__ Dual6 dexp(const Dual6& a) {
+  const double e = exp(a.v);
+  return fn(a, e, e);
+}
+
+// Contributions -G . d alpha_EPL / d p to d log L / d p for
+// p = (theta_E, gamma, q, phi, cx, cy) at the image-plane point (tx, ty):
+// the forward's deflection (epl_deflection64: the series of the
+// hypergeometric factor, the same terms and stopping rule) on dual numbers.
+__device__ void epl_grad(const MacroC& m, double tx, double ty, float Gx, float Gy, float out[6]) {
+  const Dual6 q = dnum(m.eq, 2), ph = dnum(m.e_phi, 3);
+  const Dual6 c = fn(ph, cos(m.e_phi), -sin(m.e_phi)), s = fn(ph, sin(m.e_phi), cos(m.e_phi));
+  const Dual6 dx = tx + (-1.0 * dnum(m.ecx, 4)), dy = ty + (-1.0 * dnum(m.ecy, 5));
+  const Dual6 xp = c * dx + s * dy, yp = c * dy - s * dx;
+  const Dual6 qx = q * xp;
+  const Dual6 R2 = qx * qx + yp * yp;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) out[i] = 0.f;
+  if (!(R2.v > 0.0)) return;
+  const Dual6 iR = inv(dsqrt(R2));
+  const Dual6 er = qx * iR, ei = yp * iR;
+  const Dual6 c2 = er * er - ei * ei, s2 = 2.0 * (er * ei);
+  const Dual6 f = (1.0 + (-1.0 * q)) * inv(1.0 + q);
+  const Dual6 e2mt = 3.0 + (-1.0 * dnum(m.e_gamma, 1));   // 2 - t, t = gamma - 1
+  Dual6 wr = er, wi = ei, sr = er, si = ei;
+  for (int n = 1; n < kEplMaxTerms; ++n) {
+    const Dual6 k = (-1.0 * f) * ((2.0 * n) + (-1.0 * e2mt)) * inv((2.0 * n) + e2mt);
+    const Dual6 nr = k * (c2 * wr - s2 * wi);
+    const Dual6 ni = k * (s2 * wr + c2 * wi);
+    wr = nr;
+    wi = ni;
+    sr = sr + nr;
+    si = si + ni;
+    if (fabs(nr.v) + fabs(ni.v) <= 0x1p-56 * (fabs(sr.v) + fabs(si.v))) break;
+  }
+  const Dual6 b = dnum(m.e_te, 0) * dsqrt(q);
+  const Dual6 tm1 = -2.0 + dnum(m.e_gamma, 1);            // t - 1
+  const Dual6 a = 2.0 * b * inv(1.0 + q) * dexp(tm1 * dlog(b * iR));
+  const Dual6 axp = a * sr, ayp = a * si;
+  const Dual6 ax = c * axp - s * ayp, ay = s * axp + c * ayp;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) out[i] = (float)(-((double)Gx * ax.d[i] + (double)Gy * ay.d[i]));
+}
+
+// ---------------------------------------------------------------------------
 // residual weights and log-likelihood block partials
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_residual(int npix, const float* __restrict__ model,
@@ -159,7 +272,7 @@ __global__ __launch_bounds__(256) void k_residual(int npix, const float* __restr
 // ---------------------------------------------------------------------------
 // per-sub-pixel adjoint
 // ---------------------------------------------------------------------------
-constexpr int kGradMaxP = 7 + 7 * 3;   // SIE 5 + shear 2 + 7 per Sersic component (<= 3)
+constexpr int kGradMaxP = 8 + 7 * 3;   // EPL 6 (SIE 5) + shear 2 + 7 per Sersic component (<= 3)
 
 // Deterministic sum of v over one wave (xor butterfly, fixed pattern).
 __device__ __forceinline__ float wave_sum(float v) {
@@ -168,7 +281,10 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-template <int kSplit, bool kKept>
+// kEpl: the draws' main deflector is an EPL (partials by epl_grad, macro row
+// [EPL 6, shear 2, Sersic ...]) instead of an SIE ([SIE 5, shear 2, ...]);
+// P: the subhalo pair kernel of the recomputed deflection.
+template <int kSplit, bool kKept, class P_ = NfwPairs, bool kEpl = false>
 __global__ __launch_bounds__(split_threads(kSplit)) void k_grad_pixel(const ImageDesc* __restrict__ descs, int bpi,
                                                                      const float* __restrict__ lamU,
                                                                      float4* __restrict__ rec, int rec_stride,
@@ -195,7 +311,7 @@ __global__ __launch_bounds__(split_threads(kSplit)) void k_grad_pixel(const Imag
   const float tx = (float)tx64, ty = (float)ty64;
   double sx = 0.0, sy = 0.0;
   if (!kKept) {
-    subhalo_ranges<kSplit>(tx, ty, d.sub, d.nloop, grp, t, scratch, sx, sy);
+    subhalo_ranges<kSplit, P_>(tx, ty, d.sub, d.nloop, grp, t, scratch, sx, sy);
     __syncthreads();
   }
   float c[kGradMaxP];
@@ -218,23 +334,28 @@ __global__ __launch_bounds__(split_threads(kSplit)) void k_grad_pixel(const Imag
     const float lam = valid ? lamU[(size_t)di * npix + pp] * g.area_over_s2 : 0.f;
     float Gx = 0.f, Gy = 0.f, dd[7], gx, gy;
     const int ns = d.src.n, nl = d.ll.n;
+    constexpr int kM = kEpl ? 6 : 5;   // main-deflector parameters
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       if (k < ns) {
         sersic_grad(d.src.c[k], bx, by, dd, gx, gy);
 #pragma unroll
-        for (int m = 0; m < 7; ++m) c[7 + 7 * k + m] = lam * dd[m];
+        for (int m = 0; m < 7; ++m) c[kM + 2 + 7 * k + m] = lam * dd[m];
         Gx = fmaf(lam, gx, Gx);
         Gy = fmaf(lam, gy, Gy);
       } else if (k < ns + nl) {
         sersic_grad(d.ll.c[k - ns], tx, ty, dd, gx, gy);
 #pragma unroll
-        for (int m = 0; m < 7; ++m) c[7 + 7 * k + m] = lam * dd[m];
+        for (int m = 0; m < 7; ++m) c[kM + 2 + 7 * k + m] = lam * dd[m];
       }
     }
-    if (d.mc.has_sie) sie_grad(d.mc, tx, ty, Gx, Gy, c);
-    c[5] = -(Gx * tx - Gy * ty);
-    c[6] = -(Gx * ty + Gy * tx);
+    if (kEpl) {
+      if (d.mc.has_epl) epl_grad(d.mc, tx64, ty64, Gx, Gy, c);
+    } else if (d.mc.has_sie) {
+      sie_grad(d.mc, tx, ty, Gx, Gy, c);
+    }
+    c[kM] = -(Gx * tx - Gy * ty);
+    c[kM + 1] = -(Gx * ty + Gy * tx);
     if (valid) rec[(size_t)di * rec_stride + (size_t)pp * g.s2 + si] = make_float4(tx, ty, Gx, Gy);
   }
   // padding records past the last sub-pixel: G = 0 and a finite x^2 for any
@@ -422,6 +543,106 @@ __global__ __launch_bounds__(kSubhaloBlock) void k_grad_subhalo(const float* __r
   }
 }
 
+// h = c2 T(x) and dh = dh/d(X2) of the truncated pair term for the record r
+// (X2 = x^2 = r^2 c1).  Far field (X2 >= Xf, the record's polynomial
+// W(u) = sum a_k u^k, u = y k1 - 1, y = 1/x): h = y^2 W and, with
+// dy/dX2 = -y^3/2, dh = -y^4 (W + (k1 y / 2) W'(u)).  Otherwise the general
+// form, and from the projected mass's derivative -- the surface density of
+// the truncated profile (Baltz, Marshall & Oguri 2009) --
+//   dG/dX2 = (A/2) K,  K = (tau^2 + 1)(1 - F)/(x^2 - 1) + 2F - pi/s
+//                          + (tau^2 - 1) L/(tau s),  L = ln(x/(s + tau)),
+// dh = (c2 K/2 - h)/X2 (c2 carries A).  (1 - F)/(x^2 - 1) is the series
+// 1/3 - v/5 + v^2/7 - ... in v = x^2 - 1 near x = 1.  0 at the centre.
+__device__ __forceinline__ void tnfw_h_dh(float X2, const TRec& r, float& h, float& dh) {
+  constexpr float kPi = 3.14159265358979323846f;
+  if (X2 >= r.Xf) {
+    const float y = __builtin_amdgcn_rsqf(X2);
+    const float u = fmaf(y, r.k1, -1.0f);
+    float p = r.a[kTnfwFarDeg], dp = 0.f;
+#pragma unroll
+    for (int k = kTnfwFarDeg - 1; k >= 0; --k) {
+      dp = fmaf(dp, u, p);
+      p = fmaf(p, u, r.a[k]);
+    }
+    const float y2 = y * y;
+    h = p * y2;
+    dh = -(y2 * y2) * fmaf(0.5f * r.k1 * y, dp, p);
+    return;
+  }
+  if (!(X2 > 1e-30f)) {
+    h = 0.f;
+    dh = 0.f;
+    return;
+  }
+  float F, s, lp1;
+  h = r.c2 * tnfw_T_general(X2, r, F, s, lp1);
+  const float v = X2 - 1.0f;
+  float oneF;   // (1 - F)/(x^2 - 1)
+  if (fabsf(v) < 0.2f) {
+    float S = -1.0f / 25.0f;
+    S = fmaf(S, v, 1.0f / 23.0f);
+    S = fmaf(S, v, -1.0f / 21.0f);
+    S = fmaf(S, v, 1.0f / 19.0f);
+    S = fmaf(S, v, -1.0f / 17.0f);
+    S = fmaf(S, v, 1.0f / 15.0f);
+    S = fmaf(S, v, -1.0f / 13.0f);
+    S = fmaf(S, v, 1.0f / 11.0f);
+    S = fmaf(S, v, -1.0f / 9.0f);
+    S = fmaf(S, v, 1.0f / 7.0f);
+    S = fmaf(S, v, -1.0f / 5.0f);
+    oneF = fmaf(S, v, 1.0f / 3.0f);
+  } else {
+    oneF = (1.0f - F) * __builtin_amdgcn_rcpf(v);
+  }
+  const float is = __builtin_amdgcn_rcpf(s);
+  const float K = fmaf(r.t2 + 1.0f, oneF, fmaf(2.0f, F, -kPi * is)) - r.t2m1 * lp1 * r.itau * is;
+  dh = fmaf(0.5f * r.c2, K, -h) * __builtin_amdgcn_rcpf(X2);
+}
+
+// The subhalo-major pass for truncated subhalos: as k_grad_subhalo, with each
+// lane's record read from the draw's table built for alpha_Rs = 1 (utab
+// [B][records]), so that the sums are per unit alpha_Rs: d log L/d(x, y) is
+// alpha_Rs times them and d log L/d alpha_Rs is minus the h G.d sum.
+__global__ __launch_bounds__(kSubhaloBlock) void k_grad_subhalo_tnfw(const TRec* __restrict__ utab, int records,
+                                                                    const float* __restrict__ sub_ars,
+                                                                    const float4* __restrict__ rec, int rec_stride,
+                                                                    int nrec_loop, int n, float* __restrict__ gpart) {
+  const int b = blockIdx.y, q = blockIdx.z, B = gridDim.y;
+  const int k = blockIdx.x * kSubhaloBlock + threadIdx.x;
+  const bool valid = k < n;
+  const TRec R = utab[(size_t)b * records + (valid ? k : 0)];
+  const float c1x2 = 2.0f * R.c1;
+  const float4* __restrict__ r = rec + (size_t)b * rec_stride;
+  const int kb = part_bound(nrec_loop, kRecParts, q), ke = part_bound(nrec_loop, kRecParts, q + 1);
+  float hx = 0.f, lx = 0.f, hy = 0.f, ly = 0.f, ha = 0.f, la = 0.f;
+  for (int j0 = kb; j0 < ke; j0 += 64) {
+    const int jend = min(j0 + 64, ke);
+    float px = 0.f, py = 0.f, pa = 0.f;
+    for (int j = j0; j < jend; ++j) {
+      const float4 rr = r[j];
+      const float dx = rr.x - R.x, dy = rr.y - R.y;
+      const float X2 = fmaf(dy, dy, dx * dx) * R.c1;
+      float h, dh;
+      tnfw_h_dh(X2, R, h, dh);
+      const float GD = fmaf(rr.z, dx, rr.w * dy);
+      const float e = c1x2 * dh * GD;
+      px = fmaf(e, dx, fmaf(h, rr.z, px));
+      py = fmaf(e, dy, fmaf(h, rr.w, py));
+      pa = fmaf(h, GD, pa);
+    }
+    two_sum_acc(hx, lx, px);
+    two_sum_acc(hy, ly, py);
+    two_sum_acc(ha, la, pa);
+  }
+  if (valid) {
+    const float ars = sub_ars[(size_t)b * n + k];
+    float* o = gpart + (((size_t)q * B + b) * n + k) * 3;
+    o[0] = ars * (hx + lx);
+    o[1] = ars * (hy + ly);
+    o[2] = -(ha + la);
+  }
+}
+
 // Fixed-order final sums: macro partials over blocks (TwoSum), log L over
 // residual blocks (FP64), subhalo quarters in order.
 __global__ __launch_bounds__(256) void k_grad_finalize(int B, int P, int bpi, const float* __restrict__ part,
@@ -460,18 +681,23 @@ hipError_t launch_residual(int B, int npix, const float* model, const float* dat
   return hipGetLastError();
 }
 
-hipError_t launch_grad_pixel(int split, bool kept, int B, int bpi, const ImageDesc* descs, const float* lamU,
-                             float4* rec, int rec_stride, float* part, int P, hipStream_t st) {
+hipError_t launch_grad_pixel(int split, bool kept, bool tnfw, bool epl, int B, int bpi, const ImageDesc* descs,
+                             const float* lamU, float4* rec, int rec_stride, float* part, int P, hipStream_t st) {
   const dim3 grid((unsigned)((long)B * bpi));
-#define JT_GP(S, K) hipLaunchKernelGGL((k_grad_pixel<S, K>), grid, dim3(split_threads(S)), 0, st, descs, bpi, lamU, \
-                                       rec, rec_stride, part, P)
+#define JT_GP(S, K, Q, E) hipLaunchKernelGGL((k_grad_pixel<S, K, Q, E>), grid, dim3(split_threads(S)), 0, st, descs, \
+                                             bpi, lamU, rec, rec_stride, part, P)
+#define JT_GP_S(K, Q, E) \
+  if (split == 1) JT_GP(1, K, Q, E); else if (split == 2) JT_GP(2, K, Q, E); \
+  else if (split == 4) JT_GP(4, K, Q, E); else JT_GP(8, K, Q, E)
   if (kept) {
-    if (split == 1) JT_GP(1, true); else if (split == 2) JT_GP(2, true); else if (split == 4) JT_GP(4, true);
-    else JT_GP(8, true);
+    // the positions come from the forward launch: no pair kernel is run
+    if (epl) { JT_GP_S(true, NfwPairs, true); } else { JT_GP_S(true, NfwPairs, false); }
+  } else if (tnfw) {
+    if (epl) { JT_GP_S(false, TnfwPairs, true); } else { JT_GP_S(false, TnfwPairs, false); }
   } else {
-    if (split == 1) JT_GP(1, false); else if (split == 2) JT_GP(2, false); else if (split == 4) JT_GP(4, false);
-    else JT_GP(8, false);
+    if (epl) { JT_GP_S(false, NfwPairs, true); } else { JT_GP_S(false, NfwPairs, false); }
   }
+#undef JT_GP_S
 #undef JT_GP
   return hipGetLastError();
 }
@@ -482,6 +708,14 @@ hipError_t launch_grad_subhalo(int B, int n, const float* x, const float* y, con
   hipLaunchKernelGGL(k_grad_subhalo, dim3((n + kSubhaloBlock - 1) / kSubhaloBlock, B, kRecParts), dim3(kSubhaloBlock),
                      0, st, x, y, rs, ars, rec,
                      rec_stride, nrec_loop, n, gpart);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_subhalo_tnfw(int B, int n, const TRec* utab, int records, const float* ars,
+                                    const float4* rec, int rec_stride, int nrec_loop, float* gpart, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_grad_subhalo_tnfw, dim3((n + kSubhaloBlock - 1) / kSubhaloBlock, B, kRecParts),
+                     dim3(kSubhaloBlock), 0, st, utab, records, ars, rec, rec_stride, nrec_loop, n, gpart);
   return hipGetLastError();
 }
 

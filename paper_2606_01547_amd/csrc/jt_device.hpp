@@ -58,6 +58,7 @@ struct MacroC {
   // alpha' = epref (eb / R)^etm1 * Omega, Omega the series of the
   // hypergeometric factor with ratio -ef (2n - e2mt)/(2n + e2mt) e^{2 i varphi}
   double ecx, ecy, ecphi, esphi, eq, ef, e2mt, eb, etm1, epref;
+  double e_te, e_gamma, e_phi;   // theta_E, gamma, phi themselves (the adjoint's partials)
   double pm_x[kMaxPointMass], pm_y[kMaxPointMass], pm_te2[kMaxPointMass];
 };
 
@@ -526,32 +527,20 @@ __host__ __device__ inline TRec trec_pad() {
 // cancelling difference; nine per distant pair, reciprocals shared where two
 // are needed) and the polynomial arctangent.  0 at the centre
 // (X2 below 1e-30, where the term is below 1e-28 of alpha_Rs).
-__device__ __forceinline__ void tnfw_pair(float tx, float ty, const TRec& r, float& sx, float& sy) {
+// The general form, for 1e-30 < X2: returns T = (tau^2 - 1) P1 + P2 (the
+// pair term is c2 T) and also F(x), s = sqrt(tau^2 + x^2) and
+// lp1 = log1p(z1) = -ln(x/(s + tau)), which the adjoint's derivative uses.
+__device__ __forceinline__ float tnfw_T_general(float X2, const TRec& r, float& F, float& s, float& lp1) {
   constexpr float kPi = 3.14159265358979323846f;
   constexpr float kHalfPi = 1.57079632679489661923f;
-  const float dx = tx - r.x, dy = ty - r.y;
-  const float X2 = fmaf(dy, dy, dx * dx) * r.c1;
-  if (X2 >= r.Xf) {
-    // far field (tnfw_far_fit): h = y^2 sum_k a_k u^k
-    const float yy = __builtin_amdgcn_rsqf(X2);
-    const float u = fmaf(yy, r.k1, -1.0f);
-    float p = r.a[kTnfwFarDeg];
-#pragma unroll
-    for (int k = kTnfwFarDeg - 1; k >= 0; --k) p = fmaf(p, u, r.a[k]);
-    const float h = p * (yy * yy);
-    sx = fmaf(h, dx, sx);
-    sy = fmaf(h, dy, sy);
-    return;
-  }
-  if (!(X2 > 1e-30f)) return;
   const float ix = __builtin_amdgcn_rsqf(X2);
   const float x = X2 * ix;
-  const float s = __builtin_amdgcn_sqrtf(r.t2 + X2);
+  s = __builtin_amdgcn_sqrtf(r.t2 + X2);
   const float sp = s + r.tau;
   const float isp = __builtin_amdgcn_rcpf(sp);
   const float Lh = fmaf(__builtin_amdgcn_logf(X2), 0.5f * kLn2, -kLn2);   // ln(x/2)
   const float spx = s + x;
-  float F, g, P2, isx;   // isx = 1/(s + x)
+  float g, P2, isx;   // isx = 1/(s + x)
   if (X2 < 0.8f) {
     const float w = __builtin_amdgcn_sqrtf(1.0f - X2);
     const float i1w = __builtin_amdgcn_rcpf(1.0f + w);
@@ -596,10 +585,30 @@ __device__ __forceinline__ void tnfw_pair(float tx, float ty, const TRec& r, flo
   const float d1 = w1 - 1.0f, d2 = w2 - 1.0f;
   const float e1 = d1 == 0.0f ? 1.0f : d1, e2 = d2 == 0.0f ? 1.0f : d2;
   const float rd = __builtin_amdgcn_rcpf(e1 * e2);
-  const float lp1 = d1 == 0.0f ? z1 : __builtin_amdgcn_logf(w1) * kLn2 * z1 * (rd * e2);
+  lp1 = d1 == 0.0f ? z1 : __builtin_amdgcn_logf(w1) * kLn2 * z1 * (rd * e2);
   const float lp2 = d2 == 0.0f ? z2 : __builtin_amdgcn_logf(w2) * kLn2 * z2 * (rd * e1);
   const float P1 = (g - lp2) * (ix * ix) - lp1 * r.itau * isp;
-  const float h = r.c2 * fmaf(r.t2m1, P1, P2);
+  return fmaf(r.t2m1, P1, P2);
+}
+
+__device__ __forceinline__ void tnfw_pair(float tx, float ty, const TRec& r, float& sx, float& sy) {
+  const float dx = tx - r.x, dy = ty - r.y;
+  const float X2 = fmaf(dy, dy, dx * dx) * r.c1;
+  if (X2 >= r.Xf) {
+    // far field (tnfw_far_fit): h = y^2 sum_k a_k u^k
+    const float yy = __builtin_amdgcn_rsqf(X2);
+    const float u = fmaf(yy, r.k1, -1.0f);
+    float p = r.a[kTnfwFarDeg];
+#pragma unroll
+    for (int k = kTnfwFarDeg - 1; k >= 0; --k) p = fmaf(p, u, r.a[k]);
+    const float h = p * (yy * yy);
+    sx = fmaf(h, dx, sx);
+    sy = fmaf(h, dy, sy);
+    return;
+  }
+  if (!(X2 > 1e-30f)) return;
+  float F, s, lp1;
+  const float h = r.c2 * tnfw_T_general(X2, r, F, s, lp1);
   sx = fmaf(h, dx, sx);
   sy = fmaf(h, dy, sy);
 }

@@ -30,13 +30,15 @@ struct Batch {
   GridC g;
   int B = 0, n = 0, nloop = 0, records = 0, npix = 0, nsubpix = 0;
   int split = 1, bpi = 0, P = 0;
+  bool epl = false, tnfw = false;   // EPL main deflector; truncated subhalos
+  size_t rec_bytes = sizeof(SubRec);
   std::vector<ImageDesc> descs;
 };
 
 jt_status check_draws(const jt_draws* d, bool for_grad) {
   if (!d) return fail(JT_EINVAL, "null draws");
   if (d->B < 1) return fail(JT_EINVAL, "draws: B = %d", d->B);
-  if (!d->sie || !d->shear) return fail(JT_EINVAL, "draws: null SIE or shear array");
+  if ((!d->sie && !d->epl) || !d->shear) return fail(JT_EINVAL, "draws: null main-deflector or shear array");
   if (d->n_sub < 0) return fail(JT_EINVAL, "draws: n_sub = %d", d->n_sub);
   if (d->n_sub > 0 && (!d->sub_x || !d->sub_y || !d->sub_Rs || !d->sub_alpha_Rs))
     return fail(JT_EINVAL, "draws: null subhalo array");
@@ -61,13 +63,21 @@ jt_status make_batch(const jt_grid* grid, const jt_draws* d, bool for_grad, Batc
   bt.split = pick_split((long)bt.B * bt.nsubpix, bt.g.s2, bt.nloop);
   bt.g.ppb = split_lanes(bt.split) / bt.g.s2;
   bt.bpi = (bt.npix + bt.g.ppb - 1) / bt.g.ppb;
-  bt.P = 7 + 7 * (d->n_src + d->n_ll);
+  bt.epl = d->epl != nullptr;
+  bt.tnfw = d->n_sub > 0 && d->sub_r_trunc != nullptr;
+  bt.rec_bytes = bt.tnfw ? sizeof(TRec) : sizeof(SubRec);
+  bt.P = (bt.epl ? 8 : 7) + 7 * (d->n_src + d->n_ll);
   bt.descs.resize(bt.B);
   for (int b = 0; b < bt.B; ++b) {
     jt_lens lens;
     std::memset(&lens, 0, sizeof(lens));
-    lens.has_sie = 1;
-    lens.sie = d->sie[b];
+    if (bt.epl) {
+      lens.has_epl = 1;
+      lens.epl = d->epl[b];
+    } else {
+      lens.has_sie = 1;
+      lens.sie = d->sie[b];
+    }
     lens.has_shear = 1;
     lens.shear = d->shear[b];
     ImageDesc& D = bt.descs[b];
@@ -86,20 +96,28 @@ jt_status make_batch(const jt_grid* grid, const jt_draws* d, bool for_grad, Batc
 // Forward images: tables, descriptors, fused kernel, convolution.  Fills the
 // device pointers of the descriptors from the carved workspace and uploads
 // them.  model_u / model: [B][npix].
-jt_status run_forward(jt_ctx* ctx, Batch& bt, const jt_draws* d, const float* psf, int k, SubRec* tables,
+jt_status run_forward(jt_ctx* ctx, Batch& bt, const jt_draws* d, const float* psf, int k, void* tables,
                       ImageDesc* ddescs, float* model_u, float* model, hipStream_t st, float2* beta = nullptr) {
   for (int b = 0; b < bt.B; ++b) {
-    bt.descs[b].sub = bt.n > 0 ? tables + (size_t)b * bt.records : ctx_empty_table(ctx);
+    bt.descs[b].sub = bt.n > 0 ? (const void*)((const char*)tables + bt.rec_bytes * (size_t)b * bt.records)
+                               : (const void*)ctx_empty_table(ctx);
     bt.descs[b].img = model_u + (size_t)b * bt.npix;
     bt.descs[b].beta = beta ? beta + (size_t)b * bt.nsubpix : nullptr;
   }
   JT_TRY(ctx_upload(ctx, st, ddescs, bt.descs.data(), sizeof(ImageDesc) * bt.B));
-  if (bt.n > 0)
+  if (bt.n > 0 && bt.tnfw)
     JT_TRY(timed_launch(ctx, JT_K_PREP, st, [&] {
-      return launch_prep_subhalos_batched(bt.B, bt.n, d->sub_x, d->sub_y, d->sub_Rs, d->sub_alpha_Rs, tables, st);
+      return launch_prep_tnfw_batched(bt.B, bt.n, d->sub_x, d->sub_y, d->sub_Rs, d->sub_alpha_Rs, d->sub_r_trunc,
+                                      false, (TRec*)tables, st);
+    }, "prep_tnfw_batched"));
+  else if (bt.n > 0)
+    JT_TRY(timed_launch(ctx, JT_K_PREP, st, [&] {
+      return launch_prep_subhalos_batched(bt.B, bt.n, d->sub_x, d->sub_y, d->sub_Rs, d->sub_alpha_Rs,
+                                          (SubRec*)tables, st);
     }, "prep_subhalos_batched"));
   JT_TRY(timed_launch(ctx, JT_K_SIM, st, [&] {
-    return launch_simulate_desc(bt.split, false, false, beta != nullptr, ddescs, nullptr, bt.B * bt.bpi, bt.bpi, st);
+    return launch_simulate_desc(bt.split, bt.tnfw, false, beta != nullptr, ddescs, nullptr, bt.B * bt.bpi, bt.bpi,
+                                st);
   }, "simulate_batch"));
   if (psf && model != model_u)
     JT_TRY(timed_launch(ctx, JT_K_CONV, st, [&] {
@@ -129,13 +147,13 @@ extern "C" jt_status jt_simulate_batch(jt_ctx* ctx, const jt_grid* grid, const j
     const size_t no = sizeof(float) * (size_t)bt.B * bt.npix, np = sizeof(float) * (size_t)k * k;
     if (po < pp + np && pp < po + no) return fail(JT_EINVAL, "simulate_batch: output overlaps the PSF");
   }
-  const size_t bytes = align256(sizeof(ImageDesc) * bt.B) + align256(sizeof(SubRec) * (size_t)bt.B * bt.records) +
+  const size_t bytes = align256(sizeof(ImageDesc) * bt.B) + align256(bt.rec_bytes * (size_t)bt.B * bt.records) +
                        align256(sizeof(float) * (size_t)bt.B * bt.npix);
   void* ws = nullptr;
   JT_TRY(ctx_workspace(ctx, stream, bytes, &ws));
   Carve cv{(char*)ws};
   ImageDesc* dd = cv.take<ImageDesc>(bt.B);
-  SubRec* tables = cv.take<SubRec>((size_t)bt.B * bt.records);
+  void* tables = cv.take<char>(bt.rec_bytes * (size_t)bt.B * bt.records);
   float* mu = psf ? cv.take<float>((size_t)bt.B * bt.npix) : out;
   return run_forward(ctx, bt, draws, psf, k, tables, dd, mu, psf ? out : mu, stream);
 }
@@ -157,18 +175,19 @@ jt_status chi2_common(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, c
   const int nres = (bt.npix + 255) / 256;
   const int nrec_loop = (bt.nsubpix + 3) & ~3;
   const int rec_stride = nrec_loop + 4;
-  size_t bytes = align256(sizeof(ImageDesc) * bt.B) + align256(sizeof(SubRec) * (size_t)bt.B * bt.records) +
+  size_t bytes = align256(sizeof(ImageDesc) * bt.B) + align256(bt.rec_bytes * (size_t)bt.B * bt.records) +
                  3 * align256(sizeof(float) * BN) + align256(sizeof(float) * (size_t)bt.B * nres);
   if (grad)
     bytes += align256(sizeof(float) * BN) + align256(sizeof(float4) * (size_t)bt.B * rec_stride) +
              align256(sizeof(float) * (size_t)bt.B * bt.bpi * bt.P) +
              align256(sizeof(float) * (size_t)kRecPartsHost * bt.B * bt.n * 3) +
-             (keep ? align256(sizeof(float2) * (size_t)bt.B * bt.nsubpix) : 0);
+             (keep ? align256(sizeof(float2) * (size_t)bt.B * bt.nsubpix) : 0) +
+             (bt.tnfw ? align256(sizeof(TRec) * (size_t)bt.B * bt.records) : 0);
   void* ws = nullptr;
   JT_TRY(ctx_workspace(ctx, st, bytes, &ws));
   Carve cv{(char*)ws};
   ImageDesc* dd = cv.take<ImageDesc>(bt.B);
-  SubRec* tables = cv.take<SubRec>((size_t)bt.B * bt.records);
+  void* tables = cv.take<char>(bt.rec_bytes * (size_t)bt.B * bt.records);
   float* mu = cv.take<float>(BN);
   float* model = psf ? cv.take<float>(BN) : mu;
   float* resid = cv.take<float>(BN);
@@ -194,12 +213,26 @@ jt_status chi2_common(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, c
       return launch_conv_direct_batched(true, bt.B, resid, bt.npix, bt.g.nx, bt.g.ny, psf, k, lamU, bt.npix, st);
     }, "conv_adjoint"));
   JT_TRY(timed_launch(ctx, JT_K_GRAD, st, [&] {
-    return launch_grad_pixel(bt.split, keep, bt.B, bt.bpi, dd, lamU, rec, rec_stride, part, bt.P, st);
+    return launch_grad_pixel(bt.split, keep, bt.tnfw, bt.epl, bt.B, bt.bpi, dd, lamU, rec, rec_stride, part, bt.P,
+                             st);
   }, "grad_pixel"));
-  JT_TRY(timed_launch(ctx, JT_K_GRAD, st, [&] {
-    return launch_grad_subhalo(bt.B, bt.n, draws->sub_x, draws->sub_y, draws->sub_Rs, draws->sub_alpha_Rs, rec,
-                               rec_stride, nrec_loop, gpart, st);
-  }, "grad_subhalo"));
+  if (bt.tnfw) {
+    // per-lane constants of the truncated subhalos, for alpha_Rs = 1
+    TRec* utab = cv.take<TRec>((size_t)bt.B * bt.records);
+    JT_TRY(timed_launch(ctx, JT_K_PREP, st, [&] {
+      return launch_prep_tnfw_batched(bt.B, bt.n, draws->sub_x, draws->sub_y, draws->sub_Rs, draws->sub_alpha_Rs,
+                                      draws->sub_r_trunc, true, utab, st);
+    }, "prep_tnfw_unit"));
+    JT_TRY(timed_launch(ctx, JT_K_GRAD, st, [&] {
+      return launch_grad_subhalo_tnfw(bt.B, bt.n, utab, bt.records, draws->sub_alpha_Rs, rec, rec_stride, nrec_loop,
+                                      gpart, st);
+    }, "grad_subhalo_tnfw"));
+  } else {
+    JT_TRY(timed_launch(ctx, JT_K_GRAD, st, [&] {
+      return launch_grad_subhalo(bt.B, bt.n, draws->sub_x, draws->sub_y, draws->sub_Rs, draws->sub_alpha_Rs, rec,
+                                 rec_stride, nrec_loop, gpart, st);
+    }, "grad_subhalo"));
+  }
   return timed_launch(ctx, JT_K_GRAD, st, [&] {
     return launch_grad_finalize(bt.B, bt.P, bt.bpi, part, g_macro, nres, lpart, logL, bt.n, gpart,
                                 bt.n > 0 ? g_sub : nullptr, st);

@@ -68,6 +68,10 @@ hipError_t launch_simulate_desc(int split, bool tnfw, bool extra, bool keep_beta
 // subhalo_table_records(n) records.
 hipError_t launch_prep_subhalos_batched(int B, int n, const float* x, const float* y, const float* rs,
                                         const float* ars, SubRec* out, hipStream_t st);
+// Truncated tables of B draws, out [B][subhalo_table_records(n)]; unit: every
+// record built for alpha_Rs = 1 (the adjoint's per-lane constants).
+hipError_t launch_prep_tnfw_batched(int B, int n, const float* x, const float* y, const float* rs, const float* ars,
+                                    const float* rt, bool unit, TRec* out, hipStream_t st);
 
 // ---- FFT convolution (fft.hip) ----
 // Cost model of the direct/FFT choice (method 0), fitted to kernel times on
@@ -95,8 +99,15 @@ hipError_t launch_fft_convolve(const float* img, int nx, int ny, const float* ps
 constexpr int kRecPartsHost = 4;  // parts of the adjoint's subhalo-major pass
 hipError_t launch_residual(int B, int npix, const float* model, const float* data, const float* w, float* resid,
                            float* part, int* nblocks, hipStream_t st);
-hipError_t launch_grad_pixel(int split, bool kept, int B, int bpi, const ImageDesc* descs, const float* lamU,
-                             float4* rec, int rec_stride, float* part, int P, hipStream_t st);
+// tnfw: the draws' subhalos are truncated (the recomputed deflection uses the
+// TNFW tables); epl: their main deflector is an EPL (macro row [EPL 6, shear 2,
+// Sersic ...]).
+hipError_t launch_grad_pixel(int split, bool kept, bool tnfw, bool epl, int B, int bpi, const ImageDesc* descs,
+                             const float* lamU, float4* rec, int rec_stride, float* part, int P, hipStream_t st);
+// Subhalo-major pass for truncated subhalos; utab [B][records]: each draw's
+// table built for alpha_Rs = 1 (launch_prep_tnfw_batched with unit set).
+hipError_t launch_grad_subhalo_tnfw(int B, int n, const TRec* utab, int records, const float* ars,
+                                    const float4* rec, int rec_stride, int nrec_loop, float* gpart, hipStream_t st);
 // draws' subhalo SoA x, y, rs, ars: device [B][n]
 hipError_t launch_grad_subhalo(int B, int n, const float* x, const float* y, const float* rs, const float* ars,
                                const float4* rec, int rec_stride, int nrec_loop, float* gpart, hipStream_t st);

@@ -119,6 +119,9 @@ jt_status make_macro(const jt_lens* lens, MacroC& m) {
     m.eb = b;
     m.etm1 = t - 1.0;
     m.epref = 2.0 * b / (1.0 + e.q);
+    m.e_te = e.theta_E;
+    m.e_gamma = e.gamma;
+    m.e_phi = e.phi;
   }
   if (lens->has_shear) {
     if (!finite(lens->shear.gamma1) || !finite(lens->shear.gamma2))

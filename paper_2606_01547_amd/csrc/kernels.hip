@@ -555,13 +555,15 @@ int conv_tiles_y(int ny) { return (ny + kConvTY - 1) / kConvTY; }
 hipError_t launch_simulate_desc(int split, bool tnfw, bool extra, bool keep_beta, const ImageDesc* descs,
                                 const int2* tiles, int nblocks, int blocks_per_image, hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
-  if (tnfw && keep_beta) return hipErrorInvalidValue;
+
 #define JT_SIMD(S, P, E, K) hipLaunchKernelGGL((k_simulate_desc<S, P, E, K>), dim3((unsigned)nblocks), \
                                                dim3(split_threads(S)), 0, st, descs, tiles, blocks_per_image)
 #define JT_SIMD_S(P, E, K) \
   if (split == 1) JT_SIMD(1, P, E, K); else if (split == 2) JT_SIMD(2, P, E, K); \
   else if (split == 4) JT_SIMD(4, P, E, K); else JT_SIMD(8, P, E, K)
-  if (keep_beta) {
+  if (keep_beta && tnfw) {
+    JT_SIMD_S(TnfwPairs, false, true);
+  } else if (keep_beta) {
     JT_SIMD_S(NfwPairs, false, true);
   } else if (tnfw && extra) {
     JT_SIMD_S(TnfwPairs, true, false);
@@ -593,6 +595,31 @@ __global__ __launch_bounds__(256) void k_prep_subhalos_batched(int n, int record
   }
   const size_t j = (size_t)b * n + i;
   o[i] = make_subrec(x[j], y[j], rs[j], ars[j]);
+}
+
+__global__ __launch_bounds__(256) void k_prep_tnfw_batched(int n, int records, const float* __restrict__ x,
+                                                          const float* __restrict__ y, const float* __restrict__ rs,
+                                                          const float* __restrict__ ars,
+                                                          const float* __restrict__ rt, int unit,
+                                                          TRec* __restrict__ out) {
+  const int b = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= records) return;
+  TRec* o = out + (size_t)b * records;
+  if (i >= n) {
+    o[i] = trec_pad();
+    return;
+  }
+  const size_t j = (size_t)b * n + i;
+  o[i] = make_trec(x[j], y[j], rs[j], unit ? 1.0f : ars[j], rt[j]);
+}
+
+hipError_t launch_prep_tnfw_batched(int B, int n, const float* x, const float* y, const float* rs, const float* ars,
+                                    const float* rt, bool unit, TRec* out, hipStream_t st) {
+  const int records = subhalo_table_records(n);
+  hipLaunchKernelGGL(k_prep_tnfw_batched, dim3((records + 255) / 256, B), dim3(256), 0, st, n, records, x, y, rs,
+                     ars, rt, unit ? 1 : 0, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_prep_subhalos_batched(int B, int n, const float* x, const float* y, const float* rs,

@@ -1,10 +1,12 @@
 """Batches of parameter draws and the chi^2 log-likelihood as a
 torch.autograd.Function whose backward is libjt's hand-written adjoint.
 
-Parameter layout per draw (the macro row): SIE (theta_E, q, phi, cx, cy),
-shear (gamma1, gamma2), then (amp, R_sersic, n_sersic, q, phi, cx, cy) for
-each source and then each lens-light component.  Subhalos: x, y, Rs and
-alpha_Rs as [B, n] tensors; gradients flow to x, y and alpha_Rs.
+Parameter layout per draw (the macro row): SIE (theta_E, q, phi, cx, cy) --
+or, with main = "epl", EPL (theta_E, gamma, q, phi, cx, cy) -- then shear
+(gamma1, gamma2), then (amp, R_sersic, n_sersic, q, phi, cx, cy) for each
+source and then each lens-light component.  Subhalos: x, y, Rs and alpha_Rs
+as [B, n] tensors (and r_trunc for truncated ones); gradients flow to x, y and
+alpha_Rs.
 """
 from __future__ import annotations
 
@@ -23,12 +25,19 @@ class DrawBatch:
     sub_y: Optional[Any] = None
     sub_Rs: Optional[Any] = None
     sub_alpha_Rs: Optional[Any] = None
+    main: str = "sie"               # "sie" or "epl": the main deflector of the macro rows
+    sub_r_trunc: Optional[Any] = None   # [B, n]: truncated (TNFW) subhalos
 
 
 def macro_row(lens, source, lens_light=()):
-    """The macro row of one scene (same order as the adjoint's gradient)."""
-    v = [lens.sie.theta_E, lens.sie.q, lens.sie.phi, lens.sie.cx, lens.sie.cy, lens.shear.gamma1,
-         lens.shear.gamma2]
+    """The macro row of one scene (same order as the adjoint's gradient): an
+    EPL main deflector when the lens has one, else its SIE."""
+    if getattr(lens, "epl", None) is not None:
+        e = lens.epl
+        v = [e.theta_E, e.gamma, e.q, e.phi, e.cx, e.cy]
+    else:
+        v = [lens.sie.theta_E, lens.sie.q, lens.sie.phi, lens.sie.cx, lens.sie.cy]
+    v += [lens.shear.gamma1, lens.shear.gamma2]
     for c in list(source) + list(lens_light):
         v += [c.amp, c.R_sersic, c.n_sersic, c.q, c.phi, c.cx, c.cy]
     return np.array(v, dtype=np.float64)

@@ -71,6 +71,7 @@ int main(void) {
   P(jt_gaussian); P(jt_core_sersic); O(jt_core_sersic, alpha); P(jt_shapelets); O(jt_shapelets, beta);
   O(jt_shapelets, coeff);
   P(jt_draws); O(jt_draws, sie); O(jt_draws, n_sub); O(jt_draws, sub_alpha_Rs); O(jt_draws, n_ll); O(jt_draws, ll);
+  O(jt_draws, epl); O(jt_draws, sub_r_trunc);
   P(jt_server_stats); O(jt_server_stats, device_seconds); O(jt_server_stats, max_wait_seconds);
   P(jt_fit_problem); O(jt_fit_problem, lower); O(jt_fit_problem, n_sub); O(jt_fit_problem, sub_alpha_Rs);
   O(jt_fit_problem, psf); O(jt_fit_problem, k); O(jt_fit_problem, inv_var);

@@ -37,12 +37,14 @@ def _np(t):
 def _batch(scenes):
     from paper_2606_01547_amd.grad import DrawBatch, macro_row
     macro = np.stack([macro_row(s.lens, s.source, s.lens_light) for s in scenes])
+    main = "epl" if getattr(scenes[0].lens, "epl", None) is not None else "sie"
     n = scenes[0].lens.nfw.n if scenes[0].lens.nfw is not None else 0
     if n == 0:
-        return DrawBatch(macro, len(scenes[0].source), len(scenes[0].lens_light))
+        return DrawBatch(macro, len(scenes[0].source), len(scenes[0].lens_light), main=main)
     st = lambda a: np.stack([getattr(s.lens.nfw, a) for s in scenes]).astype(np.float32)
+    rt = st("r_trunc") if getattr(scenes[0].lens.nfw, "r_trunc", None) is not None else None
     return DrawBatch(macro, len(scenes[0].source), len(scenes[0].lens_light), st("x"), st("y"), st("Rs"),
-                     st("alpha_Rs"))
+                     st("alpha_Rs"), main=main, sub_r_trunc=rt)
 
 
 def _group_err(g, e):
@@ -257,3 +259,36 @@ def test_gradient_argument_errors(ctx):
     assert e.value.status == JT_EUNSUPPORTED
     with pytest.raises(JtError):
         ctx.chi2(grid, _batch(draws), d, w, np.ones((4, 4), np.float32))
+
+
+# ------------------------------------- EPL main deflector, truncated subhalos
+@pytest.mark.parametrize("epl,tnfw", [(True, False), (False, True), (True, True)])
+def test_chi2_grad_epl_and_truncated_subhalos(ctx, epl, tnfw):
+    """The adjoint with an EPL main deflector (its six partials, the slope
+    included) and/or truncated subhalos, against the oracle's autograd
+    gradient: 48x44 px, s = 2, 300 subhalos, 7x7 PSF, 3 draws."""
+    grid = W.Grid(nx=48, ny=44, pixel_scale=0.1, x0=0.02, y0=-0.03, supersample=2)
+    truth, draws = W.config4_profile_draws(B=3, n_sub=300, grid=grid, epl=epl, tnfw=tnfw)
+    d, w = _data(truth, seed=8)
+    b = _batch(draws)
+    assert b.main == ("epl" if epl else "sie") and (b.sub_r_trunc is not None) == tnfw
+    _check_grad(ctx, truth, draws, d, w)
+
+
+def test_epl_tnfw_batch_forward_equals_single_images(ctx):
+    grid = W.Grid(nx=40, ny=36, pixel_scale=0.1, supersample=3)
+    truth, draws = W.config4_profile_draws(B=4, n_sub=200, grid=grid, epl=True, tnfw=True)
+    out = _np(ctx.simulate_batch(truth.grid, _batch(draws), truth.psf))
+    for k, sc in enumerate(draws):
+        np.testing.assert_array_equal(out[k], _np(ctx.simulate_scene(sc)))
+    assert image_error(out[1], O.simulate_image(draws[1])) <= IMAGE_TOL
+
+
+def test_epl_tnfw_kept_positions_bit_for_bit(ctx):
+    grid = W.Grid(nx=44, ny=41, pixel_scale=0.09, supersample=2)
+    truth, draws = W.config4_profile_draws(B=4, n_sub=250, grid=grid, epl=True, tnfw=True)
+    d, w = _data(truth, seed=9)
+    a = ctx.chi2_grad(truth.grid, _batch(draws), d, w, truth.psf)
+    b = ctx.chi2_grad(truth.grid, _batch(draws), d, w, truth.psf, keep_positions=True)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(_np(x), _np(y))

@@ -479,6 +479,34 @@ def config4_draws(B: int = 256, seed: int = 1004, n_sub: int = 1000, grid: Optio
     return truth, out
 
 
+def config4_profile_draws(B: int, n_sub: int, grid: Grid, epl: bool, tnfw: bool, seed: int = 1008,
+                          psf_size: int = 7):
+    """The differentiation case with the other profiles of the deflector
+    table: an EPL main deflector (slope 1.9, the SIE's other parameters) in
+    place of the SIE and/or truncated subhalos (tau = r_trunc/Rs log-uniform in
+    [3, 30]).  Draws jitter the macro parameters (the slope too) by
+    (1 + 0.01 N(0,1)) and the subhalos as config4_draws; r_trunc stays fixed.
+    Returns (truth, [scene_b])."""
+    import copy
+    truth, draws = config4_draws(B=B, seed=seed, n_sub=n_sub, grid=grid, psf_size=psf_size)
+    rng, = _rngs(seed + 2, 1)
+    rt = None
+    if tnfw and truth.lens.nfw is not None:
+        nfw = truth.lens.nfw
+        rt = (10.0 ** rng.uniform(np.log10(3.0), np.log10(30.0), nfw.n) * nfw.Rs).astype(np.float32)
+        truth.lens.nfw.r_trunc = rt
+    for sc in [truth] + draws:
+        if epl:
+            s = sc.lens.sie
+            g = 1.9 if sc is truth else f32(1.9 * (1.0 + 0.01 * rng.standard_normal()))
+            sc.lens.epl = EPL(s.theta_E, g, s.q, s.phi, s.cx, s.cy)
+            sc.lens.sie = None
+        if rt is not None and sc is not truth:
+            sc.lens.nfw = copy.deepcopy(sc.lens.nfw)
+            sc.lens.nfw.r_trunc = rt.copy()
+    return truth, draws
+
+
 def random_points(n: int, half_width: float, seed: int):
     """n FP32 points uniform in the square [-half_width, half_width]^2."""
     rng = np.random.default_rng(seed)
