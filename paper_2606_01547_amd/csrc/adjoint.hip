@@ -349,11 +349,10 @@ __global__ __launch_bounds__(split_threads(kSplit)) void k_grad_pixel(const Imag
         for (int m = 0; m < 7; ++m) c[kM + 2 + 7 * k + m] = lam * dd[m];
       }
     }
-    if (kEpl) {
-      if (d.mc.has_epl) epl_grad(d.mc, tx64, ty64, Gx, Gy, c);
-    } else if (d.mc.has_sie) {
-      sie_grad(d.mc, tx, ty, Gx, Gy, c);
-    }
+    // the EPL's partials (slots 0..5) are written afterwards by k_grad_epl,
+    // from the (theta, G) records, so that this kernel keeps the pair loop's
+    // register budget
+    if (!kEpl && d.mc.has_sie) sie_grad(d.mc, tx, ty, Gx, Gy, c);
     c[kM] = -(Gx * tx - Gy * ty);
     c[kM + 1] = -(Gx * ty + Gy * tx);
     if (valid) rec[(size_t)di * rec_stride + (size_t)pp * g.s2 + si] = make_float4(tx, ty, Gx, Gy);
@@ -378,6 +377,50 @@ __global__ __launch_bounds__(split_threads(kSplit)) void k_grad_pixel(const Imag
   if (threadIdx.x < P) {
     float acc = 0.f;
     for (int w = 0; w < kWaves0; ++w) acc += wsum[w][threadIdx.x];
+    part[((size_t)di * bpi + blk) * P + threadIdx.x] = acc;
+  }
+}
+
+// The EPL main deflector's partials per block, in the block decomposition of
+// k_grad_pixel (its first wave-group's sub-pixels, its wave order): reads each
+// sub-pixel's (theta, G) record and overwrites slots 0..5 of the block's
+// partials.  The dual-number arithmetic needs about 200 VGPRs, which is why it
+// is not part of k_grad_pixel's pair loop.
+template <int kSplit>
+__global__ __launch_bounds__(split_lanes(kSplit)) void k_grad_epl(const ImageDesc* __restrict__ descs, int bpi,
+                                                                   const float4* __restrict__ rec, int rec_stride,
+                                                                   float* __restrict__ part, int P) {
+  __shared__ float wsum[4][6];
+  constexpr int kW = split_lanes(kSplit);
+  const int di = blockIdx.x / bpi;
+  const int blk = blockIdx.x - di * bpi;
+  const ImageDesc& d = descs[di];
+  const GridC& g = d.g;
+  const int t = threadIdx.x;
+  const int lp = t / g.s2;
+  const int si = t - lp * g.s2;
+  const int npix = g.nx * g.ny;
+  const int p = blk * g.ppb + lp;
+  const bool valid = (lp < g.ppb) && (p < npix);
+  float c[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (valid && d.mc.has_epl) {
+    const int row = p / g.nx, col = p - (p / g.nx) * g.nx;
+    const int a = si / g.s, b = si - (si / g.s) * g.s;
+    const double tx64 = g.ox + g.step * ((double)(col * g.s + b) + 0.5);
+    const double ty64 = g.oy + g.step * ((double)(row * g.s + a) + 0.5);
+    const float4 r = rec[(size_t)di * rec_stride + (size_t)p * g.s2 + si];
+    epl_grad(d.mc, tx64, ty64, r.z, r.w, c);
+  }
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const float v = wave_sum(c[i]);
+    if ((threadIdx.x & 63) == 0) wsum[wave][i] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    float acc = 0.f;
+    for (int w = 0; w < kW / 64; ++w) acc += wsum[w][threadIdx.x];
     part[((size_t)di * bpi + blk) * P + threadIdx.x] = acc;
   }
 }
@@ -699,6 +742,12 @@ hipError_t launch_grad_pixel(int split, bool kept, bool tnfw, bool epl, int B, i
   }
 #undef JT_GP_S
 #undef JT_GP
+  if (epl) {
+#define JT_GE(S) hipLaunchKernelGGL((k_grad_epl<S>), grid, dim3(split_lanes(S)), 0, st, descs, bpi, rec, rec_stride, \
+                                    part, P)
+    if (split == 1) JT_GE(1); else if (split == 2) JT_GE(2); else if (split == 4) JT_GE(4); else JT_GE(8);
+#undef JT_GE
+  }
   return hipGetLastError();
 }
 
