@@ -23,6 +23,7 @@ namespace jt {
 
 // Parts of the subhalo-major pass over sub-pixel records (summed in order).
 constexpr int kRecParts = kRecPartsHost;
+constexpr int kRecPartsTnfw = kRecPartsTnfwHost;
 // Subhalos per block of that pass: its waves read the same records, so a
 // block of several waves shares them through its CU's scalar cache.
 constexpr int kSubhaloBlock = 256;
@@ -642,21 +643,76 @@ __device__ __forceinline__ void tnfw_h_dh(float X2, const TRec& r, float& h, flo
   dh = fmaf(0.5f * r.c2, K, -h) * __builtin_amdgcn_rcpf(X2);
 }
 
+// Lane order of the truncated subhalos in the subhalo-major pass.  A pair
+// takes the general (non-polynomial) form within rho = Xf^(1/2) Rs of the
+// subhalo, and a wave pays for that form whenever any of its lanes needs it.
+// Lanes are therefore grouped by rho (bins of a factor 4 in rho^2, largest
+// first) and, within a bin, by position (a Morton code on a 1/8" grid over
+// +-64"), so that the lanes of a wave need the general form for the same
+// sub-pixels.  The order only decides which lane holds which subhalo: every
+// subhalo's sums are the same whatever it is.  key = (bin, Morton code, k),
+// unique; t0: the first draw's table.
+__device__ __forceinline__ unsigned spread_bits10(unsigned v) {
+  v &= 1023u;
+  v = (v | (v << 8)) & 0x00FF00FFu;
+  v = (v | (v << 4)) & 0x0F0F0F0Fu;
+  v = (v | (v << 2)) & 0x33333333u;
+  v = (v | (v << 1)) & 0x55555555u;
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_tnfw_lane_keys(const TRec* __restrict__ t0, int n,
+                                                        unsigned long long* __restrict__ keys) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  const TRec r = t0[k];
+  const float rho2 = r.Xf / r.c1;   // squared radius of the general form, arcsec^2
+  const int bin = min(max((int)floorf(__builtin_amdgcn_logf(rho2) * 0.25f) + 32, 0), 63);
+  const auto cell = [](float v) { return (unsigned)min(max((v + 64.0f) * 8.0f, 0.0f), 1023.0f); };
+  const unsigned code = (spread_bits10(cell(r.y)) << 1) | spread_bits10(cell(r.x));
+  keys[k] = ((unsigned long long)(63 - bin) << 52) | ((unsigned long long)code << 32) | (unsigned)k;
+}
+
+// perm[rank of keys[i]] = i: each thread counts the smaller keys, read in
+// tiles through LDS (n^2 comparisons; n is the subhalo count of one draw).
+__global__ __launch_bounds__(256) void k_rank_perm(const unsigned long long* __restrict__ keys, int n,
+                                                   int* __restrict__ perm) {
+  __shared__ unsigned long long tile[256];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const unsigned long long mine = i < n ? keys[i] : ~0ull;
+  int rank = 0;
+  for (int j0 = 0; j0 < n; j0 += 256) {
+    __syncthreads();
+    tile[threadIdx.x] = j0 + (int)threadIdx.x < n ? keys[j0 + threadIdx.x] : ~0ull;
+    __syncthreads();
+    const int m = min(256, n - j0);
+    for (int j = 0; j < m; ++j) rank += tile[j] < mine;
+  }
+  if (i < n) perm[rank] = i;
+}
+
 // The subhalo-major pass for truncated subhalos: as k_grad_subhalo, with each
 // lane's record read from the draw's table built for alpha_Rs = 1 (utab
 // [B][records]), so that the sums are per unit alpha_Rs: d log L/d(x, y) is
-// alpha_Rs times them and d log L/d alpha_Rs is minus the h G.d sum.
+// alpha_Rs times them and d log L/d alpha_Rs is minus the h G.d sum.  Lane l
+// holds subhalo perm[l] (k_tnfw_lane_keys).
 __global__ __launch_bounds__(kSubhaloBlock) void k_grad_subhalo_tnfw(const TRec* __restrict__ utab, int records,
+                                                                    const int* __restrict__ perm,
                                                                     const float* __restrict__ sub_ars,
                                                                     const float4* __restrict__ rec, int rec_stride,
                                                                     int nrec_loop, int n, float* __restrict__ gpart) {
   const int b = blockIdx.y, q = blockIdx.z, B = gridDim.y;
-  const int k = blockIdx.x * kSubhaloBlock + threadIdx.x;
-  const bool valid = k < n;
+  // the lane block rotates with the draw and the part: consecutive blocks go
+  // to different XCDs, and without the rotation the costliest lane block
+  // (largest rho) of every draw would land on the same two of them
+  const int xb = (int)((blockIdx.x + blockIdx.y + blockIdx.z) % gridDim.x);
+  const int l = xb * kSubhaloBlock + threadIdx.x;
+  const bool valid = l < n;
+  const int k = valid ? perm[l] : 0;
   const TRec R = utab[(size_t)b * records + (valid ? k : 0)];
   const float c1x2 = 2.0f * R.c1;
   const float4* __restrict__ r = rec + (size_t)b * rec_stride;
-  const int kb = part_bound(nrec_loop, kRecParts, q), ke = part_bound(nrec_loop, kRecParts, q + 1);
+  const int kb = part_bound(nrec_loop, kRecPartsTnfw, q), ke = part_bound(nrec_loop, kRecPartsTnfw, q + 1);
   float hx = 0.f, lx = 0.f, hy = 0.f, ly = 0.f, ha = 0.f, la = 0.f;
   for (int j0 = kb; j0 < ke; j0 += 64) {
     const int jend = min(j0 + 64, ke);
@@ -691,7 +747,7 @@ __global__ __launch_bounds__(kSubhaloBlock) void k_grad_subhalo_tnfw(const TRec*
 __global__ __launch_bounds__(256) void k_grad_finalize(int B, int P, int bpi, const float* __restrict__ part,
                                                       float* __restrict__ g_macro, int nres,
                                                       const float* __restrict__ lpart, double* __restrict__ logL,
-                                                      int n, const float* __restrict__ gpart,
+                                                      int n, int parts, const float* __restrict__ gpart,
                                                       float* __restrict__ g_sub) {
   const long i = (long)blockIdx.x * 256 + threadIdx.x;
   const long nm = (long)B * P, nl = B, ns = (long)B * n * 3;
@@ -708,7 +764,7 @@ __global__ __launch_bounds__(256) void k_grad_finalize(int B, int P, int bpi, co
   } else if (i < nm + nl + ns && g_sub) {
     const long e = i - nm - nl;
     float hi = 0.f, lo = 0.f;
-    for (int q = 0; q < kRecParts; ++q) two_sum_acc(hi, lo, gpart[(size_t)q * ns + e]);
+    for (int q = 0; q < parts; ++q) two_sum_acc(hi, lo, gpart[(size_t)q * ns + e]);
     g_sub[e] = hi + lo;
   }
 }
@@ -761,19 +817,23 @@ hipError_t launch_grad_subhalo(int B, int n, const float* x, const float* y, con
 }
 
 hipError_t launch_grad_subhalo_tnfw(int B, int n, const TRec* utab, int records, const float* ars,
-                                    const float4* rec, int rec_stride, int nrec_loop, float* gpart, hipStream_t st) {
+                                    const float4* rec, int rec_stride, int nrec_loop, unsigned long long* keys,
+                                    int* perm, float* gpart, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_grad_subhalo_tnfw, dim3((n + kSubhaloBlock - 1) / kSubhaloBlock, B, kRecParts),
-                     dim3(kSubhaloBlock), 0, st, utab, records, ars, rec, rec_stride, nrec_loop, n, gpart);
+  const dim3 g1((n + 255) / 256);
+  hipLaunchKernelGGL(k_tnfw_lane_keys, g1, dim3(256), 0, st, utab, n, keys);
+  hipLaunchKernelGGL(k_rank_perm, g1, dim3(256), 0, st, keys, n, perm);
+  hipLaunchKernelGGL(k_grad_subhalo_tnfw, dim3((n + kSubhaloBlock - 1) / kSubhaloBlock, B, kRecPartsTnfw),
+                     dim3(kSubhaloBlock), 0, st, utab, records, perm, ars, rec, rec_stride, nrec_loop, n, gpart);
   return hipGetLastError();
 }
 
 hipError_t launch_grad_finalize(int B, int P, int bpi, const float* part, float* g_macro, int nres,
-                                const float* lpart, double* logL, int n, const float* gpart, float* g_sub,
+                                const float* lpart, double* logL, int n, int parts, const float* gpart, float* g_sub,
                                 hipStream_t st) {
   const long total = (long)B * P + B + (long)B * n * 3;
   hipLaunchKernelGGL(k_grad_finalize, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, B, P, bpi, part,
-                     g_macro, nres, lpart, logL, n, gpart, g_sub);
+                     g_macro, nres, lpart, logL, n, parts, gpart, g_sub);
   return hipGetLastError();
 }
 

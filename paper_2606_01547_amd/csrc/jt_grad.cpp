@@ -175,14 +175,17 @@ jt_status chi2_common(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, c
   const int nres = (bt.npix + 255) / 256;
   const int nrec_loop = (bt.nsubpix + 3) & ~3;
   const int rec_stride = nrec_loop + 4;
+  const int rec_parts = bt.tnfw ? kRecPartsTnfwHost : kRecPartsHost;
   size_t bytes = align256(sizeof(ImageDesc) * bt.B) + align256(bt.rec_bytes * (size_t)bt.B * bt.records) +
                  3 * align256(sizeof(float) * BN) + align256(sizeof(float) * (size_t)bt.B * nres);
   if (grad)
     bytes += align256(sizeof(float) * BN) + align256(sizeof(float4) * (size_t)bt.B * rec_stride) +
              align256(sizeof(float) * (size_t)bt.B * bt.bpi * bt.P) +
-             align256(sizeof(float) * (size_t)kRecPartsHost * bt.B * bt.n * 3) +
+             align256(sizeof(float) * (size_t)rec_parts * bt.B * bt.n * 3) +
              (keep ? align256(sizeof(float2) * (size_t)bt.B * bt.nsubpix) : 0) +
-             (bt.tnfw ? align256(sizeof(TRec) * (size_t)bt.B * bt.records) : 0);
+             (bt.tnfw ? align256(sizeof(TRec) * (size_t)bt.B * bt.records) +
+                            align256(sizeof(unsigned long long) * (size_t)bt.n) + align256(sizeof(int) * (size_t)bt.n)
+                      : 0);
   void* ws = nullptr;
   JT_TRY(ctx_workspace(ctx, st, bytes, &ws));
   Carve cv{(char*)ws};
@@ -202,12 +205,12 @@ jt_status chi2_common(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, c
   }, "residual"));
   if (!grad)
     return timed_launch(ctx, JT_K_GRAD, st, [&] {
-      return launch_grad_finalize(bt.B, 0, 0, nullptr, nullptr, nres, lpart, logL, 0, nullptr, nullptr, st);
+      return launch_grad_finalize(bt.B, 0, 0, nullptr, nullptr, nres, lpart, logL, 0, 0, nullptr, nullptr, st);
     }, "chi2_finalize");
   float* lamU = psf ? cv.take<float>(BN) : resid;
   float4* rec = cv.take<float4>((size_t)bt.B * rec_stride);
   float* part = cv.take<float>((size_t)bt.B * bt.bpi * bt.P);
-  float* gpart = cv.take<float>((size_t)kRecPartsHost * bt.B * bt.n * 3);
+  float* gpart = cv.take<float>((size_t)rec_parts * bt.B * bt.n * 3);
   if (psf)
     JT_TRY(timed_launch(ctx, JT_K_CONV, st, [&] {
       return launch_conv_direct_batched(true, bt.B, resid, bt.npix, bt.g.nx, bt.g.ny, psf, k, lamU, bt.npix, st);
@@ -219,13 +222,15 @@ jt_status chi2_common(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, c
   if (bt.tnfw) {
     // per-lane constants of the truncated subhalos, for alpha_Rs = 1
     TRec* utab = cv.take<TRec>((size_t)bt.B * bt.records);
+    unsigned long long* keys = cv.take<unsigned long long>(bt.n);
+    int* perm = cv.take<int>(bt.n);
     JT_TRY(timed_launch(ctx, JT_K_PREP, st, [&] {
       return launch_prep_tnfw_batched(bt.B, bt.n, draws->sub_x, draws->sub_y, draws->sub_Rs, draws->sub_alpha_Rs,
                                       draws->sub_r_trunc, true, utab, st);
     }, "prep_tnfw_unit"));
     JT_TRY(timed_launch(ctx, JT_K_GRAD, st, [&] {
       return launch_grad_subhalo_tnfw(bt.B, bt.n, utab, bt.records, draws->sub_alpha_Rs, rec, rec_stride, nrec_loop,
-                                      gpart, st);
+                                      keys, perm, gpart, st);
     }, "grad_subhalo_tnfw"));
   } else {
     JT_TRY(timed_launch(ctx, JT_K_GRAD, st, [&] {
@@ -234,7 +239,7 @@ jt_status chi2_common(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, c
     }, "grad_subhalo"));
   }
   return timed_launch(ctx, JT_K_GRAD, st, [&] {
-    return launch_grad_finalize(bt.B, bt.P, bt.bpi, part, g_macro, nres, lpart, logL, bt.n, gpart,
+    return launch_grad_finalize(bt.B, bt.P, bt.bpi, part, g_macro, nres, lpart, logL, bt.n, rec_parts, gpart,
                                 bt.n > 0 ? g_sub : nullptr, st);
   }, "grad_finalize");
 }
