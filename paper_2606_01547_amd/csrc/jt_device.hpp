@@ -591,17 +591,22 @@ __device__ __forceinline__ float tnfw_T_general(float X2, const TRec& r, float& 
   return fmaf(r.t2m1, P1, P2);
 }
 
+// Far field of the truncated pair term (tnfw_far_fit), X2 >= r.Xf:
+// h = y^2 sum_k a_k u^k.
+__device__ __forceinline__ float tnfw_far_h(float X2, const TRec& r) {
+  const float yy = __builtin_amdgcn_rsqf(X2);
+  const float u = fmaf(yy, r.k1, -1.0f);
+  float p = r.a[kTnfwFarDeg];
+#pragma unroll
+  for (int k = kTnfwFarDeg - 1; k >= 0; --k) p = fmaf(p, u, r.a[k]);
+  return p * (yy * yy);
+}
+
 __device__ __forceinline__ void tnfw_pair(float tx, float ty, const TRec& r, float& sx, float& sy) {
   const float dx = tx - r.x, dy = ty - r.y;
   const float X2 = fmaf(dy, dy, dx * dx) * r.c1;
   if (X2 >= r.Xf) {
-    // far field (tnfw_far_fit): h = y^2 sum_k a_k u^k
-    const float yy = __builtin_amdgcn_rsqf(X2);
-    const float u = fmaf(yy, r.k1, -1.0f);
-    float p = r.a[kTnfwFarDeg];
-#pragma unroll
-    for (int k = kTnfwFarDeg - 1; k >= 0; --k) p = fmaf(p, u, r.a[k]);
-    const float h = p * (yy * yy);
+    const float h = tnfw_far_h(X2, r);
     sx = fmaf(h, dx, sx);
     sy = fmaf(h, dy, sy);
     return;

@@ -2,6 +2,8 @@
 // kernels (gfx950).
 #pragma once
 
+#include <type_traits>
+
 #include "jt_device.hpp"
 
 namespace jt {
@@ -107,22 +109,64 @@ __device__ __forceinline__ float4 subhalo_range_sum(float tx, float ty, const vo
   return make_float4(hx, lx, hy, ly);
 }
 
-// The truncated profile's 80-byte records one at a time with one prefetched
-// (two at a time would hold 80 scalar registers of records): the same pairs in
-// the same order as the general loop, so the same sums.
-template <>
-__device__ __forceinline__ float4 subhalo_range_sum<TnfwPairs>(float tx, float ty, const void* table, int kb,
-                                                               int ke) {
-  const SubTable sub = (SubTable)(const float*)table;
+// The truncated profile's 80-byte records go through LDS instead of scalar
+// loads: on gfx950 an FMA reading a scalar register issues at half rate, and
+// the far field's nine polynomial coefficients are FMA operands.  Each wave
+// copies kStage records at a time into its own LDS stage (coalesced 16-byte
+// loads, a few per lane) and every lane then reads the current record at the
+// same address (a broadcast) into vector registers.  Same pairs, same order,
+// same arithmetic as the scalar-operand form, so the same sums.  Must be
+// called by whole waves (every lane active; the copy is shared out by lane),
+// at most kWaves waves per block.
+// One staged record (five float4s in LDS) as a TRec.
+__device__ __forceinline__ TRec stage_rec(const float4* q) {
+  const float4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3], q4 = q[4];
+  TRec r;
+  r.x = q0.x;
+  r.y = q0.y;
+  r.c1 = q0.z;
+  r.c2 = q0.w;
+  r.tau = q1.x;
+  r.t2 = q1.y;
+  r.t2m1 = q1.z;
+  r.itau = q1.w;
+  r.Xf = q2.x;
+  r.k1 = q2.y;
+  r.a[0] = q2.z;
+  r.a[1] = q2.w;
+  r.a[2] = q3.x;
+  r.a[3] = q3.y;
+  r.a[4] = q3.z;
+  r.a[5] = q3.w;
+  r.a[6] = q4.x;
+  r.a[7] = q4.y;
+  r.a[8] = q4.z;
+  r.pad = 0.0f;
+  return r;
+}
+
+template <int kWaves, int kStage>
+__device__ __forceinline__ float4 tnfw_range_sum(float tx, float ty, const void* table, int kb, int ke) {
+  __shared__ float4 stage[kWaves][kStage * 5];
+  float4* st = stage[threadIdx.x >> 6];
+  const int lane = threadIdx.x & 63;
+  const float4* __restrict__ g4 = (const float4*)table;
   float hx = 0.f, lx = 0.f, hy = 0.f, ly = 0.f;
-  TRec n0 = TnfwPairs::load(sub, kb);
   for (int k0 = kb; k0 < ke; k0 += kSubTile) {
     const int kend = min(k0 + kSubTile, ke);
     float px = 0.f, py = 0.f;
-    for (int k = k0; k < kend; ++k) {
-      const TRec s0 = n0;
-      n0 = TnfwPairs::load(sub, k + 1);
-      tnfw_pair(tx, ty, s0, px, py);
+    for (int s0 = k0; s0 < kend; s0 += kStage) {
+      const int m = min(kStage, kend - s0);
+      // the previous stage's reads come before these writes, and these writes
+      // before the reads below (one wave's LDS operations execute in order)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int e = lane; e < m * 5; e += 64) st[e] = g4[(size_t)s0 * 5 + e];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int k = 0; k < m; ++k) tnfw_pair(tx, ty, stage_rec(st + 5 * k), px, py);
     }
     two_sum_acc(hx, lx, px);
     two_sum_acc(hy, ly, py);
@@ -145,10 +189,19 @@ template <int kSplit, class P = NfwPairs>
 __device__ __forceinline__ void subhalo_ranges(float tx, float ty, const void* __restrict__ sub, int nloop, int g,
                                                int slot, RangeScratch<kSplit>& scratch, double& sx, double& sy) {
   constexpr int kOwn = kRanges / kSplit;
+  // LDS stage of the truncated profile: about 20 KB per block with the range
+  // partials (40 KB for 8-wave blocks), so that 8 waves per SIMD stay resident
+  constexpr int kWaves = split_threads(kSplit) / 64;
+  constexpr int kBudget = (kWaves == 8 ? 40960 : 20480) - (int)sizeof(RangeScratch<kSplit>) - 1024;
+  constexpr int kStage = kBudget / (kWaves * 80) >= 32 ? 32 : kBudget / (kWaves * 80) >= 16 ? 16 : 8;
 #pragma unroll 1
   for (int i = 0; i < kOwn; ++i) {
     const int e = g * kOwn + i;
-    const float4 v = subhalo_range_sum<P>(tx, ty, sub, range_bound(nloop, e), range_bound(nloop, e + 1));
+    float4 v;
+    if constexpr (std::is_same<P, TnfwPairs>::value)
+      v = tnfw_range_sum<kWaves, kStage>(tx, ty, sub, range_bound(nloop, e), range_bound(nloop, e + 1));
+    else
+      v = subhalo_range_sum<P>(tx, ty, sub, range_bound(nloop, e), range_bound(nloop, e + 1));
     if (kSplit == 1) {
       sx += (double)v.x + (double)v.y;
       sy += (double)v.z + (double)v.w;
