@@ -599,7 +599,9 @@ __global__ __launch_bounds__(kSubhaloBlock) void k_grad_subhalo(const float* __r
 // 1/3 - v/5 + v^2/7 - ... in v = x^2 - 1 near x = 1.  0 at the centre.
 __device__ __forceinline__ void tnfw_h_dh(float X2, const TRec& r, float& h, float& dh) {
   constexpr float kPi = 3.14159265358979323846f;
-  if (X2 >= r.Xf) {
+  {
+    // the far form for every lane, replaced below where X2 < Xf (one
+    // exec-masked region instead of an if/else)
     const float y = __builtin_amdgcn_rsqf(X2);
     const float u = fmaf(y, r.k1, -1.0f);
     float p = r.a[kTnfwFarDeg], dp = 0.f;
@@ -611,8 +613,8 @@ __device__ __forceinline__ void tnfw_h_dh(float X2, const TRec& r, float& h, flo
     const float y2 = y * y;
     h = p * y2;
     dh = -(y2 * y2) * fmaf(0.5f * r.k1 * y, dp, p);
-    return;
   }
+  if (!(X2 < r.Xf)) return;
   if (!(X2 > 1e-30f)) {
     h = 0.f;
     dh = 0.f;

@@ -602,18 +602,19 @@ __device__ __forceinline__ float tnfw_far_h(float X2, const TRec& r) {
   return p * (yy * yy);
 }
 
+// The far form is evaluated by every lane, without a branch (a wave's lanes
+// are neighbouring sub-pixels, nearly always all far), and replaced where
+// X2 < Xf: one exec-masked region per pair instead of an if/else, which cost
+// more scalar instructions and branches than the far form's arithmetic.  A
+// pair at the centre itself (X2 <= 1e-30) adds 0.
 __device__ __forceinline__ void tnfw_pair(float tx, float ty, const TRec& r, float& sx, float& sy) {
   const float dx = tx - r.x, dy = ty - r.y;
   const float X2 = fmaf(dy, dy, dx * dx) * r.c1;
-  if (X2 >= r.Xf) {
-    const float h = tnfw_far_h(X2, r);
-    sx = fmaf(h, dx, sx);
-    sy = fmaf(h, dy, sy);
-    return;
+  float h = tnfw_far_h(X2, r);
+  if (X2 < r.Xf) {
+    float F, s, lp1;
+    h = X2 > 1e-30f ? r.c2 * tnfw_T_general(X2, r, F, s, lp1) : 0.0f;
   }
-  if (!(X2 > 1e-30f)) return;
-  float F, s, lp1;
-  const float h = r.c2 * tnfw_T_general(X2, r, F, s, lp1);
   sx = fmaf(h, dx, sx);
   sy = fmaf(h, dy, sy);
 }
