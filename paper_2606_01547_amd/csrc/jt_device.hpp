@@ -146,12 +146,16 @@ constexpr SubRec kSubRecPad{1e18f, 1e18f, 0.25f, 0.0f};
 // tau = r_trunc/Rs with tau^2, tau^2 - 1, 1/tau, each rounded once from FP64;
 // then the far-field form: for x^2 = r^2 c1 >= Xf the pair term is
 // c2 T(x) = y^2 sum_k a_k u^k, y = 1/x, u = y k1 - 1 (see tnfw_far_fit).
-constexpr int kTnfwFarDeg = 8;
+constexpr int kTnfwFarDeg = 12;
+// The first 32 bytes (what every pair and the general form read as scalar
+// operands of full-rate instructions, or only inside the general form) are
+// read through scalar loads; the last 64 (k1, c2 and the coefficients, FMA
+// operands of the far form) are staged through LDS.
 struct __align__(16) TRec {
-  float x, y, c1, c2, tau, t2, t2m1, itau;
-  float Xf, k1, a[kTnfwFarDeg + 1], pad;
+  float x, y, c1, Xf, tau, t2, t2m1, itau;
+  float k1, c2, a[kTnfwFarDeg + 1], pad;
 };
-static_assert(sizeof(TRec) == 80, "TRec is read as 20 floats");
+static_assert(sizeof(TRec) == 96, "TRec is read as 8 scalar floats and four float4s");
 
 struct ImageDesc {
   GridC g;               // g.ppb matches the launch's wave split
@@ -419,20 +423,23 @@ __host__ __device__ inline double tnfw_T64_far(double X2, double tau) {
 }
 
 // Far field of the truncated pair term as a polynomial in 1/x: for
-// x >= x_f = kTnfwFarX max(tau, 1), W(y) = T(1/y) / y^2 is analytic in y = 1/x
-// on [0, 1/x_f] (its nearest singularities are y = -1 and y = +-i/tau), so the
-// interpolant at kTnfwFarDeg + 1 Chebyshev points of that interval, written as
-// a polynomial in u = 2 y x_f - 1 in [-1, 1], matches it to about 2e-8
-// relative for tau in [0.4, 300] (FP32 Horner evaluation: under 1e-7).  The
-// record stores Xf = x_f^2, k1 = 2 x_f and a_k = c2 (1 - 2 kRsqBias) m_k, m_k
-// the interpolant's monomial coefficients (the factor removes the mean bias of
-// the hardware rsq that forms y^2).  The pair then costs one reciprocal square
-// root and a degree-8 polynomial instead of nine transcendentals.
-constexpr double kTnfwFarX = 1.5;
+// x >= x_f = max(kTnfwFarX tau, kTnfwFarMin), W(y) = T(1/y) / y^2 is analytic
+// in y = 1/x on [0, 1/x_f] (its nearest singularities are y = -1 and
+// y = +-i/tau), so the interpolant at kTnfwFarDeg + 1 Chebyshev points of that
+// interval, written as a polynomial in u = 2 y x_f - 1 in [-1, 1], matches it
+// to about 3e-9 relative for tau in [0.4, 1e4] (FP32 Horner evaluation: about
+// 1.1e-7).  The record stores Xf = x_f^2, k1 = 2 x_f and a_k = c2 (1 - 2
+// kRsqBias) m_k, m_k the interpolant's monomial coefficients (the factor
+// removes the mean bias of the hardware rsq that forms y^2).  The pair then
+// costs one reciprocal square root and a degree-12 polynomial instead of nine
+// transcendentals.  x_f = 0.75 tau (down from 1.5 tau with degree 8) leaves
+// about a third as many pairs to the general form for four more FMAs each.
+constexpr double kTnfwFarX = 0.75;
+constexpr double kTnfwFarMin = 1.5;
 __host__ __device__ inline void tnfw_far_fit(double tau, double c2, TRec& r) {
   constexpr double kPiD = 3.14159265358979323846;
   constexpr int N = kTnfwFarDeg + 1;
-  const double xf = kTnfwFarX * (tau > 1.0 ? tau : 1.0);
+  const double xf = kTnfwFarX * tau > kTnfwFarMin ? kTnfwFarX * tau : kTnfwFarMin;
   double f[N], uj[N], tj[N], tjm1[N];
   for (int j = 0; j < N; ++j) {
     uj[j] = cos(kPiD * (2 * j + 1) / (2 * N));

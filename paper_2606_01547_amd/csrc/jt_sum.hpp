@@ -54,33 +54,10 @@ struct NfwPairs {
   }
 };
 
+// The truncated profile: its records are staged through LDS (tnfw_range_sum),
+// so the type only names the record.
 struct TnfwPairs {
   using Rec = TRec;
-  static __device__ __forceinline__ Rec load(SubTable t, int k) {
-    const SubTable p = t + 20 * k;
-    TRec r;
-    r.x = p[0];
-    r.y = p[1];
-    r.c1 = p[2];
-    r.c2 = p[3];
-    r.tau = p[4];
-    r.t2 = p[5];
-    r.t2m1 = p[6];
-    r.itau = p[7];
-    r.Xf = p[8];
-    r.k1 = p[9];
-#pragma unroll
-    for (int i = 0; i <= kTnfwFarDeg; ++i) r.a[i] = p[10 + i];
-    r.pad = 0.0f;
-    return r;
-  }
-  static __device__ __forceinline__ void run4(float tx, float ty, const Rec& a, const Rec& b, const Rec& c,
-                                              const Rec& d, float& px, float& py) {
-    tnfw_pair(tx, ty, a, px, py);
-    tnfw_pair(tx, ty, b, px, py);
-    tnfw_pair(tx, ty, c, px, py);
-    tnfw_pair(tx, ty, d, px, py);
-  }
 };
 
 // Sum of the pair terms over records [kb, ke) as (hi, lo) per component.  The
@@ -109,29 +86,33 @@ __device__ __forceinline__ float4 subhalo_range_sum(float tx, float ty, const vo
   return make_float4(hx, lx, hy, ly);
 }
 
-// The truncated profile's 80-byte records go through LDS instead of scalar
-// loads: on gfx950 an FMA reading a scalar register issues at half rate, and
-// the far field's nine polynomial coefficients are FMA operands.  Each wave
-// copies kStage records at a time into its own LDS stage (coalesced 16-byte
-// loads, a few per lane) and every lane then reads the current record at the
-// same address (a broadcast) into vector registers.  Same pairs, same order,
-// same arithmetic as the scalar-operand form, so the same sums.  Must be
+// The truncated profile's 96-byte records: the first 32 bytes (centre, c1, Xf
+// and the general form's tau constants: scalar operands of full-rate
+// instructions, or used only in the general form) through scalar loads, one
+// record prefetched; the last 64 (k1, c2, the far field's 13 coefficients)
+// through LDS, because an FMA reading a scalar register issues at half rate on
+// gfx950.  Each wave copies kStage records' 64-byte tails at a time into its
+// own LDS stage (coalesced 16-byte loads) and every lane then reads the current
+// tail at one address (a broadcast) into vector registers.  Same pairs, same
+// order, same arithmetic as an all-scalar read, so the same sums.  Must be
 // called by whole waves (every lane active; the copy is shared out by lane),
 // at most kWaves waves per block.
-// One staged record (five float4s in LDS) as a TRec.
-__device__ __forceinline__ TRec stage_rec(const float4* q) {
-  const float4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3], q4 = q[4];
+constexpr int kTnfwTailQ = 4;   // float4s of a record's LDS tail
+static_assert(kTnfwFarDeg == 12 && sizeof(TRec) == (2 + kTnfwTailQ) * sizeof(float4), "TRec layout");
+
+__device__ __forceinline__ TRec tnfw_rec(const float (&h)[8], const float4* q) {
+  const float4 q2 = q[0], q3 = q[1], q4 = q[2], q5 = q[3];
   TRec r;
-  r.x = q0.x;
-  r.y = q0.y;
-  r.c1 = q0.z;
-  r.c2 = q0.w;
-  r.tau = q1.x;
-  r.t2 = q1.y;
-  r.t2m1 = q1.z;
-  r.itau = q1.w;
-  r.Xf = q2.x;
-  r.k1 = q2.y;
+  r.x = h[0];
+  r.y = h[1];
+  r.c1 = h[2];
+  r.Xf = h[3];
+  r.tau = h[4];
+  r.t2 = h[5];
+  r.t2m1 = h[6];
+  r.itau = h[7];
+  r.k1 = q2.x;
+  r.c2 = q2.y;
   r.a[0] = q2.z;
   r.a[1] = q2.w;
   r.a[2] = q3.x;
@@ -141,17 +122,29 @@ __device__ __forceinline__ TRec stage_rec(const float4* q) {
   r.a[6] = q4.x;
   r.a[7] = q4.y;
   r.a[8] = q4.z;
+  r.a[9] = q4.w;
+  r.a[10] = q5.x;
+  r.a[11] = q5.y;
+  r.a[12] = q5.z;
   r.pad = 0.0f;
   return r;
 }
 
 template <int kWaves, int kStage>
 __device__ __forceinline__ float4 tnfw_range_sum(float tx, float ty, const void* table, int kb, int ke) {
-  __shared__ float4 stage[kWaves][kStage * 5];
+  __shared__ float4 stage[kWaves][kStage * kTnfwTailQ];
   float4* st = stage[threadIdx.x >> 6];
   const int lane = threadIdx.x & 63;
   const float4* __restrict__ g4 = (const float4*)table;
+  const SubTable sub = (SubTable)(const float*)table;
+  constexpr int kF = (int)(sizeof(TRec) / sizeof(float));   // floats per record
+  auto head = [&](int k, float (&h)[8]) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) h[i] = sub[kF * k + i];
+  };
   float hx = 0.f, lx = 0.f, hy = 0.f, ly = 0.f;
+  float nh[8];
+  head(kb, nh);
   for (int k0 = kb; k0 < ke; k0 += kSubTile) {
     const int kend = min(k0 + kSubTile, ke);
     float px = 0.f, py = 0.f;
@@ -162,11 +155,20 @@ __device__ __forceinline__ float4 tnfw_range_sum(float tx, float ty, const void*
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int e = lane; e < m * 5; e += 64) st[e] = g4[(size_t)s0 * 5 + e];
+      for (int e = lane; e < m * kTnfwTailQ; e += 64) {
+        const int rk = e / kTnfwTailQ;
+        st[e] = g4[(size_t)(s0 + rk) * (2 + kTnfwTailQ) + 2 + (e - rk * kTnfwTailQ)];
+      }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int k = 0; k < m; ++k) tnfw_pair(tx, ty, stage_rec(st + 5 * k), px, py);
+      for (int k = 0; k < m; ++k) {
+        float h[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) h[i] = nh[i];
+        head(s0 + k + 1, nh);   // the table has a readable record past every range end
+        tnfw_pair(tx, ty, tnfw_rec(h, st + kTnfwTailQ * k), px, py);
+      }
     }
     two_sum_acc(hx, lx, px);
     two_sum_acc(hy, ly, py);
@@ -193,7 +195,8 @@ __device__ __forceinline__ void subhalo_ranges(float tx, float ty, const void* _
   // partials (40 KB for 8-wave blocks), so that 8 waves per SIMD stay resident
   constexpr int kWaves = split_threads(kSplit) / 64;
   constexpr int kBudget = (kWaves == 8 ? 40960 : 20480) - (int)sizeof(RangeScratch<kSplit>) - 1024;
-  constexpr int kStage = kBudget / (kWaves * 80) >= 32 ? 32 : kBudget / (kWaves * 80) >= 16 ? 16 : 8;
+  constexpr int kRecB = kTnfwTailQ * 16;   // LDS bytes per staged record
+  constexpr int kStage = kBudget / (kWaves * kRecB) >= 32 ? 32 : kBudget / (kWaves * kRecB) >= 16 ? 16 : 8;
 #pragma unroll 1
   for (int i = 0; i < kOwn; ++i) {
     const int e = g * kOwn + i;

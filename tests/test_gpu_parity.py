@@ -238,11 +238,11 @@ def test_single_tnfw_every_branch(ctx, tau):
 
 @pytest.mark.parametrize("tau", [0.4, 2.0, 7.0, 40.0, 300.0, 1e4])
 def test_single_tnfw_far_field_boundary(ctx, tau):
-    """Points just inside and outside x_f = 1.5 max(tau, 1), where the pair
+    """Points just inside and outside x_f = max(0.75 tau, 1.5), where the pair
     switches between the general form and the far-field polynomial, and far
     beyond it: per-point relative error of the deflection."""
     Rs, aRs, cx, cy = 0.1, 2e-3, 0.3, -0.2
-    xf = 1.5 * max(tau, 1.0)
+    xf = max(0.75 * tau, 1.5)
     X = xf * np.array([0.95, 0.99, 0.999, 1.0005, 1.001, 1.01, 1.1, 1.5, 3.0, 10.0, 100.0, 1000.0])
     ang = np.linspace(0.2, 6.1, X.size)
     x = _f32(cx + X * Rs * np.cos(ang))
