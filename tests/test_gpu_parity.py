@@ -201,6 +201,21 @@ def test_deflection_independent_of_launch_split(ctx):
     np.testing.assert_array_equal(_np(small[1]), _np(big[1])[:100])
 
 
+def test_truncated_deflection_independent_of_launch_split(ctx):
+    """The truncated profile's records pass through a per-wave LDS stage whose
+    length follows the launch's wave split (8 records with two wave-groups, 32
+    otherwise): the same 100 points alone (split 8) and at the head of batches
+    launched with splits 4, 2 and 1 give bitwise the same deflection."""
+    sc = W.tnfw_scene(n_sub=2000)
+    x, y = W.random_points(100, 4.0, seed=14)
+    small = ctx.deflection(x, y, sc.lens)
+    for n, seed in ((600_000, 15), (1_200_000, 16), (2_200_000, 17)):
+        bx, by = W.random_points(n, 4.0, seed=seed)
+        big = ctx.deflection(np.concatenate([x, bx]), np.concatenate([y, by]), sc.lens)
+        np.testing.assert_array_equal(_np(small[0]), _np(big[0])[:100])
+        np.testing.assert_array_equal(_np(small[1]), _np(big[1])[:100])
+
+
 def test_resident_table_matches_device_soa_bitwise(ctx):
     sc = W.config2_scene(n_sub=777)
     x, y = W.random_points(5000, 4.0, seed=1)
