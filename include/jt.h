@@ -202,7 +202,8 @@ jt_status jt_source_sb(jt_ctx* ctx, int n, const float* x, const float* y,
  * float32 [ny][nx], out overlapping neither img nor psf (JT_EINVAL); psf:
  * device float32 [k][k], k odd.
  * method: 0 = auto (direct below the measured crossover), 1 = direct
- * (LDS-tiled, k <= JT_MAX_PSF), 2 = FFT (FP64 transform). */
+ * (FP32 matrix-core products of LDS-staged tiles, k <= JT_MAX_PSF), 2 = FFT
+ * (FP64 transform). */
 jt_status jt_convolve(jt_ctx* ctx, const float* img, int nx, int ny, const float* psf,
                       int k, int method, float* out, hipStream_t stream);
 

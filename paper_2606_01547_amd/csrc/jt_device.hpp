@@ -173,7 +173,7 @@ struct ConvDesc {
   float* out;
   const float* psf;
   int nx, ny, k;
-  int rb;                // kernel rows per staged chunk: conv_rows_per_chunk(k)
+  int t;                 // input rows per staged chunk: conv_shape(nx, ny, k).t
 };
 
 // ---------------------------------------------------------------------------

@@ -41,25 +41,29 @@ hipError_t launch_linear_solve(int npix, int n, const float* basis, const float*
                                double* part, double* amps, float* model, double* logL, hipStream_t st);
 // Wave-groups per block for `points` sub-pixels in whole units of `unit`.
 int pick_split(long points, int unit, int nloop);
-size_t conv_direct_lds_bytes(int k);
-// Kernel rows per LDS-staged chunk, and whether the direct convolution of
-// `tiles` output tiles with a k x k kernel takes 16-wave blocks (else 4).
-// Both fix the order of the sums, so a batch that convolves an image with
-// the values the image alone would get gives the same bits.
-int conv_rows_per_chunk(int k);
-bool conv_wide_blocks(long tiles, int k);
+// Direct convolution on the matrix cores (k_conv_mfma).  The launch shape of
+// an nx x ny image with a k x k kernel: column groups of 16 outputs per block
+// (nc), waves splitting each column group's input rows (s) and input rows per
+// LDS-staged chunk (t).  It depends on (nx, ny, k) alone and fixes the order
+// of every sum, so an image convolved alone, in a batch of draws or in a
+// served batch gives the same bits.
+struct ConvShape {
+  int nc, s, t;
+};
+ConvShape conv_shape(int nx, int ny, int k);
+int conv_shape_kind(const ConvShape& sh);      // 0: (4, 1), 1: (2, 2), 2: (1, 8)
+size_t conv_lds_bytes(int k, const ConvShape& sh);
+int conv_tiles_x(int nx, const ConvShape& sh);  // 16 nc output columns per tile
+int conv_tiles_y(int ny);                       // 16 output rows per tile
 // `batch` images at img + z * in_stride -> out + z * out_stride; flip = the
 // adjoint (correlation with the kernel).
 hipError_t launch_conv_direct_batched(bool flip, int batch, const float* img, long in_stride, int nx, int ny,
                                       const float* psf, int k, float* out, long out_stride, hipStream_t st);
-// Heterogeneous convolutions: tiles (desc, tile_x, tile_y, -) over 64 x 4
-// output tiles, in 16-wave blocks when `wide`, else 4-wave blocks; each
-// descriptor carries its own row chunk, and `lds` bytes cover the largest
-// conv_direct_lds_bytes(k) of the launch's descriptors.
-hipError_t launch_conv_desc(bool wide, const ConvDesc* descs, const int4* tiles, int ntiles, size_t lds,
+// Heterogeneous convolutions of one shape kind: tiles (desc, tile_x, tile_y,
+// -), each descriptor with its own k and rows per chunk; `lds` bytes cover the
+// largest conv_lds_bytes of the launch's descriptors.
+hipError_t launch_conv_desc(int kind, const ConvDesc* descs, const int4* tiles, int ntiles, size_t lds,
                             hipStream_t st);
-int conv_tiles_x(int nx);
-int conv_tiles_y(int ny);
 // Batched fused simulation over image descriptors (see k_simulate_desc).
 // tnfw: every descriptor's table holds TRec records (not with keep_beta).
 hipError_t launch_simulate_desc(int split, bool tnfw, bool extra, bool keep_beta, const ImageDesc* descs,
@@ -75,13 +79,14 @@ hipError_t launch_prep_tnfw_batched(int B, int n, const float* x, const float* y
 
 // ---- FFT convolution (fft.hip) ----
 // Cost model of the direct/FFT choice (method 0), fitted to kernel times on
-// MI355X (images 100^2..1000^2, k = 3..255):
-//   direct: kConvDirectFixedS + nx ny k^2 / min(kConvDirectFmaPerS, tiles * kConvDirectFmaPerTileS)
-//           (small images have too few 64 x 4 tiles to fill the chip)
+// MI355X (images 100^2..1000^2, k = 21..101):
+//   direct: kConvDirectFixedS + E / min(kConvMfmaMacPerS, waves * kConvMfmaMacPerWaveS),
+//           E = nx ny (16 + k - 1) kp multiply-adds issued (the banded operand's
+//           zeros included), waves = tiles * nc * s of conv_shape
 //   FFT:    kConvFftFixedS + Nx Ny / kConvFftPointsPerS (padded 2-3-5 sizes)
 constexpr double kConvDirectFixedS = 6e-6;
-constexpr double kConvDirectFmaPerS = 1.55e13;
-constexpr double kConvDirectFmaPerTileS = 5e10;
+constexpr double kConvMfmaMacPerS = 4.9e13;
+constexpr double kConvMfmaMacPerWaveS = 1.35e10;
 constexpr double kConvFftFixedS = 30e-6;
 constexpr double kConvFftPointsPerS = 1.45e10;
 bool conv_prefers_fft(int nx, int ny, int k);

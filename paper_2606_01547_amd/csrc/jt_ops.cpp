@@ -56,9 +56,11 @@ bool conv_prefers_fft(int nx, int ny, int k) {
   const bool fft_ok = fft_size_for(nx, k) <= kFftMaxN && fft_size_for(ny, k) <= kFftMaxN;
   if (!fft_ok) return false;
   if (k > JT_MAX_PSF) return true;
-  const double tiles = (double)conv_tiles_x(nx) * conv_tiles_y(ny);
-  const double rate = std::min(kConvDirectFmaPerS, tiles * kConvDirectFmaPerTileS);
-  const double direct_s = kConvDirectFixedS + (double)nx * ny * k * (double)k / rate;
+  const ConvShape sh = conv_shape(nx, ny, k);
+  const double waves = (double)conv_tiles_x(nx, sh) * conv_tiles_y(ny) * sh.nc * sh.s;
+  const double rate = std::min(kConvMfmaMacPerS, waves * kConvMfmaMacPerWaveS);
+  const double macs = (double)nx * ny * (16.0 + k - 1) * (double)((k + 3) & ~3);
+  const double direct_s = kConvDirectFixedS + macs / rate;
   const double N2 = (double)fft_size_for(nx, k) * fft_size_for(ny, k);
   const double fft_s = kConvFftFixedS + N2 / kConvFftPointsPerS;
   return fft_s < direct_s;

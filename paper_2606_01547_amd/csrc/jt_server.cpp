@@ -163,7 +163,7 @@ size_t request_footprint(const GridC& g, int k) {
   const long npix = (long)g.nx * g.ny;
   const long ppb_min = std::max(1, 64 / g.s2);
   const long tiles = (npix + ppb_min - 1) / ppb_min;
-  const long ctiles = k ? (long)conv_tiles_x(g.nx) * conv_tiles_y(g.ny) : 0;
+  const long ctiles = k ? (long)conv_tiles_x(g.nx, conv_shape(g.nx, g.ny, k)) * conv_tiles_y(g.ny) : 0;
   return a256(sizeof(ImageDesc)) + a256(sizeof(ConvDesc)) + a256(8 * tiles) + a256(16 * ctiles) +
          (k ? a256(4 * npix) : 0);
 }
@@ -184,8 +184,8 @@ size_t chunk_footprint(int chunk_blocks) {
   return a256(sizeof(ImageDesc)) + a256(8 * (size_t)chunk_blocks);
 }
 
-size_t conv_footprint(const GridC& g) {
-  return a256(sizeof(ConvDesc)) + a256(16 * (size_t)conv_tiles_x(g.nx) * conv_tiles_y(g.ny));
+size_t conv_footprint(const GridC& g, int k) {
+  return a256(sizeof(ConvDesc)) + a256(16 * (size_t)conv_tiles_x(g.nx, conv_shape(g.nx, g.ny, k)) * conv_tiles_y(g.ny));
 }
 
 }  // namespace
@@ -263,10 +263,10 @@ jt_status jt_server::launch_hip(Batch& b) {
   std::vector<ImageDesc> descs(n);
   std::vector<ConvDesc> cdescs;
   std::vector<int2> tiles;
-  // convolution tiles of the requests that alone would take 4-wave blocks
-  // (first) and 16-wave blocks (second), and the LDS each launch needs
-  std::vector<int4> ctiles[2];
-  size_t clds[2] = {0, 0};
+  // convolution tiles by the shape kind each request alone would take (one
+  // launch per kind), and the LDS each launch needs
+  std::vector<int4> ctiles[3];
+  size_t clds[3] = {0, 0, 0};
   // block layout: descs | conv descs | tiles | conv tiles | images
   size_t img_total = 0;
   for (Req* r : order) img_total += r->k ? a256(4 * (size_t)r->g.nx * r->g.ny) : 0;
@@ -277,7 +277,7 @@ jt_status jt_server::launch_hip(Batch& b) {
     ntiles += ((long)r->g.nx * r->g.ny + ppb - 1) / ppb;
     extra = extra || light_has_extra(r->src) || light_has_extra(r->ll);
     if (r->k) {
-      nctiles += (size_t)conv_tiles_x(r->g.nx) * conv_tiles_y(r->g.ny);
+      nctiles += (size_t)conv_tiles_x(r->g.nx, conv_shape(r->g.nx, r->g.ny, r->k)) * conv_tiles_y(r->g.ny);
       ++ncon;
     }
   }
@@ -305,14 +305,14 @@ jt_status jt_server::launch_hip(Batch& b) {
       D.img = (float*)(base + img_off);
       img_off += a256(4 * (size_t)r->g.nx * r->g.ny);
       const int ci = (int)cdescs.size();
-      // the row chunk and block width the request alone would get, so its
-      // image does not depend on what else the batch holds
-      cdescs.push_back(ConvDesc{D.img, r->out, r->psf, r->g.nx, r->g.ny, r->k, conv_rows_per_chunk(r->k)});
-      const long nct = (long)conv_tiles_x(r->g.nx) * conv_tiles_y(r->g.ny);
-      const int wide = conv_wide_blocks(nct, r->k) ? 1 : 0;
-      clds[wide] = std::max(clds[wide], conv_direct_lds_bytes(r->k));
+      // the shape the request alone would get, so its image does not depend
+      // on what else the batch holds
+      const ConvShape sh = conv_shape(r->g.nx, r->g.ny, r->k);
+      cdescs.push_back(ConvDesc{D.img, r->out, r->psf, r->g.nx, r->g.ny, r->k, sh.t});
+      const int kind = conv_shape_kind(sh);
+      clds[kind] = std::max(clds[kind], conv_lds_bytes(r->k, sh));
       for (int ty = 0; ty < conv_tiles_y(r->g.ny); ++ty)
-        for (int tx = 0; tx < conv_tiles_x(r->g.nx); ++tx) ctiles[wide].push_back(make_int4(ci, tx, ty, 0));
+        for (int tx = 0; tx < conv_tiles_x(r->g.nx, sh); ++tx) ctiles[kind].push_back(make_int4(ci, tx, ty, 0));
     } else {
       D.img = r->out;
     }
@@ -321,19 +321,23 @@ jt_status jt_server::launch_hip(Batch& b) {
   std::memcpy(host.data(), descs.data(), sizeof(ImageDesc) * n);
   if (ncon) std::memcpy(host.data() + o_cd, cdescs.data(), sizeof(ConvDesc) * ncon);
   std::memcpy(host.data() + o_t, tiles.data(), sizeof(int2) * ntiles);
-  const size_t nct0 = ctiles[0].size();
-  if (nct0) std::memcpy(host.data() + o_ct, ctiles[0].data(), sizeof(int4) * nct0);
-  if (ctiles[1].size()) std::memcpy(host.data() + o_ct + sizeof(int4) * nct0, ctiles[1].data(), sizeof(int4) * ctiles[1].size());
+  size_t ct_off[3], nct_all = 0;
+  for (int kind = 0; kind < 3; ++kind) {
+    ct_off[kind] = nct_all;
+    if (!ctiles[kind].empty())
+      std::memcpy(host.data() + o_ct + sizeof(int4) * nct_all, ctiles[kind].data(), sizeof(int4) * ctiles[kind].size());
+    nct_all += ctiles[kind].size();
+  }
   JT_TRY(upload(b, host.data(), o_img, base, s));
   JT_TRY(timed_launch(ctx, JT_K_SIM, s, [&] {
     return launch_simulate_desc(split, order[0]->tnfw, extra, false, (const ImageDesc*)base, (const int2*)(base + o_t), (int)ntiles,
                                 0, s);
   }, "server simulate"));
-  for (int wide = 0; wide < 2; ++wide) {
-    if (ctiles[wide].empty()) continue;
-    const int4* tl = (const int4*)(base + o_ct) + (wide ? nct0 : 0);
+  for (int kind = 0; kind < 3; ++kind) {
+    if (ctiles[kind].empty()) continue;
+    const int4* tl = (const int4*)(base + o_ct) + ct_off[kind];
     JT_TRY(timed_launch(ctx, JT_K_CONV, s, [&] {
-      return launch_conv_desc(wide == 1, (const ConvDesc*)(base + o_cd), tl, (int)ctiles[wide].size(), clds[wide], s);
+      return launch_conv_desc(kind, (const ConvDesc*)(base + o_cd), tl, (int)ctiles[kind].size(), clds[kind], s);
     }, "server convolve"));
   }
   return check_hip(hipEventRecord(b.ev, s), "hipEventRecord(batch)");
@@ -372,22 +376,23 @@ jt_status jt_server::launch_conv_hip(Batch& b) {
   JT_TRY(ctx_enter(ctx));
   Req* r = b.reqs[0];
   hipStream_t s = streams[b.stream];
-  const long nct = (long)conv_tiles_x(r->g.nx) * conv_tiles_y(r->g.ny);
+  const ConvShape sh = conv_shape(r->g.nx, r->g.ny, r->k);
+  const long nct = (long)conv_tiles_x(r->g.nx, sh) * conv_tiles_y(r->g.ny);
   const size_t o_ct = a256(sizeof(ConvDesc));
   const size_t end = o_ct + a256(sizeof(int4) * (size_t)nct);
   if (end > b.bytes) return fail(JT_EDEVICE, "server: convolution block too small (internal)");
   char* base = arena_dev + b.off;
   std::vector<char> host(end, 0);
   *(ConvDesc*)host.data() = ConvDesc{(const float*)(arena_dev + r->img_off), r->out, r->psf, r->g.nx, r->g.ny, r->k,
-                                     conv_rows_per_chunk(r->k)};
+                                     sh.t};
   int4* ct = (int4*)(host.data() + o_ct);
   long j = 0;
   for (int ty = 0; ty < conv_tiles_y(r->g.ny); ++ty)
-    for (int tx = 0; tx < conv_tiles_x(r->g.nx); ++tx) ct[j++] = make_int4(0, tx, ty, 0);
+    for (int tx = 0; tx < conv_tiles_x(r->g.nx, sh); ++tx) ct[j++] = make_int4(0, tx, ty, 0);
   JT_TRY(upload(b, host.data(), end, base, s));
   JT_TRY(timed_launch(ctx, JT_K_CONV, s, [&] {
-    return launch_conv_desc(conv_wide_blocks(nct, r->k), (const ConvDesc*)base, (const int4*)(base + o_ct), (int)nct,
-                            conv_direct_lds_bytes(r->k), s);
+    return launch_conv_desc(conv_shape_kind(sh), (const ConvDesc*)base, (const int4*)(base + o_ct), (int)nct,
+                            conv_lds_bytes(r->k, sh), s);
   }, "server convolve"));
   return check_hip(hipEventRecord(b.ev, s), "hipEventRecord(batch)");
 }
@@ -656,7 +661,7 @@ void jt_server::launch_ready() {
     if (r) {
       const int cb = shared ? std::min(r->chunk_blocks, kChunkSharedBlocks) : r->chunk_blocks;
       const int b0 = r->next_block, b1 = conv ? b0 : std::min(r->blocks, b0 + cb);
-      const size_t bytes = conv ? conv_footprint(r->g) : chunk_footprint(b1 - b0);
+      const size_t bytes = conv ? conv_footprint(r->g, r->k) : chunk_footprint(b1 - b0);
       size_t off = 0, so = 0;
       if (!arena.alloc(bytes, &off)) return;
       if (!take_stage(bytes, &so)) {
@@ -882,11 +887,11 @@ extern "C" jt_status jt_server_submit(jt_server* srv, const jt_request* req, uin
     const double per_block = r->pairs / r->blocks;
     r->chunk_blocks = (int)std::max((double)kChunkMinBlocks, std::floor(srv->cfg.max_batch_pairs / per_block));
     r->footprint = (r->k ? a256(4 * (size_t)r->g.nx * r->g.ny) : 0) +
-                   std::max(2 * chunk_footprint(std::min(r->blocks, r->chunk_blocks)), r->k ? conv_footprint(r->g) : 0);
+                   std::max(2 * chunk_footprint(std::min(r->blocks, r->chunk_blocks)), r->k ? conv_footprint(r->g, r->k) : 0);
   } else {
     r->footprint = request_footprint(r->g, r->k);
   }
-  const size_t hdr = r->chunked ? (r->k ? conv_footprint(r->g) : 0) : header_bytes(r.get());
+  const size_t hdr = r->chunked ? (r->k ? conv_footprint(r->g, r->k) : 0) : header_bytes(r.get());
   if (hdr > kStagingBytes)
     return fail(JT_ENOMEM, "server submit: request descriptors need %zu bytes of staging, %zu available", hdr,
                 kStagingBytes);

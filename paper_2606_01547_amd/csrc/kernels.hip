@@ -5,7 +5,7 @@
 //  k_ray_shoot      step 1 at explicit points: beta = theta - alpha (or alpha)
 //  k_source_sb      step 2 at explicit points
 //  k_simulate       steps 1-2 plus the supersample average, fused
-//  k_conv_direct    step 3, LDS-tiled direct convolution
+//  k_conv_mfma      step 3, direct convolution on the matrix cores
 //
 // Subhalo records are read with wave-uniform indices from a read-only table, so
 // the 16-byte NFW records arrive through scalar loads into SGPRs and feed the
@@ -269,117 +269,163 @@ __global__ __launch_bounds__(split_threads(kSplit)) void k_simulate_desc(const I
                                                d.beta);
 }
 
-// Direct convolution tiles: 64 x 4 outputs per block of kW waves.  Thread
-// (q, r, w) computes the four outputs (i0 + r, j0 + 4q .. 4q + 3) over the
-// kernel rows a = w, w + kW, ... of each staged chunk: wave w owns 1/kW of the
-// kernel rows, so the weights it reads are wave-uniform (scalar loads), and a
-// sliding window of four input values in registers feeds four FMAs per LDS
-// read.  The kW per-wave partials are added in wave order at the end.  Small
-// images (too few tiles to fill the chip) use kW = 16 so that each CU still
-// runs enough waves to hide the LDS latency.
-constexpr int kConvTX = 64, kConvTY = 4, kConvQ = 4;
-constexpr size_t kConvLdsCap = 48 * 1024;
+// ---------------------------------------------------------------------------
+// Direct convolution on the matrix cores.  The "same" convolution is a dense
+// contraction: for a 16-row output block, out[i][j] = sum over input rows t
+// and taps b of K[i + 2c - t][b] X[t][j - b + c] (rows t of the block's input
+// window, K zero outside its k x k support), i.e. C = A B with A[i][(t, b)] =
+// K[i + 2c - t][b] (a banded Toeplitz matrix of the kernel) and B[(t, b)][j] =
+// X[t][j - b + c] (a Hankel matrix of the image rows).  Each wave forms a
+// 16 x 16 output tile with v_mfma_f32_16x16x4f32 (FP32 products and sums),
+// four taps per instruction, both operands read from LDS: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16] and holds C[4 (l / 16) + v][l % 16].
+// A block of NC x S waves covers 16 rows x 16 NC columns; the S waves of a
+// column group split the input rows of each staged chunk and their partial
+// tiles are added in wave order, so that small images still give the chip
+// enough waves.  The input window is staged T rows at a time (T from the LDS
+// budget) with the kernel rows those rows meet; the order of every sum is
+// fixed by (k, NC, S, T), which depend on the image size and k only, so
+// results are reproducible and independent of batching.
+typedef float jt_floatx4 __attribute__((ext_vector_type(4)));
 
-// Kernel rows staged per chunk so that the input window fits kConvLdsCap.
-int conv_rows_per_chunk(int k) {
-  const long cols = kConvTX + k - 1;
-  long rb = (long)(kConvLdsCap / (sizeof(float) * cols)) - (kConvTY - 1);
-  if (rb > k) rb = k;
-  if (rb < 1) rb = 1;
-  return (int)rb;
+__host__ __device__ constexpr int conv_mfma_kp(int k) { return (k + 3) & ~3; }
+
+// The launch shape of an nx x ny image with a k x k kernel: 16 x 64 tiles
+// (4 waves, one per column group) when they alone give at least 512 blocks,
+// else 16 x 32 tiles with 2 waves per column group, else 16 x 16 tiles with 8
+// waves splitting the rows; it depends on (nx, ny, k) alone.
+ConvShape conv_shape(int nx, int ny, int k) {
+  ConvShape sh;
+  const long ty = (ny + 15) / 16;
+  if ((long)((nx + 63) / 64) * ty >= 512) {
+    sh.nc = 4;
+    sh.s = 1;
+  } else if ((long)((nx + 31) / 32) * ty >= 512) {
+    sh.nc = 2;
+    sh.s = 2;
+  } else {
+    sh.nc = 1;
+    sh.s = 8;
+  }
+  // rows per chunk: all 16 + k - 1 window rows if they fit the LDS budget
+  // (32 KB for the 4-wave large-image blocks, so that several stay resident;
+  // 64 KB otherwise), never fewer than 8
+  const int kp = conv_mfma_kp(k), xw = 16 * sh.nc + kp - 1, kw = kp + 1;
+  const long budget = (sh.nc == 4 ? 32768 : 65536) / (long)sizeof(float) - (sh.s > 1 ? 256L * sh.nc * sh.s : 0);
+  long t = (budget - 15L * kw) / (xw + kw);
+  const int nrows = 16 + k - 1;
+  if (t > nrows) t = nrows;
+  if (t < 8) t = 8;
+  sh.t = (int)t;
+  return sh;
 }
 
-// 16-wave blocks when the tiles alone would leave CUs short of waves and the
-// kernel has enough rows to share out.
-bool conv_wide_blocks(long tiles, int k) { return k >= 16 && tiles < 4L * 256; }
-
-size_t conv_direct_lds_bytes(int k) {
-  return sizeof(float) * (size_t)(kConvTY + conv_rows_per_chunk(k) - 1) * (size_t)(kConvTX + k - 1);
+size_t conv_lds_bytes(int k, const ConvShape& sh) {
+  const int kp = conv_mfma_kp(k);
+  const size_t xs = (size_t)sh.t * (16 * sh.nc + kp - 1);
+  const size_t ks = (size_t)(sh.t + 15) * (kp + 1);
+  const size_t part = sh.s > 1 ? (size_t)256 * sh.nc * sh.s : 0;
+  return sizeof(float) * (xs + ks + part);
 }
 
-// kFlip: correlate instead (the kernel read as psf[k-1-a][k-1-b]), which is the
-// adjoint of the convolution.  rb: kernel rows per staged chunk (the launch's
-// LDS holds (kConvTY + rb - 1) x (kConvTX + k - 1) floats).
-template <bool kFlip, int kW>
-__device__ __forceinline__ void conv_tile(const float* __restrict__ img, int nx, int ny, const float* __restrict__ psf,
-                                          int k, int rb, float* __restrict__ out, int tile_x, int tile_y, float* tile) {
-  static_assert(kW == 4 || kW == 16, "4 or 16 waves per block");
-  __shared__ float part[kW][kConvTY][kConvTX];
-  const int q = threadIdx.x % (kConvTX / kConvQ);
-  const int r = (threadIdx.x / (kConvTX / kConvQ)) % kConvTY;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);  // wave index, uniform
-  const int c = (k - 1) / 2;
-  const int j0 = tile_x * kConvTX, i0 = tile_y * kConvTY;
-  const int cols = kConvTX + k - 1;
-  const int colmin = j0 + c - (k - 1);
-  const int base = kConvQ * q;
-  float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
-  for (int a0 = 0; a0 < k; a0 += rb) {
-    const int ka = min(rb, k - a0);
-    const int rows = kConvTY + ka - 1;
-    const int rowmin = i0 + c - (a0 + ka - 1);
+template <bool kFlip, int NC, int S>
+__device__ __forceinline__ void conv_tile_mfma(const float* __restrict__ img, int nx, int ny,
+                                               const float* __restrict__ psf, int k, int T,
+                                               float* __restrict__ out, int tile_x, int tile_y, float* lds) {
+  constexpr int kThreads = 64 * NC * S;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int wc = w % NC, ws = w / NC;
+  const int c = (k - 1) / 2, kp = conv_mfma_kp(k);
+  const int XW = 16 * NC + kp - 1, KW = kp + 1;
+  float* xs = lds;                          // [T][XW]       input rows of the chunk
+  float* ks = lds + T * XW;                 // [T + 15][KW]  kernel rows they meet
+  float* part = ks + (T + 15) * KW;         // [NC S][256]   partial tiles (S > 1)
+  const int i0 = tile_y * 16, j0 = tile_x * 16 * NC;
+  const int colmin = j0 - (kp - 1) + c;
+  const int nrows = 16 + k - 1;
+  const int rows_per_wave = (T + S - 1) / S;
+  const int il = lane & 15, bb = lane >> 4;
+  jt_floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+  for (int t0 = 0; t0 < nrows; t0 += T) {
+    const int tn = min(T, nrows - t0);
+    const int amin = 2 * c - t0 - (T - 1);
     __syncthreads();
-    for (int e = threadIdx.x; e < rows * cols; e += blockDim.x) {
-      const int lr = e / cols, lc = e - lr * cols;
-      const int gi = rowmin + lr, gj = colmin + lc;
-      tile[e] = (gi >= 0 && gi < ny && gj >= 0 && gj < nx) ? img[gi * nx + gj] : 0.f;
-    }
-    __syncthreads();
-    for (int da = w; da < ka; da += kW) {
-      const int arow = a0 + da;
-      // input row i - a + c  ->  local row r + (ka - 1 - da); output 4q + t at
-      // kernel column b reads local column 4q + t + (k - 1 - b)
-      const float* trow = tile + (r + ka - 1 - da) * cols + base;
-      const float* __restrict__ wrow = kFlip ? psf + (k - 1 - arow) * k : psf + arow * k;
-      float x0 = trow[0], x1 = trow[1], x2 = trow[2];
-#pragma unroll 4
-      for (int m = 0; m < k; ++m) {
-        const float x3 = trow[m + 3];
-        const float wv = kFlip ? wrow[m] : wrow[k - 1 - m];
-        acc0 = fmaf(wv, x0, acc0);
-        acc1 = fmaf(wv, x1, acc1);
-        acc2 = fmaf(wv, x2, acc2);
-        acc3 = fmaf(wv, x3, acc3);
-        x0 = x1;
-        x1 = x2;
-        x2 = x3;
+    // wave w stages rows w, w + NC S, ...; its lanes the columns
+    for (int tt = w; tt < T; tt += NC * S) {
+      const int gi = i0 - c + t0 + tt;
+      const bool row_in = tt < tn && gi >= 0 && gi < ny;
+      for (int cc = lane; cc < XW; cc += 64) {
+        const int gj = colmin + cc;
+        xs[tt * XW + cc] = (row_in && gj >= 0 && gj < nx) ? img[(long)gi * nx + gj] : 0.f;
       }
     }
+    for (int rr = w; rr < T + 15; rr += NC * S) {
+      const int a = amin + rr;
+      const bool row_in = a >= 0 && a < k;
+      const float* prow = kFlip ? psf + (k - 1 - a) * k + (k - 1) : psf + a * k;
+      for (int b = lane; b < KW; b += 64)
+        ks[rr * KW + b] = (row_in && b < k) ? (kFlip ? prow[-b] : prow[b]) : 0.f;
+    }
+    __syncthreads();
+    const int tb = ws * rows_per_wave, te = min(tb + rows_per_wave, tn);
+    for (int tt = tb; tt < te; ++tt) {
+      // A[i][bb] = K[i + 2c - t][b0 + bb]: ks row i - tt + T - 1
+      const float* arow = ks + (il - tt + T - 1) * KW + bb;
+      // B[bb][j] = X[t][j - (b0 + bb) + c]: xs row tt, column 16 wc + j - b0 - bb + kp - 1
+      const float* brow = xs + tt * XW + 16 * wc + il - bb + kp - 1;
+      int b0 = 0;
+      for (; b0 + 8 <= kp; b0 += 8) {
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[b0], brow[-b0], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[b0 + 4], brow[-(b0 + 4)], acc1, 0, 0, 0);
+      }
+      if (b0 < kp) acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[b0], brow[-b0], acc0, 0, 0, 0);
+    }
   }
-  part[w][r][base] = acc0;
-  part[w][r][base + 1] = acc1;
-  part[w][r][base + 2] = acc2;
-  part[w][r][base + 3] = acc3;
-  __syncthreads();
-  // the first 256 threads cover the 64 x 4 outputs once
-  if (threadIdx.x >= kConvTX * kConvTY) return;
-  const int oc = threadIdx.x % kConvTX, orow = threadIdx.x / kConvTX;
-  float v = part[0][orow][oc];
+  jt_floatx4 acc = acc0 + acc1;
+  if (S > 1) {
 #pragma unroll
-  for (int u = 1; u < kW; ++u) v += part[u][orow][oc];
-  const int i = i0 + orow, j = j0 + oc;
-  if (i < ny && j < nx) out[i * nx + j] = v;
+    for (int v = 0; v < 4; ++v) part[w * 256 + v * 64 + lane] = acc[v];
+    __syncthreads();
+    if (ws != 0) return;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float sum = part[wc * 256 + v * 64 + lane];
+      for (int u = 1; u < S; ++u) sum += part[(u * NC + wc) * 256 + v * 64 + lane];
+      acc[v] = sum;
+    }
+  }
+  const int j = j0 + 16 * wc + il;
+  if (j < nx) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + 4 * bb + v;
+      if (i < ny) out[(long)i * nx + j] = acc[v];
+    }
+  }
 }
 
+
 // blockIdx.z selects an image of a batch (strided images, one PSF).
-template <bool kFlip, int kW>
-__global__ __launch_bounds__(kW * 64) void k_conv_direct(const float* __restrict__ img, long in_stride, int nx, int ny,
-                                                        const float* __restrict__ psf, int k, int rb,
-                                                        float* __restrict__ out, long out_stride) {
-  extern __shared__ float tile[];
-  conv_tile<kFlip, kW>(img + blockIdx.z * in_stride, nx, ny, psf, k, rb, out + blockIdx.z * out_stride, blockIdx.x,
-                       blockIdx.y, tile);
+template <bool kFlip, int NC, int S>
+__global__ __launch_bounds__(64 * NC * S) void k_conv_mfma(const float* __restrict__ img, long in_stride, int nx,
+                                                           int ny, const float* __restrict__ psf, int k, int T,
+                                                           float* __restrict__ out, long out_stride) {
+  extern __shared__ float lds[];
+  conv_tile_mfma<kFlip, NC, S>(img + blockIdx.z * in_stride, nx, ny, psf, k, T, out + blockIdx.z * out_stride,
+                               blockIdx.x, blockIdx.y, lds);
 }
 
 // Heterogeneous batch: block b convolves tile (tiles[b].y, tiles[b].z) of
-// image descs[tiles[b].x]; the dynamic LDS fits the batch's largest kernel.
-template <int kW>
-__global__ __launch_bounds__(kW * 64) void k_conv_desc(const ConvDesc* __restrict__ descs,
-                                                      const int4* __restrict__ tiles) {
-  extern __shared__ float tile[];
+// image descs[tiles[b].x]; every descriptor of the launch has this shape's
+// (NC, S), its own k and rows per chunk, and the dynamic LDS fits the largest.
+template <int NC, int S>
+__global__ __launch_bounds__(64 * NC * S) void k_conv_desc(const ConvDesc* __restrict__ descs,
+                                                           const int4* __restrict__ tiles) {
+  extern __shared__ float lds[];
   const int4 tl = tiles[blockIdx.x];
   const ConvDesc& d = descs[tl.x];
-  conv_tile<false, kW>(d.img, d.nx, d.ny, d.psf, d.k, d.rb, d.out, tl.y, tl.z, tile);
+  conv_tile_mfma<false, NC, S>(d.img, d.nx, d.ny, d.psf, d.k, d.t, d.out, tl.y, tl.z, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -525,35 +571,39 @@ hipError_t launch_conv_direct(const float* img, int nx, int ny, const float* psf
   return launch_conv_direct_batched(false, 1, img, 0, nx, ny, psf, k, out, 0, st);
 }
 
+int conv_shape_kind(const ConvShape& sh) { return sh.nc == 4 ? 0 : sh.nc == 2 ? 1 : 2; }
+int conv_tiles_x(int nx, const ConvShape& sh) { return (nx + 16 * sh.nc - 1) / (16 * sh.nc); }
+int conv_tiles_y(int ny) { return (ny + 15) / 16; }
+
 hipError_t launch_conv_direct_batched(bool flip, int batch, const float* img, long in_stride, int nx, int ny,
                                       const float* psf, int k, float* out, long out_stride, hipStream_t st) {
-  const dim3 grid((nx + kConvTX - 1) / kConvTX, (ny + kConvTY - 1) / kConvTY, batch);
-  const size_t lds = conv_direct_lds_bytes(k);
-  const int rb = conv_rows_per_chunk(k);
-  const bool wide = conv_wide_blocks((long)grid.x * grid.y * grid.z, k);
-#define JT_CONV(F, W) hipLaunchKernelGGL((k_conv_direct<F, W>), grid, dim3(W * 64), lds, st, img, in_stride, nx, ny, \
-                                         psf, k, rb, out, out_stride)
+  const ConvShape sh = conv_shape(nx, ny, k);
+  const dim3 grid(conv_tiles_x(nx, sh), conv_tiles_y(ny), batch);
+  const size_t lds = conv_lds_bytes(k, sh);
+#define JT_CM(F, N, S) hipLaunchKernelGGL((k_conv_mfma<F, N, S>), grid, dim3(64 * N * S), lds, st, img, in_stride, \
+                                          nx, ny, psf, k, sh.t, out, out_stride)
   if (flip) {
-    if (wide) JT_CONV(true, 16); else JT_CONV(true, 4);
+    if (sh.nc == 4) JT_CM(true, 4, 1); else if (sh.nc == 2) JT_CM(true, 2, 2); else JT_CM(true, 1, 8);
   } else {
-    if (wide) JT_CONV(false, 16); else JT_CONV(false, 4);
+    if (sh.nc == 4) JT_CM(false, 4, 1); else if (sh.nc == 2) JT_CM(false, 2, 2); else JT_CM(false, 1, 8);
   }
-#undef JT_CONV
+#undef JT_CM
   return hipGetLastError();
 }
 
-hipError_t launch_conv_desc(bool wide, const ConvDesc* descs, const int4* tiles, int ntiles, size_t lds,
+hipError_t launch_conv_desc(int kind, const ConvDesc* descs, const int4* tiles, int ntiles, size_t lds,
                             hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-  if (wide)
-    hipLaunchKernelGGL(k_conv_desc<16>, dim3((unsigned)ntiles), dim3(1024), lds, st, descs, tiles);
+  const dim3 grid((unsigned)ntiles);
+  if (kind == 0)
+    hipLaunchKernelGGL((k_conv_desc<4, 1>), grid, dim3(256), lds, st, descs, tiles);
+  else if (kind == 1)
+    hipLaunchKernelGGL((k_conv_desc<2, 2>), grid, dim3(256), lds, st, descs, tiles);
   else
-    hipLaunchKernelGGL(k_conv_desc<4>, dim3((unsigned)ntiles), dim3(256), lds, st, descs, tiles);
+    hipLaunchKernelGGL((k_conv_desc<1, 8>), grid, dim3(512), lds, st, descs, tiles);
   return hipGetLastError();
 }
 
-int conv_tiles_x(int nx) { return (nx + kConvTX - 1) / kConvTX; }
-int conv_tiles_y(int ny) { return (ny + kConvTY - 1) / kConvTY; }
 
 hipError_t launch_simulate_desc(int split, bool tnfw, bool extra, bool keep_beta, const ImageDesc* descs,
                                 const int2* tiles, int nblocks, int blocks_per_image, hipStream_t st) {

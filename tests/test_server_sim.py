@@ -228,9 +228,11 @@ def test_injected_failure_inside_a_chunked_request():
     the failure completed, the rest fail, and later submissions are refused."""
     from paper_2606_01547_amd import JtError
     from paper_2606_01547_amd._native import JT_EDEVICE
-    srv = _srv(max_batch_pairs=1e7, max_inflight_batches=3, n_streams=2, simulated_pairs_per_s=1e10)
+    # chunks of ~0.5 s, so that the three small requests are submitted well
+    # before the failing second chunk ends, even on a loaded host
+    srv = _srv(max_batch_pairs=1e7, max_inflight_batches=3, n_streams=2, simulated_pairs_per_s=2e9)
     srv.simulate_failure(2)
-    big = _submit(srv, _sc(1200, 3), nsub=2000)                        # 26 chunks of ~0.1 s + a convolution
+    big = _submit(srv, _sc(1200, 3), nsub=2000)                        # 26 chunks of ~0.5 s + a convolution
     small = [_submit(srv, _sc(), nsub=10) for _ in range(3)]
     with pytest.raises(JtError) as e:
         srv.wait(big, timeout=30.0)
