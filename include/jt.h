@@ -228,7 +228,7 @@ jt_status jt_simulate_image(jt_ctx* ctx, const jt_grid* grid, const jt_lens* len
  * whenever that call convolves directly (bit for bit); this one always
  * convolves directly, so a PSF larger than JT_MAX_PSF is JT_EUNSUPPORTED.
  * It calls no hipMalloc, hipFree or other allocating routine: the packed
- * subhalo table (16 B per NFW subhalo, 96 B per TNFW subhalo, rounded up to
+ * subhalo table (16 B per NFW subhalo, 80 B per TNFW subhalo, rounded up to
  * a multiple of 4 plus 4 padding records, 256-byte aligned; none with a
  * resident subhalo handle) and the unconvolved image (4 B per pixel, 256-byte
  * aligned; none without a PSF) live in one static device array of
@@ -429,7 +429,7 @@ typedef struct {
   size_t hbm_budget_bytes;   /* device arena for in-flight request buffers (> 0) */
   int max_batch_images;      /* requests per batch (>= 1) */
   double max_batch_pairs;    /* work cap per batch in (sub-pixel, subhalo) pairs (> 0;
-                                a truncated-NFW pair counts as 1.75, its measured cost);
+                                a truncated-NFW pair counts as 1.55, its measured cost);
                                 a larger request runs in chunks of its pixel blocks of
                                 at most this much work, one such request at a time,
                                 while later requests are batched beside it */

@@ -641,7 +641,7 @@ __device__ __forceinline__ void tnfw_h_dh(float X2, const TRec& r, float& h, flo
     oneF = (1.0f - F) * __builtin_amdgcn_rcpf(v);
   }
   const float is = __builtin_amdgcn_rcpf(s);
-  const float K = fmaf(r.t2 + 1.0f, oneF, fmaf(2.0f, F, -kPi * is)) - r.t2m1 * lp1 * r.itau * is;
+  const float K = fmaf(r.t2 + 1.0f, oneF, fmaf(2.0f, F, -kPi * is)) - (r.t2 - 1.0f) * lp1 * r.itau * is;
   dh = fmaf(0.5f * r.c2, K, -h) * __builtin_amdgcn_rcpf(X2);
 }
 

@@ -142,20 +142,20 @@ __host__ __device__ inline SubRec make_subrec(float x, float y, float rs, float 
 constexpr SubRec kSubRecPad{1e18f, 1e18f, 0.25f, 0.0f};
 
 // Truncated NFW record (Baltz, Marshall & Oguri 2009, truncation exponent 1):
-// centre, c1 = 1/Rs^2, c2 = alpha_Rs/((1 - ln 2) Rs) * tau^2/(tau^2 + 1)^2 and
-// tau = r_trunc/Rs with tau^2, tau^2 - 1, 1/tau, each rounded once from FP64;
-// then the far-field form: for x^2 = r^2 c1 >= Xf the pair term is
+// centre, c1 = 1/Rs^2, tau = r_trunc/Rs with tau^2 and 1/tau, and
+// c2 = alpha_Rs/((1 - ln 2) Rs) * tau^2/(tau^2 + 1)^2, each rounded once from
+// FP64; then the far-field form: for x^2 = r^2 c1 >= Xf the pair term is
 // c2 T(x) = y^2 sum_k a_k u^k, y = 1/x, u = y k1 - 1 (see tnfw_far_fit).
-constexpr int kTnfwFarDeg = 12;
+constexpr int kTnfwFarDeg = 10;
 // The first 32 bytes (what every pair and the general form read as scalar
 // operands of full-rate instructions, or only inside the general form) are
-// read through scalar loads; the last 64 (k1, c2 and the coefficients, FMA
+// read through scalar loads; the last 48 (k1 and the coefficients, FMA
 // operands of the far form) are staged through LDS.
 struct __align__(16) TRec {
-  float x, y, c1, Xf, tau, t2, t2m1, itau;
-  float k1, c2, a[kTnfwFarDeg + 1], pad;
+  float x, y, c1, Xf, tau, t2, itau, c2;
+  float k1, a[kTnfwFarDeg + 1];
 };
-static_assert(sizeof(TRec) == 96, "TRec is read as 8 scalar floats and four float4s");
+static_assert(sizeof(TRec) == 80, "TRec is read as 8 scalar floats and three float4s");
 
 struct ImageDesc {
   GridC g;               // g.ppb matches the launch's wave split
@@ -427,13 +427,14 @@ __host__ __device__ inline double tnfw_T64_far(double X2, double tau) {
 // in y = 1/x on [0, 1/x_f] (its nearest singularities are y = -1 and
 // y = +-i/tau), so the interpolant at kTnfwFarDeg + 1 Chebyshev points of that
 // interval, written as a polynomial in u = 2 y x_f - 1 in [-1, 1], matches it
-// to about 3e-9 relative for tau in [0.4, 1e4] (FP32 Horner evaluation: about
-// 1.1e-7).  The record stores Xf = x_f^2, k1 = 2 x_f and a_k = c2 (1 - 2
-// kRsqBias) m_k, m_k the interpolant's monomial coefficients (the factor
-// removes the mean bias of the hardware rsq that forms y^2).  The pair then
-// costs one reciprocal square root and a degree-12 polynomial instead of nine
-// transcendentals.  x_f = 0.75 tau (down from 1.5 tau with degree 8) leaves
-// about a third as many pairs to the general form for four more FMAs each.
+// to about 3e-8 relative for tau in [0.4, 1e4] (degree 12 would give 3e-9;
+// the FP32 Horner evaluation adds about 1e-7 either way).  The record stores
+// Xf = x_f^2, k1 = 2 x_f and a_k = c2 (1 - 2 kRsqBias) m_k, m_k the
+// interpolant's monomial coefficients (the factor removes the mean bias of the
+// hardware rsq that forms y^2).  The pair then costs one reciprocal square
+// root and a degree-10 polynomial instead of nine transcendentals.  x_f =
+// 0.75 tau (down from 1.5 tau with degree 8) leaves about a third as many
+// pairs to the general form for two more FMAs each.
 constexpr double kTnfwFarX = 0.75;
 constexpr double kTnfwFarMin = 1.5;
 __host__ __device__ inline void tnfw_far_fit(double tau, double c2, TRec& r) {
@@ -482,7 +483,6 @@ __host__ __device__ inline void tnfw_far_fit(double tau, double c2, TRec& r) {
   r.Xf = (float)(xf * xf);
   r.k1 = (float)(2.0 * xf);
   for (int i = 0; i < N; ++i) r.a[i] = (float)(scale * m[i]);
-  r.pad = 0.0f;
 }
 
 // The record of one truncated subhalo (c2 includes A; every value rounded
@@ -497,7 +497,6 @@ __host__ __device__ inline TRec make_trec(float x, float y, float rs, float ars,
   out.c2 = (float)c2;
   out.tau = (float)tau;
   out.t2 = (float)t2;
-  out.t2m1 = (float)(t2 - 1.0);
   out.itau = (float)(1.0 / tau);
   tnfw_far_fit(tau, c2, out);
   return out;
@@ -510,11 +509,9 @@ __host__ __device__ inline TRec trec_pad() {
   out.c1 = 1.0f;
   out.c2 = 0.0f;
   out.tau = out.t2 = out.itau = 1.0f;
-  out.t2m1 = 0.0f;
   out.Xf = 0.0f;
   out.k1 = 0.0f;
   for (int i = 0; i <= kTnfwFarDeg; ++i) out.a[i] = 0.0f;
-  out.pad = 0.0f;
   return out;
 }
 
@@ -595,7 +592,7 @@ __device__ __forceinline__ float tnfw_T_general(float X2, const TRec& r, float& 
   lp1 = d1 == 0.0f ? z1 : __builtin_amdgcn_logf(w1) * kLn2 * z1 * (rd * e2);
   const float lp2 = d2 == 0.0f ? z2 : __builtin_amdgcn_logf(w2) * kLn2 * z2 * (rd * e1);
   const float P1 = (g - lp2) * (ix * ix) - lp1 * r.itau * isp;
-  return fmaf(r.t2m1, P1, P2);
+  return fmaf(r.t2 - 1.0f, P1, P2);
 }
 
 // Far field of the truncated pair term (tnfw_far_fit), X2 >= r.Xf:

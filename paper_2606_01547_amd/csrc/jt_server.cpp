@@ -63,9 +63,9 @@ constexpr int kChunkMinBlocks = 2048;
 // run the request goes back to full chunks, two queued.
 constexpr int kChunkSharedBlocks = 1024;
 
-// A truncated-NFW pair costs about 1.75 NFW pairs of GPU time (headline image:
-// 2.31 ms against 1.33 ms); the work caps count it so.
-constexpr double kTnfwPairCost = 1.75;
+// A truncated-NFW pair costs about 1.55 NFW pairs of GPU time (headline image:
+// 2.08 ms against 1.33 ms); the work caps count it so.
+constexpr double kTnfwPairCost = 1.55;
 
 // Pinned host memory for the batches' descriptor uploads.  Each batch keeps its
 // own slice until it completes, so forming a batch never waits for a copy

@@ -86,22 +86,22 @@ __device__ __forceinline__ float4 subhalo_range_sum(float tx, float ty, const vo
   return make_float4(hx, lx, hy, ly);
 }
 
-// The truncated profile's 96-byte records: the first 32 bytes (centre, c1, Xf
-// and the general form's tau constants: scalar operands of full-rate
+// The truncated profile's 80-byte records: the first 32 bytes (centre, c1, Xf,
+// c2 and the general form's tau constants: scalar operands of full-rate
 // instructions, or used only in the general form) through scalar loads, one
-// record prefetched; the last 64 (k1, c2, the far field's 13 coefficients)
+// record prefetched; the last 48 (k1 and the far field's 11 coefficients)
 // through LDS, because an FMA reading a scalar register issues at half rate on
-// gfx950.  Each wave copies kStage records' 64-byte tails at a time into its
+// gfx950.  Each wave copies kStage records' 48-byte tails at a time into its
 // own LDS stage (coalesced 16-byte loads) and every lane then reads the current
 // tail at one address (a broadcast) into vector registers.  Same pairs, same
 // order, same arithmetic as an all-scalar read, so the same sums.  Must be
 // called by whole waves (every lane active; the copy is shared out by lane),
 // at most kWaves waves per block.
-constexpr int kTnfwTailQ = 4;   // float4s of a record's LDS tail
-static_assert(kTnfwFarDeg == 12 && sizeof(TRec) == (2 + kTnfwTailQ) * sizeof(float4), "TRec layout");
+constexpr int kTnfwTailQ = 3;   // float4s of a record's LDS tail
+static_assert(kTnfwFarDeg == 10 && sizeof(TRec) == (2 + kTnfwTailQ) * sizeof(float4), "TRec layout");
 
 __device__ __forceinline__ TRec tnfw_rec(const float (&h)[8], const float4* q) {
-  const float4 q2 = q[0], q3 = q[1], q4 = q[2], q5 = q[3];
+  const float4 q2 = q[0], q3 = q[1], q4 = q[2];
   TRec r;
   r.x = h[0];
   r.y = h[1];
@@ -109,24 +109,20 @@ __device__ __forceinline__ TRec tnfw_rec(const float (&h)[8], const float4* q) {
   r.Xf = h[3];
   r.tau = h[4];
   r.t2 = h[5];
-  r.t2m1 = h[6];
-  r.itau = h[7];
+  r.itau = h[6];
+  r.c2 = h[7];
   r.k1 = q2.x;
-  r.c2 = q2.y;
-  r.a[0] = q2.z;
-  r.a[1] = q2.w;
-  r.a[2] = q3.x;
-  r.a[3] = q3.y;
-  r.a[4] = q3.z;
-  r.a[5] = q3.w;
-  r.a[6] = q4.x;
-  r.a[7] = q4.y;
-  r.a[8] = q4.z;
-  r.a[9] = q4.w;
-  r.a[10] = q5.x;
-  r.a[11] = q5.y;
-  r.a[12] = q5.z;
-  r.pad = 0.0f;
+  r.a[0] = q2.y;
+  r.a[1] = q2.z;
+  r.a[2] = q2.w;
+  r.a[3] = q3.x;
+  r.a[4] = q3.y;
+  r.a[5] = q3.z;
+  r.a[6] = q3.w;
+  r.a[7] = q4.x;
+  r.a[8] = q4.y;
+  r.a[9] = q4.z;
+  r.a[10] = q4.w;
   return r;
 }
 

@@ -10,7 +10,7 @@
 // Subhalo records are read with wave-uniform indices from a read-only table, so
 // the 16-byte NFW records arrive through scalar loads into SGPRs and feed the
 // VALU as scalar operands (they enter only subtractions and multiplies, which
-// issue at full rate with one); the 96-byte truncated-NFW records, whose
+// issue at full rate with one); the 80-byte truncated-NFW records, whose
 // polynomial coefficients are FMA operands, are staged through LDS per wave
 // instead.  Every lane runs the same subhalo at its own sub-pixel.  The
 // per-sub-pixel subhalo sum is formed tile by tile: a tile of kSubTile pairs is

@@ -465,6 +465,41 @@ def test_convolve_large_image_both_paths(ctx):
     assert np.array_equal(auto, direct) or np.array_equal(auto, fft)
 
 
+def _conv_shape_kind(nx, ny):
+    """The direct path's launch shape for an nx x ny image: 0 = four 16-column
+    groups per block (>= 512 such blocks), 1 = two groups with two waves each
+    (>= 512 such blocks), 2 = one group split over eight waves."""
+    ty = (ny + 15) // 16
+    if (nx + 63) // 64 * ty >= 512:
+        return 0
+    return 1 if (nx + 31) // 32 * ty >= 512 else 2
+
+
+@pytest.mark.parametrize("nx,ny,k,kind", [(1024, 512, 21, 0), (1024, 496, 21, 1), (512, 512, 41, 1),
+                                          (512, 496, 41, 2), (1000, 517, 255, 0), (1003, 301, 129, 1),
+                                          (1000, 517, 3, 0)])
+def test_convolve_direct_every_launch_shape(ctx, nx, ny, k, kind):
+    """Each of the direct path's three launch shapes, on both sides of the
+    tile counts that select them, with ragged edges, and with kernels whose
+    window needs several LDS-staged row chunks (k = 255 on the four-group
+    shape stages only 8 input rows at a time): 2000 sampled pixels (corners
+    and every border included) against the oracle one pixel at a time."""
+    assert _conv_shape_kind(nx, ny) == kind
+    rng = np.random.default_rng(nx + 7 * ny + k)
+    img = rng.uniform(-0.5, 1.0, (ny, nx)).astype(np.float32)
+    psf = rng.uniform(0, 1, (k, k))
+    psf[0, :] *= 3.0
+    psf[:, -1] *= 2.0
+    psf = (psf / psf.sum()).astype(np.float32)
+    m = 1600
+    rows = np.concatenate([rng.integers(0, ny, m), [0, 0, ny - 1, ny - 1], rng.integers(0, ny, 98),
+                           np.zeros(98, int), np.full(100, ny - 1)])
+    cols = np.concatenate([rng.integers(0, nx, m), [0, nx - 1, 0, nx - 1], np.zeros(98, int),
+                           rng.integers(0, nx, 98), rng.integers(0, nx, 100)])
+    got = _np(ctx.convolve(img, psf, method=1))
+    assert image_error(got[rows, cols], O.convolve_at(img, psf, rows, cols)) <= (2e-5 if k <= 41 else IMAGE_TOL)
+
+
 def test_convolve_fft_size_limit(ctx):
     from paper_2606_01547_amd import JtError
     img = np.ones((1, 2000), np.float32)

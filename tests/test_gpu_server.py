@@ -1,6 +1,6 @@
 """The continuous-batching server on the GPU: every request's image is
 bitwise the same as the same request simulated alone (fixed summation order;
-each convolution takes the block width and kernel-row chunk the image alone
+each convolution takes the launch shape and LDS row chunk the image alone
 would get), and matches the oracle; requests of very different sizes share
 launches and streams.  jt_simulate_image may pick the FFT convolution for
 large images with large kernels, where the server convolves directly: those
@@ -99,18 +99,21 @@ def _assert_direct(scenes):
 
 
 def test_mixed_psf_batch_equals_single_requests(ctx):
-    """An 11x11, a 21x21 and a 41x41 PSF request and two 400x400 ones share one
-    batch: together they pass the tile count at which a lone image switches
-    from 16-wave to 4-wave convolution blocks, and their kernels need
-    different row chunks; every image is still the request alone bit for bit.
-    A long first request on the single in-flight slot makes the rest queue
-    and launch together."""
+    """An 11x11, a 21x21 and a 41x41 PSF request, two 400x400 ones, a 500x500
+    and a 1000x1000 one share one batch: their convolutions take all three
+    launch shapes of the direct path (one 16-column group split over eight
+    waves, two groups of two waves, four groups of one wave; the server
+    launches each shape's tiles together) and different LDS row chunks; every
+    image is still the request alone bit for bit.  A long first request on
+    the single in-flight slot makes the rest queue and launch together."""
     first = W.config2_scene(seed=51, n_sub=20000, npix=400, supersample=3, psf_size=21)
     rest = [W.config2_scene(seed=52, n_sub=100, npix=64, supersample=1, psf_size=11),
             W.config2_scene(seed=53, n_sub=300, npix=100, supersample=3, psf_size=21),
             W.config2_scene(seed=54, n_sub=200, npix=400, supersample=1, psf_size=21),
             W.config2_scene(seed=55, n_sub=50, npix=400, supersample=1, psf_size=21),
-            W.config2_scene(seed=56, n_sub=500, npix=200, supersample=1, psf_size=41)]
+            W.config2_scene(seed=56, n_sub=500, npix=200, supersample=1, psf_size=41),
+            W.config2_scene(seed=57, n_sub=50, npix=500, supersample=1, psf_size=21),
+            W.config2_scene(seed=58, n_sub=30, npix=1000, supersample=1, psf_size=11)]
     scenes = [first] + rest
     _assert_direct(scenes)
     from paper_2606_01547_amd import Server
@@ -131,7 +134,7 @@ def test_mixed_psf_batch_equals_single_requests(ctx):
     for h in hs + hp:
         ctx.release(h)
     assert st["completed"] == len(scenes) and st["failed"] == 0
-    assert st["batches"] == 2, st                     # the long request, then the other five at once
+    assert st["batches"] == 2, st                     # the long request, then the other seven at once
     for sc, o in zip(scenes, outs):
         np.testing.assert_array_equal(_np(o), _np(ctx.simulate_scene(sc)))
     assert image_error(_np(outs[1]), O.simulate_image(rest[0])) <= IMAGE_TOL

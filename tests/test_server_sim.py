@@ -233,7 +233,12 @@ def test_injected_failure_inside_a_chunked_request():
     srv = _srv(max_batch_pairs=1e7, max_inflight_batches=3, n_streams=2, simulated_pairs_per_s=2e9)
     srv.simulate_failure(2)
     big = _submit(srv, _sc(1200, 3), nsub=2000)                        # 26 chunks of ~0.5 s + a convolution
-    small = [_submit(srv, _sc(), nsub=10) for _ in range(3)]
+    small = []
+    for sc in [_sc() for _ in range(3)]:
+        try:
+            small.append(_submit(srv, sc, nsub=10))
+        except JtError as e:      # only if this thread stalled past the failure (a loaded host)
+            assert e.status == JT_EDEVICE
     with pytest.raises(JtError) as e:
         srv.wait(big, timeout=30.0)
     assert e.value.status == JT_EDEVICE
