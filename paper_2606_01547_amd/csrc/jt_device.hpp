@@ -406,7 +406,7 @@ __device__ __forceinline__ float atan_pos(float z, float iz) {
 }
 
 // FP64 T(x) = G(x, tau) / (A x^2) = (tau^2 - 1) P1 + P2 of the truncated
-// profile (A = tau^2/(tau^2 + 1)^2, the regrouping of tnfw_pair below) for
+// profile (A = tau^2/(tau^2 + 1)^2, the regrouping of tnfw_T_general below) for
 // X2 = x^2 >= 1.2, the form without cancelling differences.
 __host__ __device__ inline double tnfw_T64_far(double X2, double tau) {
   constexpr double kPiD = 3.14159265358979323846;
@@ -606,21 +606,32 @@ __device__ __forceinline__ float tnfw_far_h(float X2, const TRec& r) {
   return p * (yy * yy);
 }
 
-// The far form is evaluated by every lane, without a branch (a wave's lanes
-// are neighbouring sub-pixels, nearly always all far), and replaced where
-// X2 < Xf: one exec-masked region per pair instead of an if/else, which cost
-// more scalar instructions and branches than the far form's arithmetic.  A
-// pair at the centre itself (X2 <= 1e-30) adds 0.
-__device__ __forceinline__ void tnfw_pair(float tx, float ty, const TRec& r, float& sx, float& sy) {
-  const float dx = tx - r.x, dy = ty - r.y;
-  const float X2 = fmaf(dy, dy, dx * dx) * r.c1;
-  float h = tnfw_far_h(X2, r);
-  if (X2 < r.Xf) {
+// Pair terms of two consecutive truncated-subhalo records a, b at one
+// sub-pixel, added to (sx, sy) in that order.  The far form is evaluated by
+// every lane, without a branch (a wave's lanes are neighbouring sub-pixels,
+// nearly always all far), and replaced where X2 < Xf; a pair at the centre
+// itself (X2 <= 1e-30) adds 0.  One exec-masked region covers both records'
+// general forms: an if/else per pair cost more scalar instructions and
+// branches than the far form's arithmetic, and a region per pair twice the
+// mask instructions of this one.
+__device__ __forceinline__ void tnfw_pair2(float tx, float ty, const TRec& a, const TRec& b, float& sx,
+                                           float& sy) {
+  const float dxa = tx - a.x, dya = ty - a.y;
+  const float dxb = tx - b.x, dyb = ty - b.y;
+  const float Xa = fmaf(dya, dya, dxa * dxa) * a.c1;
+  const float Xb = fmaf(dyb, dyb, dxb * dxb) * b.c1;
+  float ha = tnfw_far_h(Xa, a);
+  float hb = tnfw_far_h(Xb, b);
+  const bool na = Xa < a.Xf, nb = Xb < b.Xf;
+  if (na || nb) {
     float F, s, lp1;
-    h = X2 > 1e-30f ? r.c2 * tnfw_T_general(X2, r, F, s, lp1) : 0.0f;
+    if (na) ha = Xa > 1e-30f ? a.c2 * tnfw_T_general(Xa, a, F, s, lp1) : 0.0f;
+    if (nb) hb = Xb > 1e-30f ? b.c2 * tnfw_T_general(Xb, b, F, s, lp1) : 0.0f;
   }
-  sx = fmaf(h, dx, sx);
-  sy = fmaf(h, dy, sy);
+  sx = fmaf(ha, dxa, sx);
+  sy = fmaf(ha, dya, sy);
+  sx = fmaf(hb, dxb, sx);
+  sy = fmaf(hb, dyb, sy);
 }
 
 // Knuth's TwoSum: s + e == a + b exactly.

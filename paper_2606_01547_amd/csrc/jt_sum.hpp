@@ -88,15 +88,16 @@ __device__ __forceinline__ float4 subhalo_range_sum(float tx, float ty, const vo
 
 // The truncated profile's 80-byte records: the first 32 bytes (centre, c1, Xf,
 // c2 and the general form's tau constants: scalar operands of full-rate
-// instructions, or used only in the general form) through scalar loads, one
-// record prefetched; the last 48 (k1 and the far field's 11 coefficients)
-// through LDS, because an FMA reading a scalar register issues at half rate on
-// gfx950.  Each wave copies kStage records' 48-byte tails at a time into its
-// own LDS stage (coalesced 16-byte loads) and every lane then reads the current
-// tail at one address (a broadcast) into vector registers.  Same pairs, same
-// order, same arithmetic as an all-scalar read, so the same sums.  Must be
-// called by whole waves (every lane active; the copy is shared out by lane),
-// at most kWaves waves per block.
+// instructions, or used only in the general form) through scalar loads; the
+// last 48 (k1 and the far field's 11 coefficients) through LDS, because an FMA
+// reading a scalar register issues at half rate on gfx950.  Each wave copies
+// kStage records' 48-byte tails at a time into its own LDS stage (coalesced
+// 16-byte loads) and every lane then reads the current tails at one address (a
+// broadcast) into vector registers.  Records go two per step (tnfw_pair2), the
+// next step's heads loaded while this one computes.  Same pairs, same order,
+// same arithmetic as one record at a time from scalar registers, so the same
+// sums.  Must be called by whole waves (every lane active; the copy is shared
+// out by lane), at most kWaves waves per block.
 constexpr int kTnfwTailQ = 3;   // float4s of a record's LDS tail
 static_assert(kTnfwFarDeg == 10 && sizeof(TRec) == (2 + kTnfwTailQ) * sizeof(float4), "TRec layout");
 
@@ -126,6 +127,17 @@ __device__ __forceinline__ TRec tnfw_rec(const float (&h)[8], const float4* q) {
   return r;
 }
 
+// Waits for a step's LDS tail reads before the next step's heads are
+// requested: LDS reads and scalar loads count on one counter and scalar loads
+// may return out of order, so with the loads issued first the wait for the
+// tails would cover the loads as well and the prefetch would gain nothing.
+// lgkmcnt(0) with the vector-memory and export counts left open, then a
+// scheduling barrier so that the loads are not moved above the wait.
+__device__ __forceinline__ void tail_wait() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_sched_barrier(0);
+}
+
 template <int kWaves, int kStage>
 __device__ __forceinline__ float4 tnfw_range_sum(float tx, float ty, const void* table, int kb, int ke) {
   __shared__ float4 stage[kWaves][kStage * kTnfwTailQ];
@@ -139,8 +151,11 @@ __device__ __forceinline__ float4 tnfw_range_sum(float tx, float ty, const void*
     for (int i = 0; i < 8; ++i) h[i] = sub[kF * k + i];
   };
   float hx = 0.f, lx = 0.f, hy = 0.f, ly = 0.f;
-  float nh[8];
-  head(kb, nh);
+  // heads of the next two records, loaded a step ahead (the table has readable
+  // records past every range end)
+  float ha[8], hb[8];
+  head(kb, ha);
+  head(kb + 1, hb);
   for (int k0 = kb; k0 < ke; k0 += kSubTile) {
     const int kend = min(k0 + kSubTile, ke);
     float px = 0.f, py = 0.f;
@@ -158,12 +173,24 @@ __device__ __forceinline__ float4 tnfw_range_sum(float tx, float ty, const void*
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int k = 0; k < m; ++k) {
-        float h[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) h[i] = nh[i];
-        head(s0 + k + 1, nh);   // the table has a readable record past every range end
-        tnfw_pair(tx, ty, tnfw_rec(h, st + kTnfwTailQ * k), px, py);
+      // two records per step (m is a multiple of 4: range bounds, tiles and
+      // stages all are)
+      for (int k = 0; k < m; k += 4) {
+        float hc[8], hd[8];
+        {
+          const TRec ra = tnfw_rec(ha, st + kTnfwTailQ * k), rb = tnfw_rec(hb, st + kTnfwTailQ * (k + 1));
+          tail_wait();
+          head(s0 + k + 2, hc);
+          head(s0 + k + 3, hd);
+          tnfw_pair2(tx, ty, ra, rb, px, py);
+        }
+        {
+          const TRec rc = tnfw_rec(hc, st + kTnfwTailQ * (k + 2)), rd = tnfw_rec(hd, st + kTnfwTailQ * (k + 3));
+          tail_wait();
+          head(s0 + k + 4, ha);
+          head(s0 + k + 5, hb);
+          tnfw_pair2(tx, ty, rc, rd, px, py);
+        }
       }
     }
     two_sum_acc(hx, lx, px);
