@@ -13,6 +13,8 @@
 //   block                                             k_grad_pixel
 //   subhalo (x, y, alpha_Rs) gradients: a subhalo-major pass over the
 //   sub-pixel records (theta, G)                      k_grad_subhalo
+//   (truncated subhalos: the far pairs so, the near
+//   pairs by a wave per subhalo over its box)         k_grad_subhalo_tnfw(_near)
 //   fixed-order sums of the partials                  k_grad_finalize
 // Every sum has a fixed order (no atomics), so gradients are reproducible.
 #include "jt_device.hpp"
@@ -590,18 +592,9 @@ __global__ __launch_bounds__(kSubhaloBlock) void k_grad_subhalo(const float* __r
 // h = c2 T(x) and dh = dh/d(X2) of the truncated pair term for the record r
 // (X2 = x^2 = r^2 c1).  Far field (X2 >= Xf, the record's polynomial
 // W(u) = sum a_k u^k, u = y k1 - 1, y = 1/x): h = y^2 W and, with
-// dy/dX2 = -y^3/2, dh = -y^4 (W + (k1 y / 2) W'(u)).  Otherwise the general
-// form, and from the projected mass's derivative -- the surface density of
-// the truncated profile (Baltz, Marshall & Oguri 2009) --
-//   dG/dX2 = (A/2) K,  K = (tau^2 + 1)(1 - F)/(x^2 - 1) + 2F - pi/s
-//                          + (tau^2 - 1) L/(tau s),  L = ln(x/(s + tau)),
-// dh = (c2 K/2 - h)/X2 (c2 carries A).  (1 - F)/(x^2 - 1) is the series
-// 1/3 - v/5 + v^2/7 - ... in v = x^2 - 1 near x = 1.  0 at the centre.
-__device__ __forceinline__ void tnfw_h_dh(float X2, const TRec& r, float& h, float& dh) {
-  constexpr float kPi = 3.14159265358979323846f;
+// dy/dX2 = -y^3/2, dh = -y^4 (W + (k1 y / 2) W'(u)).
+__device__ __forceinline__ void tnfw_h_dh_far(float X2, const TRec& r, float& h, float& dh) {
   {
-    // the far form for every lane, replaced below where X2 < Xf (one
-    // exec-masked region instead of an if/else)
     const float y = __builtin_amdgcn_rsqf(X2);
     const float u = fmaf(y, r.k1, -1.0f);
     float p = r.a[kTnfwFarDeg], dp = 0.f;
@@ -614,7 +607,17 @@ __device__ __forceinline__ void tnfw_h_dh(float X2, const TRec& r, float& h, flo
     h = p * y2;
     dh = -(y2 * y2) * fmaf(0.5f * r.k1 * y, dp, p);
   }
-  if (!(X2 < r.Xf)) return;
+}
+
+// The same for X2 < Xf: the general form, and from the projected mass's
+// derivative -- the surface density of the truncated profile (Baltz, Marshall
+// & Oguri 2009) --
+//   dG/dX2 = (A/2) K,  K = (tau^2 + 1)(1 - F)/(x^2 - 1) + 2F - pi/s
+//                          + (tau^2 - 1) L/(tau s),  L = ln(x/(s + tau)),
+// dh = (c2 K/2 - h)/X2 (c2 carries A).  (1 - F)/(x^2 - 1) is the series
+// 1/3 - v/5 + v^2/7 - ... in v = x^2 - 1 near x = 1.  0 at the centre.
+__device__ __forceinline__ void tnfw_h_dh_near(float X2, const TRec& r, float& h, float& dh) {
+  constexpr float kPi = 3.14159265358979323846f;
   if (!(X2 > 1e-30f)) {
     h = 0.f;
     dh = 0.f;
@@ -645,72 +648,24 @@ __device__ __forceinline__ void tnfw_h_dh(float X2, const TRec& r, float& h, flo
   dh = fmaf(0.5f * r.c2, K, -h) * __builtin_amdgcn_rcpf(X2);
 }
 
-// Lane order of the truncated subhalos in the subhalo-major pass.  A pair
-// takes the general (non-polynomial) form within rho = Xf^(1/2) Rs of the
-// subhalo, and a wave pays for that form whenever any of its lanes needs it.
-// Lanes are therefore grouped by rho (bins of a factor 4 in rho^2, largest
-// first) and, within a bin, by position (a Morton code on a 1/8" grid over
-// +-64"), so that the lanes of a wave need the general form for the same
-// sub-pixels.  The order only decides which lane holds which subhalo: every
-// subhalo's sums are the same whatever it is.  key = (bin, Morton code, k),
-// unique; t0: the first draw's table.
-__device__ __forceinline__ unsigned spread_bits10(unsigned v) {
-  v &= 1023u;
-  v = (v | (v << 8)) & 0x00FF00FFu;
-  v = (v | (v << 4)) & 0x0F0F0F0Fu;
-  v = (v | (v << 2)) & 0x33333333u;
-  v = (v | (v << 1)) & 0x55555555u;
-  return v;
-}
-
-__global__ __launch_bounds__(256) void k_tnfw_lane_keys(const TRec* __restrict__ t0, int n,
-                                                        unsigned long long* __restrict__ keys) {
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k >= n) return;
-  const TRec r = t0[k];
-  const float rho2 = r.Xf / r.c1;   // squared radius of the general form, arcsec^2
-  const int bin = min(max((int)floorf(__builtin_amdgcn_logf(rho2) * 0.25f) + 32, 0), 63);
-  const auto cell = [](float v) { return (unsigned)min(max((v + 64.0f) * 8.0f, 0.0f), 1023.0f); };
-  const unsigned code = (spread_bits10(cell(r.y)) << 1) | spread_bits10(cell(r.x));
-  keys[k] = ((unsigned long long)(63 - bin) << 52) | ((unsigned long long)code << 32) | (unsigned)k;
-}
-
-// perm[rank of keys[i]] = i: each thread counts the smaller keys, read in
-// tiles through LDS (n^2 comparisons; n is the subhalo count of one draw).
-__global__ __launch_bounds__(256) void k_rank_perm(const unsigned long long* __restrict__ keys, int n,
-                                                   int* __restrict__ perm) {
-  __shared__ unsigned long long tile[256];
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  const unsigned long long mine = i < n ? keys[i] : ~0ull;
-  int rank = 0;
-  for (int j0 = 0; j0 < n; j0 += 256) {
-    __syncthreads();
-    tile[threadIdx.x] = j0 + (int)threadIdx.x < n ? keys[j0 + threadIdx.x] : ~0ull;
-    __syncthreads();
-    const int m = min(256, n - j0);
-    for (int j = 0; j < m; ++j) rank += tile[j] < mine;
-  }
-  if (i < n) perm[rank] = i;
-}
-
-// The subhalo-major pass for truncated subhalos: as k_grad_subhalo, with each
-// lane's record read from the draw's table built for alpha_Rs = 1 (utab
-// [B][records]), so that the sums are per unit alpha_Rs: d log L/d(x, y) is
-// alpha_Rs times them and d log L/d alpha_Rs is minus the h G.d sum.  Lane l
-// holds subhalo perm[l] (k_tnfw_lane_keys).
+// The subhalo-major pass for truncated subhalos, far pairs: as k_grad_subhalo,
+// with each lane's record read from the draw's table built for alpha_Rs = 1
+// (utab [B][records]), so that the sums are per unit alpha_Rs: d log L/d(x, y)
+// is alpha_Rs times them and d log L/d alpha_Rs is minus the h G.d sum.  Every
+// lane evaluates the far form, and pairs with X2 < Xf add zero here: the lanes
+// of a wave are different subhalos, so a general form evaluated here would run
+// for the whole wave wherever any of its 64 subhalos is near, and
+// k_grad_subhalo_tnfw_near takes those pairs instead.
 __global__ __launch_bounds__(kSubhaloBlock) void k_grad_subhalo_tnfw(const TRec* __restrict__ utab, int records,
-                                                                    const int* __restrict__ perm,
                                                                     const float* __restrict__ sub_ars,
                                                                     const float4* __restrict__ rec, int rec_stride,
                                                                     int nrec_loop, int n, float* __restrict__ gpart) {
   const int b = blockIdx.y, q = blockIdx.z, B = gridDim.y;
-  // the lane block rotates with the draw and the part: consecutive blocks go
-  // to different XCDs, and without the rotation the costliest lane block
-  // (largest rho) of every draw would land on the same two of them
+  // the lane block rotates with the draw and the part, so that consecutive
+  // blocks of a draw spread over the XCDs
   const int xb = (int)((blockIdx.x + blockIdx.y + blockIdx.z) % gridDim.x);
-  const int l = xb * kSubhaloBlock + threadIdx.x;
-  const bool valid = l < n;
-  const int k = valid ? perm[l] : 0;
+  const int k = xb * kSubhaloBlock + threadIdx.x;
+  const bool valid = k < n;
   const TRec R = utab[(size_t)b * records + (valid ? k : 0)];
   const float c1x2 = 2.0f * R.c1;
   const float4* __restrict__ r = rec + (size_t)b * rec_stride;
@@ -724,7 +679,10 @@ __global__ __launch_bounds__(kSubhaloBlock) void k_grad_subhalo_tnfw(const TRec*
       const float dx = rr.x - R.x, dy = rr.y - R.y;
       const float X2 = fmaf(dy, dy, dx * dx) * R.c1;
       float h, dh;
-      tnfw_h_dh(X2, R, h, dh);
+      tnfw_h_dh_far(X2, R, h, dh);
+      const bool far = !(X2 < R.Xf);
+      h = far ? h : 0.0f;
+      dh = far ? dh : 0.0f;
       const float GD = fmaf(rr.z, dx, rr.w * dy);
       const float e = c1x2 * dh * GD;
       px = fmaf(e, dx, fmaf(h, rr.z, px));
@@ -741,6 +699,71 @@ __global__ __launch_bounds__(kSubhaloBlock) void k_grad_subhalo_tnfw(const TRec*
     o[0] = ars * (hx + lx);
     o[1] = ars * (hy + ly);
     o[2] = -(ha + la);
+  }
+}
+
+// The near pairs of the truncated subhalos (X2 < Xf, within
+// rho = (Xf / c1)^(1/2) of the centre), which the far pass leaves out: one
+// wave per (subhalo k, draw b) visits the box of the sub-pixel grid around the
+// centre (rho widened by 0.1% and two sub-pixels, so that no pair the X2 test
+// admits lies outside it), lane l the box cells l, l + 64, ...; the same X2
+// test as the far pass decides each pair, so every pair is counted by exactly
+// one of the two passes, and the lanes of a wave run the general form
+// together.  The lane sums are added in a fixed butterfly order and written as
+// part kRecPartsTnfw of gpart.  rec holds the sub-pixel records
+// [b][pixel * s^2 + sub-pixel]; g is the draws' common grid.
+__global__ __launch_bounds__(64) void k_grad_subhalo_tnfw_near(const TRec* __restrict__ utab, int records,
+                                                              const float* __restrict__ sub_ars,
+                                                              const float4* __restrict__ rec, int rec_stride, GridC g,
+                                                              int n, float* __restrict__ gpart) {
+  const int k = blockIdx.x, b = blockIdx.y, B = gridDim.y;
+  const int lane = threadIdx.x;
+  const TRec R = utab[(size_t)b * records + k];
+  const int W = g.nx * g.s, H = g.ny * g.s;
+  const double is = 1.0 / g.step;
+  const double rho = sqrt((double)R.Xf / (double)R.c1) * 1.001 + 2.0 * g.step;
+  // sub-pixel column c sits at ox + step (c + 1/2); clamp in FP64 before the
+  // conversion to int, so that a far-away centre cannot overflow it
+  auto lo = [&](double c, double o, int m) {
+    return (int)fmin(fmax(ceil((c - rho - o) * is - 0.5), 0.0), (double)m);
+  };
+  auto hi = [&](double c, double o, int m) {
+    return (int)fmin(fmax(floor((c + rho - o) * is - 0.5), -1.0), (double)(m - 1));
+  };
+  const int cx0 = lo(R.x, g.ox, W), cx1 = hi(R.x, g.ox, W);
+  const int cy0 = lo(R.y, g.oy, H), cy1 = hi(R.y, g.oy, H);
+  const int bw = cx1 - cx0 + 1, bh = cy1 - cy0 + 1;
+  const int cells = bw > 0 && bh > 0 ? bw * bh : 0;
+  const float4* __restrict__ r = rec + (size_t)b * rec_stride;
+  const float c1x2 = 2.0f * R.c1;
+  float px = 0.f, py = 0.f, pa = 0.f;
+  for (int i = lane; i < cells; i += 64) {
+    const int iy = i / bw;
+    const int cy = cy0 + iy, cx = cx0 + (i - iy * bw);
+    const int row = cy / g.s, col = cx / g.s;
+    const int si = (cy - row * g.s) * g.s + (cx - col * g.s);
+    const float4 rr = r[((size_t)row * g.nx + col) * g.s2 + si];
+    const float dx = rr.x - R.x, dy = rr.y - R.y;
+    const float X2 = fmaf(dy, dy, dx * dx) * R.c1;
+    if (X2 < R.Xf) {
+      float h, dh;
+      tnfw_h_dh_near(X2, R, h, dh);
+      const float GD = fmaf(rr.z, dx, rr.w * dy);
+      const float e = c1x2 * dh * GD;
+      px = fmaf(e, dx, fmaf(h, rr.z, px));
+      py = fmaf(e, dy, fmaf(h, rr.w, py));
+      pa = fmaf(h, GD, pa);
+    }
+  }
+  px = wave_sum(px);
+  py = wave_sum(py);
+  pa = wave_sum(pa);
+  if (lane == 0) {
+    const float ars = sub_ars[(size_t)b * n + k];
+    float* o = gpart + (((size_t)kRecPartsTnfw * B + b) * n + k) * 3;
+    o[0] = ars * px;
+    o[1] = ars * py;
+    o[2] = -pa;
   }
 }
 
@@ -819,14 +842,13 @@ hipError_t launch_grad_subhalo(int B, int n, const float* x, const float* y, con
 }
 
 hipError_t launch_grad_subhalo_tnfw(int B, int n, const TRec* utab, int records, const float* ars,
-                                    const float4* rec, int rec_stride, int nrec_loop, unsigned long long* keys,
-                                    int* perm, float* gpart, hipStream_t st) {
+                                    const float4* rec, int rec_stride, int nrec_loop, const GridC& g, float* gpart,
+                                    hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  const dim3 g1((n + 255) / 256);
-  hipLaunchKernelGGL(k_tnfw_lane_keys, g1, dim3(256), 0, st, utab, n, keys);
-  hipLaunchKernelGGL(k_rank_perm, g1, dim3(256), 0, st, keys, n, perm);
   hipLaunchKernelGGL(k_grad_subhalo_tnfw, dim3((n + kSubhaloBlock - 1) / kSubhaloBlock, B, kRecPartsTnfw),
-                     dim3(kSubhaloBlock), 0, st, utab, records, perm, ars, rec, rec_stride, nrec_loop, n, gpart);
+                     dim3(kSubhaloBlock), 0, st, utab, records, ars, rec, rec_stride, nrec_loop, n, gpart);
+  hipLaunchKernelGGL(k_grad_subhalo_tnfw_near, dim3(n, B), dim3(64), 0, st, utab, records, ars, rec, rec_stride, g,
+                     n, gpart);
   return hipGetLastError();
 }
 

@@ -175,7 +175,7 @@ jt_status chi2_common(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, c
   const int nres = (bt.npix + 255) / 256;
   const int nrec_loop = (bt.nsubpix + 3) & ~3;
   const int rec_stride = nrec_loop + 4;
-  const int rec_parts = bt.tnfw ? kRecPartsTnfwHost : kRecPartsHost;
+  const int rec_parts = bt.tnfw ? kRecPartsTnfwHost + 1 : kRecPartsHost;   // + the truncated near pass
   size_t bytes = align256(sizeof(ImageDesc) * bt.B) + align256(bt.rec_bytes * (size_t)bt.B * bt.records) +
                  3 * align256(sizeof(float) * BN) + align256(sizeof(float) * (size_t)bt.B * nres);
   if (grad)
@@ -183,9 +183,7 @@ jt_status chi2_common(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, c
              align256(sizeof(float) * (size_t)bt.B * bt.bpi * bt.P) +
              align256(sizeof(float) * (size_t)rec_parts * bt.B * bt.n * 3) +
              (keep ? align256(sizeof(float2) * (size_t)bt.B * bt.nsubpix) : 0) +
-             (bt.tnfw ? align256(sizeof(TRec) * (size_t)bt.B * bt.records) +
-                            align256(sizeof(unsigned long long) * (size_t)bt.n) + align256(sizeof(int) * (size_t)bt.n)
-                      : 0);
+             (bt.tnfw ? align256(sizeof(TRec) * (size_t)bt.B * bt.records) : 0);
   void* ws = nullptr;
   JT_TRY(ctx_workspace(ctx, st, bytes, &ws));
   Carve cv{(char*)ws};
@@ -222,15 +220,13 @@ jt_status chi2_common(jt_ctx* ctx, const jt_grid* grid, const jt_draws* draws, c
   if (bt.tnfw) {
     // per-lane constants of the truncated subhalos, for alpha_Rs = 1
     TRec* utab = cv.take<TRec>((size_t)bt.B * bt.records);
-    unsigned long long* keys = cv.take<unsigned long long>(bt.n);
-    int* perm = cv.take<int>(bt.n);
     JT_TRY(timed_launch(ctx, JT_K_PREP, st, [&] {
       return launch_prep_tnfw_batched(bt.B, bt.n, draws->sub_x, draws->sub_y, draws->sub_Rs, draws->sub_alpha_Rs,
                                       draws->sub_r_trunc, true, utab, st);
     }, "prep_tnfw_unit"));
     JT_TRY(timed_launch(ctx, JT_K_GRAD, st, [&] {
       return launch_grad_subhalo_tnfw(bt.B, bt.n, utab, bt.records, draws->sub_alpha_Rs, rec, rec_stride, nrec_loop,
-                                      keys, perm, gpart, st);
+                                      bt.g, gpart, st);
     }, "grad_subhalo_tnfw"));
   } else {
     JT_TRY(timed_launch(ctx, JT_K_GRAD, st, [&] {

@@ -102,9 +102,8 @@ hipError_t launch_fft_convolve(const float* img, int nx, int ny, const float* ps
 
 // ---- adjoint (adjoint.hip) ----
 constexpr int kRecPartsHost = 4;  // parts of the adjoint's subhalo-major pass
-// The truncated profile's pass takes more, shorter parts: its lanes are sorted
-// so that waves differ in cost, and short waves let the dispatcher even out
-// the load.
+// The truncated profile's far pass takes 16 parts, and its near pass adds one
+// more (part 16 of gpart).
 constexpr int kRecPartsTnfwHost = 16;
 hipError_t launch_residual(int B, int npix, const float* model, const float* data, const float* w, float* resid,
                            float* part, int* nblocks, hipStream_t st);
@@ -113,12 +112,14 @@ hipError_t launch_residual(int B, int npix, const float* model, const float* dat
 // Sersic ...]).
 hipError_t launch_grad_pixel(int split, bool kept, bool tnfw, bool epl, int B, int bpi, const ImageDesc* descs,
                              const float* lamU, float4* rec, int rec_stride, float* part, int P, hipStream_t st);
-// Subhalo-major pass for truncated subhalos; utab [B][records]: each draw's
-// table built for alpha_Rs = 1 (launch_prep_tnfw_batched with unit set).
-// keys [n] and perm [n]: device scratch for the lane order (its own launch).
+// Subhalo-major pass for truncated subhalos: far pairs in kRecPartsTnfwHost
+// parts, then the near pairs (the general form, a wave per subhalo and draw
+// over its box of the grid g) as one more part; gpart holds
+// kRecPartsTnfwHost + 1 parts.  utab [B][records]: each draw's table built for
+// alpha_Rs = 1 (launch_prep_tnfw_batched with unit set).
 hipError_t launch_grad_subhalo_tnfw(int B, int n, const TRec* utab, int records, const float* ars,
-                                    const float4* rec, int rec_stride, int nrec_loop, unsigned long long* keys,
-                                    int* perm, float* gpart, hipStream_t st);
+                                    const float4* rec, int rec_stride, int nrec_loop, const GridC& g, float* gpart,
+                                    hipStream_t st);
 // draws' subhalo SoA x, y, rs, ars: device [B][n]
 hipError_t launch_grad_subhalo(int B, int n, const float* x, const float* y, const float* rs, const float* ars,
                                const float4* rec, int rec_stride, int nrec_loop, float* gpart, hipStream_t st);

@@ -292,3 +292,30 @@ def test_epl_tnfw_kept_positions_bit_for_bit(ctx):
     b = ctx.chi2_grad(truth.grid, _batch(draws), d, w, truth.psf, keep_positions=True)
     for x, y in zip(a, b):
         np.testing.assert_array_equal(_np(x), _np(y))
+
+
+def test_truncated_near_pairs_at_the_grid_edges(ctx):
+    """The truncated subhalos' near pairs (the general form, a wave per subhalo
+    over its box of the sub-pixel grid) against the oracle's autograd gradient,
+    with subhalos placed where that box is clamped or empty: next to a
+    sub-pixel centre, on the left edge, centred outside a corner with its near
+    region reaching into the grid, far outside it, and one whose near region
+    covers the whole grid; the other subhalos as drawn.  42x38 px, s = 2."""
+    grid = W.Grid(nx=42, ny=38, pixel_scale=0.1, x0=0.01, y0=-0.02, supersample=2)
+    truth, draws = W.config4_profile_draws(B=2, n_sub=60, grid=grid, epl=False, tnfw=True)
+    d_px, s = grid.pixel_scale, grid.supersample
+    ox, oy = grid.x0 - d_px * grid.nx / 2, grid.y0 - d_px * grid.ny / 2
+    step = d_px / s
+    for sc in draws:
+        t = sc.lens.nfw
+        place = [(ox + step * (11 + 0.5) + 1e-3 * step, oy + step * (9 + 0.5), 0.05, 10.0),   # by a centre
+                 (ox + 0.3 * step, oy + 0.4 * (grid.ny * d_px), 0.08, 12.0),                # left edge
+                 (ox - 0.15, oy - 0.12, 0.06, 20.0),                                          # outside a corner
+                 (ox - 50.0, oy + 1.0, 0.05, 10.0),                                           # far outside
+                 (grid.x0 + 0.3, grid.y0 - 0.2, 0.3, 30.0)]                                   # covers the grid
+        for i, (x, y, rs, tau) in enumerate(place):
+            t.x[i], t.y[i], t.Rs[i], t.r_trunc[i] = x, y, rs, tau * rs
+    # near regions: rho = max(0.75 tau, 1.5) Rs
+    assert 0.75 * 30.0 * 0.3 > np.hypot(grid.nx * d_px / 2 + 0.3, grid.ny * d_px / 2 + 0.2)
+    d, w = _data(truth, seed=12)
+    _check_grad(ctx, truth, draws, d, w)
