@@ -147,15 +147,13 @@ constexpr SubRec kSubRecPad{1e18f, 1e18f, 0.25f, 0.0f};
 // FP64; then the far-field form: for x^2 = r^2 c1 >= Xf the pair term is
 // c2 T(x) = y^2 sum_k a_k u^k, y = 1/x, u = y k1 - 1 (see tnfw_far_fit).
 constexpr int kTnfwFarDeg = 10;
-// The first 32 bytes (what every pair and the general form read as scalar
-// operands of full-rate instructions, or only inside the general form) are
-// read through scalar loads; the last 48 (k1 and the coefficients, FMA
-// operands of the far form) are staged through LDS.
+// In the fused kernels the first 48 bytes (through k1 and a_2) are read
+// through scalar loads and the last 32 (a_3 .. a_10) staged through LDS.
 struct __align__(16) TRec {
   float x, y, c1, Xf, tau, t2, itau, c2;
   float k1, a[kTnfwFarDeg + 1];
 };
-static_assert(sizeof(TRec) == 80, "TRec is read as 8 scalar floats and three float4s");
+static_assert(sizeof(TRec) == 80, "TRec is read as 12 scalar floats and two float4s");
 
 struct ImageDesc {
   GridC g;               // g.ppb matches the launch's wave split

@@ -2,6 +2,7 @@
 // kernels (gfx950).
 #pragma once
 
+#include <cstddef>
 #include <type_traits>
 
 #include "jt_device.hpp"
@@ -86,23 +87,30 @@ __device__ __forceinline__ float4 subhalo_range_sum(float tx, float ty, const vo
   return make_float4(hx, lx, hy, ly);
 }
 
-// The truncated profile's 80-byte records: the first 32 bytes (centre, c1, Xf,
-// c2 and the general form's tau constants: scalar operands of full-rate
-// instructions, or used only in the general form) through scalar loads; the
-// last 48 (k1 and the far field's 11 coefficients) through LDS, because an FMA
-// reading a scalar register issues at half rate on gfx950.  Each wave copies
-// kStage records' 48-byte tails at a time into its own LDS stage (coalesced
-// 16-byte loads) and every lane then reads the current tails at one address (a
+// The truncated profile's 80-byte records: the first 48 bytes (centre, c1, Xf,
+// c2, the general form's tau constants, k1 and the far field's three lowest
+// coefficients) through scalar loads; the last 32 (the other eight
+// coefficients) through LDS.  An FMA reading a scalar register issues at half
+// rate on gfx950, but the broadcast LDS reads of a wave (1 KB per 16-byte read)
+// share the CU's LDS bandwidth with the other waves, and with three 16-byte
+// reads per record they, not the FMAs, set the loop's pace; with two the four
+// half-rate FMAs cost less than the read saved.  Each wave copies kStage
+// records' 32-byte tails at a time into its own LDS stage (coalesced 16-byte
+// loads) and every lane then reads the current tails at one address (a
 // broadcast) into vector registers.  Records go two per step (tnfw_pair2), the
 // next step's heads loaded while this one computes.  Same pairs, same order,
 // same arithmetic as one record at a time from scalar registers, so the same
 // sums.  Must be called by whole waves (every lane active; the copy is shared
 // out by lane), at most kWaves waves per block.
-constexpr int kTnfwTailQ = 3;   // float4s of a record's LDS tail
-static_assert(kTnfwFarDeg == 10 && sizeof(TRec) == (2 + kTnfwTailQ) * sizeof(float4), "TRec layout");
+constexpr int kTnfwHeadF = 12;  // floats of a record's scalar head
+constexpr int kTnfwHeadQ = kTnfwHeadF / 4;
+constexpr int kTnfwTailQ = 2;   // float4s of a record's LDS tail
+static_assert(kTnfwFarDeg == 10 && sizeof(TRec) == (kTnfwHeadQ + kTnfwTailQ) * sizeof(float4) &&
+                  offsetof(TRec, a) + 3 * sizeof(float) == kTnfwHeadF * sizeof(float),
+              "TRec layout");
 
-__device__ __forceinline__ TRec tnfw_rec(const float (&h)[8], const float4* q) {
-  const float4 q2 = q[0], q3 = q[1], q4 = q[2];
+__device__ __forceinline__ TRec tnfw_rec(const float (&h)[kTnfwHeadF], const float4* q) {
+  const float4 q0 = q[0], q1 = q[1];
   TRec r;
   r.x = h[0];
   r.y = h[1];
@@ -112,18 +120,18 @@ __device__ __forceinline__ TRec tnfw_rec(const float (&h)[8], const float4* q) {
   r.t2 = h[5];
   r.itau = h[6];
   r.c2 = h[7];
-  r.k1 = q2.x;
-  r.a[0] = q2.y;
-  r.a[1] = q2.z;
-  r.a[2] = q2.w;
-  r.a[3] = q3.x;
-  r.a[4] = q3.y;
-  r.a[5] = q3.z;
-  r.a[6] = q3.w;
-  r.a[7] = q4.x;
-  r.a[8] = q4.y;
-  r.a[9] = q4.z;
-  r.a[10] = q4.w;
+  r.k1 = h[8];
+  r.a[0] = h[9];
+  r.a[1] = h[10];
+  r.a[2] = h[11];
+  r.a[3] = q0.x;
+  r.a[4] = q0.y;
+  r.a[5] = q0.z;
+  r.a[6] = q0.w;
+  r.a[7] = q1.x;
+  r.a[8] = q1.y;
+  r.a[9] = q1.z;
+  r.a[10] = q1.w;
   return r;
 }
 
@@ -146,14 +154,14 @@ __device__ __forceinline__ float4 tnfw_range_sum(float tx, float ty, const void*
   const float4* __restrict__ g4 = (const float4*)table;
   const SubTable sub = (SubTable)(const float*)table;
   constexpr int kF = (int)(sizeof(TRec) / sizeof(float));   // floats per record
-  auto head = [&](int k, float (&h)[8]) {
+  auto head = [&](int k, float (&h)[kTnfwHeadF]) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) h[i] = sub[kF * k + i];
+    for (int i = 0; i < kTnfwHeadF; ++i) h[i] = sub[kF * k + i];
   };
   float hx = 0.f, lx = 0.f, hy = 0.f, ly = 0.f;
   // heads of the next two records, loaded a step ahead (the table has readable
   // records past every range end)
-  float ha[8], hb[8];
+  float ha[kTnfwHeadF], hb[kTnfwHeadF];
   head(kb, ha);
   head(kb + 1, hb);
   for (int k0 = kb; k0 < ke; k0 += kSubTile) {
@@ -168,7 +176,7 @@ __device__ __forceinline__ float4 tnfw_range_sum(float tx, float ty, const void*
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       for (int e = lane; e < m * kTnfwTailQ; e += 64) {
         const int rk = e / kTnfwTailQ;
-        st[e] = g4[(size_t)(s0 + rk) * (2 + kTnfwTailQ) + 2 + (e - rk * kTnfwTailQ)];
+        st[e] = g4[(size_t)(s0 + rk) * (kTnfwHeadQ + kTnfwTailQ) + kTnfwHeadQ + (e - rk * kTnfwTailQ)];
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -176,7 +184,7 @@ __device__ __forceinline__ float4 tnfw_range_sum(float tx, float ty, const void*
       // two records per step (m is a multiple of 4: range bounds, tiles and
       // stages all are)
       for (int k = 0; k < m; k += 4) {
-        float hc[8], hd[8];
+        float hc[kTnfwHeadF], hd[kTnfwHeadF];
         {
           const TRec ra = tnfw_rec(ha, st + kTnfwTailQ * k), rb = tnfw_rec(hb, st + kTnfwTailQ * (k + 1));
           tail_wait();
