@@ -15,9 +15,10 @@
 // workgroup of a queued kernel before it turns to another queue, but switches
 // at kernel boundaries of one queue: batches of the requests behind a large
 // one therefore start at the next chunk boundary instead of after the whole
-// image.  While whole requests are queued or running, chunks shrink to half a
-// round of wave slots, one at a time (kChunkSharedBlocks), so the small
-// batches always find half the chip open.
+// image.  While whole requests are queued or running, chunks shrink to 768
+// blocks, three eighths of a round of wave slots, one at a time
+// (kChunkSharedBlocks), so the small batches always find most of the chip
+// open.
 //
 // A batch that fails on the device (its completion event reports an error,
 // or its launch fails) puts the server in a failed state: a device fault can
@@ -55,13 +56,15 @@ size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 // of wave slots on 256 CUs at 8 waves per SIMD.
 constexpr int kChunkMinBlocks = 2048;
 // While whole requests wait in the queue or run, a chunked request takes
-// chunks of at most this many blocks (half a round of wave slots), one at a
-// time, so that at least half the chip stays open to the small batches: the
-// blocks of a large image each run for milliseconds, and the hardware hands a
-// freed slot to whichever queue's kernel is next, so a full-round chunk would
-// hold the whole chip for one block lifetime per chunk.  With nothing else to
-// run the request goes back to full chunks, two queued.
-constexpr int kChunkSharedBlocks = 1024;
+// chunks of at most this many blocks (three eighths of a round of wave
+// slots), one at a time, so that most of the chip stays open to the small
+// batches: the blocks of a large image each run for milliseconds, and the
+// hardware hands a freed slot to whichever queue's kernel is next, so a
+// full-round chunk would hold the whole chip for one block lifetime per chunk.
+// Measured: 512 blocks starve the large images at full load, 1024 leave the
+// small requests a longer tail at half load.  With nothing else to run the
+// request goes back to full chunks, two queued.
+constexpr int kChunkSharedBlocks = 768;
 
 // A truncated-NFW pair costs about 1.55 NFW pairs of GPU time (headline image:
 // 2.08 ms against 1.33 ms); the work caps count it so.
